@@ -1,0 +1,166 @@
+/*
+ * sfm_gm.h -- geometry-aware guided feature matching on one MI355X (gfx950).
+ *
+ * C ABI of libsfmgm.so.  No exceptions, C++ types or torch types cross it;
+ * every call returns an int status (SFM_OK or a negative SFM_E* code) and
+ * sfm_strerror() names it.
+ *
+ * What it computes (Section 6.2 of the paper, "Fast Geometry-aware Feature
+ * Matching", and Appendix A).  For an image pair (a, b) with fundamental
+ * matrix F, every feature of a is a query.  Its epipolar line in b is
+ * l = F (x, y, 1)^T (convention x_b^T F x_a = 0).  Its candidate set is
+ *     C = { features p' of b : |l . (x', y', 1)| / sqrt(l_0^2 + l_1^2) <= d }
+ * (eqs. 2-3, inclusive, d = band_px, the maximum perpendicular distance).  Its
+ * match is the candidate with the smallest squared L2 descriptor distance D1
+ * (exact integer over uint8 values 0..127, ties to the lowest index of b),
+ * accepted when at least two candidates exist and
+ *     ratio_den * D1 < ratio_num * D2            (default 100*D1 < 64*D2),
+ * D2 being the second-smallest distance over the other candidates (the 2-NN
+ * ratio test of Section 6.2.2 / Appendix A step 4 with ratio 0.8 on
+ * distances).  A query whose line is degenerate (l_0 = l_1 = 0) has no
+ * candidates.
+ *
+ * Exactness.  Epipolar distances are evaluated in FP32 on centred
+ * coordinates from lines normalised in FP64; a candidate whose FP64 distance
+ * lies within 1e-3 px of d may be classified differently from an FP64
+ * evaluation.  Every other result -- membership, the match index, D1, D2 and
+ * the candidate count -- equals an FP64 evaluation bit for bit.
+ *
+ * Memory.  All image, descriptor and output buffers are device memory owned
+ * by the caller.  Pair lists and fundamental matrices are host memory, read
+ * before the call returns.  The library owns only its context: the table of
+ * registered images, per-feature squared norms and a workspace it grows on
+ * demand up to the budget given to sfm_create().
+ *
+ * Streams.  Matching calls enqueue their work on the given HIP stream
+ * (hipStream_t passed as void*, NULL = the default stream) and return without
+ * waiting.  Errors found on the host return immediately; an error raised on
+ * the device is reported by sfm_sync() as SFM_EKERNEL.  Calls on one context
+ * must not overlap: they share its workspace.
+ */
+#ifndef SFM_GM_H
+#define SFM_GM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SFM_OK = 0,
+  SFM_EINVAL = -1,     /* an argument is invalid (message in sfm_last_error) */
+  SFM_ENOMEM = -2,     /* a device or pinned host allocation failed */
+  SFM_EHIP = -3,       /* the HIP runtime returned an error */
+  SFM_ECAPACITY = -4,  /* workspace budget or output capacity too small */
+  SFM_EKERNEL = -5,    /* a kernel raised its device error flag */
+  SFM_EBUSY = -6,      /* the server queue is full, or the server is not running */
+  SFM_ETIMEOUT = -7,   /* sfm_server_poll: result not ready within the timeout */
+  SFM_ENOTFOUND = -8   /* sfm_server_poll: unknown or already collected ticket */
+};
+
+typedef struct sfm_ctx sfm_ctx;
+
+/* One image: n features, keypoints xy = float[2*n] (x, y in pixels, x to the
+ * right, y down) and descriptors desc = uint8[128*n] row-major, every byte in
+ * 0..127.  Both are device pointers; n may be 0 (pointers then unused). */
+typedef struct {
+  const float* xy;
+  const uint8_t* desc;
+  int32_t n;
+} sfm_image;
+
+/* Match the features of registered image a (queries) into image b (targets)
+ * with band half-width band_px >= 0 (pixels; +inf = every feature of b). */
+typedef struct {
+  int32_t a;
+  int32_t b;
+  double band_px;
+} sfm_pair;
+
+typedef struct {
+  int32_t ratio_num;      /* 64: accept iff ratio_den * D1 < ratio_num * D2 */
+  int32_t ratio_den;      /* 100 */
+  int32_t accept_single;  /* 0: a query with exactly one candidate is rejected */
+  int32_t emit_all;       /* 0: fill the all_* arrays of sfm_matches when nonzero */
+} sfm_options;
+
+/* Outputs, all device memory owned by the caller.
+ * Accepted matches are written pair after pair in input order and, within a
+ * pair, in ascending query index: rows offset[p] .. offset[p+1]-1 belong to
+ * pair p and hold (query index in a, match index in b, D1, D2).
+ * capacity must be >= the sum of n_a over the pairs (one row per query at
+ * most), so a call never runs out of room.
+ * n_comparisons (optional, int64[n_pairs]) receives the number of candidate
+ * comparisons of each pair, i.e. the sum over its queries of |C|.
+ * With emit_all, all_match/all_d1/all_d2/all_count (int32[sum n_a], pair-major,
+ * query order) receive every query's match (-1 if no candidate), D1, D2
+ * (INT32_MAX if absent) and |C|. */
+typedef struct {
+  int32_t* query;
+  int32_t* match;
+  int32_t* d1;
+  int32_t* d2;
+  int64_t capacity;
+  int64_t* offset;          /* int64[n_pairs + 1] */
+  int64_t* n_comparisons;   /* optional */
+  int32_t* all_match;       /* optional, emit_all */
+  int32_t* all_d1;
+  int32_t* all_d2;
+  int32_t* all_count;
+} sfm_matches;
+
+/* Create a context on HIP device `device`.  workspace_budget_bytes caps the
+ * device workspace (0 = 8 GiB).  Returns SFM_EINVAL for a bad device. */
+int sfm_create(sfm_ctx** ctx, int32_t device, size_t workspace_budget_bytes);
+
+/* Stop the server if running, free the context and everything it owns. */
+int sfm_destroy(sfm_ctx* ctx);
+
+/* Register the images that pairs refer to by index (replaces any previous
+ * set).  Checks that every descriptor byte is <= 127 (SFM_EINVAL otherwise),
+ * precomputes squared norms and keypoint bounding boxes.  Blocks until done.
+ * The caller's buffers must stay valid while the registration is in use. */
+int sfm_register_images(sfm_ctx* ctx, const sfm_image* images, int32_t n_images);
+
+/* Device workspace bytes that matching these pairs needs. */
+int sfm_workspace_size(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, size_t* bytes);
+
+/* Batched guided matching (Section 6.2, Appendix A steps 1-4), every pair in
+ * one sequence of launches: per-pair geometry, binning of b along the
+ * epipolar pencil, query lines and tiles, the fused band test + int8-MFMA
+ * distance + two-nearest kernel, ordered emission.
+ * pairs: host sfm_pair[n_pairs]; F: host double[9*n_pairs], row-major,
+ * x_b^T F x_a = 0, finite and not all zero; opt may be NULL (defaults).
+ * SFM_EINVAL: bad index, band, F or options; SFM_ECAPACITY: out->capacity or
+ * the workspace budget is too small. */
+int sfm_guided_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                     const sfm_options* opt, const sfm_matches* out, void* stream);
+
+/* Same result as sfm_guided_match, computed one pair per launch sequence
+ * (the plain per-pair form the batched form is measured against). */
+int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
+                           const double* F, const sfm_options* opt, const sfm_matches* out,
+                           void* stream);
+
+/* Exhaustive matching: every feature of b is a candidate of every query
+ * (band and F ignored; F may be NULL).  Same outputs; equals guided matching
+ * with band_px = +inf on queries whose line is not degenerate. */
+int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                         const sfm_options* opt, const sfm_matches* out, void* stream);
+
+/* Wait for the context's work on `stream`, then report a device error flag
+ * raised since the last sfm_sync (SFM_EKERNEL) or a HIP error (SFM_EHIP). */
+int sfm_sync(sfm_ctx* ctx, void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* sfm_strerror(int status);
+
+/* Copy the last error message of this context into buf (NUL-terminated). */
+int sfm_last_error(sfm_ctx* ctx, char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFM_GM_H */

@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(LIB_PATH):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
-    cmd = ["g++", "-O3", "-march=native", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["g++", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math",
            "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", tmp] + SOURCES
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)

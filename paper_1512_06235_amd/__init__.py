@@ -1,0 +1,283 @@
+"""MI355X-native geometry-aware guided feature matching.
+
+Thin ctypes binding of libsfmgm.so (C ABI declared in include/sfm_gm.h).  The
+functions below carry the C names and only marshal arguments; every step of
+the matching runs in the library's HIP kernels.  PyTorch supplies device
+memory and streams.  Importing this package does not need a GPU; calling
+into the library does, and fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+from .build import LIB_PATH, build  # noqa: F401
+
+SFM_OK = 0
+SFM_EINVAL = -1
+SFM_ENOMEM = -2
+SFM_EHIP = -3
+SFM_ECAPACITY = -4
+SFM_EKERNEL = -5
+SFM_EBUSY = -6
+SFM_ETIMEOUT = -7
+SFM_ENOTFOUND = -8
+INT32_MAX = 2**31 - 1
+
+
+class SfmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class sfm_image(C.Structure):
+    _fields_ = [("xy", C.c_void_p), ("desc", C.c_void_p), ("n", C.c_int32)]
+
+
+class sfm_pair(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("band_px", C.c_double)]
+
+
+class sfm_options(C.Structure):
+    _fields_ = [("ratio_num", C.c_int32), ("ratio_den", C.c_int32),
+                ("accept_single", C.c_int32), ("emit_all", C.c_int32)]
+
+
+class sfm_matches(C.Structure):
+    _fields_ = [("query", C.c_void_p), ("match", C.c_void_p), ("d1", C.c_void_p),
+                ("d2", C.c_void_p), ("capacity", C.c_int64), ("offset", C.c_void_p),
+                ("n_comparisons", C.c_void_p), ("all_match", C.c_void_p),
+                ("all_d1", C.c_void_p), ("all_d2", C.c_void_p), ("all_count", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded libsfmgm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_1512_06235_amd.build() first "
+                           "(there is no fallback path)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    sig = {
+        "sfm_create": [C.POINTER(vp), i32, sz],
+        "sfm_destroy": [vp],
+        "sfm_register_images": [vp, C.POINTER(sfm_image), i32],
+        "sfm_workspace_size": [vp, C.POINTER(sfm_pair), i32, C.POINTER(sz)],
+        "sfm_guided_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
+                             C.POINTER(sfm_matches), vp],
+        "sfm_guided_match_plain": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
+                                   C.POINTER(sfm_matches), vp],
+        "sfm_bruteforce_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
+                                 C.POINTER(sfm_matches), vp],
+        "sfm_sync": [vp, vp],
+        "sfm_last_error": [vp, C.c_char_p, sz],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.sfm_strerror.argtypes = [C.c_int]
+    L.sfm_strerror.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names of the entry points include/sfm_gm.h declares."""
+    return ["sfm_create", "sfm_destroy", "sfm_register_images", "sfm_workspace_size",
+            "sfm_guided_match", "sfm_guided_match_plain", "sfm_bruteforce_match", "sfm_sync",
+            "sfm_strerror", "sfm_last_error"]
+
+
+# --- C names, marshalling only ------------------------------------------------------------
+
+def sfm_strerror(status: int) -> str:
+    return lib().sfm_strerror(int(status)).decode()
+
+
+def sfm_last_error(ctx) -> str:
+    buf = C.create_string_buffer(512)
+    lib().sfm_last_error(ctx, buf, len(buf))
+    return buf.value.decode()
+
+
+def _check(ctx, status: int):
+    if status != SFM_OK:
+        msg = sfm_last_error(ctx) if ctx else ""
+        raise SfmError(status, f"{sfm_strerror(status)}: {msg}")
+
+
+def sfm_create(device: int = 0, workspace_budget_bytes: int = 0):
+    ctx = C.c_void_p()
+    st = lib().sfm_create(C.byref(ctx), int(device), int(workspace_budget_bytes))
+    if st != SFM_OK:
+        raise SfmError(st, f"sfm_create failed: {sfm_strerror(st)}")
+    return ctx
+
+
+def sfm_destroy(ctx) -> None:
+    _check(None, lib().sfm_destroy(ctx))
+
+
+def sfm_register_images(ctx, images) -> None:
+    """images: list of (xy, desc) torch tensors on the context's device."""
+    arr = (sfm_image * max(1, len(images)))()
+    for k, (xy, desc) in enumerate(images):
+        arr[k] = sfm_image(xy.data_ptr() if xy.numel() else None,
+                           desc.data_ptr() if desc.numel() else None, int(xy.shape[0]))
+    _check(ctx, lib().sfm_register_images(ctx, arr, len(images)))
+
+
+def _pairs(pairs):
+    arr = (sfm_pair * max(1, len(pairs)))()
+    for k, (a, b, band) in enumerate(pairs):
+        arr[k] = sfm_pair(int(a), int(b), float(band))
+    return arr
+
+
+def sfm_workspace_size(ctx, pairs) -> int:
+    n = C.c_size_t()
+    _check(ctx, lib().sfm_workspace_size(ctx, _pairs(pairs), len(pairs), C.byref(n)))
+    return n.value
+
+
+def _call(fn_name, ctx, pairs, F, out: "MatchBuffers", opt: sfm_options, stream):
+    Fh = None
+    if F is not None:
+        Fh = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(len(pairs), 9))
+    st = getattr(lib(), fn_name)(ctx, _pairs(pairs), len(pairs),
+                                 Fh.ctypes.data if Fh is not None else None,
+                                 C.byref(opt), C.byref(out.c_struct()),
+                                 stream.cuda_stream if stream is not None else None)
+    _check(ctx, st)
+
+
+def sfm_guided_match(ctx, pairs, F, out, opt, stream=None):
+    _call("sfm_guided_match", ctx, pairs, F, out, opt, stream)
+
+
+def sfm_guided_match_plain(ctx, pairs, F, out, opt, stream=None):
+    _call("sfm_guided_match_plain", ctx, pairs, F, out, opt, stream)
+
+
+def sfm_bruteforce_match(ctx, pairs, F, out, opt, stream=None):
+    _call("sfm_bruteforce_match", ctx, pairs, F, out, opt, stream)
+
+
+def sfm_sync(ctx, stream=None) -> None:
+    _check(ctx, lib().sfm_sync(ctx, stream.cuda_stream if stream is not None else None))
+
+
+def options(ratio_num=64, ratio_den=100, accept_single=False, emit_all=False) -> sfm_options:
+    return sfm_options(int(ratio_num), int(ratio_den), int(bool(accept_single)),
+                       int(bool(emit_all)))
+
+
+class MatchBuffers:
+    """Device output tensors for up to `capacity` queries over `n_pairs` pairs."""
+
+    def __init__(self, capacity: int, n_pairs: int, device, emit_all: bool = False):
+        import torch
+        i32 = dict(dtype=torch.int32, device=device)
+        cap = max(1, int(capacity))
+        self.capacity = int(capacity)
+        self.n_pairs = int(n_pairs)
+        self.query = torch.empty(cap, **i32)
+        self.match = torch.empty(cap, **i32)
+        self.d1 = torch.empty(cap, **i32)
+        self.d2 = torch.empty(cap, **i32)
+        self.offset = torch.zeros(n_pairs + 1, dtype=torch.int64, device=device)
+        self.n_comparisons = torch.zeros(max(1, n_pairs), dtype=torch.int64, device=device)
+        self.emit_all = emit_all
+        if emit_all:
+            self.all_match = torch.empty(cap, **i32)
+            self.all_d1 = torch.empty(cap, **i32)
+            self.all_d2 = torch.empty(cap, **i32)
+            self.all_count = torch.empty(cap, **i32)
+
+    def c_struct(self) -> sfm_matches:
+        ea = self.emit_all
+        return sfm_matches(self.query.data_ptr(), self.match.data_ptr(), self.d1.data_ptr(),
+                           self.d2.data_ptr(), self.capacity, self.offset.data_ptr(),
+                           self.n_comparisons.data_ptr(),
+                           self.all_match.data_ptr() if ea else None,
+                           self.all_d1.data_ptr() if ea else None,
+                           self.all_d2.data_ptr() if ea else None,
+                           self.all_count.data_ptr() if ea else None)
+
+    def pair(self, p: int):
+        """Host copies of pair p's accepted (query, match, d1, d2)."""
+        off = self.offset.cpu().numpy()
+        s, e = int(off[p]), int(off[p + 1])
+        return tuple(t[s:e].cpu().numpy() for t in (self.query, self.match, self.d1, self.d2))
+
+
+class Matcher:
+    """Context + registered images; results land in MatchBuffers."""
+
+    def __init__(self, device: int = 0, workspace_budget_bytes: int = 0):
+        self.device = device
+        self.ctx = sfm_create(device, workspace_budget_bytes)
+        self.images = []
+
+    def close(self):
+        if self.ctx is not None:
+            sfm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def register(self, images):
+        """images: list of (xy, desc) numpy arrays or device tensors."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        held = []
+        for xy, desc in images:
+            xy_t = torch.as_tensor(np.ascontiguousarray(xy, dtype=np.float32)).reshape(-1, 2) \
+                if not torch.is_tensor(xy) else xy
+            d_t = torch.as_tensor(np.ascontiguousarray(desc, dtype=np.uint8)).reshape(-1, 128) \
+                if not torch.is_tensor(desc) else desc
+            held.append((xy_t.to(dev).contiguous(), d_t.to(dev).contiguous()))
+        sfm_register_images(self.ctx, held)
+        self.images = held
+        return self
+
+    def n_features(self, k: int) -> int:
+        return int(self.images[k][0].shape[0])
+
+    def buffers(self, pairs, emit_all: bool = False) -> MatchBuffers:
+        cap = sum(self.n_features(a) for a, _, _ in pairs)
+        return MatchBuffers(cap, len(pairs), f"cuda:{self.device}", emit_all)
+
+    def match(self, pairs, F, form: str = "batched", emit_all: bool = False, out=None,
+              stream=None, sync: bool = True, **opt_kw) -> MatchBuffers:
+        out = out if out is not None else self.buffers(pairs, emit_all)
+        opt = options(emit_all=emit_all, **opt_kw)
+        if form == "batched":
+            sfm_guided_match(self.ctx, pairs, F, out, opt, stream)
+        elif form == "plain":
+            sfm_guided_match_plain(self.ctx, pairs, F, out, opt, stream)
+        elif form == "bruteforce":
+            sfm_bruteforce_match(self.ctx, pairs, F, out, opt, stream)
+        else:
+            raise ValueError(form)
+        if sync:
+            sfm_sync(self.ctx, stream)
+        return out
+
+
+def infinite_band() -> float:
+    return math.inf

@@ -1,0 +1,445 @@
+// C ABI of libsfmgm: context, image registration, workspace and the launch
+// sequences of the plain, batched and exhaustive forms.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sfm_gm.h"
+#include "sfm_internal.h"
+
+using namespace sfm;
+
+struct sfm_ctx {
+  int32_t device = 0;
+  size_t budget = 0;
+  std::string last_error;
+  std::mutex mu;
+
+  // Registered images.
+  int32_t n_images = 0;
+  std::vector<int32_t> n_host;
+  ImageDev* images_dev = nullptr;
+  int32_t* norm2_dev = nullptr;
+  int64_t* norm_off_dev = nullptr;
+
+  // Workspace and its host staging.
+  char* ws = nullptr;
+  size_t ws_cap = 0;
+  char* pinned = nullptr;
+  size_t pinned_cap = 0;
+  hipEvent_t staging_done = nullptr;   // last copy out of the pinned buffer
+  hipEvent_t work_done = nullptr;      // end of the last matching call
+  int32_t* err_dev = nullptr;
+  bool has_work = false;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int fail(sfm_ctx* ctx, int status, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return status;
+}
+
+int hip_fail(sfm_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, e == hipErrorOutOfMemory ? SFM_ENOMEM : SFM_EHIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return hip_fail((ctx), _e, #expr); \
+  } while (0)
+
+// Sections of one call's workspace.
+struct Layout {
+  size_t pairs, F, geom, counters, cand, bins, qrec, res, blk, total, staged;
+  int64_t sum_na = 0, sum_nb = 0, sum_bins = 0, sum_blocks = 0;
+};
+
+int32_t bins_for(int32_t nb) {
+  return std::max<int32_t>(1, std::min<int32_t>(kMaxBins, nb / 8));
+}
+
+Layout plan(const std::vector<PairDesc>& pd) {
+  Layout L;
+  for (const PairDesc& p : pd) {
+    L.sum_na += p.na;
+    L.sum_nb += p.nb;
+    L.sum_bins += p.nbins + 1;
+    L.sum_blocks += p.nblocks;
+  }
+  const size_t P = pd.size();
+  size_t o = 0;
+  L.pairs = o; o = align_up(o + P * sizeof(PairDesc));
+  L.F = o; o = align_up(o + P * 9 * sizeof(double));
+  L.staged = o;
+  L.geom = o; o = align_up(o + P * sizeof(PairGeom));
+  L.counters = o; o = align_up(o + P * sizeof(PairCounters));
+  L.cand = o; o = align_up(o + size_t(L.sum_nb) * sizeof(CandRec));
+  L.bins = o; o = align_up(o + size_t(L.sum_bins) * sizeof(int32_t));
+  L.qrec = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryRec));
+  L.res = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryResult));
+  L.blk = o; o = align_up(o + size_t(L.sum_blocks) * sizeof(int2));
+  L.total = o;
+  return L;
+}
+
+int describe_pairs(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, bool ignore_band,
+                   std::vector<PairDesc>& pd) {
+  if (n_pairs < 0) return fail(ctx, SFM_EINVAL, "n_pairs < 0");
+  if (n_pairs > 0 && !pairs) return fail(ctx, SFM_EINVAL, "pairs is NULL");
+  pd.resize(size_t(n_pairs));
+  int64_t q = 0, c = 0, bo = 0, blk = 0;
+  for (int32_t k = 0; k < n_pairs; ++k) {
+    const sfm_pair& s = pairs[k];
+    if (s.a < 0 || s.a >= ctx->n_images || s.b < 0 || s.b >= ctx->n_images) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "pair %d: image index out of range (a=%d b=%d, %d registered)", k,
+               s.a, s.b, ctx->n_images);
+      return fail(ctx, SFM_EINVAL, buf);
+    }
+    if (!ignore_band && !(s.band_px >= 0.0)) {
+      char buf[96];
+      snprintf(buf, sizeof buf, "pair %d: band_px must be >= 0 (got %g)", k, s.band_px);
+      return fail(ctx, SFM_EINVAL, buf);
+    }
+    PairDesc& p = pd[size_t(k)];
+    memset(&p, 0, sizeof p);
+    p.a = s.a;
+    p.b = s.b;
+    p.na = ctx->n_host[size_t(s.a)];
+    p.nb = ctx->n_host[size_t(s.b)];
+    p.nbins = ignore_band ? 1 : bins_for(p.nb);
+    p.nblocks = (p.na + kQueryTile - 1) / kQueryTile;
+    p.q_off = q;
+    p.c_off = c;
+    p.bin_off = bo;
+    p.blk_off = blk;
+    p.band = ignore_band ? INFINITY : s.band_px;
+    p.ignore_band = ignore_band ? 1 : 0;
+    q += p.na;
+    c += p.nb;
+    bo += p.nbins + 1;
+    blk += p.nblocks;
+  }
+  if (blk > INT32_MAX / 2) return fail(ctx, SFM_ECAPACITY, "too many query tiles in one call");
+  return SFM_OK;
+}
+
+int ensure_workspace(sfm_ctx* ctx, size_t bytes) {
+  if (bytes > ctx->budget) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "workspace of %zu bytes exceeds the budget of %zu bytes", bytes,
+             ctx->budget);
+    return fail(ctx, SFM_ECAPACITY, buf);
+  }
+  if (bytes <= ctx->ws_cap) return SFM_OK;
+  if (ctx->has_work) HIP_TRY(ctx, hipEventSynchronize(ctx->work_done));
+  if (ctx->ws) HIP_TRY(ctx, hipFree(ctx->ws));
+  ctx->ws = nullptr;
+  ctx->ws_cap = 0;
+  const size_t cap = std::min(ctx->budget, std::max(bytes, bytes + bytes / 4));
+  HIP_TRY(ctx, hipMalloc(&ctx->ws, cap));
+  ctx->ws_cap = cap;
+  return SFM_OK;
+}
+
+int ensure_pinned(sfm_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->pinned_cap) return SFM_OK;
+  HIP_TRY(ctx, hipEventSynchronize(ctx->staging_done));
+  if (ctx->pinned) HIP_TRY(ctx, hipHostFree(ctx->pinned));
+  ctx->pinned = nullptr;
+  ctx->pinned_cap = 0;
+  const size_t cap = std::max<size_t>(bytes, 1 << 16);
+  HIP_TRY(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), cap, hipHostMallocDefault));
+  ctx->pinned_cap = cap;
+  return SFM_OK;
+}
+
+enum class Form { kBatched, kPlain, kExhaustive };
+
+int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+              const sfm_options* opt_in, const sfm_matches* out, void* stream, Form form) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (!out) return fail(ctx, SFM_EINVAL, "out is NULL");
+  sfm_options opt = {64, 100, 0, 0};
+  if (opt_in) opt = *opt_in;
+  if (opt.ratio_den <= 0 || opt.ratio_num < 0)
+    return fail(ctx, SFM_EINVAL, "ratio_den must be > 0 and ratio_num >= 0");
+  const bool exhaustive = form == Form::kExhaustive;
+  std::vector<PairDesc> pd;
+  int rc = describe_pairs(ctx, pairs, n_pairs, exhaustive, pd);
+  if (rc) return rc;
+  if (!exhaustive) {
+    if (n_pairs > 0 && !F) return fail(ctx, SFM_EINVAL, "F is NULL");
+    for (int32_t k = 0; k < n_pairs; ++k) {
+      bool nonzero = false;
+      for (int t = 0; t < 9; ++t) {
+        const double f = F[9 * size_t(k) + size_t(t)];
+        if (!std::isfinite(f)) {
+          char buf[64];
+          snprintf(buf, sizeof buf, "pair %d: F is not finite", k);
+          return fail(ctx, SFM_EINVAL, buf);
+        }
+        nonzero |= f != 0.0;
+      }
+      if (!nonzero) {
+        char buf[64];
+        snprintf(buf, sizeof buf, "pair %d: F is all zero", k);
+        return fail(ctx, SFM_EINVAL, buf);
+      }
+    }
+  }
+  const Layout L = plan(pd);
+  if (!out->offset) return fail(ctx, SFM_EINVAL, "out->offset is NULL");
+  if (out->capacity < L.sum_na) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "output capacity %lld < %lld queries", (long long)out->capacity,
+             (long long)L.sum_na);
+    return fail(ctx, SFM_ECAPACITY, buf);
+  }
+  if (L.sum_na > 0 && (!out->query || !out->match || !out->d1 || !out->d2))
+    return fail(ctx, SFM_EINVAL, "output arrays are NULL");
+  if (opt.emit_all && L.sum_na > 0 &&
+      (!out->all_match || !out->all_d1 || !out->all_d2 || !out->all_count))
+    return fail(ctx, SFM_EINVAL, "emit_all needs all_match, all_d1, all_d2 and all_count");
+
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (n_pairs == 0) {
+    HIP_TRY(ctx, hipMemsetAsync(out->offset, 0, sizeof(int64_t), st));
+    return SFM_OK;
+  }
+  if ((rc = ensure_workspace(ctx, L.total))) return rc;
+  if ((rc = ensure_pinned(ctx, L.staged))) return rc;
+  // Calls on one context are ordered: wait for the previous one on this stream.
+  if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
+
+  HIP_TRY(ctx, hipEventSynchronize(ctx->staging_done));
+  memcpy(ctx->pinned + L.pairs, pd.data(), pd.size() * sizeof(PairDesc));
+  if (exhaustive) {
+    memset(ctx->pinned + L.F, 0, pd.size() * 9 * sizeof(double));
+  } else {
+    memcpy(ctx->pinned + L.F, F, pd.size() * 9 * sizeof(double));
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->ws, ctx->pinned, L.staged, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->staging_done, st));
+
+  BatchView v;
+  v.images = ctx->images_dev;
+  v.pairs = reinterpret_cast<const PairDesc*>(ctx->ws + L.pairs);
+  v.F = reinterpret_cast<const double*>(ctx->ws + L.F);
+  v.geom = reinterpret_cast<PairGeom*>(ctx->ws + L.geom);
+  v.counters = reinterpret_cast<PairCounters*>(ctx->ws + L.counters);
+  v.cand = reinterpret_cast<CandRec*>(ctx->ws + L.cand);
+  v.bin_start = reinterpret_cast<int32_t*>(ctx->ws + L.bins);
+  v.qrec = reinterpret_cast<QueryRec*>(ctx->ws + L.qrec);
+  v.res = reinterpret_cast<QueryResult*>(ctx->ws + L.res);
+  v.blk_win = reinterpret_cast<int2*>(ctx->ws + L.blk);
+  v.err = ctx->err_dev;
+  v.n_pairs = n_pairs;
+  v.total_blocks = int32_t(L.sum_blocks);
+  v.ratio_num = opt.ratio_num;
+  v.ratio_den = opt.ratio_den;
+  v.accept_single = opt.accept_single ? 1 : 0;
+  v.keep_counts = opt.emit_all ? 1 : 0;
+
+  int32_t* am = opt.emit_all ? out->all_match : nullptr;
+  int32_t* ad1 = opt.emit_all ? out->all_d1 : nullptr;
+  int32_t* ad2 = opt.emit_all ? out->all_d2 : nullptr;
+  int32_t* ac = opt.emit_all ? out->all_count : nullptr;
+  if (form == Form::kPlain) {
+    for (int32_t p = 0; p < n_pairs; ++p) {
+      HIP_TRY(ctx, launch_prepare(v, p, 1, st));
+      HIP_TRY(ctx, launch_match(v, int32_t(pd[size_t(p)].blk_off), pd[size_t(p)].nblocks, p, p + 1,
+                                st));
+      HIP_TRY(ctx, launch_emit(v, p, 1, out->offset, out->query, out->match, out->d1, out->d2,
+                               out->n_comparisons, am, ad1, ad2, ac, st));
+    }
+  } else {
+    HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, st));
+    HIP_TRY(ctx, launch_match(v, 0, int32_t(L.sum_blocks), 0, n_pairs, st));
+    HIP_TRY(ctx, launch_emit(v, 0, n_pairs, out->offset, out->query, out->match, out->d1,
+                             out->d2, out->n_comparisons, am, ad1, ad2, ac, st));
+  }
+  HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
+  ctx->has_work = true;
+  return SFM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sfm_strerror(int status) {
+  switch (status) {
+    case SFM_OK: return "ok";
+    case SFM_EINVAL: return "invalid argument";
+    case SFM_ENOMEM: return "out of memory";
+    case SFM_EHIP: return "HIP runtime error";
+    case SFM_ECAPACITY: return "capacity exceeded";
+    case SFM_EKERNEL: return "device error flag raised";
+    case SFM_EBUSY: return "busy";
+    case SFM_ETIMEOUT: return "timed out";
+    case SFM_ENOTFOUND: return "not found";
+    default: return "unknown status";
+  }
+}
+
+int sfm_last_error(sfm_ctx* ctx, char* buf, size_t len) {
+  if (!ctx || !buf || len == 0) return SFM_EINVAL;
+  snprintf(buf, len, "%s", ctx->last_error.c_str());
+  return SFM_OK;
+}
+
+int sfm_create(sfm_ctx** out, int32_t device, size_t budget) {
+  if (!out) return SFM_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SFM_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return SFM_EHIP;
+  sfm_ctx* ctx = new sfm_ctx();
+  ctx->device = device;
+  ctx->budget = budget ? budget : (size_t(8) << 30);
+  if (hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->work_done, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&ctx->err_dev, sizeof(int32_t)) != hipSuccess ||
+      hipMemset(ctx->err_dev, 0, sizeof(int32_t)) != hipSuccess) {
+    sfm_destroy(ctx);
+    return SFM_EHIP;
+  }
+  *out = ctx;
+  return SFM_OK;
+}
+
+static void free_registration(sfm_ctx* ctx) {
+  if (ctx->images_dev) (void)hipFree(ctx->images_dev);
+  if (ctx->norm2_dev) (void)hipFree(ctx->norm2_dev);
+  if (ctx->norm_off_dev) (void)hipFree(ctx->norm_off_dev);
+  ctx->images_dev = nullptr;
+  ctx->norm2_dev = nullptr;
+  ctx->norm_off_dev = nullptr;
+  ctx->n_images = 0;
+  ctx->n_host.clear();
+}
+
+int sfm_destroy(sfm_ctx* ctx) {
+  if (!ctx) return SFM_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  free_registration(ctx);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->err_dev) (void)hipFree(ctx->err_dev);
+  if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+  if (ctx->work_done) (void)hipEventDestroy(ctx->work_done);
+  delete ctx;
+  return SFM_OK;
+}
+
+int sfm_register_images(sfm_ctx* ctx, const sfm_image* images, int32_t n_images) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (n_images < 0 || (n_images > 0 && !images)) return fail(ctx, SFM_EINVAL, "bad image list");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (ctx->has_work) HIP_TRY(ctx, hipEventSynchronize(ctx->work_done));
+  free_registration(ctx);
+  std::vector<ImageDev> host(static_cast<size_t>(n_images));
+  std::vector<int64_t> off(size_t(n_images) + 1, 0);
+  for (int32_t k = 0; k < n_images; ++k) {
+    const sfm_image& s = images[k];
+    if (s.n < 0 || (s.n > 0 && (!s.xy || !s.desc))) {
+      char buf[64];
+      snprintf(buf, sizeof buf, "image %d: bad pointers or size", k);
+      return fail(ctx, SFM_EINVAL, buf);
+    }
+    off[size_t(k) + 1] = off[size_t(k)] + s.n;
+  }
+  if (n_images == 0) return SFM_OK;
+  HIP_TRY(ctx, hipMalloc(&ctx->norm2_dev, std::max<size_t>(4, size_t(off.back()) * 4)));
+  HIP_TRY(ctx, hipMalloc(&ctx->norm_off_dev, off.size() * sizeof(int64_t)));
+  HIP_TRY(ctx, hipMalloc(&ctx->images_dev, host.size() * sizeof(ImageDev)));
+  for (int32_t k = 0; k < n_images; ++k) {
+    ImageDev& d = host[size_t(k)];
+    memset(&d, 0, sizeof d);
+    d.xy = images[k].xy;
+    d.desc = images[k].desc;
+    d.norm2 = ctx->norm2_dev + off[size_t(k)];
+    d.n = images[k].n;
+  }
+  HIP_TRY(ctx, hipMemcpy(ctx->norm_off_dev, off.data(), off.size() * sizeof(int64_t),
+                         hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->images_dev, host.data(), host.size() * sizeof(ImageDev),
+                         hipMemcpyHostToDevice));
+  int32_t* bad = nullptr;
+  HIP_TRY(ctx, hipMalloc(&bad, sizeof(int32_t)));
+  hipError_t e = hipMemset(bad, 0, sizeof(int32_t));
+  if (e == hipSuccess)
+    e = launch_register(host.data(), ctx->images_dev, n_images, ctx->norm2_dev,
+                        ctx->norm_off_dev, nullptr, bad, nullptr);
+  int32_t bad_h = 0;
+  if (e == hipSuccess) e = hipMemcpy(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost);
+  (void)hipFree(bad);
+  if (e != hipSuccess) {
+    free_registration(ctx);
+    return hip_fail(ctx, e, "image registration");
+  }
+  if (bad_h) {
+    free_registration(ctx);
+    return fail(ctx, SFM_EINVAL, "a descriptor byte exceeds 127 or a keypoint is not finite");
+  }
+  ctx->n_images = n_images;
+  ctx->n_host.resize(size_t(n_images));
+  for (int32_t k = 0; k < n_images; ++k) ctx->n_host[size_t(k)] = images[k].n;
+  return SFM_OK;
+}
+
+int sfm_workspace_size(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, size_t* bytes) {
+  if (!ctx || !bytes) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  std::vector<PairDesc> pd;
+  const int rc = describe_pairs(ctx, pairs, n_pairs, false, pd);
+  if (rc) return rc;
+  *bytes = plan(pd).total;
+  return SFM_OK;
+}
+
+int sfm_guided_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                     const sfm_options* opt, const sfm_matches* out, void* stream) {
+  return run_match(ctx, pairs, n_pairs, F, opt, out, stream, Form::kBatched);
+}
+
+int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
+                           const double* F, const sfm_options* opt, const sfm_matches* out,
+                           void* stream) {
+  return run_match(ctx, pairs, n_pairs, F, opt, out, stream, Form::kPlain);
+}
+
+int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                         const sfm_options* opt, const sfm_matches* out, void* stream) {
+  return run_match(ctx, pairs, n_pairs, F, opt, out, stream, Form::kExhaustive);
+}
+
+int sfm_sync(sfm_ctx* ctx, void* stream) {
+  if (!ctx) return SFM_EINVAL;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  int32_t flag = 0;
+  HIP_TRY(ctx, hipMemcpy(&flag, ctx->err_dev, sizeof flag, hipMemcpyDeviceToHost));
+  if (flag) {
+    HIP_TRY(ctx, hipMemset(ctx->err_dev, 0, sizeof(int32_t)));
+    return fail(ctx, SFM_EKERNEL, "a kernel raised the device error flag");
+  }
+  return SFM_OK;
+}
+
+}  // extern "C"

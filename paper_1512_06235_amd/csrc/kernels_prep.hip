@@ -1,0 +1,402 @@
+// Registration, per-pair geometry and binning kernels.
+//
+// Geometry (a1) follows the epipolar relations of Section 6.2: every line
+// l = F x_a passes through the epipole e of image b (e^T F = 0), so the band
+// of eq. (2) around l only holds features of b whose own line through e is
+// close to l.  Binning (a3, Appendix A step 1) sorts b's features by a
+// coordinate of that pencil of lines; query tiling (a2, Appendix A step 2)
+// sorts a's queries by the same coordinate of their lines, so that a tile of
+// consecutive queries needs one contiguous range of b.  Unlike the paper's
+// four overlapping 2d x 2d grids and centre-most cells (eqs. 6-9), the range
+// is a provable superset of every member of the band; the exact test happens
+// in the match kernel.
+#include <cmath>
+
+#include "sfm_internal.h"
+
+namespace sfm {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Registration: squared norms, byte range check, keypoint bounding box.
+// One workgroup per image.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void register_kernel(ImageDev* imgs, int32_t* norm2_all,
+                                                       const int64_t* norm_off, int32_t* bad) {
+  const int k = blockIdx.x;
+  const ImageDev im = imgs[k];
+  int32_t* nrm = norm2_all + norm_off[k];
+  float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+  uint32_t orbits = 0;
+  for (int32_t f = threadIdx.x; f < im.n; f += blockDim.x) {
+    const uint4* row = reinterpret_cast<const uint4*>(im.desc + int64_t(f) * kDescBytes);
+    int32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      const uint4 v = row[w];
+      const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        orbits |= d[t];
+        s = __builtin_amdgcn_udot4(d[t], d[t], uint32_t(s), false);
+      }
+    }
+    nrm[f] = s;
+    const float x = im.xy[2 * f], y = im.xy[2 * f + 1];
+    if (!(isfinite(x) && isfinite(y))) orbits |= 0x80u;  // reported as invalid input
+    mnx = fminf(mnx, x); mny = fminf(mny, y);
+    mxx = fmaxf(mxx, x); mxy = fmaxf(mxy, y);
+  }
+  if (orbits & 0x80808080u) atomicOr(bad, 1);
+  __shared__ float red[4][256];
+  red[0][threadIdx.x] = mnx; red[1][threadIdx.x] = mny;
+  red[2][threadIdx.x] = mxx; red[3][threadIdx.x] = mxy;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) {
+      red[0][threadIdx.x] = fminf(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+      red[1][threadIdx.x] = fminf(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+      red[2][threadIdx.x] = fmaxf(red[2][threadIdx.x], red[2][threadIdx.x + s]);
+      red[3][threadIdx.x] = fmaxf(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (im.n == 0) {
+      imgs[k].bbox[0] = imgs[k].bbox[1] = imgs[k].bbox[2] = imgs[k].bbox[3] = 0.0f;
+    } else {
+      imgs[k].bbox[0] = red[0][0]; imgs[k].bbox[1] = red[1][0];
+      imgs[k].bbox[2] = red[2][0]; imgs[k].bbox[3] = red[3][0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a1: per-pair geometry in FP64.
+// ---------------------------------------------------------------------------
+__device__ inline void cross3(const double* p, const double* q, double* r) {
+  r[0] = p[1] * q[2] - p[2] * q[1];
+  r[1] = p[2] * q[0] - p[0] * q[2];
+  r[2] = p[0] * q[1] - p[1] * q[0];
+}
+
+__device__ void setup_pair(const PairDesc& P, const ImageDev& B, const double* Fin, PairGeom& g) {
+  double fro = 0.0;
+  for (int k = 0; k < 9; ++k) fro += Fin[k] * Fin[k];
+  fro = sqrt(fro);
+  for (int k = 0; k < 9; ++k) g.F[k] = Fin[k] / fro;
+  const double* F = g.F;
+
+  // Epipole of b: e^T F = 0, orthogonal to every column of F.  Take the
+  // cross product of the best-conditioned pair of columns.
+  const double c0[3] = {F[0], F[3], F[6]}, c1[3] = {F[1], F[4], F[7]}, c2[3] = {F[2], F[5], F[8]};
+  double e[3], t[3];
+  cross3(c0, c1, e);
+  double best = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+  cross3(c0, c2, t);
+  double n2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  if (n2 > best) { best = n2; e[0] = t[0]; e[1] = t[1]; e[2] = t[2]; }
+  cross3(c1, c2, t);
+  n2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  if (n2 > best) { best = n2; e[0] = t[0]; e[1] = t[1]; e[2] = t[2]; }
+  const double en = sqrt(best);
+
+  const double bx0 = B.bbox[0], by0 = B.bbox[1], bx1 = B.bbox[2], by1 = B.bbox[3];
+  g.ox = floor(0.5 * (bx0 + bx1));
+  g.oy = floor(0.5 * (by0 + by1));
+  const double cx[4] = {bx0, bx1, bx0, bx1}, cy[4] = {by0, by0, by1, by1};
+  double rbox = 0.0;
+  for (int k = 0; k < 4; ++k) rbox = fmax(rbox, hypot(cx[k] - g.ox, cy[k] - g.oy));
+  g.rbox = rbox;
+  g.half_width = P.band + kBandSlackPx;
+  g.band32 = float(P.band);
+  g.nbins = P.nbins;
+  g.mode = kModeFullScan;
+  g.ex = g.ey = 0.0; g.ux = 1.0; g.uy = 0.0; g.S = 1.0;
+  g.kmin = 0.0; g.kmax = 0.0; g.inv_delta = 0.0;
+  if (P.ignore_band || !(P.band < 1e30) || P.nb == 0 || !(en > 0.0)) return;
+
+  for (int k = 0; k < 3; ++k) e[k] /= en;
+  const double exy = hypot(e[0], e[1]);
+  double kmin = INFINITY, kmax = -INFINITY;
+  if (fabs(e[2]) <= 1e-12 * exy) {
+    // Epipole at infinity: all lines run along u; key = offset along n.
+    g.ux = e[0] / exy; g.uy = e[1] / exy;
+    const double nx = -g.uy, ny = g.ux;
+    for (int k = 0; k < 4; ++k) {
+      const double key = nx * (cx[k] - g.ox) + ny * (cy[k] - g.oy);
+      kmin = fmin(kmin, key); kmax = fmax(kmax, key);
+    }
+    g.mode = kModeParallel;
+  } else {
+    const double Ex = e[0] / e[2], Ey = e[1] / e[2];
+    double ux = g.ox - Ex, uy = g.oy - Ey;
+    const double un = hypot(ux, uy);
+    if (!(un > 0.0)) return;
+    ux /= un; uy /= un;
+    double vmin = INFINITY;
+    for (int k = 0; k < 4; ++k) vmin = fmin(vmin, (cx[k] - Ex) * ux + (cy[k] - Ey) * uy);
+    // The pencil coordinate needs b's box strictly on one side of the epipole,
+    // well clear of the band; otherwise fall back to scanning all of b.
+    if (!(vmin > 4.0 * g.half_width) || !(vmin > 1.0)) return;
+    g.ex = Ex; g.ey = Ey; g.ux = ux; g.uy = uy; g.S = vmin;
+    for (int k = 0; k < 4; ++k) {
+      const double vx = cx[k] - Ex, vy = cy[k] - Ey;
+      const double key = vmin * (-uy * vx + ux * vy) / (ux * vx + uy * vy);
+      kmin = fmin(kmin, key); kmax = fmax(kmax, key);
+    }
+    g.mode = kModePencil;
+  }
+  g.kmin = kmin; g.kmax = kmax;
+  g.inv_delta = (kmax > kmin) ? double(P.nbins) / (kmax - kmin) : 0.0;
+}
+
+__global__ void geometry_kernel(BatchView v, int32_t pb, int32_t pc) {
+  const int32_t p = pb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= pb + pc) return;
+  const PairDesc P = v.pairs[p];
+  PairGeom g;
+  setup_pair(P, v.images[P.b], v.F + 9 * int64_t(p), g);
+  v.geom[p] = g;
+  PairCounters z;
+  z.comparisons = 0;
+  z.accepted = 0;
+  z.ties = 0;
+  v.counters[p] = z;
+}
+
+// ---------------------------------------------------------------------------
+// Keys of the pencil coordinate (shared by a2 and a3).
+// ---------------------------------------------------------------------------
+__device__ inline double point_key(const PairGeom& g, double x, double y) {
+  if (g.mode == kModePencil) {
+    const double vx = x - g.ex, vy = y - g.ey;
+    return g.S * (-g.uy * vx + g.ux * vy) / (g.ux * vx + g.uy * vy);
+  }
+  if (g.mode == kModeParallel) return -g.uy * (x - g.ox) + g.ux * (y - g.oy);
+  return 0.0;
+}
+
+__device__ inline int32_t key_bin(const PairGeom& g, double key) {
+  double t = (key - g.kmin) * g.inv_delta;
+  t = fmin(fmax(t, 0.0), double(g.nbins - 1));
+  return int32_t(floor(t));
+}
+
+// Query line on centred coordinates, its sort bin and its window of bins.
+struct QueryLine {
+  float a, b, c;
+  int32_t sort_bin;
+  int32_t wlo, whi;     // wlo > whi: no feature of b can be in the band
+};
+
+__device__ QueryLine query_line(const PairGeom& g, float xq, float yq) {
+  QueryLine q;
+  const double* F = g.F;
+  const double x = xq, y = yq;
+  double a = F[0] * x + F[1] * y + F[2];
+  double b = F[3] * x + F[4] * y + F[5];
+  double c = F[6] * x + F[7] * y + F[8];
+  const double s = sqrt(a * a + b * b);
+  if (!(s > 0.0) || !isfinite(s) || !isfinite(c)) {
+    q.a = q.b = q.c = NAN;   // the FP32 band test is false for every target
+    q.sort_bin = g.nbins;
+    q.wlo = 1; q.whi = 0;
+    return q;
+  }
+  a /= s; b /= s; c /= s;
+  const double cc = c + a * g.ox + b * g.oy;   // offset on centred coordinates
+  q.a = float(a); q.b = float(b); q.c = float(cc);
+  if (g.mode == kModeFullScan) {
+    q.sort_bin = 0; q.wlo = 0; q.whi = 0;
+    return q;
+  }
+  double lam, h;
+  const double nx = -g.uy, ny = g.ux;
+  if (g.mode == kModePencil) {
+    // Line direction w = (-b, a); key S * tan of its angle to u.
+    const double wpar = -b * g.ux + a * g.uy;
+    const double wper = -b * nx + a * ny;
+    const double eps = fabs(a * g.ex + b * g.ey + c);  // distance of e from the line
+    if (!(eps < 0.5 * g.S)) {                            // inconsistent F: scan everything
+      q.sort_bin = 0; q.wlo = 0; q.whi = g.nbins - 1;
+      return q;
+    }
+    if (fabs(wpar) < 1e-300) { q.sort_bin = g.nbins; q.wlo = 1; q.whi = 0; return q; }
+    lam = g.S * wper / wpar;
+    const double r = lam / g.S;
+    h = (g.half_width + eps) * sqrt(1.0 + r * r);
+  } else {
+    const double dot = a * nx + b * ny;
+    const double sg = dot >= 0.0 ? 1.0 : -1.0;
+    lam = -sg * cc;
+    const double dx = a - sg * nx, dy = b - sg * ny;
+    h = g.half_width + sqrt(dx * dx + dy * dy) * g.rbox;
+  }
+  if (!(lam + h >= g.kmin) || !(lam - h <= g.kmax)) {
+    q.sort_bin = g.nbins; q.wlo = 1; q.whi = 0;
+    return q;
+  }
+  q.sort_bin = key_bin(g, lam);
+  q.wlo = key_bin(g, lam - h);
+  q.whi = key_bin(g, lam + h);
+  return q;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup-wide exclusive scan of cnt[0..n) in LDS (n <= 8 * blockDim).
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void block_exclusive_scan(int32_t* cnt, int32_t n, int32_t* wsum) {
+  constexpr int PER = (kMaxBins + 2 + NT - 1) / NT;
+  const int t = threadIdx.x;
+  int32_t local[PER];
+  int32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = t * PER + k;
+    local[k] = idx < n ? cnt[idx] : 0;
+    sum += local[k];
+  }
+  // Inclusive scan of per-thread sums: within waves, then across waves.
+  const int lane = t & 63, wv = t >> 6;
+  int32_t x = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  if (t == 0) {
+    int32_t run = 0;
+    for (int w = 0; w < NT / 64; ++w) { const int32_t s = wsum[w]; wsum[w] = run; run += s; }
+  }
+  __syncthreads();
+  int32_t run = x - sum + wsum[wv];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = t * PER + k;
+    if (idx < n) cnt[idx] = run;
+    run += local[k];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// a2 + a3: one workgroup per (pair, image).  blockIdx.y = 0 bins the targets
+// of b, blockIdx.y = 1 lines up and tiles the queries of a.
+// ---------------------------------------------------------------------------
+constexpr int kBinThreads = 1024;
+
+__global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t pb) {
+  __shared__ int32_t hist[kMaxBins + 2];
+  __shared__ int32_t wsum[kBinThreads / 64];
+  const int32_t p = pb + blockIdx.x;
+  const PairDesc P = v.pairs[p];
+  const PairGeom g = v.geom[p];
+  const bool targets = blockIdx.y == 0;
+  const int32_t nh = targets ? g.nbins : g.nbins + 1;
+  for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0;
+  __syncthreads();
+
+  if (targets) {
+    const ImageDev B = v.images[P.b];
+    if (P.ignore_band) {
+      // Exhaustive matching keeps b in its own order: one bin, position = index.
+      for (int32_t j = threadIdx.x; j < P.nb; j += blockDim.x) {
+        CandRec r;
+        r.x = 0.0f; r.y = 0.0f;
+        r.ncpos = ((uint32_t(B.norm2[j]) + kDistBias) << kPosBits) | uint32_t(j & (kChunk - 1));
+        r.j = j;
+        v.cand[P.c_off + j] = r;
+      }
+      if (threadIdx.x == 0) {
+        v.bin_start[P.bin_off] = 0;
+        for (int k = 1; k <= g.nbins; ++k) v.bin_start[P.bin_off + k] = P.nb;
+      }
+      return;
+    }
+    for (int32_t j = threadIdx.x; j < P.nb; j += blockDim.x) {
+      const int32_t bin = key_bin(g, point_key(g, B.xy[2 * j], B.xy[2 * j + 1]));
+      atomicAdd(&hist[bin], 1);
+    }
+    __syncthreads();
+    block_exclusive_scan<kBinThreads>(hist, nh, wsum);
+    for (int k = threadIdx.x; k < nh; k += blockDim.x) v.bin_start[P.bin_off + k] = hist[k];
+    if (threadIdx.x == 0) v.bin_start[P.bin_off + nh] = P.nb;
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < P.nb; j += blockDim.x) {
+      const double x = B.xy[2 * j], y = B.xy[2 * j + 1];
+      const int32_t bin = key_bin(g, point_key(g, x, y));
+      const int32_t pos = atomicAdd(&hist[bin], 1);
+      CandRec r;
+      r.x = float(x - g.ox);
+      r.y = float(y - g.oy);
+      r.ncpos = ((uint32_t(B.norm2[j]) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
+      r.j = j;
+      v.cand[P.c_off + pos] = r;
+    }
+    return;
+  }
+
+  // Queries of a.
+  const ImageDev A = v.images[P.a];
+  int2* win = reinterpret_cast<int2*>(v.res + P.q_off);   // scratch until the match kernel
+  if (P.ignore_band) {
+    for (int32_t i = threadIdx.x; i < P.na; i += blockDim.x) {
+      QueryRec r;
+      r.a = 0.0f; r.b = 0.0f; r.c = 0.0f; r.i = i;
+      v.qrec[P.q_off + i] = r;
+    }
+    for (int32_t k = threadIdx.x; k < P.nblocks; k += blockDim.x)
+      v.blk_win[P.blk_off + k] = make_int2(0, 0);
+    return;
+  }
+  for (int32_t i = threadIdx.x; i < P.na; i += blockDim.x) {
+    const QueryLine q = query_line(g, A.xy[2 * i], A.xy[2 * i + 1]);
+    atomicAdd(&hist[q.sort_bin], 1);
+  }
+  __syncthreads();
+  block_exclusive_scan<kBinThreads>(hist, nh, wsum);
+  for (int32_t i = threadIdx.x; i < P.na; i += blockDim.x) {
+    const QueryLine q = query_line(g, A.xy[2 * i], A.xy[2 * i + 1]);
+    const int32_t pos = atomicAdd(&hist[q.sort_bin], 1);
+    QueryRec r;
+    r.a = q.a; r.b = q.b; r.c = q.c; r.i = i;
+    v.qrec[P.q_off + pos] = r;
+    win[pos] = make_int2(q.wlo, q.whi);
+  }
+  __threadfence();
+  __syncthreads();
+  for (int32_t k = threadIdx.x; k < P.nblocks; k += blockDim.x) {
+    int32_t lo = 0x7FFFFFFF, hi = -1;
+    const int32_t e = min(P.na, (k + 1) * kQueryTile);
+    for (int32_t s = k * kQueryTile; s < e; ++s) {
+      const int2 w = win[s];
+      if (w.x <= w.y) { lo = min(lo, w.x); hi = max(hi, w.y); }
+    }
+    v.blk_win[P.blk_off + k] = make_int2(lo, hi);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_t n_images,
+                           int32_t* norm2_all, const int64_t* norm_off, float* bbox_dev,
+                           int32_t* bad_flag, hipStream_t st) {
+  (void)imgs_host;
+  (void)bbox_dev;
+  if (n_images == 0) return hipSuccess;
+  hipLaunchKernelGGL(register_kernel, dim3(n_images), dim3(256), 0, st, imgs_dev, norm2_all,
+                     norm_off, bad_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, hipStream_t st) {
+  if (pc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
+  hipLaunchKernelGGL(bin_kernel, dim3(pc, 2), dim3(kBinThreads), 0, st, v, pb);
+  return hipGetLastError();
+}
+
+}  // namespace sfm

@@ -1,0 +1,127 @@
+// Internal layouts shared by the host driver and the HIP kernels of libsfmgm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfm {
+
+constexpr int kDescBytes = 128;
+constexpr int kQueryTile = 32;          // queries per wave work item (MFMA N)
+constexpr int kCandTile = 32;           // candidates per MFMA step (MFMA M)
+constexpr int kChunk = 1024;            // candidate positions one key encodes
+constexpr int kPosBits = 10;            // log2(kChunk)
+constexpr uint32_t kKeyInf = 0xFFFFFFFFu;
+constexpr int32_t kDistInf = 0x7FFFFFFF;
+constexpr uint32_t kDistBias = 1u << 21;  // makes norm2(c) - 2 q.c >= 0
+constexpr int kMaxBins = 8192;          // LDS histogram size per pair
+constexpr double kBandSlackPx = 1e-2;   // bin windows widen the band by this
+
+// Per image, built at registration.
+struct ImageDev {
+  const float* xy;          // float2[n]
+  const uint8_t* desc;      // uint8[n][128]
+  const int32_t* norm2;     // int32[n], owned by the context
+  int32_t n;
+  int32_t pad;
+  float bbox[4];            // min x, min y, max x, max y of the keypoints
+};
+
+// Per pair, filled on the host: sizes and workspace offsets.
+struct PairDesc {
+  int32_t a, b;
+  int32_t na, nb;
+  int32_t nbins;            // bins of b (full-scan mode uses bin 0 only)
+  int32_t nblocks;          // ceil(na / kQueryTile)
+  int64_t q_off;            // into per-query arrays (prefix of na)
+  int64_t c_off;            // into per-candidate arrays (prefix of nb)
+  int64_t bin_off;          // into bin arrays (prefix of nbins + 1)
+  int64_t blk_off;          // into per-block arrays and the work-item space
+  double band;              // d, pixels (may be +inf)
+  int32_t ignore_band;      // exhaustive matching
+  int32_t pad;
+};
+
+enum GeomMode : int32_t {
+  kModeFullScan = 0,        // every query scans all of b
+  kModePencil = 1,          // finite epipole: key = S * tan(angle about e)
+  kModeParallel = 2,        // epipole at infinity: key = offset across lines
+};
+
+// Per pair, written by the geometry kernel (a1).
+struct PairGeom {
+  double F[9];              // F / ||F||_F
+  double ex, ey;            // finite epipole in b (pencil mode)
+  double ux, uy;            // frame: u along the pencil centre line, n = (-uy, ux)
+  double ox, oy;            // origin of the FP32 centred coordinates
+  double S;                 // key scale (min distance along u, pencil mode)
+  double kmin, kmax;        // key range of b's bounding box
+  double inv_delta;         // nbins / (kmax - kmin)
+  double rbox;              // max distance of a bbox corner from the origin
+  double half_width;        // d + slack, pixels
+  float band32;             // d rounded to FP32 (+inf allowed)
+  int32_t mode;
+  int32_t nbins;
+  int32_t pad;
+};
+
+// One target feature in binned order (16 bytes).
+struct CandRec {
+  float x, y;               // centred FP32 coordinates
+  uint32_t ncpos;           // ((norm2 + kDistBias) << kPosBits) | (pos & (kChunk-1))
+  int32_t j;                // original index in b
+};
+
+// One query in tile order (16 bytes): normalised line on centred coordinates.
+struct QueryRec {
+  float a, b, c;
+  int32_t i;                // original index in a
+};
+
+// Per-query result in original query order (16 bytes).
+struct QueryResult {
+  int32_t match;            // -1 if no candidate
+  int32_t d1, d2;           // kDistInf if absent
+  int32_t flags;            // bit 0 accept; count << 1 when counts are kept
+};
+
+struct PairCounters {
+  unsigned long long comparisons;
+  uint32_t accepted;
+  uint32_t ties;            // chunks that needed the tie-break pass
+};
+
+// Everything a batch launch needs, passed by value.
+struct BatchView {
+  const ImageDev* images;
+  const PairDesc* pairs;
+  PairGeom* geom;
+  CandRec* cand;
+  int32_t* bin_start;       // nbins + 1 per pair
+  QueryRec* qrec;
+  int2* blk_win;            // per block: first, last bin (first > last = empty)
+  QueryResult* res;
+  PairCounters* counters;
+  const double* F;          // 9 per pair
+  int32_t* err;             // device error flag
+  int32_t n_pairs;
+  int32_t total_blocks;
+  int32_t ratio_num, ratio_den;
+  int32_t accept_single;
+  int32_t keep_counts;
+};
+
+// Host launchers (one translation unit each).
+hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_t n_images,
+                           int32_t* norm2_all, const int64_t* norm_off, float* bbox_dev,
+                           int32_t* bad_flag, hipStream_t st);
+hipError_t launch_prepare(const BatchView& v, int32_t pair_begin, int32_t pair_count,
+                          hipStream_t st);
+hipError_t launch_match(const BatchView& v, int32_t blk_begin, int32_t blk_count, int32_t pb,
+                        int32_t pe, hipStream_t st);
+hipError_t launch_emit(const BatchView& v, int32_t pair_begin, int32_t pair_count,
+                       int64_t* offset, int32_t* out_q, int32_t* out_m, int32_t* out_d1,
+                       int32_t* out_d2, int64_t* n_cmp, int32_t* all_m, int32_t* all_d1,
+                       int32_t* all_d2, int32_t* all_c, hipStream_t st);
+
+}  // namespace sfm
