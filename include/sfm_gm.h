@@ -154,6 +154,22 @@ int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, c
  * raised since the last sfm_sync (SFM_EKERNEL) or a HIP error (SFM_EHIP). */
 int sfm_sync(sfm_ctx* ctx, void* stream);
 
+/* Phase timing.  While enabled, every matching call records HIP events on its
+ * stream around its three phases: preparation (geometry, binning, query
+ * tiles), the match kernel, and emission (one record per pair in the plain
+ * form).  sfm_phase_times() waits for the recorded calls, writes the summed
+ * milliseconds of each phase to ms[0..2] and the number of records to
+ * *n_records, and clears the records. */
+int sfm_set_profiling(sfm_ctx* ctx, int32_t enable);
+int sfm_phase_times(sfm_ctx* ctx, double ms[3], int64_t* n_records);
+
+/* Totals of the last matching call, summed over its pairs (waits for it):
+ * out[0] candidate comparisons (sum of |C|), out[1] (query, candidate) slots
+ * the match kernel evaluated (superset ranges padded to 32, so
+ * out[0] / out[1] is the fraction of useful work), out[2] chunks that took the
+ * exact tie-break pass, out[3] accepted matches. */
+int sfm_last_stats(sfm_ctx* ctx, int64_t out[4]);
+
 /* Human-readable name of a status code (static string). */
 const char* sfm_strerror(int status);
 

@@ -79,6 +79,9 @@ def lib() -> C.CDLL:
         "sfm_bruteforce_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
                                  C.POINTER(sfm_matches), vp],
         "sfm_sync": [vp, vp],
+        "sfm_set_profiling": [vp, i32],
+        "sfm_phase_times": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
+        "sfm_last_stats": [vp, C.POINTER(i64)],
         "sfm_last_error": [vp, C.c_char_p, sz],
     }
     for name, args in sig.items():
@@ -95,7 +98,8 @@ def exported_symbols():
     """Names of the entry points include/sfm_gm.h declares."""
     return ["sfm_create", "sfm_destroy", "sfm_register_images", "sfm_workspace_size",
             "sfm_guided_match", "sfm_guided_match_plain", "sfm_bruteforce_match", "sfm_sync",
-            "sfm_strerror", "sfm_last_error"]
+            "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
+            "sfm_last_error"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -175,6 +179,25 @@ def sfm_bruteforce_match(ctx, pairs, F, out, opt, stream=None):
 
 def sfm_sync(ctx, stream=None) -> None:
     _check(ctx, lib().sfm_sync(ctx, stream.cuda_stream if stream is not None else None))
+
+
+def sfm_set_profiling(ctx, enable: bool) -> None:
+    _check(ctx, lib().sfm_set_profiling(ctx, int(bool(enable))))
+
+
+def sfm_phase_times(ctx):
+    """(prepare_ms, match_ms, emit_ms, n_records) summed since the last call."""
+    ms = (C.c_double * 3)()
+    n = C.c_int64()
+    _check(ctx, lib().sfm_phase_times(ctx, ms, C.byref(n)))
+    return ms[0], ms[1], ms[2], n.value
+
+
+def sfm_last_stats(ctx) -> dict:
+    """Totals of the last matching call (waits for it)."""
+    v = (C.c_int64 * 4)()
+    _check(ctx, lib().sfm_last_stats(ctx, v))
+    return {"comparisons": v[0], "slots": v[1], "tie_passes": v[2], "accepted": v[3]}
 
 
 def options(ratio_num=64, ratio_den=100, accept_single=False, emit_all=False) -> sfm_options:

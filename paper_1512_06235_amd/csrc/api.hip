@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -35,6 +36,13 @@ struct sfm_ctx {
   hipEvent_t work_done = nullptr;      // end of the last matching call
   int32_t* err_dev = nullptr;
   bool has_work = false;
+  int32_t last_pairs = 0;              // pairs of the last matching call
+  size_t last_counters = 0;            // workspace offset of its counters
+
+  // Phase timing: 4 events per record (start, after prepare, after match, end).
+  bool profiling = false;
+  std::vector<hipEvent_t> prof_events;
+  std::vector<hipEvent_t> prof_pool;
 };
 
 namespace {
@@ -60,12 +68,22 @@ int hip_fail(sfm_ctx* ctx, hipError_t e, const char* what) {
 
 // Sections of one call's workspace.
 struct Layout {
-  size_t pairs, F, geom, counters, cand, bins, qrec, res, blk, total, staged;
+  size_t pairs, F, geom, counters, cand, bins, qrec, res, qwin, tiles, total, staged;
   int64_t sum_na = 0, sum_nb = 0, sum_bins = 0, sum_blocks = 0;
 };
 
 int32_t bins_for(int32_t nb) {
   return std::max<int32_t>(1, std::min<int32_t>(kMaxBins, nb / 8));
+}
+
+// Consecutive query tiles per wave: enough waves to fill every SIMD a few
+// times over, several tiles each once the batch is large.
+int32_t tiles_per_wave(int64_t tiles) {
+  static const int64_t target = [] {
+    const char* e = getenv("SFM_TARGET_WAVES");
+    return e ? std::max<int64_t>(1, atoll(e)) : int64_t(256) * 4 * 24;
+  }();
+  return int32_t(std::max<int64_t>(1, std::min<int64_t>(8, tiles / target)));
 }
 
 Layout plan(const std::vector<PairDesc>& pd) {
@@ -87,7 +105,8 @@ Layout plan(const std::vector<PairDesc>& pd) {
   L.bins = o; o = align_up(o + size_t(L.sum_bins) * sizeof(int32_t));
   L.qrec = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryRec));
   L.res = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryResult));
-  L.blk = o; o = align_up(o + size_t(L.sum_blocks) * sizeof(int2));
+  L.qwin = o; o = align_up(o + size_t(L.sum_na) * sizeof(int2));
+  L.tiles = o; o = align_up(o + size_t(L.sum_blocks) * sizeof(int4));
   L.total = o;
   return L;
 }
@@ -165,6 +184,21 @@ int ensure_pinned(sfm_ctx* ctx, size_t bytes) {
 }
 
 enum class Form { kBatched, kPlain, kExhaustive };
+
+// Records an event on `st` when profiling is enabled.
+hipError_t prof_mark(sfm_ctx* ctx, hipStream_t st) {
+  if (!ctx->profiling) return hipSuccess;
+  hipEvent_t e;
+  if (!ctx->prof_pool.empty()) {
+    e = ctx->prof_pool.back();
+    ctx->prof_pool.pop_back();
+  } else {
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+  }
+  ctx->prof_events.push_back(e);
+  return hipEventRecord(e, st);
+}
 
 int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
               const sfm_options* opt_in, const sfm_matches* out, void* stream, Form form) {
@@ -244,7 +278,8 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   v.bin_start = reinterpret_cast<int32_t*>(ctx->ws + L.bins);
   v.qrec = reinterpret_cast<QueryRec*>(ctx->ws + L.qrec);
   v.res = reinterpret_cast<QueryResult*>(ctx->ws + L.res);
-  v.blk_win = reinterpret_cast<int2*>(ctx->ws + L.blk);
+  v.qwin = reinterpret_cast<int2*>(ctx->ws + L.qwin);
+  v.tiles = reinterpret_cast<int4*>(ctx->ws + L.tiles);
   v.err = ctx->err_dev;
   v.n_pairs = n_pairs;
   v.total_blocks = int32_t(L.sum_blocks);
@@ -252,6 +287,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   v.ratio_den = opt.ratio_den;
   v.accept_single = opt.accept_single ? 1 : 0;
   v.keep_counts = opt.emit_all ? 1 : 0;
+  v.tiles_per_wave = tiles_per_wave(L.sum_blocks);
 
   int32_t* am = opt.emit_all ? out->all_match : nullptr;
   int32_t* ad1 = opt.emit_all ? out->all_d1 : nullptr;
@@ -259,20 +295,29 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   int32_t* ac = opt.emit_all ? out->all_count : nullptr;
   if (form == Form::kPlain) {
     for (int32_t p = 0; p < n_pairs; ++p) {
+      HIP_TRY(ctx, prof_mark(ctx, st));
       HIP_TRY(ctx, launch_prepare(v, p, 1, st));
-      HIP_TRY(ctx, launch_match(v, int32_t(pd[size_t(p)].blk_off), pd[size_t(p)].nblocks, p, p + 1,
-                                st));
+      HIP_TRY(ctx, prof_mark(ctx, st));
+      HIP_TRY(ctx, launch_match(v, int32_t(pd[size_t(p)].blk_off), pd[size_t(p)].nblocks, st));
+      HIP_TRY(ctx, prof_mark(ctx, st));
       HIP_TRY(ctx, launch_emit(v, p, 1, out->offset, out->query, out->match, out->d1, out->d2,
                                out->n_comparisons, am, ad1, ad2, ac, st));
+      HIP_TRY(ctx, prof_mark(ctx, st));
     }
   } else {
+    HIP_TRY(ctx, prof_mark(ctx, st));
     HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, st));
-    HIP_TRY(ctx, launch_match(v, 0, int32_t(L.sum_blocks), 0, n_pairs, st));
+    HIP_TRY(ctx, prof_mark(ctx, st));
+    HIP_TRY(ctx, launch_match(v, 0, int32_t(L.sum_blocks), st));
+    HIP_TRY(ctx, prof_mark(ctx, st));
     HIP_TRY(ctx, launch_emit(v, 0, n_pairs, out->offset, out->query, out->match, out->d1,
                              out->d2, out->n_comparisons, am, ad1, ad2, ac, st));
+    HIP_TRY(ctx, prof_mark(ctx, st));
   }
   HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
   ctx->has_work = true;
+  ctx->last_pairs = n_pairs;
+  ctx->last_counters = L.counters;
   return SFM_OK;
 }
 
@@ -340,6 +385,8 @@ int sfm_destroy(sfm_ctx* ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->err_dev) (void)hipFree(ctx->err_dev);
+  for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
   if (ctx->work_done) (void)hipEventDestroy(ctx->work_done);
   delete ctx;
@@ -427,6 +474,52 @@ int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
 int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                          const sfm_options* opt, const sfm_matches* out, void* stream) {
   return run_match(ctx, pairs, n_pairs, F, opt, out, stream, Form::kExhaustive);
+}
+
+int sfm_set_profiling(sfm_ctx* ctx, int32_t enable) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  ctx->profiling = enable != 0;
+  return SFM_OK;
+}
+
+int sfm_phase_times(sfm_ctx* ctx, double ms[3], int64_t* n_records) {
+  if (!ctx || !ms) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  ms[0] = ms[1] = ms[2] = 0.0;
+  const size_t n = ctx->prof_events.size() / 4;
+  if (!ctx->prof_events.empty()) HIP_TRY(ctx, hipEventSynchronize(ctx->prof_events.back()));
+  for (size_t r = 0; r < n; ++r) {
+    for (int k = 0; k < 3; ++k) {
+      float t = 0.0f;
+      HIP_TRY(ctx, hipEventElapsedTime(&t, ctx->prof_events[4 * r + k],
+                                       ctx->prof_events[4 * r + k + 1]));
+      ms[k] += t;
+    }
+  }
+  for (hipEvent_t e : ctx->prof_events) ctx->prof_pool.push_back(e);
+  ctx->prof_events.clear();
+  if (n_records) *n_records = int64_t(n);
+  return SFM_OK;
+}
+
+int sfm_last_stats(sfm_ctx* ctx, int64_t out[4]) {
+  if (!ctx || !out) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  out[0] = out[1] = out[2] = out[3] = 0;
+  if (!ctx->has_work || ctx->last_pairs == 0) return SFM_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipEventSynchronize(ctx->work_done));
+  std::vector<PairCounters> c(size_t(ctx->last_pairs));
+  HIP_TRY(ctx, hipMemcpy(c.data(), ctx->ws + ctx->last_counters, c.size() * sizeof(PairCounters),
+                         hipMemcpyDeviceToHost));
+  for (const PairCounters& k : c) {
+    out[0] += int64_t(k.comparisons);
+    out[1] += int64_t(k.elements);
+    out[2] += k.ties;
+    out[3] += k.accepted;
+  }
+  return SFM_OK;
 }
 
 int sfm_sync(sfm_ctx* ctx, void* stream) {

@@ -16,6 +16,8 @@
 //         key = ((||c||^2 - 2 q.c + 2^21) << 10) | (position mod 1024),
 //     so one unsigned min and one med3 keep (D1, its position) and D2;
 //   - the 32 + 32 lanes of one query merge with one cross-half exchange.
+// Loads are software-pipelined: the binned record of tile t+2 and the
+// descriptor rows of tile t+1 are in flight while tile t is computed.
 // The key orders equal distances by binned position, not by index in b; when
 // the two smallest keys of a chunk share the distance, an exact pass picks the
 // lowest index among the tied candidates, so results equal the definition.
@@ -47,14 +49,6 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
   return max(min(a, b), min(max(a, b), c));   // selects v_med3_u32
 }
 
-// Largest p in [lo, hi) with pairs[p].blk_off <= item.
-__device__ inline int32_t find_pair(const PairDesc* pairs, int32_t lo, int32_t hi, int64_t item) {
-  while (hi - lo > 1) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (pairs[mid].blk_off <= item) lo = mid; else hi = mid;
-  }
-  return lo;
-}
 
 // Workgroups are dealt to the 8 XCDs round-robin; renumber them so each XCD
 // gets one contiguous run of work items (neighbouring query tiles of one pair
@@ -79,122 +73,171 @@ __device__ inline int32_t row_dist(const uint8_t* p, const uint8_t* q, int32_t n
   return np + nq - 2 * int32_t(dot);
 }
 
-template <bool kKeepCounts>
-__global__ __launch_bounds__(256) void match_kernel(BatchView v, int32_t blk_begin,
-                                                    int32_t blk_count, int32_t pb, int32_t pe) {
-  __shared__ __attribute__((aligned(16))) float smX[kWaves][kCandTile];
-  __shared__ __attribute__((aligned(16))) float smY[kWaves][kCandTile];
-  __shared__ __attribute__((aligned(16))) uint32_t smN[kWaves][kCandTile];
+// Global-address-space views: loads through them compile to global_load_*,
+// which only count against vmcnt (flat loads would also hold up LDS waits).
+typedef unsigned int nv4u __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) nv4u g_nv4u;
+typedef const __attribute__((address_space(1))) int32_t g_i32;
 
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t item = xcd_contiguous(blockIdx.x, gridDim.x) * kWaves + wave;
-  if (item >= blk_count) return;
-  const int64_t gblk = int64_t(blk_begin) + item;
-  const int32_t p = find_pair(v.pairs, pb, pe, gblk);
-  const PairDesc P = v.pairs[p];
-  const int32_t blk = int32_t(gblk - P.blk_off);
-  const ImageDev A = v.images[P.a];
-  const ImageDev B = v.images[P.b];
-  const float band = v.geom[p].band32;
+__device__ __forceinline__ nv4u gload16(const void* p) { return *(g_nv4u*)p; }
+
+// Raw binned record {x, y, ncpos, j} of position min(cp, c1 - 1); the caller
+// masks positions >= c1 when it stages the record (c1 > 0 is guaranteed).
+__device__ __forceinline__ nv4u load_rec(const CandRec* cand, int32_t cp, int32_t c1) {
+  return gload16(cand + min(cp, c1 - 1));
+}
+
+// This lane's 4 x 16 bytes of candidate row j (k-slices 16 * half + 32 * s).
+// Rows of masked candidates are loaded too; their products are discarded.
+__device__ __forceinline__ void load_rows(const uint8_t* desc, int32_t j, int half, v4i* a) {
+  const uint8_t* row = desc + int64_t(j) * kDescBytes + 16 * half;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const nv4u u = gload16(row + 32 * s);
+    a[s] = v4i{int(u.x), int(u.y), int(u.z), int(u.w)};
+  }
+}
+
+// One 32-candidate step of a query tile, in two parts.
+// tile_loads: stage the coordinates and keys of record r (positions t0 ..
+// t0+31) in LDS, then issue the descriptor rows of the next step (record rn,
+// loaded two steps ago) into an and the record three steps ahead into r.  It
+// runs unconditionally -- every address is clamped into the range -- so the
+// number of loads in flight never depends on the path taken, and the compiler
+// can wait for exactly the loads a step consumes.
+__device__ __forceinline__ void tile_loads(int32_t t0, int32_t c1, const CandRec* cand,
+                                           const uint8_t* bdesc, nv4u& r, const nv4u& rn,
+                                           v4i (&an)[4], float* smX, float* smY, uint32_t* smN,
+                                           int col, int half) {
+  // Both halves hold the same 32 records and store identical values, which
+  // keeps the stores out of a divergent branch.  Positions past the range get
+  // a NaN coordinate: no band test passes.
+  smX[col] = t0 + col < c1 ? __uint_as_float(r.x) : NAN;
+  smY[col] = __uint_as_float(r.y);
+  smN[col] = r.z;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  load_rows(bdesc, int32_t(rn.w), half, an);
+  r = load_rec(cand, t0 + 3 * kCandTile + col, c1);
+}
+
+// tile_compute: the four MFMAs on this step's rows ac, then this lane's 16
+// results folded into the running two smallest keys (k1, k2).
+template <bool kKeepCounts>
+__device__ __forceinline__ void tile_compute(const v4i (&ac)[4], const v4i (&bq)[4],
+                                             const QueryRec& qr, float band, const float* smX,
+                                             const float* smY, const uint32_t* smN, int half,
+                                             uint32_t& k1, uint32_t& k2, uint32_t& total,
+                                             int32_t& cnt) {
+  v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(ac[s], bq[s], acc, 0, 0, 0);
+
+  // Lane (col, half) holds rows 8g + 4*half + e of the tile, e = 0..3.
+  uint32_t tile_total = 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int r0 = 8 * g + 4 * half;
+    const float4 xs = *reinterpret_cast<const float4*>(&smX[r0]);
+    const float4 ys = *reinterpret_cast<const float4*>(&smY[r0]);
+    const uint4 ns = *reinterpret_cast<const uint4*>(&smN[r0]);
+    const float xv[4] = {xs.x, xs.y, xs.z, xs.w};
+    const float yv[4] = {ys.x, ys.y, ys.z, ys.w};
+    const uint32_t nv[4] = {ns.x, ns.y, ns.z, ns.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool mem = in_band(qr.a, qr.b, qr.c, xv[e], yv[e], band);
+      uint32_t key = nv[e] + (uint32_t(acc[4 * g + e]) << 11);
+      key = mem ? key : kKeyInf;
+      k2 = umed3(k1, key, k2);
+      k1 = min(k1, key);
+      tile_total += __builtin_popcountll(__ballot(mem));
+      if (kKeepCounts) cnt += mem ? 1 : 0;
+    }
+  }
+  total += tile_total;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One query tile: its 32 queries against the candidate range [s_begin, s_end).
+template <bool kKeepCounts>
+__device__ __forceinline__ void match_tile(const BatchView& v, const PairDesc& P, int32_t p,
+                                           const ImageDev& A, const ImageDev& B, float band,
+                                           int32_t blk, int32_t s_begin, int32_t s_end,
+                                           float* smX, float* smY, uint32_t* smN, int lane) {
   const int col = lane & 31, half = lane >> 5;
 
   // This lane's query column: line, squared norm and negated descriptor
-  // bytes as the MFMA B operand (k-slice 16 * half + 32 * s of the row).
+  // bytes as the MFMA B operand.
   const int32_t qs = blk * kQueryTile + col;
   const bool qv = qs < P.na;
   QueryRec qr;
   if (qv) {
-    qr = v.qrec[P.q_off + qs];
+    const nv4u u = gload16(v.qrec + P.q_off + qs);
+    qr.a = __uint_as_float(u.x);
+    qr.b = __uint_as_float(u.y);
+    qr.c = __uint_as_float(u.z);
+    qr.i = int32_t(u.w);
   } else {
     qr.a = qr.b = qr.c = NAN;
     qr.i = 0;
   }
+  const CandRec* cand = v.cand + P.c_off;
+  // First candidate records go out together with the query loads.
+  nv4u r0 = {0u, 0u, 0u, 0u}, r1 = r0, r2 = r0;
+  if (s_end > s_begin) {
+    r0 = load_rec(cand, s_begin + col, s_end);
+    r1 = load_rec(cand, s_begin + kCandTile + col, s_end);
+    r2 = load_rec(cand, s_begin + 2 * kCandTile + col, s_end);
+  }
   v4i bq[4];
   int32_t nq = 0;
-  if (qv) {
-    const uint4* qrow = reinterpret_cast<const uint4*>(A.desc + int64_t(qr.i) * kDescBytes + 16 * half);
+  {
+    // Padding columns (qv false) read query row 0; their line is NaN.
+    const uint8_t* qrow = A.desc + int64_t(qr.i) * kDescBytes + 16 * half;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const uint4 w = qrow[2 * s];
-      bq[s] = v4i{neg_bytes(w.x), neg_bytes(w.y), neg_bytes(w.z), neg_bytes(w.w)};
+      const nv4u u = gload16(qrow + 32 * s);
+      bq[s] = v4i{neg_bytes(u.x), neg_bytes(u.y), neg_bytes(u.z), neg_bytes(u.w)};
     }
-    nq = A.norm2[qr.i];
-  } else {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) bq[s] = v4i{0, 0, 0, 0};
-  }
-
-  int32_t s_begin = 0, s_end = 0;
-  const int2 w = v.blk_win[P.blk_off + blk];
-  if (w.x <= w.y) {
-    s_begin = v.bin_start[P.bin_off + w.x];
-    s_end = v.bin_start[P.bin_off + w.y + 1];
+    nq = ((g_i32*)A.norm2)[qr.i];
   }
 
   int32_t d1 = kDistInf, d2 = kDistInf, j1 = -1, cnt = 0;
   unsigned long long total = 0;    // in-band comparisons of this tile (wave-uniform)
   uint32_t ties = 0;
-  const CandRec* cand = v.cand + P.c_off;
 
   for (int32_t c0 = s_begin; c0 < s_end; c0 += kChunk) {
     const int32_t c1 = min(s_end, c0 + kChunk);
     uint32_t k1 = kKeyInf, k2 = kKeyInf;
-    for (int32_t t0 = c0; t0 < c1; t0 += kCandTile) {
-      const int32_t cp = t0 + col;
-      const bool cv = cp < c1;
-      CandRec cr;
-      v4i ac[4];
-      if (cv) {
-        cr = cand[cp];
-        const uint4* crow = reinterpret_cast<const uint4*>(B.desc + int64_t(cr.j) * kDescBytes + 16 * half);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const uint4 u = crow[2 * s];
-          ac[s] = v4i{int(u.x), int(u.y), int(u.z), int(u.w)};
-        }
-      } else {
-        cr.x = cr.y = NAN;
-        cr.ncpos = 0;
-        cr.j = 0;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) ac[s] = v4i{0, 0, 0, 0};
-      }
-      if (half == 0) {
-        smX[wave][col] = cr.x;
-        smY[wave][col] = cr.y;
-        smN[wave][col] = cr.ncpos;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-      v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(ac[s], bq[s], acc, 0, 0, 0);
-
-      // Lane (col, half) holds rows 8g + 4*half + e of the tile, e = 0..3.
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int r0 = 8 * g + 4 * half;
-        const float4 xs = *reinterpret_cast<const float4*>(&smX[wave][r0]);
-        const float4 ys = *reinterpret_cast<const float4*>(&smY[wave][r0]);
-        const uint4 ns = *reinterpret_cast<const uint4*>(&smN[wave][r0]);
-        const float xv[4] = {xs.x, xs.y, xs.z, xs.w};
-        const float yv[4] = {ys.x, ys.y, ys.z, ys.w};
-        const uint32_t nv[4] = {ns.x, ns.y, ns.z, ns.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool mem = in_band(qr.a, qr.b, qr.c, xv[e], yv[e], band);
-          uint32_t key = nv[e] + (uint32_t(acc[4 * g + e]) << 11);
-          key = mem ? key : kKeyInf;
-          k2 = umed3(k1, key, k2);
-          k1 = min(k1, key);
-          total += __builtin_popcountll(__ballot(mem));
-          if (kKeepCounts) cnt += mem ? 1 : 0;
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
+    uint32_t chunk_total = 0;
+    if (c0 != s_begin) {
+      // Later chunks of a long range (the first chunk's records were issued
+      // with the query loads; a chunk is longer than three steps).
+      r0 = load_rec(cand, c0 + col, c1);
+      r1 = load_rec(cand, c0 + kCandTile + col, c1);
+      r2 = load_rec(cand, c0 + 2 * kCandTile + col, c1);
     }
+    // Three record and two row register sets rotate over six consecutive
+    // 32-candidate steps, so no in-flight load is ever copied (a copy would
+    // wait for it).
+    v4i a0[4], a1[4];
+    load_rows(B.desc, int32_t(r0.w), half, a0);
+#define SFM_STEP(k, rc, rn, ac, an)                                                             \
+  tile_loads(t0 + (k) * kCandTile, c1, cand, B.desc, rc, rn, an, smX, smY, smN, col, half);    \
+  if (t0 + (k) * kCandTile < c1)                                                                \
+    tile_compute<kKeepCounts>(ac, bq, qr, band, smX, smY, smN, half, k1, k2, chunk_total, cnt);
+    for (int32_t t0 = c0; t0 < c1; t0 += 6 * kCandTile) {
+      SFM_STEP(0, r0, r1, a0, a1)
+      SFM_STEP(1, r1, r2, a1, a0)
+      SFM_STEP(2, r2, r0, a0, a1)
+      SFM_STEP(3, r0, r1, a1, a0)
+      SFM_STEP(4, r1, r2, a0, a1)
+      SFM_STEP(5, r2, r0, a1, a0)
+    }
+#undef SFM_STEP
+    total += chunk_total;
 
     // Merge the two halves of each query column.
     {
@@ -260,24 +303,62 @@ __global__ __launch_bounds__(256) void match_kernel(BatchView v, int32_t blk_beg
   }
   const uint32_t nacc = __builtin_popcountll(__ballot(accept && qv && half == 0));
   if (lane == 0) {
+    const unsigned long long padded =
+        (unsigned long long)((s_end - s_begin + kCandTile - 1) / kCandTile) * (kCandTile * kQueryTile);
     if (total) atomicAdd(&v.counters[p].comparisons, total);
+    if (padded) atomicAdd(&v.counters[p].elements, padded);
     if (nacc) atomicAdd(&v.counters[p].accepted, nacc);
     if (ties) atomicAdd(&v.counters[p].ties, ties);
   }
 }
 
+// Each wave walks tiles_per_wave consecutive query tiles of [blk_begin, blk_end)
+// (they may belong to different pairs); per-pair data is reloaded on change.
+#ifndef SFM_MATCH_WAVES_PER_EU
+#define SFM_MATCH_WAVES_PER_EU 3
+#endif
+template <bool kKeepCounts>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
+void match_kernel(BatchView v, int32_t blk_begin, int32_t blk_end) {
+  __shared__ __attribute__((aligned(16))) float smX[kWaves][kCandTile];
+  __shared__ __attribute__((aligned(16))) float smY[kWaves][kCandTile];
+  __shared__ __attribute__((aligned(16))) uint32_t smN[kWaves][kCandTile];
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t item = xcd_contiguous(blockIdx.x, gridDim.x) * kWaves + wave;
+  const int64_t t_first = int64_t(blk_begin) + int64_t(item) * v.tiles_per_wave;
+  const int64_t t_last = min(int64_t(blk_end), t_first + v.tiles_per_wave);
+  int32_t cur = -1;
+  PairDesc P;
+  ImageDev A, B;
+  float band = 0.0f;
+  for (int64_t t = t_first; t < t_last; ++t) {
+    const int4 ti = v.tiles[t];
+    if (ti.x != cur) {
+      cur = ti.x;
+      P = v.pairs[cur];
+      A = v.images[P.a];
+      B = v.images[P.b];
+      band = v.geom[cur].band32;
+    }
+    match_tile<kKeepCounts>(v, P, cur, A, B, band, ti.y, ti.z, ti.w, smX[wave], smY[wave],
+                            smN[wave], lane);
+  }
+}
+
 }  // namespace
 
-hipError_t launch_match(const BatchView& v, int32_t blk_begin, int32_t blk_count, int32_t pb,
-                        int32_t pe, hipStream_t st) {
+hipError_t launch_match(const BatchView& v, int32_t blk_begin, int32_t blk_count, hipStream_t st) {
   if (blk_count <= 0) return hipSuccess;
-  const int32_t groups = (blk_count + kWaves - 1) / kWaves;
+  const int32_t per_wave = v.tiles_per_wave;
+  const int32_t waves = (blk_count + per_wave - 1) / per_wave;
+  const int32_t groups = (waves + kWaves - 1) / kWaves;
   if (v.keep_counts)
     hipLaunchKernelGGL(match_kernel<true>, dim3(groups), dim3(64 * kWaves), 0, st, v, blk_begin,
-                       blk_count, pb, pe);
+                       blk_begin + blk_count);
   else
     hipLaunchKernelGGL(match_kernel<false>, dim3(groups), dim3(64 * kWaves), 0, st, v, blk_begin,
-                       blk_count, pb, pe);
+                       blk_begin + blk_count);
   return hipGetLastError();
 }
 

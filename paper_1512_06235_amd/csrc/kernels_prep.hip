@@ -160,6 +160,7 @@ __global__ void geometry_kernel(BatchView v, int32_t pb, int32_t pc) {
   v.geom[p] = g;
   PairCounters z;
   z.comparisons = 0;
+  z.elements = 0;
   z.accepted = 0;
   z.ties = 0;
   v.counters[p] = z;
@@ -287,6 +288,7 @@ __device__ void block_exclusive_scan(int32_t* cnt, int32_t n, int32_t* wsum) {
 // of b, blockIdx.y = 1 lines up and tiles the queries of a.
 // ---------------------------------------------------------------------------
 constexpr int kBinThreads = 1024;
+constexpr int kBatch = 8;   // items per thread per round; their loads are issued together
 
 __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t pb) {
   __shared__ int32_t hist[kMaxBins + 2];
@@ -298,6 +300,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
   const int32_t nh = targets ? g.nbins : g.nbins + 1;
   for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0;
   __syncthreads();
+  constexpr int32_t kStride = kBatch * kBinThreads;
 
   if (targets) {
     const ImageDev B = v.images[P.b];
@@ -316,66 +319,117 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
       }
       return;
     }
-    for (int32_t j = threadIdx.x; j < P.nb; j += blockDim.x) {
-      const int32_t bin = key_bin(g, point_key(g, B.xy[2 * j], B.xy[2 * j + 1]));
-      atomicAdd(&hist[bin], 1);
+    for (int32_t base = threadIdx.x; base < P.nb; base += kStride) {
+      float px[kBatch], py[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int32_t j = base + k * kBinThreads;
+        if (j < P.nb) { px[k] = B.xy[2 * j]; py[k] = B.xy[2 * j + 1]; }
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        if (base + k * kBinThreads < P.nb) atomicAdd(&hist[key_bin(g, point_key(g, px[k], py[k]))], 1);
+      }
     }
     __syncthreads();
     block_exclusive_scan<kBinThreads>(hist, nh, wsum);
     for (int k = threadIdx.x; k < nh; k += blockDim.x) v.bin_start[P.bin_off + k] = hist[k];
     if (threadIdx.x == 0) v.bin_start[P.bin_off + nh] = P.nb;
     __syncthreads();
-    for (int32_t j = threadIdx.x; j < P.nb; j += blockDim.x) {
-      const double x = B.xy[2 * j], y = B.xy[2 * j + 1];
-      const int32_t bin = key_bin(g, point_key(g, x, y));
-      const int32_t pos = atomicAdd(&hist[bin], 1);
-      CandRec r;
-      r.x = float(x - g.ox);
-      r.y = float(y - g.oy);
-      r.ncpos = ((uint32_t(B.norm2[j]) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
-      r.j = j;
-      v.cand[P.c_off + pos] = r;
+    for (int32_t base = threadIdx.x; base < P.nb; base += kStride) {
+      float px[kBatch], py[kBatch];
+      int32_t nrm[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int32_t j = base + k * kBinThreads;
+        if (j < P.nb) { px[k] = B.xy[2 * j]; py[k] = B.xy[2 * j + 1]; nrm[k] = B.norm2[j]; }
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int32_t j = base + k * kBinThreads;
+        if (j >= P.nb) continue;
+        const double x = px[k], y = py[k];
+        const int32_t pos = atomicAdd(&hist[key_bin(g, point_key(g, x, y))], 1);
+        CandRec r;
+        r.x = float(x - g.ox);
+        r.y = float(y - g.oy);
+        r.ncpos = ((uint32_t(nrm[k]) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
+        r.j = j;
+        v.cand[P.c_off + pos] = r;
+      }
     }
     return;
   }
 
   // Queries of a.
   const ImageDev A = v.images[P.a];
-  int2* win = reinterpret_cast<int2*>(v.res + P.q_off);   // scratch until the match kernel
+  int2* win = v.qwin + P.q_off;
   if (P.ignore_band) {
     for (int32_t i = threadIdx.x; i < P.na; i += blockDim.x) {
       QueryRec r;
       r.a = 0.0f; r.b = 0.0f; r.c = 0.0f; r.i = i;
       v.qrec[P.q_off + i] = r;
+      win[i] = make_int2(0, 0);
     }
-    for (int32_t k = threadIdx.x; k < P.nblocks; k += blockDim.x)
-      v.blk_win[P.blk_off + k] = make_int2(0, 0);
     return;
   }
-  for (int32_t i = threadIdx.x; i < P.na; i += blockDim.x) {
-    const QueryLine q = query_line(g, A.xy[2 * i], A.xy[2 * i + 1]);
-    atomicAdd(&hist[q.sort_bin], 1);
+  for (int32_t base = threadIdx.x; base < P.na; base += kStride) {
+    float px[kBatch], py[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t i = base + k * kBinThreads;
+      if (i < P.na) { px[k] = A.xy[2 * i]; py[k] = A.xy[2 * i + 1]; }
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      if (base + k * kBinThreads < P.na) atomicAdd(&hist[query_line(g, px[k], py[k]).sort_bin], 1);
+    }
   }
   __syncthreads();
   block_exclusive_scan<kBinThreads>(hist, nh, wsum);
-  for (int32_t i = threadIdx.x; i < P.na; i += blockDim.x) {
-    const QueryLine q = query_line(g, A.xy[2 * i], A.xy[2 * i + 1]);
-    const int32_t pos = atomicAdd(&hist[q.sort_bin], 1);
-    QueryRec r;
-    r.a = q.a; r.b = q.b; r.c = q.c; r.i = i;
-    v.qrec[P.q_off + pos] = r;
-    win[pos] = make_int2(q.wlo, q.whi);
-  }
-  __threadfence();
-  __syncthreads();
-  for (int32_t k = threadIdx.x; k < P.nblocks; k += blockDim.x) {
-    int32_t lo = 0x7FFFFFFF, hi = -1;
-    const int32_t e = min(P.na, (k + 1) * kQueryTile);
-    for (int32_t s = k * kQueryTile; s < e; ++s) {
-      const int2 w = win[s];
-      if (w.x <= w.y) { lo = min(lo, w.x); hi = max(hi, w.y); }
+  for (int32_t base = threadIdx.x; base < P.na; base += kStride) {
+    float px[kBatch], py[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t i = base + k * kBinThreads;
+      if (i < P.na) { px[k] = A.xy[2 * i]; py[k] = A.xy[2 * i + 1]; }
     }
-    v.blk_win[P.blk_off + k] = make_int2(lo, hi);
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t i = base + k * kBinThreads;
+      if (i >= P.na) continue;
+      const QueryLine q = query_line(g, px[k], py[k]);
+      const int32_t pos = atomicAdd(&hist[q.sort_bin], 1);
+      QueryRec r;
+      r.a = q.a; r.b = q.b; r.c = q.c; r.i = i;
+      v.qrec[P.q_off + pos] = r;
+      win[pos] = make_int2(q.wlo, q.whi);
+    }
+  }
+}
+
+// Candidate range of every query tile: the union of its queries' bin windows
+// mapped through b's bin starts.  One workgroup per pair, one thread per tile.
+__global__ __launch_bounds__(256) void tile_ranges_kernel(BatchView v, int32_t pb) {
+  const int32_t p = pb + blockIdx.x;
+  const PairDesc P = v.pairs[p];
+  for (int32_t k = threadIdx.x; k < P.nblocks; k += blockDim.x) {
+    const int32_t s0 = k * kQueryTile;
+    int2 w[kQueryTile];
+#pragma unroll
+    for (int s = 0; s < kQueryTile; ++s)
+      w[s] = s0 + s < P.na ? v.qwin[P.q_off + s0 + s] : make_int2(1, 0);
+    int32_t lo = 0x7FFFFFFF, hi = -1;
+#pragma unroll
+    for (int s = 0; s < kQueryTile; ++s) {
+      if (w[s].x <= w[s].y) { lo = min(lo, w[s].x); hi = max(hi, w[s].y); }
+    }
+    int32_t sb = 0, se = 0;
+    if (lo <= hi) {
+      sb = v.bin_start[P.bin_off + lo];
+      se = v.bin_start[P.bin_off + hi + 1];
+    }
+    v.tiles[P.blk_off + k] = make_int4(p, k, sb, se);
   }
 }
 
@@ -396,6 +450,7 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, hipStream_
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
   hipLaunchKernelGGL(bin_kernel, dim3(pc, 2), dim3(kBinThreads), 0, st, v, pb);
+  hipLaunchKernelGGL(tile_ranges_kernel, dim3(pc), dim3(256), 0, st, v, pb);
   return hipGetLastError();
 }
 

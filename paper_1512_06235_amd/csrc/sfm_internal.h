@@ -87,6 +87,7 @@ struct QueryResult {
 
 struct PairCounters {
   unsigned long long comparisons;
+  unsigned long long elements;   // (query, candidate) slots evaluated, padding included
   uint32_t accepted;
   uint32_t ties;            // chunks that needed the tie-break pass
 };
@@ -99,7 +100,8 @@ struct BatchView {
   CandRec* cand;
   int32_t* bin_start;       // nbins + 1 per pair
   QueryRec* qrec;
-  int2* blk_win;            // per block: first, last bin (first > last = empty)
+  int2* qwin;               // per query in tile order: first, last bin (first > last = none)
+  int4* tiles;              // per query tile: pair, tile index, first and end candidate
   QueryResult* res;
   PairCounters* counters;
   const double* F;          // 9 per pair
@@ -109,6 +111,7 @@ struct BatchView {
   int32_t ratio_num, ratio_den;
   int32_t accept_single;
   int32_t keep_counts;
+  int32_t tiles_per_wave;   // consecutive query tiles one wave walks
 };
 
 // Host launchers (one translation unit each).
@@ -117,8 +120,7 @@ hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_
                            int32_t* bad_flag, hipStream_t st);
 hipError_t launch_prepare(const BatchView& v, int32_t pair_begin, int32_t pair_count,
                           hipStream_t st);
-hipError_t launch_match(const BatchView& v, int32_t blk_begin, int32_t blk_count, int32_t pb,
-                        int32_t pe, hipStream_t st);
+hipError_t launch_match(const BatchView& v, int32_t blk_begin, int32_t blk_count, hipStream_t st);
 hipError_t launch_emit(const BatchView& v, int32_t pair_begin, int32_t pair_count,
                        int64_t* offset, int32_t* out_q, int32_t* out_m, int32_t* out_d1,
                        int32_t* out_d2, int64_t* n_cmp, int32_t* all_m, int32_t* all_d1,
