@@ -87,55 +87,77 @@ __device__ __forceinline__ nv4u load_rec(const CandRec* cand, int32_t cp, int32_
   return gload16(cand + min(cp, c1 - 1));
 }
 
-// This lane's 4 x 16 bytes of candidate row j (k-slices 16 * half + 32 * s).
-// Rows of masked candidates are loaded too; their products are discarded.
-__device__ __forceinline__ void load_rows(const uint8_t* desc, int32_t j, int half, v4i* a) {
-  const uint8_t* row = desc + int64_t(j) * kDescBytes + 16 * half;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const nv4u u = gload16(row + 32 * s);
-    a[s] = v4i{int(u.x), int(u.y), int(u.z), int(u.w)};
-  }
-}
+// Per-wave LDS: two stages of 32 candidate rows and their metadata.  A row is
+// stored as eight 16-byte chunks with chunk c of row r at slot c ^ (r & 7), so
+// that both the coalesced stores (eight lanes per row) and the MFMA operand
+// reads (one row per lane) hit all 32 banks without conflicts.
+struct WaveLds {
+  uint8_t rows[2][kCandTile * kDescBytes];
+  float x[2][kCandTile];
+  float y[2][kCandTile];
+  uint32_t nc[2][kCandTile];
+  int32_t jt[2][8][4];       // row index of candidate 8k + m at jt[m][k]
+};
 
-// One 32-candidate step of a query tile, in two parts.
-// tile_loads: stage the coordinates and keys of record r (positions t0 ..
-// t0+31) in LDS, then issue the descriptor rows of the next step (record rn,
-// loaded two steps ago) into an and the record three steps ahead into r.  It
-// runs unconditionally -- every address is clamped into the range -- so the
-// number of loads in flight never depends on the path taken, and the compiler
-// can wait for exactly the loads a step consumes.
-__device__ __forceinline__ void tile_loads(int32_t t0, int32_t c1, const CandRec* cand,
-                                           const uint8_t* bdesc, nv4u& r, const nv4u& rn,
-                                           v4i (&an)[4], float* smX, float* smY, uint32_t* smN,
-                                           int col, int half) {
-  // Both halves hold the same 32 records and store identical values, which
-  // keeps the stores out of a divergent branch.  Positions past the range get
-  // a NaN coordinate: no band test passes.
-  smX[col] = t0 + col < c1 ? __uint_as_float(r.x) : NAN;
-  smY[col] = __uint_as_float(r.y);
-  smN[col] = r.z;
+__device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  load_rows(bdesc, int32_t(rn.w), half, an);
-  r = load_rec(cand, t0 + 3 * kCandTile + col, c1);
+}
+
+// Stage record r of position t0 + col into metadata slot st.  Both halves
+// hold the same 32 records and store identical values (no divergent branch).
+// Positions past the range get a NaN coordinate: no band test passes.
+__device__ __forceinline__ void stage_meta(WaveLds& L, int st, const nv4u& r, int32_t t0,
+                                           int32_t c1, int col) {
+  L.x[st][col] = t0 + col < c1 ? __uint_as_float(r.x) : NAN;
+  L.y[st][col] = __uint_as_float(r.y);
+  L.nc[st][col] = r.z;
+  L.jt[st][col & 7][col >> 3] = int32_t(r.w);
+}
+
+// Coalesced loads of the 32 rows named in slot st: lane l fetches 16-byte
+// chunk (l & 7) of row 8k + (l >> 3), k = 0..3, so eight lanes read one
+// contiguous 128-byte row.
+__device__ __forceinline__ void load_rows_coalesced(const WaveLds& L, int st,
+                                                    const uint8_t* desc, int lane, nv4u (&rw)[4]) {
+  const int4 j = *reinterpret_cast<const int4*>(&L.jt[st][lane >> 3][0]);
+  const int32_t jj[4] = {j.x, j.y, j.z, j.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) rw[k] = gload16(desc + int64_t(jj[k]) * kDescBytes + 16 * (lane & 7));
+}
+
+__device__ __forceinline__ void store_rows(WaveLds& L, int st, int lane, const nv4u (&rw)[4]) {
+  const int m = lane >> 3, c = lane & 7;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    *reinterpret_cast<nv4u*>(&L.rows[st][(8 * k + m) * kDescBytes + ((c ^ (m & 7)) << 4)]) = rw[k];
+}
+
+// The MFMA A operand: row (lane & 31), k-slice 16 * half + 32 * s = chunk 2s + half.
+__device__ __forceinline__ void read_a(const WaveLds& L, int st, int lane, v4i (&a)[4]) {
+  const int r = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    a[s] = *reinterpret_cast<const v4i*>(&L.rows[st][r * kDescBytes + (((2 * s + h) ^ (r & 7)) << 4)]);
 }
 
 // tile_compute: the four MFMAs on this step's rows ac, then this lane's 16
-// results folded into the running two smallest keys (k1, k2).
+// results folded into the running two smallest keys (k1, k2), with the
+// candidates' coordinates and keys read from metadata slot st.
 template <bool kKeepCounts>
 __device__ __forceinline__ void tile_compute(const v4i (&ac)[4], const v4i (&bq)[4],
-                                             const QueryRec& qr, float band, const float* smX,
-                                             const float* smY, const uint32_t* smN, int half,
-                                             uint32_t& k1, uint32_t& k2, uint32_t& total,
+                                             const QueryRec& qr, float band, const WaveLds& L,
+                                             int st, int half, uint32_t& k1, uint32_t& k2,
                                              int32_t& cnt) {
+  const float* smX = L.x[st];
+  const float* smY = L.y[st];
+  const uint32_t* smN = L.nc[st];
   v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(ac[s], bq[s], acc, 0, 0, 0);
 
   // Lane (col, half) holds rows 8g + 4*half + e of the tile, e = 0..3.
-  uint32_t tile_total = 0;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     const int r0 = 8 * g + 4 * half;
@@ -152,11 +174,9 @@ __device__ __forceinline__ void tile_compute(const v4i (&ac)[4], const v4i (&bq)
       key = mem ? key : kKeyInf;
       k2 = umed3(k1, key, k2);
       k1 = min(k1, key);
-      tile_total += __builtin_popcountll(__ballot(mem));
-      if (kKeepCounts) cnt += mem ? 1 : 0;
+      cnt += mem ? 1 : 0;   // per lane, in VALU: no VALU -> SALU hand-off per slot
     }
   }
-  total += tile_total;
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -165,7 +185,7 @@ template <bool kKeepCounts>
 __device__ __forceinline__ void match_tile(const BatchView& v, const PairDesc& P, int32_t p,
                                            const ImageDev& A, const ImageDev& B, float band,
                                            int32_t blk, int32_t s_begin, int32_t s_end,
-                                           float* smX, float* smY, uint32_t* smN, int lane) {
+                                           WaveLds& L, int lane) {
   const int col = lane & 31, half = lane >> 5;
 
   // This lane's query column: line, squared norm and negated descriptor
@@ -184,13 +204,9 @@ __device__ __forceinline__ void match_tile(const BatchView& v, const PairDesc& P
     qr.i = 0;
   }
   const CandRec* cand = v.cand + P.c_off;
-  // First candidate records go out together with the query loads.
-  nv4u r0 = {0u, 0u, 0u, 0u}, r1 = r0, r2 = r0;
-  if (s_end > s_begin) {
-    r0 = load_rec(cand, s_begin + col, s_end);
-    r1 = load_rec(cand, s_begin + kCandTile + col, s_end);
-    r2 = load_rec(cand, s_begin + 2 * kCandTile + col, s_end);
-  }
+  // The first candidate record goes out together with the query loads.
+  nv4u rc = {0u, 0u, 0u, 0u};
+  if (s_end > s_begin) rc = load_rec(cand, s_begin + col, s_end);
   v4i bq[4];
   int32_t nq = 0;
   {
@@ -205,39 +221,32 @@ __device__ __forceinline__ void match_tile(const BatchView& v, const PairDesc& P
   }
 
   int32_t d1 = kDistInf, d2 = kDistInf, j1 = -1, cnt = 0;
-  unsigned long long total = 0;    // in-band comparisons of this tile (wave-uniform)
   uint32_t ties = 0;
 
   for (int32_t c0 = s_begin; c0 < s_end; c0 += kChunk) {
     const int32_t c1 = min(s_end, c0 + kChunk);
     uint32_t k1 = kKeyInf, k2 = kKeyInf;
-    uint32_t chunk_total = 0;
-    if (c0 != s_begin) {
-      // Later chunks of a long range (the first chunk's records were issued
-      // with the query loads; a chunk is longer than three steps).
-      r0 = load_rec(cand, c0 + col, c1);
-      r1 = load_rec(cand, c0 + kCandTile + col, c1);
-      r2 = load_rec(cand, c0 + 2 * kCandTile + col, c1);
+    if (c0 != s_begin) rc = load_rec(cand, c0 + col, c1);
+    // Step u works on positions c0 + 32u .. +31 from LDS slot u & 1.  While it
+    // computes, the rows of step u+1 and the record of step u+2 are in flight;
+    // rows are addressed from LDS and always read as whole 128-byte rows, eight
+    // lanes per row.
+    stage_meta(L, 0, rc, c0, c1, col);
+    wave_sync_lds();
+    nv4u rw[4];
+    load_rows_coalesced(L, 0, B.desc, lane, rw);
+    rc = load_rec(cand, c0 + kCandTile + col, c1);
+    int st = 0;
+    for (int32_t t0 = c0; t0 < c1; t0 += kCandTile, st ^= 1) {
+      store_rows(L, st, lane, rw);
+      stage_meta(L, st ^ 1, rc, t0 + kCandTile, c1, col);
+      wave_sync_lds();
+      load_rows_coalesced(L, st ^ 1, B.desc, lane, rw);
+      rc = load_rec(cand, t0 + 2 * kCandTile + col, c1);
+      v4i a[4];
+      read_a(L, st, lane, a);
+      tile_compute<kKeepCounts>(a, bq, qr, band, L, st, half, k1, k2, cnt);
     }
-    // Three record and two row register sets rotate over six consecutive
-    // 32-candidate steps, so no in-flight load is ever copied (a copy would
-    // wait for it).
-    v4i a0[4], a1[4];
-    load_rows(B.desc, int32_t(r0.w), half, a0);
-#define SFM_STEP(k, rc, rn, ac, an)                                                             \
-  tile_loads(t0 + (k) * kCandTile, c1, cand, B.desc, rc, rn, an, smX, smY, smN, col, half);    \
-  if (t0 + (k) * kCandTile < c1)                                                                \
-    tile_compute<kKeepCounts>(ac, bq, qr, band, smX, smY, smN, half, k1, k2, chunk_total, cnt);
-    for (int32_t t0 = c0; t0 < c1; t0 += 6 * kCandTile) {
-      SFM_STEP(0, r0, r1, a0, a1)
-      SFM_STEP(1, r1, r2, a1, a0)
-      SFM_STEP(2, r2, r0, a0, a1)
-      SFM_STEP(3, r0, r1, a1, a0)
-      SFM_STEP(4, r1, r2, a0, a1)
-      SFM_STEP(5, r2, r0, a1, a0)
-    }
-#undef SFM_STEP
-    total += chunk_total;
 
     // Merge the two halves of each query column.
     {
@@ -292,7 +301,11 @@ __device__ __forceinline__ void match_tile(const BatchView& v, const PairDesc& P
   } else {
     accept = d1 != kDistInf && v.accept_single;
   }
-  if (kKeepCounts) cnt += __shfl_xor(cnt, 32, 64);
+  cnt += __shfl_xor(cnt, 32, 64);   // |C| of this lane's query
+  // In-band comparisons of the tile: the sum of its queries' counts.
+  int32_t tsum = (half == 0) ? cnt : 0;
+  for (int o = 16; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
+  const unsigned long long total = (unsigned long long)__shfl(tsum, 0, 64);
   if (qv && half == 0) {
     QueryResult out;
     out.match = j1;
@@ -320,9 +333,7 @@ __device__ __forceinline__ void match_tile(const BatchView& v, const PairDesc& P
 template <bool kKeepCounts>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
 void match_kernel(BatchView v, int32_t blk_begin, int32_t blk_end) {
-  __shared__ __attribute__((aligned(16))) float smX[kWaves][kCandTile];
-  __shared__ __attribute__((aligned(16))) float smY[kWaves][kCandTile];
-  __shared__ __attribute__((aligned(16))) uint32_t smN[kWaves][kCandTile];
+  __shared__ __attribute__((aligned(16))) WaveLds lds[kWaves];
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int32_t item = xcd_contiguous(blockIdx.x, gridDim.x) * kWaves + wave;
@@ -341,8 +352,7 @@ void match_kernel(BatchView v, int32_t blk_begin, int32_t blk_end) {
       B = v.images[P.b];
       band = v.geom[cur].band32;
     }
-    match_tile<kKeepCounts>(v, P, cur, A, B, band, ti.y, ti.z, ti.w, smX[wave], smY[wave],
-                            smN[wave], lane);
+    match_tile<kKeepCounts>(v, P, cur, A, B, band, ti.y, ti.z, ti.w, lds[wave], lane);
   }
 }
 
