@@ -68,31 +68,23 @@ int hip_fail(sfm_ctx* ctx, hipError_t e, const char* what) {
 
 // Sections of one call's workspace.
 struct Layout {
-  size_t pairs, F, geom, counters, cand, bins, qrec, res, qwin, tiles, total, staged;
-  int64_t sum_na = 0, sum_nb = 0, sum_bins = 0, sum_blocks = 0;
+  size_t pairs, F, geom, counters, wg_start, cand, bins, qrec, res, qwin, groups, gcost, total, staged;
+  int32_t wgs = 0;
+  int64_t sum_na = 0, sum_nb = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
 };
 
 int32_t bins_for(int32_t nb) {
   return std::max<int32_t>(1, std::min<int32_t>(kMaxBins, nb / 8));
 }
 
-// Consecutive query tiles per wave: enough waves to fill every SIMD a few
-// times over, several tiles each once the batch is large.
-int32_t tiles_per_wave(int64_t tiles) {
-  static const int64_t target = [] {
-    const char* e = getenv("SFM_TARGET_WAVES");
-    return e ? std::max<int64_t>(1, atoll(e)) : int64_t(256) * 4 * 24;
-  }();
-  return int32_t(std::max<int64_t>(1, std::min<int64_t>(8, tiles / target)));
-}
-
-Layout plan(const std::vector<PairDesc>& pd) {
+Layout plan(const std::vector<PairDesc>& pd, int32_t device) {
   Layout L;
   for (const PairDesc& p : pd) {
     L.sum_na += p.na;
     L.sum_nb += p.nb;
     L.sum_bins += p.nbins + 1;
     L.sum_blocks += p.nblocks;
+    L.sum_groups += p.ngroups;
   }
   const size_t P = pd.size();
   size_t o = 0;
@@ -101,12 +93,15 @@ Layout plan(const std::vector<PairDesc>& pd) {
   L.staged = o;
   L.geom = o; o = align_up(o + P * sizeof(PairGeom));
   L.counters = o; o = align_up(o + P * sizeof(PairCounters));
+  L.wgs = match_workgroups(device, L.sum_groups);
+  L.wg_start = o; o = align_up(o + size_t(L.wgs + 1) * sizeof(int32_t));
   L.cand = o; o = align_up(o + size_t(L.sum_nb) * sizeof(CandRec));
   L.bins = o; o = align_up(o + size_t(L.sum_bins) * sizeof(int32_t));
   L.qrec = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryRec));
   L.res = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryResult));
   L.qwin = o; o = align_up(o + size_t(L.sum_na) * sizeof(int2));
-  L.tiles = o; o = align_up(o + size_t(L.sum_blocks) * sizeof(int4));
+  L.groups = o; o = align_up(o + size_t(L.sum_groups) * sizeof(TileGroup));
+  L.gcost = o; o = align_up(o + size_t(L.sum_groups) * sizeof(int32_t));
   L.total = o;
   return L;
 }
@@ -116,7 +111,7 @@ int describe_pairs(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, bool ig
   if (n_pairs < 0) return fail(ctx, SFM_EINVAL, "n_pairs < 0");
   if (n_pairs > 0 && !pairs) return fail(ctx, SFM_EINVAL, "pairs is NULL");
   pd.resize(size_t(n_pairs));
-  int64_t q = 0, c = 0, bo = 0, blk = 0;
+  int64_t q = 0, c = 0, bo = 0, blk = 0, grp = 0;
   for (int32_t k = 0; k < n_pairs; ++k) {
     const sfm_pair& s = pairs[k];
     if (s.a < 0 || s.a >= ctx->n_images || s.b < 0 || s.b >= ctx->n_images) {
@@ -138,16 +133,19 @@ int describe_pairs(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, bool ig
     p.nb = ctx->n_host[size_t(s.b)];
     p.nbins = ignore_band ? 1 : bins_for(p.nb);
     p.nblocks = (p.na + kQueryTile - 1) / kQueryTile;
+    p.ngroups = (p.nblocks + kGroupTiles - 1) / kGroupTiles;
     p.q_off = q;
     p.c_off = c;
     p.bin_off = bo;
     p.blk_off = blk;
+    p.grp_off = grp;
     p.band = ignore_band ? INFINITY : s.band_px;
     p.ignore_band = ignore_band ? 1 : 0;
     q += p.na;
     c += p.nb;
     bo += p.nbins + 1;
     blk += p.nblocks;
+    grp += p.ngroups;
   }
   if (blk > INT32_MAX / 2) return fail(ctx, SFM_ECAPACITY, "too many query tiles in one call");
   return SFM_OK;
@@ -233,7 +231,8 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
       }
     }
   }
-  const Layout L = plan(pd);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const Layout L = plan(pd, ctx->device);
   if (!out->offset) return fail(ctx, SFM_EINVAL, "out->offset is NULL");
   if (out->capacity < L.sum_na) {
     char buf[128];
@@ -248,7 +247,6 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
     return fail(ctx, SFM_EINVAL, "emit_all needs all_match, all_d1, all_d2 and all_count");
 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
   if (n_pairs == 0) {
     HIP_TRY(ctx, hipMemsetAsync(out->offset, 0, sizeof(int64_t), st));
     return SFM_OK;
@@ -279,7 +277,8 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   v.qrec = reinterpret_cast<QueryRec*>(ctx->ws + L.qrec);
   v.res = reinterpret_cast<QueryResult*>(ctx->ws + L.res);
   v.qwin = reinterpret_cast<int2*>(ctx->ws + L.qwin);
-  v.tiles = reinterpret_cast<int4*>(ctx->ws + L.tiles);
+  v.wg_start = reinterpret_cast<int32_t*>(ctx->ws + L.wg_start);
+  v.gcost = reinterpret_cast<int32_t*>(ctx->ws + L.gcost);
   v.err = ctx->err_dev;
   v.n_pairs = n_pairs;
   v.total_blocks = int32_t(L.sum_blocks);
@@ -287,7 +286,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   v.ratio_den = opt.ratio_den;
   v.accept_single = opt.accept_single ? 1 : 0;
   v.keep_counts = opt.emit_all ? 1 : 0;
-  v.tiles_per_wave = tiles_per_wave(L.sum_blocks);
+  v.groups = reinterpret_cast<TileGroup*>(ctx->ws + L.groups);
 
   int32_t* am = opt.emit_all ? out->all_match : nullptr;
   int32_t* ad1 = opt.emit_all ? out->all_d1 : nullptr;
@@ -296,9 +295,11 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   if (form == Form::kPlain) {
     for (int32_t p = 0; p < n_pairs; ++p) {
       HIP_TRY(ctx, prof_mark(ctx, st));
-      HIP_TRY(ctx, launch_prepare(v, p, 1, st));
+      const int32_t g0 = int32_t(pd[size_t(p)].grp_off), gn = pd[size_t(p)].ngroups;
+      const int32_t wgs = match_workgroups(ctx->device, gn);
+      HIP_TRY(ctx, launch_prepare(v, p, 1, g0, gn, wgs, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
-      HIP_TRY(ctx, launch_match(v, int32_t(pd[size_t(p)].blk_off), pd[size_t(p)].nblocks, st));
+      HIP_TRY(ctx, launch_match(v, gn > 0 ? wgs : 0, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
       HIP_TRY(ctx, launch_emit(v, p, 1, out->offset, out->query, out->match, out->d1, out->d2,
                                out->n_comparisons, am, ad1, ad2, ac, st));
@@ -306,9 +307,9 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
     }
   } else {
     HIP_TRY(ctx, prof_mark(ctx, st));
-    HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, st));
+    HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, 0, int32_t(L.sum_groups), L.wgs, st));
     HIP_TRY(ctx, prof_mark(ctx, st));
-    HIP_TRY(ctx, launch_match(v, 0, int32_t(L.sum_blocks), st));
+    HIP_TRY(ctx, launch_match(v, L.sum_groups > 0 ? L.wgs : 0, st));
     HIP_TRY(ctx, prof_mark(ctx, st));
     HIP_TRY(ctx, launch_emit(v, 0, n_pairs, out->offset, out->query, out->match, out->d1,
                              out->d2, out->n_comparisons, am, ad1, ad2, ac, st));
@@ -456,7 +457,8 @@ int sfm_workspace_size(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, siz
   std::vector<PairDesc> pd;
   const int rc = describe_pairs(ctx, pairs, n_pairs, false, pd);
   if (rc) return rc;
-  *bytes = plan(pd).total;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  *bytes = plan(pd, ctx->device).total;
   return SFM_OK;
 }
 

@@ -1,26 +1,28 @@
 // Fused candidate test + distance + two-nearest kernel (a4-a6), Appendix A
 // steps 3-4 redesigned for CDNA4.
 //
-// One wave owns a tile of 32 consecutive queries (in pencil order) and walks
-// the contiguous range of b's binned features that covers their bands, 32
-// candidates per step:
-//   - the candidates' 128-byte descriptor rows are loaded straight into the
-//     A operand of v_mfma_i32_32x32x32_i8 (16 bytes per lane per k-step), the
-//     negated query rows stay resident as the B operand, so four MFMAs give
-//     -q.c for a 32x32 tile with exact int32 accumulation (bytes 0..127 fit
-//     int8, 128 * 127^2 < 2^31);
-//   - each lane then holds one query and 16 candidates of the tile; it runs
-//     the exact band test of eqs. (2)-(3) in FP32 on the candidates' centred
-//     coordinates (staged through LDS) and folds in-band distances into a
-//     running two-smallest pair of 32-bit keys
+// A workgroup of four waves owns a group of up to four consecutive query
+// tiles (32 queries each, in pencil order) of one pair.  Their candidate
+// ranges overlap heavily, so the workgroup streams the union range of b's
+// binned features through LDS once, 32 candidates per step:
+//   - each wave fetches 8 of the 32 descriptor rows with one coalesced load
+//     (eight lanes per 128-byte row) and stores them XOR-swizzled into the
+//     shared stage; one barrier per step publishes the stage;
+//   - each wave whose own range meets the step reads the rows back as the A
+//     operand of v_mfma_i32_32x32x32_i8; its negated query rows are the
+//     resident B operand, so four MFMAs give -q.c for a 32x32 tile with exact
+//     int32 accumulation (bytes 0..127 fit int8, 128 * 127^2 < 2^31);
+//   - each lane then holds one query and 16 candidates; it runs the exact
+//     band test of eqs. (2)-(3) in FP32 on the candidates' centred
+//     coordinates and folds in-band distances into a running two-smallest
+//     pair of 32-bit keys
 //         key = ((||c||^2 - 2 q.c + 2^21) << 10) | (position mod 1024),
 //     so one unsigned min and one med3 keep (D1, its position) and D2;
-//   - the 32 + 32 lanes of one query merge with one cross-half exchange.
-// Loads are software-pipelined: the binned record of tile t+2 and the
-// descriptor rows of tile t+1 are in flight while tile t is computed.
+//   - the two lanes of one query merge with one cross-half exchange.
 // The key orders equal distances by binned position, not by index in b; when
 // the two smallest keys of a chunk share the distance, an exact pass picks the
 // lowest index among the tied candidates, so results equal the definition.
+#include <algorithm>
 #include <cmath>
 
 #include "sfm_internal.h"
@@ -30,8 +32,12 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned int nv4u __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) nv4u g_nv4u;
+typedef const __attribute__((address_space(1))) int32_t g_i32;
 
-constexpr int kWaves = 4;
+constexpr int kWaves = kGroupTiles;
+constexpr int kMetaSlots = 3;
 
 // Band test of eqs. (2)-(3) on centred FP32 coordinates: |a x + b y + c| <= d
 // with (a, b) unit.  The single definition used by every pass.
@@ -49,15 +55,6 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
   return max(min(a, b), min(max(a, b), c));   // selects v_med3_u32
 }
 
-
-// Workgroups are dealt to the 8 XCDs round-robin; renumber them so each XCD
-// gets one contiguous run of work items (neighbouring query tiles of one pair
-// share candidate rows, and each XCD has its own L2).
-__device__ __forceinline__ int32_t xcd_contiguous(int32_t g, int32_t G) {
-  const int32_t x = g & 7, k = g >> 3, q = G >> 3, r = G & 7;
-  return x * q + min(x, r) + k;
-}
-
 // Exact squared L2 of two 128-byte rows with VALU dot products.
 __device__ inline int32_t row_dist(const uint8_t* p, const uint8_t* q, int32_t np, int32_t nq) {
   uint32_t dot = 0;
@@ -73,86 +70,71 @@ __device__ inline int32_t row_dist(const uint8_t* p, const uint8_t* q, int32_t n
   return np + nq - 2 * int32_t(dot);
 }
 
-// Global-address-space views: loads through them compile to global_load_*,
-// which only count against vmcnt (flat loads would also hold up LDS waits).
-typedef unsigned int nv4u __attribute__((ext_vector_type(4)));
-typedef const __attribute__((address_space(1))) nv4u g_nv4u;
-typedef const __attribute__((address_space(1))) int32_t g_i32;
-
+// Loads through global-address-space pointers compile to global_load_*,
+// which only count against vmcnt.
 __device__ __forceinline__ nv4u gload16(const void* p) { return *(g_nv4u*)p; }
 
-// Raw binned record {x, y, ncpos, j} of position min(cp, c1 - 1); the caller
-// masks positions >= c1 when it stages the record (c1 > 0 is guaranteed).
+// Raw binned record {x, y, ncpos, j} of position min(cp, c1 - 1) (c1 > 0).
 __device__ __forceinline__ nv4u load_rec(const CandRec* cand, int32_t cp, int32_t c1) {
   return gload16(cand + min(cp, c1 - 1));
 }
 
-// Per-wave LDS: two stages of 32 candidate rows and their metadata.  A row is
-// stored as eight 16-byte chunks with chunk c of row r at slot c ^ (r & 7), so
-// that both the coalesced stores (eight lanes per row) and the MFMA operand
-// reads (one row per lane) hit all 32 banks without conflicts.
-struct WaveLds {
+// Workgroup LDS: two stages of 32 candidate rows and three stages of their
+// metadata.  A row is stored as eight 16-byte chunks with chunk c of row r at
+// slot c ^ (r & 7), so both the coalesced stores (eight lanes per row) and the
+// MFMA operand reads (one row per lane) hit all 32 banks without conflicts.
+struct GroupLds {
   uint8_t rows[2][kCandTile * kDescBytes];
-  float x[2][kCandTile];
-  float y[2][kCandTile];
-  uint32_t nc[2][kCandTile];
-  int32_t jt[2][8][4];       // row index of candidate 8k + m at jt[m][k]
+  float x[kMetaSlots][kCandTile];
+  float y[kMetaSlots][kCandTile];
+  uint32_t nc[kMetaSlots][kCandTile];
+  uint32_t sink[kWaves][3][64];    // targets of the lanes that own no record
 };
 
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Wave w owns candidates 8w .. 8w+7 of every step: lane l < 8 holds the
+// record of candidate 8w + l.  Those lanes stage the metadata (the other lanes
+// write to distinct sink words: no divergent branch, no bank conflict).
+// Positions past the range get a NaN coordinate, which no band test passes.
+__device__ __forceinline__ void stage_meta(GroupLds& L, int st, const nv4u& r, int32_t t0,
+                                           int32_t c1, int wave, int lane) {
+  const int cand_i = 8 * wave + (lane & 7);
+  const bool own = lane < 8;
+  float* px = own ? &L.x[st][cand_i] : reinterpret_cast<float*>(&L.sink[wave][0][lane]);
+  float* py = own ? &L.y[st][cand_i] : reinterpret_cast<float*>(&L.sink[wave][1][lane]);
+  uint32_t* pn = own ? &L.nc[st][cand_i] : &L.sink[wave][2][lane];
+  *px = t0 + cand_i < c1 ? __uint_as_float(r.x) : NAN;
+  *py = __uint_as_float(r.y);
+  *pn = r.z;
 }
 
-// Stage record r of position t0 + col into metadata slot st.  Both halves
-// hold the same 32 records and store identical values (no divergent branch).
-// Positions past the range get a NaN coordinate: no band test passes.
-__device__ __forceinline__ void stage_meta(WaveLds& L, int st, const nv4u& r, int32_t t0,
-                                           int32_t c1, int col) {
-  L.x[st][col] = t0 + col < c1 ? __uint_as_float(r.x) : NAN;
-  L.y[st][col] = __uint_as_float(r.y);
-  L.nc[st][col] = r.z;
-  L.jt[st][col & 7][col >> 3] = int32_t(r.w);
+// This wave's coalesced share of a step's rows: lane l fetches 16-byte chunk
+// (l & 7) of row 8w + (l >> 3), whose index in b lane (l >> 3) holds.
+__device__ __forceinline__ nv4u load_row_share(const nv4u& r, const uint8_t* desc, int lane) {
+  const int32_t j = __shfl(int32_t(r.w), lane >> 3, 64);
+  return gload16(desc + int64_t(j) * kDescBytes + 16 * (lane & 7));
 }
 
-// Coalesced loads of the 32 rows named in slot st: lane l fetches 16-byte
-// chunk (l & 7) of row 8k + (l >> 3), k = 0..3, so eight lanes read one
-// contiguous 128-byte row.
-__device__ __forceinline__ void load_rows_coalesced(const WaveLds& L, int st,
-                                                    const uint8_t* desc, int lane, nv4u (&rw)[4]) {
-  const int4 j = *reinterpret_cast<const int4*>(&L.jt[st][lane >> 3][0]);
-  const int32_t jj[4] = {j.x, j.y, j.z, j.w};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) rw[k] = gload16(desc + int64_t(jj[k]) * kDescBytes + 16 * (lane & 7));
-}
-
-__device__ __forceinline__ void store_rows(WaveLds& L, int st, int lane, const nv4u (&rw)[4]) {
+__device__ __forceinline__ void store_row_share(GroupLds& L, int st, int wave, int lane,
+                                                const nv4u& rw) {
   const int m = lane >> 3, c = lane & 7;
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    *reinterpret_cast<nv4u*>(&L.rows[st][(8 * k + m) * kDescBytes + ((c ^ (m & 7)) << 4)]) = rw[k];
+  *reinterpret_cast<nv4u*>(&L.rows[st][(8 * wave + m) * kDescBytes + ((c ^ m) << 4)]) = rw;
 }
 
 // The MFMA A operand: row (lane & 31), k-slice 16 * half + 32 * s = chunk 2s + half.
-__device__ __forceinline__ void read_a(const WaveLds& L, int st, int lane, v4i (&a)[4]) {
+__device__ __forceinline__ void read_a(const GroupLds& L, int st, int lane, v4i (&a)[4]) {
   const int r = lane & 31, h = lane >> 5;
 #pragma unroll
   for (int s = 0; s < 4; ++s)
     a[s] = *reinterpret_cast<const v4i*>(&L.rows[st][r * kDescBytes + (((2 * s + h) ^ (r & 7)) << 4)]);
 }
 
-// tile_compute: the four MFMAs on this step's rows ac, then this lane's 16
-// results folded into the running two smallest keys (k1, k2), with the
-// candidates' coordinates and keys read from metadata slot st.
-template <bool kKeepCounts>
+// The four MFMAs on one step's rows, then this lane's 16 results folded into
+// the running two smallest keys (k1, k2), with the candidates' coordinates and
+// keys read from metadata slot st.
 __device__ __forceinline__ void tile_compute(const v4i (&ac)[4], const v4i (&bq)[4],
-                                             const QueryRec& qr, float band, const WaveLds& L,
+                                             const QueryRec& qr, float band, const GroupLds& L,
                                              int st, int half, uint32_t& k1, uint32_t& k2,
                                              int32_t& cnt) {
-  const float* smX = L.x[st];
-  const float* smY = L.y[st];
-  const uint32_t* smN = L.nc[st];
   v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(ac[s], bq[s], acc, 0, 0, 0);
@@ -161,9 +143,9 @@ __device__ __forceinline__ void tile_compute(const v4i (&ac)[4], const v4i (&bq)
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     const int r0 = 8 * g + 4 * half;
-    const float4 xs = *reinterpret_cast<const float4*>(&smX[r0]);
-    const float4 ys = *reinterpret_cast<const float4*>(&smY[r0]);
-    const uint4 ns = *reinterpret_cast<const uint4*>(&smN[r0]);
+    const float4 xs = *reinterpret_cast<const float4*>(&L.x[st][r0]);
+    const float4 ys = *reinterpret_cast<const float4*>(&L.y[st][r0]);
+    const uint4 ns = *reinterpret_cast<const uint4*>(&L.nc[st][r0]);
     const float xv[4] = {xs.x, xs.y, xs.z, xs.w};
     const float yv[4] = {ys.x, ys.y, ys.z, ys.w};
     const uint32_t nv[4] = {ns.x, ns.y, ns.z, ns.w};
@@ -174,201 +156,314 @@ __device__ __forceinline__ void tile_compute(const v4i (&ac)[4], const v4i (&bq)
       key = mem ? key : kKeyInf;
       k2 = umed3(k1, key, k2);
       k1 = min(k1, key);
-      cnt += mem ? 1 : 0;   // per lane, in VALU: no VALU -> SALU hand-off per slot
+      cnt += mem ? 1 : 0;
     }
   }
-  __builtin_amdgcn_wave_barrier();
 }
 
-// One query tile: its 32 queries against the candidate range [s_begin, s_end).
-template <bool kKeepCounts>
-__device__ __forceinline__ void match_tile(const BatchView& v, const PairDesc& P, int32_t p,
-                                           const ImageDev& A, const ImageDev& B, float band,
-                                           int32_t blk, int32_t s_begin, int32_t s_end,
-                                           WaveLds& L, int lane) {
-  const int col = lane & 31, half = lane >> 5;
+// Running result of one query column across chunks of 1024 positions.
+struct QueryState {
+  int32_t d1, d2, j1;
+  uint32_t ties;
+};
 
-  // This lane's query column: line, squared norm and negated descriptor
-  // bytes as the MFMA B operand.
-  const int32_t qs = blk * kQueryTile + col;
-  const bool qv = qs < P.na;
-  QueryRec qr;
-  if (qv) {
-    const nv4u u = gload16(v.qrec + P.q_off + qs);
-    qr.a = __uint_as_float(u.x);
-    qr.b = __uint_as_float(u.y);
-    qr.c = __uint_as_float(u.z);
-    qr.i = int32_t(u.w);
-  } else {
-    qr.a = qr.b = qr.c = NAN;
-    qr.i = 0;
-  }
-  const CandRec* cand = v.cand + P.c_off;
-  // The first candidate record goes out together with the query loads.
-  nv4u rc = {0u, 0u, 0u, 0u};
-  if (s_end > s_begin) rc = load_rec(cand, s_begin + col, s_end);
-  v4i bq[4];
-  int32_t nq = 0;
+// End of a chunk [c0, c1): merge the halves' keys, decode (D1, position, D2),
+// resolve equal smallest distances exactly, fold into the running result.
+__device__ __forceinline__ void finish_chunk(const CandRec* cand, const uint8_t* a_desc,
+                                             const uint8_t* b_desc, const QueryRec& qr, int32_t nq,
+                                             float band, int32_t c0, int32_t c1, int lane,
+                                             uint32_t k1, uint32_t k2, QueryState& q) {
+  const int col = lane & 31, half = lane >> 5;
   {
-    // Padding columns (qv false) read query row 0; their line is NaN.
-    const uint8_t* qrow = A.desc + int64_t(qr.i) * kDescBytes + 16 * half;
+    const uint32_t p1 = __shfl_xor(k1, 32, 64);
+    const uint32_t p2 = __shfl_xor(k2, 32, 64);
+    k2 = min(max(k1, p1), min(k2, p2));
+    k1 = min(k1, p1);
+  }
+  // The index load is unconditional and consumed at once, so no load stays
+  // in flight past the chunk end (a pending load into a register the loop
+  // reuses would make every later step wait for all prefetches).
+  const int32_t pos = int32_t(k1 & (kChunk - 1));
+  const int32_t at = min(c0 + ((pos - c0) & (kChunk - 1)), c1 - 1);
+  const int32_t jl = *(g_i32*)&cand[at].j;
+  const int32_t D1c = k1 != kKeyInf ? int32_t(k1 >> kPosBits) - int32_t(kDistBias) + nq : kDistInf;
+  const int32_t D2c = k2 != kKeyInf ? int32_t(k2 >> kPosBits) - int32_t(kDistBias) + nq : kDistInf;
+  int32_t j1c = k1 != kKeyInf ? jl : -1;
+
+  // Equal smallest distances: choose the lowest index of b exactly.
+  const bool tie = k2 != kKeyInf && (k1 >> kPosBits) == (k2 >> kPosBits);
+  unsigned long long tmask = __ballot(tie && half == 0);
+  while (tmask) {
+    const int Lq = __builtin_ctzll(tmask);
+    tmask &= tmask - 1;
+    ++q.ties;
+    const float la = __shfl(qr.a, Lq, 64), lb = __shfl(qr.b, Lq, 64), lc = __shfl(qr.c, Lq, 64);
+    const int32_t li = __shfl(qr.i, Lq, 64), lnq = __shfl(nq, Lq, 64), lD = __shfl(D1c, Lq, 64);
+    const uint8_t* qrow = a_desc + int64_t(li) * kDescBytes;
+    int32_t jbest = 0x7FFFFFFF;
+    for (int32_t s = c0 + lane; s < c1; s += 64) {
+      const CandRec r = cand[s];
+      if (!in_band(la, lb, lc, r.x, r.y, band)) continue;
+      const int32_t nc = int32_t(r.ncpos >> kPosBits) - int32_t(kDistBias);
+      const int32_t D = row_dist(qrow, b_desc + int64_t(r.j) * kDescBytes, lnq, nc);
+      if (D == lD) jbest = min(jbest, r.j);
+    }
+    for (int o = 32; o > 0; o >>= 1) jbest = min(jbest, __shfl_xor(jbest, o, 64));
+    if (col == Lq) j1c = jbest;
+  }
+
+  if (D1c < q.d1 || (D1c == q.d1 && D1c != kDistInf && j1c < q.j1)) {
+    q.d2 = min(q.d1, D2c);
+    q.d1 = D1c;
+    q.j1 = j1c;
+  } else {
+    q.d2 = min(q.d2, D1c);
+  }
+}
+
+// Per-wave statistics of the groups of one pair, flushed when the pair changes.
+struct WaveStats {
+  int32_t pair;
+  unsigned long long comparisons, elements;
+  uint32_t accepted, ties;
+};
+
+__device__ __forceinline__ void flush_stats(const BatchView& v, WaveStats& w, int lane) {
+  if (w.pair >= 0 && lane == 0) {
+    if (w.comparisons) atomicAdd(&v.counters[w.pair].comparisons, w.comparisons);
+    if (w.elements) atomicAdd(&v.counters[w.pair].elements, w.elements);
+    if (w.accepted) atomicAdd(&v.counters[w.pair].accepted, w.accepted);
+    if (w.ties) atomicAdd(&v.counters[w.pair].ties, w.ties);
+  }
+  w.comparisons = w.elements = 0;
+  w.accepted = w.ties = 0;
+}
+
+// A group record read with scalar loads (its index is uniform).
+typedef const __attribute__((address_space(4))) v4i c_v4i;
+__device__ __forceinline__ TileGroup load_group(const TileGroup* groups, int32_t g) {
+  union {
+    v4i w[sizeof(TileGroup) / 16];
+    TileGroup t;
+  } u;
+  c_v4i* src = (c_v4i*)(groups + g);
+#pragma unroll
+  for (int k = 0; k < int(sizeof(TileGroup) / 16); ++k) u.w[k] = src[k];
+  return u.t;
+}
+
+// One group: up to four query tiles (one per wave) against their union
+// candidate range, streamed through LDS 32 candidates per step with one
+// barrier per step.
+template <bool kKeepCounts>
+__device__ __forceinline__ void match_group(const BatchView& v, const TileGroup& G, GroupLds& L,
+                                            int wave, int lane, WaveStats& ws) {
+  const int col = lane & 31, half = lane >> 5;
+  const bool wv = wave < G.ntiles;
+  const int32_t blk = G.tile0 + wave;
+  // Selects, not an indexed read: a dynamic index would put the record in
+  // private memory.
+  int32_t my_b = 0, my_e = 0;
+#pragma unroll
+  for (int t = 0; t < kGroupTiles; ++t) {
+    my_b = wave == t ? G.t_begin[t] : my_b;
+    my_e = wave == t ? G.t_end[t] : my_e;
+  }
+  if (!wv) my_b = my_e = 0;
+  const float band = G.band;
+  const uint8_t* const a_desc = G.a_desc;
+  const uint8_t* const b_desc = G.b_desc;
+
+  // This lane's query column: line, squared norm and negated descriptor bytes
+  // as the MFMA B operand.  Padding columns read query row 0 with a NaN line.
+  const int32_t qs = blk * kQueryTile + col;
+  const bool qv = wv && qs < G.na;
+  const nv4u qu = gload16(v.qrec + G.q_off + min(qs, G.na - 1));
+  QueryRec qr;
+  qr.a = qv ? __uint_as_float(qu.x) : NAN;
+  qr.b = __uint_as_float(qu.y);
+  qr.c = __uint_as_float(qu.z);
+  qr.i = int32_t(qu.w);
+  const int32_t S0 = G.s_begin, S1 = G.s_end;
+  const CandRec* cand = v.cand + G.c_off;
+
+  // Records of the first two steps go out with the query record; the query
+  // row and the first candidate rows follow one latency later.
+  const int32_t own = 8 * wave + (lane & 7);
+  const bool any = S1 > S0;
+  nv4u re = {0, 0, 0, 0}, ro = {0, 0, 0, 0};
+  if (any) {
+    re = load_rec(cand, S0 + own, S1);
+    ro = load_rec(cand, S0 + kCandTile + own, S1);
+  }
+  v4i bq[4];
+  {
+    const uint8_t* qrow = a_desc + int64_t(qr.i) * kDescBytes + 16 * half;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const nv4u u = gload16(qrow + 32 * s);
       bq[s] = v4i{neg_bytes(u.x), neg_bytes(u.y), neg_bytes(u.z), neg_bytes(u.w)};
     }
-    nq = ((g_i32*)A.norm2)[qr.i];
   }
+  const int32_t nq = ((g_i32*)G.a_norm)[qr.i];
 
-  int32_t d1 = kDistInf, d2 = kDistInf, j1 = -1, cnt = 0;
-  uint32_t ties = 0;
+  QueryState q = {kDistInf, kDistInf, -1, 0};
+  int32_t cnt = 0;
 
-  for (int32_t c0 = s_begin; c0 < s_end; c0 += kChunk) {
-    const int32_t c1 = min(s_end, c0 + kChunk);
+  if (any) {
+    // Software pipeline over steps u = 0, 1, ... of 32 candidates.  Iteration
+    // u stores rows u (loaded two iterations earlier) into row stage u & 1,
+    // passes the barrier, issues the rows of u + 2 (their indices come from
+    // the record registers, so no barrier lies on that chain), stages the
+    // metadata of u + 2 into slot (u + 2) % 3, loads the record of u + 4 and
+    // computes step u from row stage u & 1 and metadata slot u % 3.  The loop
+    // is unrolled by two so the in-flight registers never move (a copy of a
+    // register with a load in flight would wait for that load).
+    const int32_t nsteps = (S1 - S0 + kCandTile - 1) / kCandTile;
+    stage_meta(L, 0, re, S0, S1, wave, lane);
+    nv4u we = load_row_share(re, b_desc, lane);
+    re = load_rec(cand, S0 + 2 * kCandTile + own, S1);
+    stage_meta(L, 1, ro, S0 + kCandTile, S1, wave, lane);
+    nv4u wo = load_row_share(ro, b_desc, lane);
+    ro = load_rec(cand, S0 + 3 * kCandTile + own, S1);
+
     uint32_t k1 = kKeyInf, k2 = kKeyInf;
-    if (c0 != s_begin) rc = load_rec(cand, c0 + col, c1);
-    // Step u works on positions c0 + 32u .. +31 from LDS slot u & 1.  While it
-    // computes, the rows of step u+1 and the record of step u+2 are in flight;
-    // rows are addressed from LDS and always read as whole 128-byte rows, eight
-    // lanes per row.
-    stage_meta(L, 0, rc, c0, c1, col);
-    wave_sync_lds();
-    nv4u rw[4];
-    load_rows_coalesced(L, 0, B.desc, lane, rw);
-    rc = load_rec(cand, c0 + kCandTile + col, c1);
-    int st = 0;
-    for (int32_t t0 = c0; t0 < c1; t0 += kCandTile, st ^= 1) {
-      store_rows(L, st, lane, rw);
-      stage_meta(L, st ^ 1, rc, t0 + kCandTile, c1, col);
-      wave_sync_lds();
-      load_rows_coalesced(L, st ^ 1, B.desc, lane, rw);
-      rc = load_rec(cand, t0 + 2 * kCandTile + col, c1);
-      v4i a[4];
-      read_a(L, st, lane, a);
-      tile_compute<kKeepCounts>(a, bq, qr, band, L, st, half, k1, k2, cnt);
-    }
-
-    // Merge the two halves of each query column.
-    {
-      const uint32_t p1 = __shfl_xor(k1, 32, 64);
-      const uint32_t p2 = __shfl_xor(k2, 32, 64);
-      k2 = min(max(k1, p1), min(k2, p2));
-      k1 = min(k1, p1);
-    }
-    int32_t D1c = kDistInf, D2c = kDistInf, j1c = -1;
-    if (k1 != kKeyInf) {
-      D1c = int32_t(k1 >> kPosBits) - int32_t(kDistBias) + nq;
-      const int32_t pos = int32_t(k1 & (kChunk - 1));
-      j1c = cand[c0 + ((pos - c0) & (kChunk - 1))].j;
-    }
-    if (k2 != kKeyInf) D2c = int32_t(k2 >> kPosBits) - int32_t(kDistBias) + nq;
-
-    // Equal smallest distances: choose the lowest index of b exactly.
-    const bool tie = k2 != kKeyInf && (k1 >> kPosBits) == (k2 >> kPosBits);
-    unsigned long long tmask = __ballot(tie && half == 0);
-    while (tmask) {
-      const int L = __builtin_ctzll(tmask);
-      tmask &= tmask - 1;
-      ++ties;
-      const float la = __shfl(qr.a, L, 64), lb = __shfl(qr.b, L, 64), lc = __shfl(qr.c, L, 64);
-      const int32_t li = __shfl(qr.i, L, 64), lnq = __shfl(nq, L, 64), lD = __shfl(D1c, L, 64);
-      const uint8_t* qrow = A.desc + int64_t(li) * kDescBytes;
-      int32_t jbest = 0x7FFFFFFF;
-      for (int32_t s = c0 + lane; s < c1; s += 64) {
-        const CandRec r = cand[s];
-        if (!in_band(la, lb, lc, r.x, r.y, band)) continue;
-        const int32_t nc = int32_t(r.ncpos >> kPosBits) - int32_t(kDistBias);
-        const int32_t D = row_dist(qrow, B.desc + int64_t(r.j) * kDescBytes, lnq, nc);
-        if (D == lD) jbest = min(jbest, r.j);
+    int32_t c0 = S0;
+    int ms = 0;   // metadata slot of step u
+    // One step; `w` and `r` are this parity's row and record registers.
+    auto step = [&](int32_t u, int rs, nv4u& w, nv4u& r) {
+      const int32_t t0 = S0 + u * kCandTile;
+      store_row_share(L, rs, wave, lane, w);
+      __syncthreads();
+      const int ms2 = ms == 0 ? 2 : ms - 1;   // (u + 2) % 3
+      stage_meta(L, ms2, r, t0 + 2 * kCandTile, S1, wave, lane);
+      w = load_row_share(r, b_desc, lane);
+      r = load_rec(cand, t0 + 4 * kCandTile + own, S1);
+      if (t0 < my_e && t0 + kCandTile > my_b) {
+        v4i a[4];
+        read_a(L, rs, lane, a);
+        tile_compute(a, bq, qr, band, L, ms, half, k1, k2, cnt);
       }
-      for (int o = 32; o > 0; o >>= 1) jbest = min(jbest, __shfl_xor(jbest, o, 64));
-      if (col == L) j1c = jbest;
+      // Keys hold positions mod 1024: close a chunk every 1024 positions.
+      const int32_t t1 = t0 + kCandTile;
+      if (t1 >= S1 || t1 - c0 >= kChunk) {
+        const int32_t c1 = min(S1, c0 + kChunk);
+        finish_chunk(cand, a_desc, b_desc, qr, nq, band, c0, c1, lane, k1, k2, q);
+        k1 = kKeyInf;
+        k2 = kKeyInf;
+        c0 = c1;
+      }
+      ms = ms == 2 ? 0 : ms + 1;
+    };
+    // The loop body always runs both steps, so the loads in flight at its
+    // head are the same on every path (an odd last step runs after it).
+    int32_t u = 0;
+    for (; u + 1 < nsteps; u += 2) {
+      step(u, 0, we, re);
+      step(u + 1, 1, wo, ro);
     }
-
-    // Fold this chunk's (D1, j1, D2) into the running result.
-    if (D1c < d1 || (D1c == d1 && D1c != kDistInf && j1c < j1)) {
-      d2 = min(d1, D2c);
-      d1 = D1c;
-      j1 = j1c;
-    } else {
-      d2 = min(d2, D1c);
-    }
+    if (u < nsteps) step(u, 0, we, re);
+    // No wave may overwrite the stage of the next group while others read it.
+    __syncthreads();
   }
 
   bool accept;
-  if (d2 != kDistInf) {
-    accept = int64_t(v.ratio_den) * d1 < int64_t(v.ratio_num) * d2;
+  if (q.d2 != kDistInf) {
+    accept = int64_t(v.ratio_den) * q.d1 < int64_t(v.ratio_num) * q.d2;
   } else {
-    accept = d1 != kDistInf && v.accept_single;
+    accept = q.d1 != kDistInf && v.accept_single;
   }
   cnt += __shfl_xor(cnt, 32, 64);   // |C| of this lane's query
+  if (qv && half == 0) {
+    QueryResult out;
+    out.match = q.j1;
+    out.d1 = q.d1;
+    out.d2 = q.d2;
+    out.flags = (accept ? 1 : 0) | (kKeepCounts ? (cnt << 1) : 0);
+    v.res[G.q_off + qr.i] = out;
+  }
   // In-band comparisons of the tile: the sum of its queries' counts.
   int32_t tsum = (half == 0) ? cnt : 0;
   for (int o = 16; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
-  const unsigned long long total = (unsigned long long)__shfl(tsum, 0, 64);
-  if (qv && half == 0) {
-    QueryResult out;
-    out.match = j1;
-    out.d1 = d1;
-    out.d2 = d2;
-    out.flags = (accept ? 1 : 0) | (kKeepCounts ? (cnt << 1) : 0);
-    v.res[P.q_off + qr.i] = out;
-  }
   const uint32_t nacc = __builtin_popcountll(__ballot(accept && qv && half == 0));
-  if (lane == 0) {
-    const unsigned long long padded =
-        (unsigned long long)((s_end - s_begin + kCandTile - 1) / kCandTile) * (kCandTile * kQueryTile);
-    if (total) atomicAdd(&v.counters[p].comparisons, total);
-    if (padded) atomicAdd(&v.counters[p].elements, padded);
-    if (nacc) atomicAdd(&v.counters[p].accepted, nacc);
-    if (ties) atomicAdd(&v.counters[p].ties, ties);
+  if (wv) {
+    if (G.pair != ws.pair) {
+      flush_stats(v, ws, lane);
+      ws.pair = G.pair;
+    }
+    int32_t steps = 0;
+    if (my_e > my_b) {
+      const int32_t first = (max(my_b, S0) - S0) / kCandTile;
+      const int32_t last = (my_e - 1 - S0) / kCandTile;
+      steps = last - first + 1;
+    }
+    ws.comparisons += (unsigned long long)__shfl(tsum, 0, 64);
+    ws.elements += (unsigned long long)steps * (kCandTile * kQueryTile);
+    ws.accepted += nacc;
+    ws.ties += q.ties;
   }
 }
 
-// Each wave walks tiles_per_wave consecutive query tiles of [blk_begin, blk_end)
-// (they may belong to different pairs); per-pair data is reloaded on change.
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so each XCD
+// takes one contiguous run of groups (neighbouring groups of one pair share
+// candidate rows, and each XCD has its own L2).
+__device__ __forceinline__ int32_t xcd_contiguous(int32_t g, int32_t G) {
+  const int32_t x = g & 7, k = g >> 3, q = G >> 3, r = G & 7;
+  return x * q + min(x, r) + k;
+}
+
+// One resident wave of workgroups; the preparation pass has split the groups
+// into one contiguous run of about equal estimated cost per workgroup.
 #ifndef SFM_MATCH_WAVES_PER_EU
 #define SFM_MATCH_WAVES_PER_EU 3
 #endif
 template <bool kKeepCounts>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
-void match_kernel(BatchView v, int32_t blk_begin, int32_t blk_end) {
-  __shared__ __attribute__((aligned(16))) WaveLds lds[kWaves];
-
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
+void match_kernel(BatchView v) {
+  __shared__ __attribute__((aligned(16))) GroupLds lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t item = xcd_contiguous(blockIdx.x, gridDim.x) * kWaves + wave;
-  const int64_t t_first = int64_t(blk_begin) + int64_t(item) * v.tiles_per_wave;
-  const int64_t t_last = min(int64_t(blk_end), t_first + v.tiles_per_wave);
-  int32_t cur = -1;
-  PairDesc P;
-  ImageDev A, B;
-  float band = 0.0f;
-  for (int64_t t = t_first; t < t_last; ++t) {
-    const int4 ti = v.tiles[t];
-    if (ti.x != cur) {
-      cur = ti.x;
-      P = v.pairs[cur];
-      A = v.images[P.a];
-      B = v.images[P.b];
-      band = v.geom[cur].band32;
-    }
-    match_tile<kKeepCounts>(v, P, cur, A, B, band, ti.y, ti.z, ti.w, lds[wave], lane);
+  const int32_t run = xcd_contiguous(blockIdx.x, gridDim.x);
+  typedef const __attribute__((address_space(4))) int32_t c_i32;
+  const int32_t g_first = ((c_i32*)v.wg_start)[run];
+  const int32_t g_end = ((c_i32*)v.wg_start)[run + 1];
+  WaveStats ws = {-1, 0, 0, 0, 0};
+  for (int32_t g = g_first; g < g_end; ++g) {
+    const TileGroup G = load_group(v.groups, g);
+    match_group<kKeepCounts>(v, G, lds, wave, lane, ws);
   }
+  flush_stats(v, ws, lane);
 }
 
 }  // namespace
 
-hipError_t launch_match(const BatchView& v, int32_t blk_begin, int32_t blk_count, hipStream_t st) {
-  if (blk_count <= 0) return hipSuccess;
-  const int32_t per_wave = v.tiles_per_wave;
-  const int32_t waves = (blk_count + per_wave - 1) / per_wave;
-  const int32_t groups = (waves + kWaves - 1) / kWaves;
+// Workgroups of the match kernel that fit on a device at once.
+static int32_t resident_workgroups(int dev) {
+  static int32_t cached[64] = {0};
+  if (dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, match_kernel<false>, 64 * kWaves, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        per_cu <= 0 || cus <= 0) {
+      per_cu = 1;
+      cus = 256;
+    }
+    cached[dev] = per_cu * cus;
+  }
+  return cached[dev];
+}
+
+int32_t match_workgroups(int32_t device, int64_t groups) {
+  return int32_t(std::max<int64_t>(1, std::min<int64_t>(groups, resident_workgroups(device))));
+}
+
+hipError_t launch_match(const BatchView& v, int32_t wgs, hipStream_t st) {
+  if (wgs <= 0) return hipSuccess;
   if (v.keep_counts)
-    hipLaunchKernelGGL(match_kernel<true>, dim3(groups), dim3(64 * kWaves), 0, st, v, blk_begin,
-                       blk_begin + blk_count);
+    hipLaunchKernelGGL(match_kernel<true>, dim3(wgs), dim3(64 * kWaves), 0, st, v);
   else
-    hipLaunchKernelGGL(match_kernel<false>, dim3(groups), dim3(64 * kWaves), 0, st, v, blk_begin,
-                       blk_begin + blk_count);
+    hipLaunchKernelGGL(match_kernel<false>, dim3(wgs), dim3(64 * kWaves), 0, st, v);
   return hipGetLastError();
 }
 

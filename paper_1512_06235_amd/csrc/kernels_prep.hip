@@ -408,28 +408,127 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
   }
 }
 
-// Candidate range of every query tile: the union of its queries' bin windows
-// mapped through b's bin starts.  One workgroup per pair, one thread per tile.
+// Candidate range of every query tile (the union of its queries' bin windows
+// mapped through b's bin starts) and of every group of kGroupTiles
+// consecutive tiles.  One workgroup per pair, one thread per group.
 __global__ __launch_bounds__(256) void tile_ranges_kernel(BatchView v, int32_t pb) {
   const int32_t p = pb + blockIdx.x;
   const PairDesc P = v.pairs[p];
-  for (int32_t k = threadIdx.x; k < P.nblocks; k += blockDim.x) {
-    const int32_t s0 = k * kQueryTile;
-    int2 w[kQueryTile];
+  const ImageDev A = v.images[P.a];
+  const ImageDev B = v.images[P.b];
+  const float band = v.geom[p].band32;
+  for (int32_t g = threadIdx.x; g < P.ngroups; g += blockDim.x) {
+    TileGroup tg;
+    const int32_t k0 = g * kGroupTiles;
+    const int32_t nt = min(kGroupTiles, P.nblocks - k0);
+    int32_t gb = 0x7FFFFFFF, ge = 0;
 #pragma unroll
-    for (int s = 0; s < kQueryTile; ++s)
-      w[s] = s0 + s < P.na ? v.qwin[P.q_off + s0 + s] : make_int2(1, 0);
-    int32_t lo = 0x7FFFFFFF, hi = -1;
+    for (int32_t t = 0; t < kGroupTiles; ++t) {
+      int32_t sb = 0, se = 0;
+      if (t < nt) {
+        const int32_t s0 = (k0 + t) * kQueryTile;
+        int32_t lo = 0x7FFFFFFF, hi = -1;
+        for (int s = 0; s < kQueryTile; ++s) {
+          const int2 w = s0 + s < P.na ? v.qwin[P.q_off + s0 + s] : make_int2(1, 0);
+          if (w.x <= w.y) { lo = min(lo, w.x); hi = max(hi, w.y); }
+        }
+        if (lo <= hi) {
+          sb = v.bin_start[P.bin_off + lo];
+          se = v.bin_start[P.bin_off + hi + 1];
+        }
+        if (se > sb) { gb = min(gb, sb); ge = max(ge, se); }
+      }
+      tg.t_begin[t] = sb;
+      tg.t_end[t] = se;
+    }
+    tg.pair = p;
+    tg.tile0 = k0;
+    tg.ntiles = nt;
+    tg.na = P.na;
+    tg.s_begin = gb <= ge ? gb : 0;
+    tg.s_end = gb <= ge ? ge : 0;
+    tg.band = band;
+    tg.pad0 = 0;
+    tg.q_off = P.q_off;
+    tg.c_off = P.c_off;
+    tg.a_desc = A.desc;
+    tg.a_norm = A.norm2;
+    tg.b_desc = B.desc;
+    tg.pad1 = 0;
 #pragma unroll
-    for (int s = 0; s < kQueryTile; ++s) {
-      if (w[s].x <= w[s].y) { lo = min(lo, w[s].x); hi = max(hi, w[s].y); }
+    for (int k = 0; k < 4; ++k) tg.pad2[k] = 0;
+    v.groups[P.grp_off + g] = tg;
+    // A group costs a fixed start-up plus one pipeline step per 32 positions
+    // of its union range (every step of the union has a computing wave).
+    const int32_t steps = (tg.s_end - tg.s_begin + kCandTile - 1) / kCandTile;
+    v.gcost[P.grp_off + g] = kGroupStartCost + kStepCost * steps;
+  }
+}
+
+// Splits groups [g0, g0 + n) into `wgs` contiguous runs of about equal cost:
+// group g goes to the run whose share of the total cost contains the cost
+// before g.  One workgroup; costs are staged through LDS a chunk at a time and
+// thread t walks its own contiguous segment of the chunk.
+constexpr int kSchedThreads = 1024;
+constexpr int kSchedChunk = 8192;
+
+__device__ __forceinline__ int32_t run_of(long long before, int32_t wgs, long long total) {
+  return int32_t(before * wgs / total);
+}
+
+__global__ __launch_bounds__(kSchedThreads) void schedule_kernel(BatchView v, int32_t g0, int32_t n,
+                                                                 int32_t wgs) {
+  __shared__ int32_t cst[kSchedChunk];
+  __shared__ long long part[kSchedThreads];
+  const int t = threadIdx.x;
+  const int32_t* cost = v.gcost + g0;
+
+  long long mine = 0;
+  for (int32_t g = t; g < n; g += kSchedThreads) mine += cost[g];
+  part[t] = mine;
+  __syncthreads();
+  for (int o = kSchedThreads / 2; o > 0; o >>= 1) {
+    if (t < o) part[t] += part[t + o];
+    __syncthreads();
+  }
+  const long long total = part[0];
+  __syncthreads();
+
+  long long base = 0;   // cost before the chunk
+  for (int32_t c0 = 0; c0 < n; c0 += kSchedChunk) {
+    const int32_t m = min(kSchedChunk, n - c0);
+    for (int32_t i = t; i < m; i += kSchedThreads) cst[i] = cost[c0 + i];
+    __syncthreads();
+    const int32_t seg = (m + kSchedThreads - 1) / kSchedThreads;
+    const int32_t lo = min(m, t * seg), hi = min(m, lo + seg);
+    mine = 0;
+    for (int32_t i = lo; i < hi; ++i) mine += cst[i];
+    part[t] = mine;
+    __syncthreads();
+    // Inclusive scan of the segment sums (Hillis-Steele over LDS).
+    for (int o = 1; o < kSchedThreads; o <<= 1) {
+      const long long add = t >= o ? part[t - o] : 0;
+      __syncthreads();
+      part[t] += add;
+      __syncthreads();
     }
-    int32_t sb = 0, se = 0;
-    if (lo <= hi) {
-      sb = v.bin_start[P.bin_off + lo];
-      se = v.bin_start[P.bin_off + hi + 1];
+    if (lo < hi) {
+      long long pre = base + part[t] - mine;   // cost before group c0 + lo
+      const int32_t gl = c0 + lo;
+      int32_t prev = gl == 0 ? -1 : run_of(pre - (lo > 0 ? cst[lo - 1] : cost[gl - 1]), wgs, total);
+      for (int32_t i = lo; i < hi; ++i) {
+        const int32_t run = run_of(pre, wgs, total);
+        for (int32_t k = prev + 1; k <= run; ++k) v.wg_start[k] = g0 + c0 + i;
+        prev = run;
+        pre += cst[i];
+      }
     }
-    v.tiles[P.blk_off + k] = make_int4(p, k, sb, se);
+    base += part[kSchedThreads - 1];
+    __syncthreads();
+  }
+  if (t == 0 && n > 0) {
+    const int32_t last = run_of(total - cost[n - 1], wgs, total);
+    for (int32_t k = last + 1; k <= wgs; ++k) v.wg_start[k] = g0 + n;
   }
 }
 
@@ -446,11 +545,15 @@ hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_
   return hipGetLastError();
 }
 
-hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, hipStream_t st) {
+hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t grp_begin,
+                          int32_t grp_count, int32_t wgs, hipStream_t st) {
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
   hipLaunchKernelGGL(bin_kernel, dim3(pc, 2), dim3(kBinThreads), 0, st, v, pb);
   hipLaunchKernelGGL(tile_ranges_kernel, dim3(pc), dim3(256), 0, st, v, pb);
+  if (grp_count > 0)
+    hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, v, grp_begin,
+                       grp_count, wgs);
   return hipGetLastError();
 }
 

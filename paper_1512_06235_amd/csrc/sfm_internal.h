@@ -8,6 +8,7 @@ namespace sfm {
 
 constexpr int kDescBytes = 128;
 constexpr int kQueryTile = 32;          // queries per wave work item (MFMA N)
+constexpr int kGroupTiles = 4;          // query tiles (waves) sharing one candidate stream
 constexpr int kCandTile = 32;           // candidates per MFMA step (MFMA M)
 constexpr int kChunk = 1024;            // candidate positions one key encodes
 constexpr int kPosBits = 10;            // log2(kChunk)
@@ -16,6 +17,8 @@ constexpr int32_t kDistInf = 0x7FFFFFFF;
 constexpr uint32_t kDistBias = 1u << 21;  // makes norm2(c) - 2 q.c >= 0
 constexpr int kMaxBins = 8192;          // LDS histogram size per pair
 constexpr double kBandSlackPx = 1e-2;   // bin windows widen the band by this
+constexpr int32_t kGroupStartCost = 11;  // schedule cost of starting a tile group
+constexpr int32_t kStepCost = 4;         // schedule cost of one 32-candidate step
 
 // Per image, built at registration.
 struct ImageDev {
@@ -37,6 +40,9 @@ struct PairDesc {
   int64_t c_off;            // into per-candidate arrays (prefix of nb)
   int64_t bin_off;          // into bin arrays (prefix of nbins + 1)
   int64_t blk_off;          // into per-block arrays and the work-item space
+  int64_t grp_off;          // into the tile-group table
+  int32_t ngroups;          // ceil(nblocks / kGroupTiles)
+  int32_t pad2;
   double band;              // d, pixels (may be +inf)
   int32_t ignore_band;      // exhaustive matching
   int32_t pad;
@@ -92,6 +98,25 @@ struct PairCounters {
   uint32_t ties;            // chunks that needed the tie-break pass
 };
 
+// Up to kGroupTiles consecutive query tiles of one pair and the union of
+// their candidate ranges; one workgroup streams the union through LDS.  The
+// record holds everything the match kernel needs about the pair (128 bytes,
+// read with scalar loads).
+struct TileGroup {
+  int32_t pair, tile0, ntiles, na;  // na: queries of the pair
+  int32_t s_begin, s_end;   // union candidate range (s_begin >= s_end: empty)
+  float band;               // d in FP32
+  int32_t pad0;
+  int64_t q_off, c_off;     // the pair's query and candidate offsets
+  const uint8_t* a_desc;
+  const int32_t* a_norm;
+  const uint8_t* b_desc;
+  int64_t pad1;
+  int32_t t_begin[kGroupTiles], t_end[kGroupTiles];   // per tile candidate range
+  int32_t pad2[8 - 2 * kGroupTiles + 4];
+};
+static_assert(sizeof(TileGroup) == 128, "TileGroup is read as eight 16-byte words");
+
 // Everything a batch launch needs, passed by value.
 struct BatchView {
   const ImageDev* images;
@@ -101,7 +126,9 @@ struct BatchView {
   int32_t* bin_start;       // nbins + 1 per pair
   QueryRec* qrec;
   int2* qwin;               // per query in tile order: first, last bin (first > last = none)
-  int4* tiles;              // per query tile: pair, tile index, first and end candidate
+  TileGroup* groups;
+  int32_t* gcost;           // per tile group: estimated cost of matching it
+  int32_t* wg_start;        // match workgroup k takes groups [wg_start[k], wg_start[k + 1])
   QueryResult* res;
   PairCounters* counters;
   const double* F;          // 9 per pair
@@ -111,16 +138,21 @@ struct BatchView {
   int32_t ratio_num, ratio_den;
   int32_t accept_single;
   int32_t keep_counts;
-  int32_t tiles_per_wave;   // consecutive query tiles one wave walks
 };
 
 // Host launchers (one translation unit each).
 hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_t n_images,
                            int32_t* norm2_all, const int64_t* norm_off, float* bbox_dev,
                            int32_t* bad_flag, hipStream_t st);
+// Preparation of pairs [pair_begin, pair_begin + pair_count), whose tile groups
+// are [grp_begin, grp_begin + grp_count), split over `wgs` match workgroups.
 hipError_t launch_prepare(const BatchView& v, int32_t pair_begin, int32_t pair_count,
-                          hipStream_t st);
-hipError_t launch_match(const BatchView& v, int32_t blk_begin, int32_t blk_count, hipStream_t st);
+                          int32_t grp_begin, int32_t grp_count, int32_t wgs, hipStream_t st);
+// Workgroups the match kernel uses for `groups` tile groups (one resident wave
+// of workgroups at most).
+int32_t match_workgroups(int32_t device, int64_t groups);
+// Matches the groups that the last preparation split over `wgs` workgroups.
+hipError_t launch_match(const BatchView& v, int32_t wgs, hipStream_t st);
 hipError_t launch_emit(const BatchView& v, int32_t pair_begin, int32_t pair_count,
                        int64_t* offset, int32_t* out_q, int32_t* out_m, int32_t* out_d1,
                        int32_t* out_d2, int64_t* n_cmp, int32_t* all_m, int32_t* all_d1,
