@@ -68,7 +68,7 @@ int hip_fail(sfm_ctx* ctx, hipError_t e, const char* what) {
 
 // Sections of one call's workspace.
 struct Layout {
-  size_t pairs, F, geom, counters, wg_start, cand, bins, qrec, res, qwin, groups, gcost, total, staged;
+  size_t pairs, F, geom, counters, wg_start, cand, bins, qrec, res, qwin, groups, gcost, pcost, total, staged;
   int32_t wgs = 0;
   int64_t sum_na = 0, sum_nb = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
 };
@@ -102,6 +102,7 @@ Layout plan(const std::vector<PairDesc>& pd, int32_t device) {
   L.qwin = o; o = align_up(o + size_t(L.sum_na) * sizeof(int2));
   L.groups = o; o = align_up(o + size_t(L.sum_groups) * sizeof(TileGroup));
   L.gcost = o; o = align_up(o + size_t(L.sum_groups) * sizeof(int32_t));
+  L.pcost = o; o = align_up(o + P * sizeof(long long));
   L.total = o;
   return L;
 }
@@ -279,6 +280,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   v.qwin = reinterpret_cast<int2*>(ctx->ws + L.qwin);
   v.wg_start = reinterpret_cast<int32_t*>(ctx->ws + L.wg_start);
   v.gcost = reinterpret_cast<int32_t*>(ctx->ws + L.gcost);
+  v.pcost = reinterpret_cast<long long*>(ctx->ws + L.pcost);
   v.err = ctx->err_dev;
   v.n_pairs = n_pairs;
   v.total_blocks = int32_t(L.sum_blocks);

@@ -417,6 +417,7 @@ __global__ __launch_bounds__(256) void tile_ranges_kernel(BatchView v, int32_t p
   const ImageDev A = v.images[P.a];
   const ImageDev B = v.images[P.b];
   const float band = v.geom[p].band32;
+  long long my_cost = 0;
   for (int32_t g = threadIdx.x; g < P.ngroups; g += blockDim.x) {
     TileGroup tg;
     const int32_t k0 = g * kGroupTiles;
@@ -461,74 +462,73 @@ __global__ __launch_bounds__(256) void tile_ranges_kernel(BatchView v, int32_t p
     // A group costs a fixed start-up plus one pipeline step per 32 positions
     // of its union range (every step of the union has a computing wave).
     const int32_t steps = (tg.s_end - tg.s_begin + kCandTile - 1) / kCandTile;
-    v.gcost[P.grp_off + g] = kGroupStartCost + kStepCost * steps;
+    const int32_t c = kGroupStartCost + kStepCost * steps;
+    v.gcost[P.grp_off + g] = c;
+    my_cost += c;
   }
+  // The pair's total cost.
+  __shared__ long long red[256];
+  red[threadIdx.x] = my_cost;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) v.pcost[p] = red[0];
 }
 
-// Splits groups [g0, g0 + n) into `wgs` contiguous runs of about equal cost:
-// group g goes to the run whose share of the total cost contains the cost
-// before g.  One workgroup; costs are staged through LDS a chunk at a time and
-// thread t walks its own contiguous segment of the chunk.
-constexpr int kSchedThreads = 1024;
-constexpr int kSchedChunk = 8192;
-
-__device__ __forceinline__ int32_t run_of(long long before, int32_t wgs, long long total) {
-  return int32_t(before * wgs / total);
-}
-
-__global__ __launch_bounds__(kSchedThreads) void schedule_kernel(BatchView v, int32_t g0, int32_t n,
-                                                                 int32_t wgs) {
-  __shared__ int32_t cst[kSchedChunk];
-  __shared__ long long part[kSchedThreads];
-  const int t = threadIdx.x;
-  const int32_t* cost = v.gcost + g0;
-
-  long long mine = 0;
-  for (int32_t g = t; g < n; g += kSchedThreads) mine += cost[g];
-  part[t] = mine;
-  __syncthreads();
-  for (int o = kSchedThreads / 2; o > 0; o >>= 1) {
-    if (t < o) part[t] += part[t + o];
-    __syncthreads();
+// Splits the tile groups of pairs [pb, pb + pc) into `wgs` contiguous runs of
+// about equal cost: group g goes to run floor(pre(g) * wgs / total), pre(g)
+// being the cost of the groups before it, so run k starts at the first group
+// with pre(g) * wgs >= k * total.  One wave per pair finds the starts that
+// fall inside its pair; the pair with the last group also closes the table.
+__global__ __launch_bounds__(256) void schedule_kernel(BatchView v, int32_t pb, int32_t pc,
+                                                       int32_t g0, int32_t n, int32_t wgs) {
+  const int lane = threadIdx.x & 63;
+  const int32_t p = pb + int32_t(blockIdx.x) * 4 + int32_t(threadIdx.x >> 6);
+  if (p >= pb + pc) return;
+  // Cost before this pair and in total.
+  long long before = 0, total = 0;
+#pragma unroll 4
+  for (int32_t q = pb + lane; q < pb + pc; q += 64) {
+    const long long c = v.pcost[q];
+    total += c;
+    before += q < p ? c : 0;
   }
-  const long long total = part[0];
-  __syncthreads();
-
-  long long base = 0;   // cost before the chunk
-  for (int32_t c0 = 0; c0 < n; c0 += kSchedChunk) {
-    const int32_t m = min(kSchedChunk, n - c0);
-    for (int32_t i = t; i < m; i += kSchedThreads) cst[i] = cost[c0 + i];
-    __syncthreads();
-    const int32_t seg = (m + kSchedThreads - 1) / kSchedThreads;
-    const int32_t lo = min(m, t * seg), hi = min(m, lo + seg);
-    mine = 0;
-    for (int32_t i = lo; i < hi; ++i) mine += cst[i];
-    part[t] = mine;
-    __syncthreads();
-    // Inclusive scan of the segment sums (Hillis-Steele over LDS).
-    for (int o = 1; o < kSchedThreads; o <<= 1) {
-      const long long add = t >= o ? part[t - o] : 0;
-      __syncthreads();
-      part[t] += add;
-      __syncthreads();
-    }
-    if (lo < hi) {
-      long long pre = base + part[t] - mine;   // cost before group c0 + lo
-      const int32_t gl = c0 + lo;
-      int32_t prev = gl == 0 ? -1 : run_of(pre - (lo > 0 ? cst[lo - 1] : cost[gl - 1]), wgs, total);
-      for (int32_t i = lo; i < hi; ++i) {
-        const int32_t run = run_of(pre, wgs, total);
-        for (int32_t k = prev + 1; k <= run; ++k) v.wg_start[k] = g0 + c0 + i;
-        prev = run;
-        pre += cst[i];
-      }
-    }
-    base += part[kSchedThreads - 1];
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    total += __shfl_xor(total, o, 64);
+    before += __shfl_xor(before, o, 64);
   }
-  if (t == 0 && n > 0) {
-    const int32_t last = run_of(total - cost[n - 1], wgs, total);
-    for (int32_t k = last + 1; k <= wgs; ++k) v.wg_start[k] = g0 + n;
+  const PairDesc P = v.pairs[p];
+  const int32_t ng = P.ngroups;
+  if (ng == 0 || total <= 0) return;
+  const int32_t gl = int32_t(P.grp_off) - g0;   // first group of the pair, local
+  const int32_t* cost = v.gcost + g0 + gl;
+  const long long W = wgs;
+  // Starts that fall in this pair: k in [k_lo, k_hi].
+  const long long last_pre = before + v.pcost[p] - cost[ng - 1];
+  const int32_t k_hi = int32_t(last_pre * W / total);
+  int32_t k = gl == 0 ? 0 : int32_t((before - v.gcost[g0 + gl - 1]) * W / total) + 1;
+  long long carry = before;
+  for (int32_t c0 = 0; c0 < ng && k <= k_hi; c0 += 64) {
+    const int32_t j = c0 + lane;
+    const long long c = j < ng ? cost[j] : 0;
+    long long inc = c;   // inclusive scan over the chunk
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long y = __shfl_up(inc, o, 64);
+      inc += lane >= o ? y : 0;
+    }
+    const long long pre = carry + inc - c;
+    while (k <= k_hi) {
+      const unsigned long long hit = __ballot(j < ng && pre * W >= (long long)k * total);
+      if (!hit) break;
+      if (lane == 0) v.wg_start[k] = g0 + gl + c0 + __builtin_ctzll(hit);
+      ++k;
+    }
+    carry += __shfl(inc, 63, 64);
+  }
+  if (gl + ng == n && lane == 0) {
+    for (int32_t kk = k_hi + 1; kk <= wgs; ++kk) v.wg_start[kk] = g0 + n;
   }
 }
 
@@ -552,8 +552,8 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t gr
   hipLaunchKernelGGL(bin_kernel, dim3(pc, 2), dim3(kBinThreads), 0, st, v, pb);
   hipLaunchKernelGGL(tile_ranges_kernel, dim3(pc), dim3(256), 0, st, v, pb);
   if (grp_count > 0)
-    hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, v, grp_begin,
-                       grp_count, wgs);
+    hipLaunchKernelGGL(schedule_kernel, dim3((pc + 3) / 4), dim3(256), 0, st, v, pb, pc,
+                       grp_begin, grp_count, wgs);
   return hipGetLastError();
 }
 

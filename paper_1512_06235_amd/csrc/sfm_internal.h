@@ -128,6 +128,7 @@ struct BatchView {
   int2* qwin;               // per query in tile order: first, last bin (first > last = none)
   TileGroup* groups;
   int32_t* gcost;           // per tile group: estimated cost of matching it
+  long long* pcost;         // per pair: the sum of its groups' costs
   int32_t* wg_start;        // match workgroup k takes groups [wg_start[k], wg_start[k + 1])
   QueryResult* res;
   PairCounters* counters;
