@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
 INT8_PEAK_TOPS = 5000.0    # MI355X dense int8 MFMA, vendor figure
+MATCH_SOURCE = os.path.join(ROOT, "paper_1512_06235_amd", "csrc", "kernels_match.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "match_kernel_500pair_arc_traffic.txt")
 
 
 def log(msg):
@@ -43,6 +45,96 @@ def algorithmic_bytes(images, pairs):
     """Bytes the match step must read: 128-B descriptor + 8-B keypoint per
     feature of both images of every pair."""
     return sum(136 * (images[a][0].shape[0] + images[b][0].shape[0]) for a, b, _ in pairs)
+
+
+def source_digest(path=MATCH_SOURCE):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per match-kernel launch from the committed counter summary,
+    or None when there is none or the kernel source changed since."""
+    try:
+        fields = dict(line.split(":", 1) for line in open(TRAFFIC_SUMMARY) if ":" in line)
+    except OSError:
+        return None
+    fields = {k.strip(): v.strip() for k, v in fields.items()}
+    if fields.get("kernel_source_sha256") != source_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _kernel_key(name):
+    import re
+    m = re.search(r"(\w+_kernel)(<[^>]*>)?\(", name)
+    return (m.group(1) + (m.group(2) or "")) if m else name.split("(")[0]
+
+
+def _counter_means(directory, counter):
+    """Mean value of `counter` per dispatch, by kernel, from rocprofv3 csv output."""
+    import csv
+    import glob
+    sums, counts = {}, {}
+    for f in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = _kernel_key(r["Kernel_Name"])
+            sums[k] = sums.get(k, 0.0) + float(r["Counter_Value"])
+            counts[k] = counts.get(k, 0) + 1
+    return {k: (sums[k] / counts[k], counts[k]) for k in sums}
+
+
+def summarize_trace(directory, command):
+    """Per-kernel durations from a `rocprofv3 --kernel-trace --stats` csv run."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)
+    rows = []
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            rows.append((_kernel_key(r["Name"]), int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                         float(r["TotalDurationNs"]) / 1e3, float(r["Percentage"])))
+    rows.sort(key=lambda r: -r[3])
+    out = ["rocprofv3 kernel statistics", f"command: {command}", "",
+           f"{'kernel':34s} {'calls':>6s} {'avg_us':>10s} {'total_us':>11s} {'percent':>8s}"]
+    out += [f"{k[:34]:34s} {c:6d} {a:10.2f} {t:11.1f} {p:8.2f}" for k, c, a, t, p in rows[:16]]
+    return "\n".join(out) + "\n"
+
+
+def summarize_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_mib, commands):
+    """HBM bytes per match-kernel launch: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), each scaled by what the same counter reads for a device copy of
+    known size."""
+    fetch = _counter_means(fetch_dir, "FETCH_SIZE")
+    write = _counter_means(write_dir, "WRITE_SIZE")
+    cfetch = _counter_means(cal_fetch_dir, "FETCH_SIZE")
+    cwrite = _counter_means(cal_write_dir, "WRITE_SIZE")
+    copy_key = max(cfetch, key=lambda k: cfetch[k][0])
+    nbytes_kib = cal_mib * 1024.0
+    f_factor = nbytes_kib / cfetch[copy_key][0]
+    w_factor = nbytes_kib / cwrite[copy_key][0]
+    kf, nf = fetch["match_kernel<false>"]
+    kw, nw = write["match_kernel<false>"]
+    hbm = (kf * f_factor + kw * w_factor) * 1024.0
+    lines = ["HBM traffic of match_kernel, 500-pair arc-scene batch (rocprofv3 --pmc)",
+             *[f"command_{i}: {c}" for i, c in enumerate(commands)], "",
+             f"copy_kernel: {copy_key}",
+             f"copy_bytes: {int(cal_mib) << 20}",
+             f"copy_fetch_kib_per_dispatch: {cfetch[copy_key][0]:.0f}",
+             f"copy_write_kib_per_dispatch: {cwrite[copy_key][0]:.0f}",
+             f"fetch_factor: {f_factor:.4f}",
+             f"write_factor: {w_factor:.4f}",
+             f"match_fetch_kib_per_dispatch: {kf:.0f}  (dispatches: {nf})",
+             f"match_write_kib_per_dispatch: {kw:.0f}  (dispatches: {nw})",
+             f"hbm_bytes_per_launch: {hbm:.0f}",
+             f"kernel_source_sha256: {source_digest()}"]
+    return "\n".join(lines) + "\n"
 
 
 def timed(fn, steps, stream):
@@ -84,7 +176,21 @@ def main():
     ap.add_argument("--no-context", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("DIR", "COMMAND"),
+                    help="print a summary of a rocprofv3 --kernel-trace --stats csv run")
+    ap.add_argument("--summarize-traffic", nargs=6,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR", "CAL_MIB",
+                             "COMMANDS"),
+                    help="print the HBM traffic summary of rocprofv3 --pmc runs "
+                         "(COMMANDS: the four commands, joined by ' || ')")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(*args.summarize_trace), end="")
+        return
+    if args.summarize_traffic:
+        f, w, cf, cw, mib, cmds = args.summarize_traffic
+        print(summarize_traffic(f, w, cf, cw, float(mib), cmds.split(" || ")), end="")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); pairs are independent, "
               "so a multi-GPU run would shard the pair list without communication.",
@@ -192,7 +298,7 @@ def main():
                                "emit": emit_ms / max(1, nrec)},
         "roofline": {"bound": "hbm", "kernel": "match_kernel", "achieved": achieved_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": bytes_launch,
+                     "traffic": measured_traffic(), "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": match_s * 1e3,
                      "int8_mfma_frac": 256.0 * comparisons / match_s / 1e12 / INT8_PEAK_TOPS},
         "context_bruteforce": context,
