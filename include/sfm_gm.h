@@ -170,6 +170,66 @@ int sfm_phase_times(sfm_ctx* ctx, double ms[3], int64_t* n_records);
  * exact tie-break pass, out[3] accepted matches. */
 int sfm_last_stats(sfm_ctx* ctx, int64_t out[4]);
 
+/* ---------------------------------------------------------------------------
+ * Serving loop.  Single-pair requests (the image pairs that Section 6.1
+ * selects, arriving one at a time) are batched on the fly: a worker thread
+ * concatenates the waiting requests into one sfm_guided_match launch on the
+ * server's own stream whenever one of max_inflight result slots is free, and
+ * a completion thread copies each request's accepted matches into pinned host
+ * memory.  Latency = done_ns - arrival_ns, on the sfm_server_now_ns() clock.
+ * One server per context; while it runs, other calls on the context still
+ * work (calls on a context are ordered through its workspace). */
+typedef struct {
+  int32_t max_batch_pairs;     /* requests per launch (default 256) */
+  int32_t max_inflight;        /* launches whose results are outstanding, 1..8 (default 2) */
+  int64_t max_batch_queries;   /* cap on the summed n_a of one launch (default 2^22);
+                                  a single larger request fails with SFM_ECAPACITY */
+  sfm_options opt;             /* emit_all must be 0 */
+} sfm_server_cfg;
+
+typedef struct {
+  int32_t* query;              /* host, caller-owned, capacity rows: accepted matches */
+  int32_t* match;              /* in ascending query order, as in sfm_matches */
+  int32_t* d1;
+  int32_t* d2;
+  int64_t capacity;
+  int64_t n_matches;           /* out */
+  int64_t n_comparisons;       /* out: candidate comparisons of the request */
+  int64_t arrival_ns;          /* out: the request's arrival time */
+  int64_t done_ns;             /* out: when its rows were in host memory */
+  int32_t status;              /* out: SFM_OK or the error of its launch */
+  int32_t pad;
+} sfm_result_view;
+
+/* Monotonic clock of the server, nanoseconds (CLOCK_MONOTONIC). */
+int64_t sfm_server_now_ns(void);
+
+/* Start the serving threads (cfg may be NULL for defaults).  Allocates the
+ * result slots: per slot four int32 device and pinned host arrays of
+ * max_batch_queries rows.  SFM_EBUSY if a server already runs on ctx. */
+int sfm_server_start(sfm_ctx* ctx, const sfm_server_cfg* cfg);
+
+/* Queue one pair (host sfm_pair and double F[9], read before returning).
+ * arrival_ns is the request's arrival time (<= 0: now).  Checks the image
+ * indices, band and F (SFM_EINVAL); SFM_EBUSY if no server runs.  *ticket
+ * identifies the request for sfm_server_poll. */
+int sfm_server_submit(sfm_ctx* ctx, const sfm_pair* pair, const double* F, int64_t arrival_ns,
+                      uint64_t* ticket);
+
+/* Collect a request's result into *out, waiting up to timeout_ms
+ * (0: do not wait, < 0: wait for ever).  SFM_ETIMEOUT: not ready yet;
+ * SFM_ENOTFOUND: unknown or already collected ticket; SFM_ECAPACITY: out
+ * cannot hold its n_matches rows (out->n_matches says how many; the result
+ * stays collectable).  A collected result is released. */
+int sfm_server_poll(sfm_ctx* ctx, uint64_t ticket, sfm_result_view* out, int32_t timeout_ms);
+
+/* out[0] launches so far, out[1] requests launched, out[2] requests waiting. */
+int sfm_server_stats(sfm_ctx* ctx, int64_t out[3]);
+
+/* Launch every waiting request, wait for all results, stop the threads and
+ * free the slots.  Uncollected results are dropped. */
+int sfm_server_stop(sfm_ctx* ctx);
+
 /* Human-readable name of a status code (static string). */
 const char* sfm_strerror(int status);
 

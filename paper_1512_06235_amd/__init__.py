@@ -54,6 +54,18 @@ class sfm_matches(C.Structure):
                 ("all_d1", C.c_void_p), ("all_d2", C.c_void_p), ("all_count", C.c_void_p)]
 
 
+class sfm_server_cfg(C.Structure):
+    _fields_ = [("max_batch_pairs", C.c_int32), ("max_inflight", C.c_int32),
+                ("max_batch_queries", C.c_int64), ("opt", sfm_options)]
+
+
+class sfm_result_view(C.Structure):
+    _fields_ = [("query", C.c_void_p), ("match", C.c_void_p), ("d1", C.c_void_p),
+                ("d2", C.c_void_p), ("capacity", C.c_int64), ("n_matches", C.c_int64),
+                ("n_comparisons", C.c_int64), ("arrival_ns", C.c_int64), ("done_ns", C.c_int64),
+                ("status", C.c_int32), ("pad", C.c_int32)]
+
+
 _lib = None
 
 
@@ -83,6 +95,11 @@ def lib() -> C.CDLL:
         "sfm_phase_times": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
         "sfm_last_stats": [vp, C.POINTER(i64)],
         "sfm_last_error": [vp, C.c_char_p, sz],
+        "sfm_server_start": [vp, C.POINTER(sfm_server_cfg)],
+        "sfm_server_submit": [vp, C.POINTER(sfm_pair), vp, i64, C.POINTER(C.c_uint64)],
+        "sfm_server_poll": [vp, C.c_uint64, C.POINTER(sfm_result_view), i32],
+        "sfm_server_stats": [vp, C.POINTER(i64)],
+        "sfm_server_stop": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -90,6 +107,8 @@ def lib() -> C.CDLL:
         fn.restype = C.c_int
     L.sfm_strerror.argtypes = [C.c_int]
     L.sfm_strerror.restype = C.c_char_p
+    L.sfm_server_now_ns.argtypes = []
+    L.sfm_server_now_ns.restype = C.c_int64
     _lib = L
     return L
 
@@ -99,7 +118,8 @@ def exported_symbols():
     return ["sfm_create", "sfm_destroy", "sfm_register_images", "sfm_workspace_size",
             "sfm_guided_match", "sfm_guided_match_plain", "sfm_bruteforce_match", "sfm_sync",
             "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
-            "sfm_last_error"]
+            "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
+            "sfm_server_poll", "sfm_server_stats", "sfm_server_stop"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -198,6 +218,51 @@ def sfm_last_stats(ctx) -> dict:
     v = (C.c_int64 * 4)()
     _check(ctx, lib().sfm_last_stats(ctx, v))
     return {"comparisons": v[0], "slots": v[1], "tie_passes": v[2], "accepted": v[3]}
+
+
+def sfm_server_now_ns() -> int:
+    return int(lib().sfm_server_now_ns())
+
+
+def sfm_server_start(ctx, max_batch_pairs=256, max_inflight=2, max_batch_queries=1 << 22,
+                     opt: sfm_options = None) -> None:
+    cfg = sfm_server_cfg(int(max_batch_pairs), int(max_inflight), int(max_batch_queries),
+                         opt if opt is not None else options())
+    _check(ctx, lib().sfm_server_start(ctx, C.byref(cfg)))
+
+
+def sfm_server_submit(ctx, pair, F, arrival_ns: int = 0) -> int:
+    a, b, band = pair
+    p = sfm_pair(int(a), int(b), float(band))
+    Fh = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(9))
+    t = C.c_uint64()
+    _check(ctx, lib().sfm_server_submit(ctx, C.byref(p), Fh.ctypes.data, int(arrival_ns),
+                                        C.byref(t)))
+    return t.value
+
+
+def sfm_server_poll(ctx, ticket: int, capacity: int, timeout_ms: int = -1):
+    """The request's result as a dict with host arrays, or None on SFM_ETIMEOUT."""
+    bufs = [np.empty(max(1, int(capacity)), dtype=np.int32) for _ in range(4)]
+    v = sfm_result_view(*(b.ctypes.data for b in bufs), int(capacity), 0, 0, 0, 0, 0, 0)
+    st = lib().sfm_server_poll(ctx, int(ticket), C.byref(v), int(timeout_ms))
+    if st == SFM_ETIMEOUT:
+        return None
+    _check(ctx, st)
+    n = int(v.n_matches)
+    return {"status": int(v.status), "query": bufs[0][:n], "match": bufs[1][:n],
+            "d1": bufs[2][:n], "d2": bufs[3][:n], "n_comparisons": int(v.n_comparisons),
+            "arrival_ns": int(v.arrival_ns), "done_ns": int(v.done_ns)}
+
+
+def sfm_server_stats(ctx) -> dict:
+    v = (C.c_int64 * 3)()
+    _check(ctx, lib().sfm_server_stats(ctx, v))
+    return {"launches": v[0], "launched": v[1], "waiting": v[2]}
+
+
+def sfm_server_stop(ctx) -> None:
+    _check(ctx, lib().sfm_server_stop(ctx))
 
 
 def options(ratio_num=64, ratio_den=100, accept_single=False, emit_all=False) -> sfm_options:

@@ -326,6 +326,14 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
 
 }  // namespace
 
+namespace sfm {
+int32_t ctx_device(const sfm_ctx* ctx) { return ctx->device; }
+int32_t ctx_n_images(const sfm_ctx* ctx) { return ctx->n_images; }
+int32_t ctx_image_size(const sfm_ctx* ctx, int32_t image) {
+  return image >= 0 && image < ctx->n_images ? ctx->n_host[size_t(image)] : 0;
+}
+}  // namespace sfm
+
 extern "C" {
 
 const char* sfm_strerror(int status) {
@@ -382,6 +390,7 @@ static void free_registration(sfm_ctx* ctx) {
 
 int sfm_destroy(sfm_ctx* ctx) {
   if (!ctx) return SFM_EINVAL;
+  server_release(ctx);
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   free_registration(ctx);

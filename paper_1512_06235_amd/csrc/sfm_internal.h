@@ -141,6 +141,19 @@ struct BatchView {
   int32_t keep_counts;
 };
 
+}  // namespace sfm
+
+struct sfm_ctx;
+
+namespace sfm {
+
+// Context accessors for the serving loop, and its teardown (called by
+// sfm_destroy before the context goes away).
+int32_t ctx_device(const sfm_ctx* ctx);
+int32_t ctx_n_images(const sfm_ctx* ctx);
+int32_t ctx_image_size(const sfm_ctx* ctx, int32_t image);
+void server_release(sfm_ctx* ctx);
+
 // Host launchers (one translation unit each).
 hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_t n_images,
                            int32_t* norm2_all, const int64_t* norm_off, float* bbox_dev,

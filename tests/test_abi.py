@@ -12,13 +12,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "sfm_gm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|const char\s*\*)\s+(sfm_\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\s*\*)\s+(sfm_\w+)\s*\(", src,
+                                 flags=re.M)))
 
 
 def test_header_declares_entry_points():
     names = declared_functions()
     for n in ("sfm_create", "sfm_register_images", "sfm_guided_match", "sfm_guided_match_plain",
-              "sfm_bruteforce_match", "sfm_strerror"):
+              "sfm_bruteforce_match", "sfm_strerror", "sfm_server_start", "sfm_server_submit",
+              "sfm_server_poll", "sfm_server_stop", "sfm_server_now_ns"):
         assert n in names
 
 
@@ -29,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(pkg.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert set(pkg.exported_symbols()) <= set(declared_functions()) | {"sfm_strerror"}
+    assert set(pkg.exported_symbols()) == set(declared_functions())
 
 
 def test_strerror_without_gpu():

@@ -1,0 +1,143 @@
+"""Serving loop (sfm_server_*) through the C ABI: results equal the batched
+form (itself checked against the oracle) and the oracle directly; error
+paths; an open-loop Poisson stream completes with sane latencies."""
+import numpy as np
+import pytest
+
+import scenes
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sfm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1512_06235_amd as sfm
+    sfm.lib()
+    return sfm
+
+
+@pytest.fixture(scope="module")
+def ring():
+    """12 cameras on a ring, 20k points, 1k-4k features; covisible pairs."""
+    centers = scenes.generator._ring(12, 20.0, 0.0)
+    scene = scenes.make_multiview_scene(centers, 1000, 4000, n_points=20_000, seed=3)
+    images = [(scene.image(k).xy, scene.image(k).desc) for k in range(scene.n_images)]
+    pairs = [(a, b, 4.0) for a, b in scenes.covisible_pairs(scene, top_k=4)]
+    Fs = np.stack([scene.F(a, b) for a, b, _ in pairs])
+    say(f"  ring scene: {len(images)} images, {len(pairs)} pairs")
+    return images, pairs, Fs
+
+
+def collect(sfm, ctx, tickets, capacity):
+    out = []
+    for t in tickets:
+        r = sfm.sfm_server_poll(ctx, t, capacity, timeout_ms=60_000)
+        assert r is not None, "result not ready within 60 s"
+        out.append(r)
+    return out
+
+
+def test_server_equals_batched_and_oracle(sfm, oracle_lib, ring):
+    images, pairs, Fs = ring
+    m = sfm.Matcher().register(images)
+    ref = m.match(pairs, Fs, form="batched")
+    cap = max(m.n_features(a) for a, _, _ in pairs)
+    sfm.sfm_server_start(m.ctx, max_batch_pairs=5, max_inflight=2)
+    try:
+        tickets = [sfm.sfm_server_submit(m.ctx, p, F) for p, F in zip(pairs, Fs)]
+        res = collect(sfm, m.ctx, tickets, cap)
+        stats = sfm.sfm_server_stats(m.ctx)
+    finally:
+        sfm.sfm_server_stop(m.ctx)
+    say(f"  {stats['launches']} launches for {stats['launched']} requests")
+    assert stats["launched"] == len(pairs)
+    assert stats["launches"] >= (len(pairs) + 4) // 5
+    ncmp = ref.n_comparisons.cpu().numpy()
+    for k, r in enumerate(res):
+        assert r["status"] == sfm.SFM_OK
+        q, mt, d1, d2 = ref.pair(k)
+        assert np.array_equal(r["query"], q) and np.array_equal(r["match"], mt)
+        assert np.array_equal(r["d1"], d1) and np.array_equal(r["d2"], d2)
+        assert r["n_comparisons"] == int(ncmp[k])
+        assert r["done_ns"] >= r["arrival_ns"] > 0
+    # Two requests straight against the oracle (non-borderline queries).
+    for k in (0, len(pairs) - 1):
+        o = oracle_lib.match(images, [pairs[k]], Fs[k:k + 1]).pair(0)
+        clean = o["borderline"] == 0
+        oq = np.nonzero(o["accept"] & clean)[0]
+        q = res[k]["query"]
+        keep = clean[q]
+        assert np.array_equal(q[keep], oq)
+        assert np.array_equal(res[k]["match"][keep], o["match"][oq])
+        assert np.array_equal(res[k]["d1"][keep], o["d1"][oq])
+        assert np.array_equal(res[k]["d2"][keep], o["d2"][oq])
+
+
+def test_server_errors(sfm, ring):
+    images, pairs, Fs = ring
+    m = sfm.Matcher().register(images)
+    with pytest.raises(sfm.SfmError) as e:
+        sfm.sfm_server_submit(m.ctx, pairs[0], Fs[0])
+    assert e.value.status == sfm.SFM_EBUSY           # no server yet
+    sfm.sfm_server_start(m.ctx, max_batch_pairs=4)
+    try:
+        with pytest.raises(sfm.SfmError) as e:
+            sfm.sfm_server_start(m.ctx)
+        assert e.value.status == sfm.SFM_EBUSY
+        for bad_pair, bad_F in (((0, len(images), 4.0), Fs[0]), ((0, 1, -1.0), Fs[0]),
+                                (pairs[0], np.zeros(9)), (pairs[0], np.full(9, np.nan))):
+            with pytest.raises(sfm.SfmError) as e:
+                sfm.sfm_server_submit(m.ctx, bad_pair, bad_F)
+            assert e.value.status == sfm.SFM_EINVAL
+        with pytest.raises(sfm.SfmError) as e:
+            sfm.sfm_server_poll(m.ctx, 10**9, 16, timeout_ms=0)
+        assert e.value.status == sfm.SFM_ENOTFOUND
+        t = sfm.sfm_server_submit(m.ctx, pairs[0], Fs[0])
+        # Too small a buffer: reported, and the result stays collectable.
+        with pytest.raises(sfm.SfmError) as e:
+            sfm.sfm_server_poll(m.ctx, t, 0, timeout_ms=60_000)
+        assert e.value.status == sfm.SFM_ECAPACITY
+        r = sfm.sfm_server_poll(m.ctx, t, m.n_features(pairs[0][0]), timeout_ms=0)
+        assert r is not None and r["status"] == sfm.SFM_OK and r["query"].size > 0
+        with pytest.raises(sfm.SfmError) as e:
+            sfm.sfm_server_poll(m.ctx, t, 16, timeout_ms=0)
+        assert e.value.status == sfm.SFM_ENOTFOUND    # collected once
+    finally:
+        sfm.sfm_server_stop(m.ctx)
+    with pytest.raises(sfm.SfmError) as e:
+        sfm.sfm_server_stop(m.ctx)
+    assert e.value.status == sfm.SFM_EBUSY
+
+
+def test_server_open_loop(sfm, ring):
+    """300 requests at 1,000 pairs/s (Poisson, open loop): every result
+    arrives, arrival <= done, and a stop with requests in flight drains them."""
+    images, pairs, Fs = ring
+    m = sfm.Matcher().register(images)
+    cap = max(m.n_features(a) for a, _, _ in pairs)
+    arrivals = scenes.poisson_arrivals(1000.0, 0.3, seed=5)
+    rng = np.random.default_rng(5)
+    pick = rng.integers(0, len(pairs), size=len(arrivals))
+    sfm.sfm_server_start(m.ctx, max_batch_pairs=64, max_inflight=2)
+    tickets = []
+    try:
+        t0 = sfm.sfm_server_now_ns() + 2_000_000
+        for t, k in zip(arrivals, pick):
+            due = t0 + int(t * 1e9)
+            while sfm.sfm_server_now_ns() < due:
+                pass
+            tickets.append(sfm.sfm_server_submit(m.ctx, pairs[k], Fs[k], due))
+        res = collect(sfm, m.ctx, tickets, cap)
+        # A last burst that stop() must drain.
+        for k in range(8):
+            sfm.sfm_server_submit(m.ctx, pairs[k % len(pairs)], Fs[k % len(pairs)])
+    finally:
+        sfm.sfm_server_stop(m.ctx)
+    lat = np.array([(r["done_ns"] - r["arrival_ns"]) / 1e6 for r in res])
+    say(f"  {len(res)} requests: p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
+    assert all(r["status"] == sfm.SFM_OK for r in res)
+    assert np.all(lat > 0)
