@@ -137,6 +137,62 @@ def summarize_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_mi
     return "\n".join(lines) + "\n"
 
 
+def serving(sfm, rates, duration_s, log_fn):
+    """Open-loop Poisson streams of single-pair requests on the 300-camera
+    three-ring scene (covisible pairs, top 30 per image), served by
+    sfm_server_*.  Latency: scheduled arrival to rows in pinned host memory."""
+    import scenes
+    log_fn("bench: serving scene (300 cameras, 4k-25k features)")
+    sc = scenes.make_config_c4()
+    images = [(sc.image(k).xy, sc.image(k).desc) for k in range(sc.n_images)]
+    pairs = [(a, b, 4.0) for a, b in scenes.covisible_pairs(sc)]
+    Fs = np.stack([sc.F(a, b) for a, b, _ in pairs])
+    m = sfm.Matcher(device=0).register(images)
+    cap = max(m.n_features(a) for a, _, _ in pairs)
+    out = {"workload": "open-loop Poisson pair requests, 300 cameras on 3 rings, "
+                       "4k-25k features per image, covisible pairs (>= 8 shared points, top 30 "
+                       "per image), band 4 px",
+           "images": len(images), "request_pool": len(pairs), "duration_s": duration_s,
+           "rates": []}
+    rng = np.random.default_rng(2)
+    for rate in rates:
+        arrivals = scenes.poisson_arrivals(rate, duration_s, seed=int(rate))
+        pick = rng.integers(0, len(pairs), size=len(arrivals))
+        sfm.sfm_server_start(m.ctx, max_batch_pairs=256, max_inflight=2)
+        try:
+            # Warm-up: one full batch sizes the workspace.
+            warm = [sfm.sfm_server_submit(m.ctx, pairs[k], Fs[k]) for k in range(256)]
+            for t in warm:
+                sfm.sfm_server_poll(m.ctx, t, cap)
+            s0 = sfm.sfm_server_stats(m.ctx)
+            log_fn(f"bench: serving {len(arrivals)} requests at {rate}/s")
+            t0 = sfm.sfm_server_now_ns() + 5_000_000
+            tickets = []
+            for t, k in zip(arrivals, pick):
+                due = t0 + int(t * 1e9)
+                while sfm.sfm_server_now_ns() < due:
+                    pass
+                tickets.append(sfm.sfm_server_submit(m.ctx, pairs[k], Fs[k], due))
+            res = [sfm.sfm_server_poll(m.ctx, t, cap, timeout_ms=120_000) for t in tickets]
+            s1 = sfm.sfm_server_stats(m.ctx)
+        finally:
+            sfm.sfm_server_stop(m.ctx)
+        assert all(r is not None and r["status"] == sfm.SFM_OK for r in res)
+        lat = np.array([(r["done_ns"] - r["arrival_ns"]) / 1e6 for r in res])
+        span = (max(r["done_ns"] for r in res) - t0) / 1e9
+        cmp_total = sum(r["n_comparisons"] for r in res)
+        launches = s1["launches"] - s0["launches"]
+        out["rates"].append({
+            "offered_pairs_per_s": rate, "requests": len(res),
+            "p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "max_ms": round(float(lat.max()), 4),
+            "launches": int(launches), "mean_batch": round(len(res) / max(1, launches), 2),
+            "comparisons_per_s": cmp_total / span})
+    m.close()
+    return out
+
+
 def timed(fn, steps, stream):
     import torch
     torch.cuda.synchronize()
@@ -174,6 +230,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=3.0)
+    ap.add_argument("--serving-rates", default="1000,5000",
+                    help="offered pair requests per second, comma-separated")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DIR", "COMMAND"),
@@ -275,6 +335,11 @@ def main():
                    "guided_speedup_vs_bruteforce": round(tb / tg, 2)}
         m2.close()
 
+    serve = None
+    if not args.no_serving:
+        serve = serving(sfm, [float(r) for r in args.serving_rates.split(",")],
+                        args.serving_seconds, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
@@ -301,6 +366,7 @@ def main():
                      "traffic": measured_traffic(), "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": match_s * 1e3,
                      "int8_mfma_frac": 256.0 * comparisons / match_s / 1e12 / INT8_PEAK_TOPS},
+        "serving": serve,
         "context_bruteforce": context,
         "cpu_baseline": cpu,
     }
