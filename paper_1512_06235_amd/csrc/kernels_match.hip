@@ -1,13 +1,13 @@
 // Fused candidate test + distance + two-nearest kernel (a4-a6), Appendix A
 // steps 3-4 redesigned for CDNA4.
 //
-// A workgroup of four waves owns a group of up to four consecutive query
-// tiles (32 queries each, in pencil order) of one pair.  Their candidate
-// ranges overlap heavily, so the workgroup streams the union range of b's
-// binned features through LDS once, 32 candidates per step:
-//   - each wave fetches 8 of the 32 descriptor rows with one coalesced load
-//     (eight lanes per 128-byte row) and stores them XOR-swizzled into the
-//     shared stage; one barrier per step publishes the stage;
+// A workgroup of kGroupTiles waves (two) owns a group of consecutive query
+// tiles (32 queries each, in pencil order) of one pair, one tile per wave.
+// Their candidate ranges overlap heavily, so the workgroup streams the union
+// range of b's binned features through LDS once, 32 candidates per step:
+//   - each wave fetches its share of the 32 descriptor rows with coalesced
+//     loads (eight lanes per 128-byte row) and stores them XOR-swizzled into
+//     the shared stage; one barrier per step publishes the stage;
 //   - each wave whose own range meets the step reads the rows back as the A
 //     operand of v_mfma_i32_32x32x32_i8; its negated query rows are the
 //     resident B operand, so four MFMAs give -q.c for a 32x32 tile with exact
@@ -22,6 +22,9 @@
 // The key orders equal distances by binned position, not by index in b; when
 // the two smallest keys of a chunk share the distance, an exact pass picks the
 // lowest index among the tied candidates, so results equal the definition.
+// Two tiles per group balance the row fetches each wave issues against the
+// steps a wave idles at the barrier outside its own range (four tiles: 13%
+// slower; one tile, no sharing: 17% slower, bound by the address units).
 #include <algorithm>
 #include <cmath>
 
@@ -37,6 +40,9 @@ typedef const __attribute__((address_space(1))) nv4u g_nv4u;
 typedef const __attribute__((address_space(1))) int32_t g_i32;
 
 constexpr int kWaves = kGroupTiles;
+constexpr int kRowsPerWave = kCandTile / kWaves;   // rows of a step each wave fetches
+constexpr int kRowLoads = kRowsPerWave / 8;        // 16-B-per-lane loads for them
+static_assert(kRowsPerWave % 8 == 0 && kRowsPerWave <= 64, "waves must split the step by 8 rows");
 constexpr int kMetaSlots = 3;
 
 // Band test of eqs. (2)-(3) on centred FP32 coordinates: |a x + b y + c| <= d
@@ -91,14 +97,15 @@ struct GroupLds {
   uint32_t sink[kWaves][3][64];    // targets of the lanes that own no record
 };
 
-// Wave w owns candidates 8w .. 8w+7 of every step: lane l < 8 holds the
-// record of candidate 8w + l.  Those lanes stage the metadata (the other lanes
-// write to distinct sink words: no divergent branch, no bank conflict).
-// Positions past the range get a NaN coordinate, which no band test passes.
+// Wave w owns candidates R*w .. R*w+R-1 of every step (R = kRowsPerWave):
+// lane l < R holds the record of candidate R*w + l.  Those lanes stage the
+// metadata (the other lanes write to distinct sink words: no divergent
+// branch, no bank conflict).  Positions past the range get a NaN coordinate,
+// which no band test passes.
 __device__ __forceinline__ void stage_meta(GroupLds& L, int st, const nv4u& r, int32_t t0,
                                            int32_t c1, int wave, int lane) {
-  const int cand_i = 8 * wave + (lane & 7);
-  const bool own = lane < 8;
+  const int cand_i = kRowsPerWave * wave + (lane % kRowsPerWave);
+  const bool own = lane < kRowsPerWave;
   float* px = own ? &L.x[st][cand_i] : reinterpret_cast<float*>(&L.sink[wave][0][lane]);
   float* py = own ? &L.y[st][cand_i] : reinterpret_cast<float*>(&L.sink[wave][1][lane]);
   uint32_t* pn = own ? &L.nc[st][cand_i] : &L.sink[wave][2][lane];
@@ -107,17 +114,20 @@ __device__ __forceinline__ void stage_meta(GroupLds& L, int st, const nv4u& r, i
   *pn = r.z;
 }
 
-// This wave's coalesced share of a step's rows: lane l fetches 16-byte chunk
-// (l & 7) of row 8w + (l >> 3), whose index in b lane (l >> 3) holds.
-__device__ __forceinline__ nv4u load_row_share(const nv4u& r, const uint8_t* desc, int lane) {
-  const int32_t j = __shfl(int32_t(r.w), lane >> 3, 64);
+// Load k of this wave's coalesced share of a step's rows: lane l fetches
+// 16-byte chunk (l & 7) of row R*w + 8k + (l >> 3), whose index in b lane
+// 8k + (l >> 3) holds.
+__device__ __forceinline__ nv4u load_row_share(const nv4u& r, const uint8_t* desc, int lane,
+                                               int k) {
+  const int32_t j = __shfl(int32_t(r.w), 8 * k + (lane >> 3), 64);
   return gload16(desc + int64_t(j) * kDescBytes + 16 * (lane & 7));
 }
 
-__device__ __forceinline__ void store_row_share(GroupLds& L, int st, int wave, int lane,
+__device__ __forceinline__ void store_row_share(GroupLds& L, int st, int wave, int lane, int k,
                                                 const nv4u& rw) {
   const int m = lane >> 3, c = lane & 7;
-  *reinterpret_cast<nv4u*>(&L.rows[st][(8 * wave + m) * kDescBytes + ((c ^ m) << 4)]) = rw;
+  const int row = kRowsPerWave * wave + 8 * k + m;   // row & 7 == m
+  *reinterpret_cast<nv4u*>(&L.rows[st][row * kDescBytes + ((c ^ m) << 4)]) = rw;
 }
 
 // The MFMA A operand: row (lane & 31), k-slice 16 * half + 32 * s = chunk 2s + half.
@@ -289,7 +299,7 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
 
   // Records of the first two steps go out with the query record; the query
   // row and the first candidate rows follow one latency later.
-  const int32_t own = 8 * wave + (lane & 7);
+  const int32_t own = kRowsPerWave * wave + (lane % kRowsPerWave);
   const bool any = S1 > S0;
   nv4u re = {0, 0, 0, 0}, ro = {0, 0, 0, 0};
   if (any) {
@@ -320,24 +330,29 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
     // is unrolled by two so the in-flight registers never move (a copy of a
     // register with a load in flight would wait for that load).
     const int32_t nsteps = (S1 - S0 + kCandTile - 1) / kCandTile;
+    nv4u we[kRowLoads], wo[kRowLoads];
     stage_meta(L, 0, re, S0, S1, wave, lane);
-    nv4u we = load_row_share(re, b_desc, lane);
+#pragma unroll
+    for (int k = 0; k < kRowLoads; ++k) we[k] = load_row_share(re, b_desc, lane, k);
     re = load_rec(cand, S0 + 2 * kCandTile + own, S1);
     stage_meta(L, 1, ro, S0 + kCandTile, S1, wave, lane);
-    nv4u wo = load_row_share(ro, b_desc, lane);
+#pragma unroll
+    for (int k = 0; k < kRowLoads; ++k) wo[k] = load_row_share(ro, b_desc, lane, k);
     ro = load_rec(cand, S0 + 3 * kCandTile + own, S1);
 
     uint32_t k1 = kKeyInf, k2 = kKeyInf;
     int32_t c0 = S0;
     int ms = 0;   // metadata slot of step u
     // One step; `w` and `r` are this parity's row and record registers.
-    auto step = [&](int32_t u, int rs, nv4u& w, nv4u& r) {
+    auto step = [&](int32_t u, int rs, nv4u (&w)[kRowLoads], nv4u& r) {
       const int32_t t0 = S0 + u * kCandTile;
-      store_row_share(L, rs, wave, lane, w);
+#pragma unroll
+      for (int k = 0; k < kRowLoads; ++k) store_row_share(L, rs, wave, lane, k, w[k]);
       __syncthreads();
       const int ms2 = ms == 0 ? 2 : ms - 1;   // (u + 2) % 3
       stage_meta(L, ms2, r, t0 + 2 * kCandTile, S1, wave, lane);
-      w = load_row_share(r, b_desc, lane);
+#pragma unroll
+      for (int k = 0; k < kRowLoads; ++k) w[k] = load_row_share(r, b_desc, lane, k);
       r = load_rec(cand, t0 + 4 * kCandTile + own, S1);
       if (t0 < my_e && t0 + kCandTile > my_b) {
         v4i a[4];

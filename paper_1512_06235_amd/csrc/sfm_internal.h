@@ -8,7 +8,10 @@ namespace sfm {
 
 constexpr int kDescBytes = 128;
 constexpr int kQueryTile = 32;          // queries per wave work item (MFMA N)
-constexpr int kGroupTiles = 4;          // query tiles (waves) sharing one candidate stream
+#ifndef SFM_GROUP_TILES
+#define SFM_GROUP_TILES 2
+#endif
+constexpr int kGroupTiles = SFM_GROUP_TILES;  // query tiles (waves) sharing one candidate stream
 constexpr int kCandTile = 32;           // candidates per MFMA step (MFMA M)
 constexpr int kChunk = 1024;            // candidate positions one key encodes
 constexpr int kPosBits = 10;            // log2(kChunk)
