@@ -68,7 +68,7 @@ int hip_fail(sfm_ctx* ctx, hipError_t e, const char* what) {
 
 // Sections of one call's workspace.
 struct Layout {
-  size_t pairs, F, geom, counters, wg_start, cand, bins, qrec, res, qwin, groups, gcost, pcost, total, staged;
+  size_t pairs, F, order, geom, counters, wg_start, cand, bins, qrec, res, qwin, groups, gcost, pcost, total, staged;
   int32_t wgs = 0;
   int64_t sum_na = 0, sum_nb = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
 };
@@ -90,6 +90,7 @@ Layout plan(const std::vector<PairDesc>& pd, int32_t device) {
   size_t o = 0;
   L.pairs = o; o = align_up(o + P * sizeof(PairDesc));
   L.F = o; o = align_up(o + P * 9 * sizeof(double));
+  L.order = o; o = align_up(o + P * sizeof(int32_t));
   L.staged = o;
   L.geom = o; o = align_up(o + P * sizeof(PairGeom));
   L.counters = o; o = align_up(o + P * sizeof(PairCounters));
@@ -264,6 +265,14 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   } else {
     memcpy(ctx->pinned + L.F, F, pd.size() * 9 * sizeof(double));
   }
+  // Binning takes the largest pairs first, so small ones fill the tail.
+  {
+    int32_t* ord = reinterpret_cast<int32_t*>(ctx->pinned + L.order);
+    for (int32_t k = 0; k < n_pairs; ++k) ord[k] = k;
+    std::stable_sort(ord, ord + n_pairs, [&](int32_t x, int32_t y) {
+      return std::max(pd[size_t(x)].na, pd[size_t(x)].nb) > std::max(pd[size_t(y)].na, pd[size_t(y)].nb);
+    });
+  }
   HIP_TRY(ctx, hipMemcpyAsync(ctx->ws, ctx->pinned, L.staged, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipEventRecord(ctx->staging_done, st));
 
@@ -299,7 +308,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
       HIP_TRY(ctx, prof_mark(ctx, st));
       const int32_t g0 = int32_t(pd[size_t(p)].grp_off), gn = pd[size_t(p)].ngroups;
       const int32_t wgs = match_workgroups(ctx->device, gn);
-      HIP_TRY(ctx, launch_prepare(v, p, 1, g0, gn, wgs, st));
+      HIP_TRY(ctx, launch_prepare(v, p, 1, g0, gn, wgs, nullptr, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
       HIP_TRY(ctx, launch_match(v, gn > 0 ? wgs : 0, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
@@ -309,7 +318,8 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
     }
   } else {
     HIP_TRY(ctx, prof_mark(ctx, st));
-    HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, 0, int32_t(L.sum_groups), L.wgs, st));
+    HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, 0, int32_t(L.sum_groups), L.wgs,
+                                reinterpret_cast<const int32_t*>(ctx->ws + L.order), st));
     HIP_TRY(ctx, prof_mark(ctx, st));
     HIP_TRY(ctx, launch_match(v, L.sum_groups > 0 ? L.wgs : 0, st));
     HIP_TRY(ctx, prof_mark(ctx, st));

@@ -187,7 +187,6 @@ __device__ inline int32_t key_bin(const PairGeom& g, double key) {
 // Query line on centred coordinates, its sort bin and its window of bins.
 struct QueryLine {
   float a, b, c;
-  int32_t sort_bin;
   int32_t wlo, whi;     // wlo > whi: no feature of b can be in the band
 };
 
@@ -201,15 +200,15 @@ __device__ QueryLine query_line(const PairGeom& g, float xq, float yq) {
   const double s = sqrt(a * a + b * b);
   if (!(s > 0.0) || !isfinite(s) || !isfinite(c)) {
     q.a = q.b = q.c = NAN;   // the FP32 band test is false for every target
-    q.sort_bin = g.nbins;
     q.wlo = 1; q.whi = 0;
     return q;
   }
-  a /= s; b /= s; c /= s;
+  const double inv_s = 1.0 / s;
+  a *= inv_s; b *= inv_s; c *= inv_s;
   const double cc = c + a * g.ox + b * g.oy;   // offset on centred coordinates
   q.a = float(a); q.b = float(b); q.c = float(cc);
   if (g.mode == kModeFullScan) {
-    q.sort_bin = 0; q.wlo = 0; q.whi = 0;
+    q.wlo = 0; q.whi = 0;
     return q;
   }
   double lam, h;
@@ -220,12 +219,12 @@ __device__ QueryLine query_line(const PairGeom& g, float xq, float yq) {
     const double wper = -b * nx + a * ny;
     const double eps = fabs(a * g.ex + b * g.ey + c);  // distance of e from the line
     if (!(eps < 0.5 * g.S)) {                            // inconsistent F: scan everything
-      q.sort_bin = 0; q.wlo = 0; q.whi = g.nbins - 1;
+      q.wlo = 0; q.whi = g.nbins - 1;
       return q;
     }
-    if (fabs(wpar) < 1e-300) { q.sort_bin = g.nbins; q.wlo = 1; q.whi = 0; return q; }
-    lam = g.S * wper / wpar;
-    const double r = lam / g.S;
+    if (fabs(wpar) < 1e-300) { q.wlo = 1; q.whi = 0; return q; }
+    const double r = wper / wpar;
+    lam = g.S * r;
     h = (g.half_width + eps) * sqrt(1.0 + r * r);
   } else {
     const double dot = a * nx + b * ny;
@@ -235,13 +234,40 @@ __device__ QueryLine query_line(const PairGeom& g, float xq, float yq) {
     h = g.half_width + sqrt(dx * dx + dy * dy) * g.rbox;
   }
   if (!(lam + h >= g.kmin) || !(lam - h <= g.kmax)) {
-    q.sort_bin = g.nbins; q.wlo = 1; q.whi = 0;
+    q.wlo = 1; q.whi = 0;
     return q;
   }
-  q.sort_bin = key_bin(g, lam);
   q.wlo = key_bin(g, lam - h);
   q.whi = key_bin(g, lam + h);
   return q;
+}
+
+// The bin a query is sorted by: the pencil key of its line (S * tan of the
+// line's angle to u about the epipole, or the offset across parallel lines),
+// clamped to b's bins; degenerate lines go to the extra bin nbins.  Only the
+// order of queries depends on it (windows come from query_line), so it skips
+// the normalisation and window arithmetic; both passes of the counting sort
+// call this same function, so they agree on every bin.
+__device__ inline int32_t query_sort_bin(const PairGeom& g, float xq, float yq) {
+  const double* F = g.F;
+  const double x = xq, y = yq;
+  const double a = F[0] * x + F[1] * y + F[2];
+  const double b = F[3] * x + F[4] * y + F[5];
+  const double s2 = a * a + b * b;
+  if (!(s2 > 0.0) || !isfinite(s2)) return g.nbins;
+  if (g.mode == kModeFullScan) return 0;
+  double lam;
+  if (g.mode == kModePencil) {
+    const double wpar = -b * g.ux + a * g.uy;
+    const double wper = b * g.uy + a * g.ux;
+    lam = g.S * wper / wpar;
+  } else {
+    const double c = F[6] * x + F[7] * y + F[8];
+    const double dot = -a * g.uy + b * g.ux;
+    lam = (dot >= 0.0 ? -1.0 : 1.0) * (c + a * g.ox + b * g.oy) / sqrt(s2);
+  }
+  if (!isfinite(lam)) return g.nbins;
+  return key_bin(g, lam);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,31 +311,119 @@ __device__ void block_exclusive_scan(int32_t* cnt, int32_t n, int32_t* wsum) {
 
 // ---------------------------------------------------------------------------
 // a2 + a3: one workgroup per (pair, image).  blockIdx.y = 0 bins the targets
-// of b, blockIdx.y = 1 lines up and tiles the queries of a.
+// of b, blockIdx.y = 1 lines up and tiles the queries of a.  Counting sort:
+// pass 1 counts bins in LDS, a scan gives bin starts, pass 2 scatters.  The
+// bins of the first kCacheRounds rounds of items stay in registers between
+// the passes, so their FP64 keys are computed once.  `order` (may be NULL)
+// maps blockIdx.x to the pair, largest pairs first.
 // ---------------------------------------------------------------------------
 constexpr int kBinThreads = 1024;
 constexpr int kBatch = 8;   // items per thread per round; their loads are issued together
+constexpr int kCacheRounds = 2;
 
-__global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t pb) {
+// Counting sort of one side of a pair: the targets of b into CandRec order
+// (and the bin starts), or the queries of a into tile order.
+template <bool kTargets>
+__device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
+                                          const PairGeom& g, const ImageDev& I, int32_t* hist,
+                                          int32_t* wsum, int32_t nh) {
+  constexpr int32_t kStride = kBatch * kBinThreads;
+  const int32_t n = kTargets ? P.nb : P.na;
+  // The bin of one item (FP64 key of a target, sort key of a query).
+  auto item_bin = [&](float x, float y) -> int32_t {
+    return kTargets ? key_bin(g, point_key(g, x, y)) : query_sort_bin(g, x, y);
+  };
+  // Pass 1 over round r: count bins; keep them in `keep` when given.
+  auto count_round = [&](int32_t r, int32_t* keep) {
+    const int32_t base = r * kStride + threadIdx.x;
+    float px[kBatch], py[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t j = base + k * kBinThreads;
+      if (j < n) { px[k] = I.xy[2 * j]; py[k] = I.xy[2 * j + 1]; }
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      if (base + k * kBinThreads < n) {
+        const int32_t bin = item_bin(px[k], py[k]);
+        atomicAdd(&hist[bin], 1);
+        if (keep) keep[k] = bin;
+      }
+    }
+  };
+  // Pass 2 over round r: place every item of the round at its sorted position.
+  auto place_round = [&](int32_t r, const int32_t* keep) {
+    const int32_t base = r * kStride + threadIdx.x;
+    float px[kBatch], py[kBatch];
+    int32_t nrm[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t j = base + k * kBinThreads;
+      if (j < n) {
+        px[k] = I.xy[2 * j]; py[k] = I.xy[2 * j + 1];
+        if (kTargets) nrm[k] = I.norm2[j];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t j = base + k * kBinThreads;
+      if (j >= n) continue;
+      const int32_t bin = keep ? keep[k] : item_bin(px[k], py[k]);
+      const int32_t pos = atomicAdd(&hist[bin], 1);
+      if (kTargets) {
+        CandRec c;
+        c.x = float(double(px[k]) - g.ox);
+        c.y = float(double(py[k]) - g.oy);
+        c.ncpos = ((uint32_t(nrm[k]) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
+        c.j = j;
+        v.cand[P.c_off + pos] = c;
+      } else {
+        const QueryLine q = query_line(g, px[k], py[k]);
+        QueryRec rq;
+        rq.a = q.a; rq.b = q.b; rq.c = q.c; rq.i = j;
+        v.qrec[P.q_off + pos] = rq;
+        v.qwin[P.q_off + pos] = make_int2(q.wlo, q.whi);
+      }
+    }
+  };
+
+  const int32_t rounds = (n + kStride - 1) / kStride;
+  int32_t keep[kCacheRounds][kBatch];
+#pragma unroll
+  for (int32_t r = 0; r < kCacheRounds; ++r)
+    if (r < rounds) count_round(r, keep[r]);
+  for (int32_t r = kCacheRounds; r < rounds; ++r) count_round(r, nullptr);
+  __syncthreads();
+  block_exclusive_scan<kBinThreads>(hist, nh, wsum);
+  if (kTargets) {
+    for (int k = threadIdx.x; k < nh; k += blockDim.x) v.bin_start[P.bin_off + k] = hist[k];
+    if (threadIdx.x == 0) v.bin_start[P.bin_off + nh] = P.nb;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int32_t r = 0; r < kCacheRounds; ++r)
+    if (r < rounds) place_round(r, keep[r]);
+  for (int32_t r = kCacheRounds; r < rounds; ++r) place_round(r, nullptr);
+}
+
+__global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t pb,
+                                                          const int32_t* order) {
   __shared__ int32_t hist[kMaxBins + 2];
   __shared__ int32_t wsum[kBinThreads / 64];
-  const int32_t p = pb + blockIdx.x;
+  const int32_t p = order ? order[pb + blockIdx.x] : pb + blockIdx.x;
   const PairDesc P = v.pairs[p];
   const PairGeom g = v.geom[p];
   const bool targets = blockIdx.y == 0;
   const int32_t nh = targets ? g.nbins : g.nbins + 1;
-  for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0;
-  __syncthreads();
-  constexpr int32_t kStride = kBatch * kBinThreads;
+  const ImageDev I = v.images[targets ? P.b : P.a];
 
-  if (targets) {
-    const ImageDev B = v.images[P.b];
-    if (P.ignore_band) {
-      // Exhaustive matching keeps b in its own order: one bin, position = index.
+  if (P.ignore_band) {
+    // Exhaustive matching keeps b in its own order: one bin, position = index.
+    if (targets) {
       for (int32_t j = threadIdx.x; j < P.nb; j += blockDim.x) {
         CandRec r;
         r.x = 0.0f; r.y = 0.0f;
-        r.ncpos = ((uint32_t(B.norm2[j]) + kDistBias) << kPosBits) | uint32_t(j & (kChunk - 1));
+        r.ncpos = ((uint32_t(I.norm2[j]) + kDistBias) << kPosBits) | uint32_t(j & (kChunk - 1));
         r.j = j;
         v.cand[P.c_off + j] = r;
       }
@@ -317,95 +431,23 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
         v.bin_start[P.bin_off] = 0;
         for (int k = 1; k <= g.nbins; ++k) v.bin_start[P.bin_off + k] = P.nb;
       }
-      return;
-    }
-    for (int32_t base = threadIdx.x; base < P.nb; base += kStride) {
-      float px[kBatch], py[kBatch];
-#pragma unroll
-      for (int k = 0; k < kBatch; ++k) {
-        const int32_t j = base + k * kBinThreads;
-        if (j < P.nb) { px[k] = B.xy[2 * j]; py[k] = B.xy[2 * j + 1]; }
-      }
-#pragma unroll
-      for (int k = 0; k < kBatch; ++k) {
-        if (base + k * kBinThreads < P.nb) atomicAdd(&hist[key_bin(g, point_key(g, px[k], py[k]))], 1);
-      }
-    }
-    __syncthreads();
-    block_exclusive_scan<kBinThreads>(hist, nh, wsum);
-    for (int k = threadIdx.x; k < nh; k += blockDim.x) v.bin_start[P.bin_off + k] = hist[k];
-    if (threadIdx.x == 0) v.bin_start[P.bin_off + nh] = P.nb;
-    __syncthreads();
-    for (int32_t base = threadIdx.x; base < P.nb; base += kStride) {
-      float px[kBatch], py[kBatch];
-      int32_t nrm[kBatch];
-#pragma unroll
-      for (int k = 0; k < kBatch; ++k) {
-        const int32_t j = base + k * kBinThreads;
-        if (j < P.nb) { px[k] = B.xy[2 * j]; py[k] = B.xy[2 * j + 1]; nrm[k] = B.norm2[j]; }
-      }
-#pragma unroll
-      for (int k = 0; k < kBatch; ++k) {
-        const int32_t j = base + k * kBinThreads;
-        if (j >= P.nb) continue;
-        const double x = px[k], y = py[k];
-        const int32_t pos = atomicAdd(&hist[key_bin(g, point_key(g, x, y))], 1);
-        CandRec r;
-        r.x = float(x - g.ox);
-        r.y = float(y - g.oy);
-        r.ncpos = ((uint32_t(nrm[k]) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
-        r.j = j;
-        v.cand[P.c_off + pos] = r;
+    } else {
+      for (int32_t i = threadIdx.x; i < P.na; i += blockDim.x) {
+        QueryRec r;
+        r.a = 0.0f; r.b = 0.0f; r.c = 0.0f; r.i = i;
+        v.qrec[P.q_off + i] = r;
+        v.qwin[P.q_off + i] = make_int2(0, 0);
       }
     }
     return;
   }
 
-  // Queries of a.
-  const ImageDev A = v.images[P.a];
-  int2* win = v.qwin + P.q_off;
-  if (P.ignore_band) {
-    for (int32_t i = threadIdx.x; i < P.na; i += blockDim.x) {
-      QueryRec r;
-      r.a = 0.0f; r.b = 0.0f; r.c = 0.0f; r.i = i;
-      v.qrec[P.q_off + i] = r;
-      win[i] = make_int2(0, 0);
-    }
-    return;
-  }
-  for (int32_t base = threadIdx.x; base < P.na; base += kStride) {
-    float px[kBatch], py[kBatch];
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-      const int32_t i = base + k * kBinThreads;
-      if (i < P.na) { px[k] = A.xy[2 * i]; py[k] = A.xy[2 * i + 1]; }
-    }
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-      if (base + k * kBinThreads < P.na) atomicAdd(&hist[query_line(g, px[k], py[k]).sort_bin], 1);
-    }
-  }
+  for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0;
   __syncthreads();
-  block_exclusive_scan<kBinThreads>(hist, nh, wsum);
-  for (int32_t base = threadIdx.x; base < P.na; base += kStride) {
-    float px[kBatch], py[kBatch];
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-      const int32_t i = base + k * kBinThreads;
-      if (i < P.na) { px[k] = A.xy[2 * i]; py[k] = A.xy[2 * i + 1]; }
-    }
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-      const int32_t i = base + k * kBinThreads;
-      if (i >= P.na) continue;
-      const QueryLine q = query_line(g, px[k], py[k]);
-      const int32_t pos = atomicAdd(&hist[q.sort_bin], 1);
-      QueryRec r;
-      r.a = q.a; r.b = q.b; r.c = q.c; r.i = i;
-      v.qrec[P.q_off + pos] = r;
-      win[pos] = make_int2(q.wlo, q.whi);
-    }
-  }
+  if (targets)
+    sort_side<true>(v, P, g, I, hist, wsum, nh);
+  else
+    sort_side<false>(v, P, g, I, hist, wsum, nh);
 }
 
 // Candidate range of every query tile (the union of its queries' bin windows
@@ -546,10 +588,10 @@ hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_
 }
 
 hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t grp_begin,
-                          int32_t grp_count, int32_t wgs, hipStream_t st) {
+                          int32_t grp_count, int32_t wgs, const int32_t* order, hipStream_t st) {
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
-  hipLaunchKernelGGL(bin_kernel, dim3(pc, 2), dim3(kBinThreads), 0, st, v, pb);
+  hipLaunchKernelGGL(bin_kernel, dim3(pc, 2), dim3(kBinThreads), 0, st, v, pb, order);
   hipLaunchKernelGGL(tile_ranges_kernel, dim3(pc), dim3(256), 0, st, v, pb);
   if (grp_count > 0)
     hipLaunchKernelGGL(schedule_kernel, dim3((pc + 3) / 4), dim3(256), 0, st, v, pb, pc,
