@@ -73,8 +73,11 @@ struct Layout {
   int64_t sum_na = 0, sum_nb = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
 };
 
+#ifndef SFM_BIN_DIV
+#define SFM_BIN_DIV 8
+#endif
 int32_t bins_for(int32_t nb) {
-  return std::max<int32_t>(1, std::min<int32_t>(kMaxBins, nb / 8));
+  return std::max<int32_t>(1, std::min<int32_t>(kMaxBins, nb / SFM_BIN_DIV));
 }
 
 Layout plan(const std::vector<PairDesc>& pd, int32_t device) {

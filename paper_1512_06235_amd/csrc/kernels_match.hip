@@ -419,30 +419,46 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
   }
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin; renumber them so each XCD
-// takes one contiguous run of groups (neighbouring groups of one pair share
-// candidate rows, and each XCD has its own L2).
+// One resident wave of workgroups.  Workgroups are dealt to the 8 XCDs
+// round-robin (workgroup k runs on XCD k mod 8), and each XCD has its own L2.
+// The preparation pass splits the groups into one contiguous share of about
+// equal estimated cost per XCD; the workgroups of an XCD sweep its share
+// together, workgroup i taking groups i, i + W, i + 2W, ... (W workgroups on
+// the XCD).  At any moment an XCD then works on about W consecutive groups,
+// one or two pairs, whose candidate and query rows stay in its L2; giving
+// each workgroup a contiguous run instead spreads an XCD over dozens of
+// pairs at once and its rows over HBM.
+#ifndef SFM_MATCH_WAVES_PER_EU
+#define SFM_MATCH_WAVES_PER_EU 3
+#endif
+#ifndef SFM_XCD_SWEEP
+#define SFM_XCD_SWEEP 0
+#endif
 __device__ __forceinline__ int32_t xcd_contiguous(int32_t g, int32_t G) {
   const int32_t x = g & 7, k = g >> 3, q = G >> 3, r = G & 7;
   return x * q + min(x, r) + k;
 }
-
-// One resident wave of workgroups; the preparation pass has split the groups
-// into one contiguous run of about equal estimated cost per workgroup.
-#ifndef SFM_MATCH_WAVES_PER_EU
-#define SFM_MATCH_WAVES_PER_EU 3
-#endif
 template <bool kKeepCounts>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
 void match_kernel(BatchView v) {
   __shared__ __attribute__((aligned(16))) GroupLds lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t run = xcd_contiguous(blockIdx.x, gridDim.x);
   typedef const __attribute__((address_space(4))) int32_t c_i32;
+#if SFM_XCD_SWEEP
+  const int32_t shares = min(8, int32_t(gridDim.x));
+  const int32_t x = blockIdx.x % shares;
+  const int32_t i = blockIdx.x / shares;
+  const int32_t w = (int32_t(gridDim.x) - x + shares - 1) / shares;
+  const int32_t g_first = ((c_i32*)v.wg_start)[x] + i;
+  const int32_t g_end = ((c_i32*)v.wg_start)[x + 1];
+#else
+  const int32_t run = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int32_t w = 1;
   const int32_t g_first = ((c_i32*)v.wg_start)[run];
   const int32_t g_end = ((c_i32*)v.wg_start)[run + 1];
+#endif
   WaveStats ws = {-1, 0, 0, 0, 0};
-  for (int32_t g = g_first; g < g_end; ++g) {
+  for (int32_t g = g_first; g < g_end; g += w) {
     const TileGroup G = load_group(v.groups, g);
     match_group<kKeepCounts>(v, G, lds, wave, lane, ws);
   }

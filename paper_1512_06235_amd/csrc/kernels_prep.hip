@@ -10,6 +10,7 @@
 // four overlapping 2d x 2d grids and centre-most cells (eqs. 6-9), the range
 // is a provable superset of every member of the band; the exact test happens
 // in the match kernel.
+#include <algorithm>
 #include <cmath>
 
 #include "sfm_internal.h"
@@ -587,6 +588,9 @@ hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_
   return hipGetLastError();
 }
 
+#ifndef SFM_XCD_SWEEP
+#define SFM_XCD_SWEEP 0
+#endif
 hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t grp_begin,
                           int32_t grp_count, int32_t wgs, const int32_t* order, hipStream_t st) {
   if (pc <= 0) return hipSuccess;
@@ -595,7 +599,7 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t gr
   hipLaunchKernelGGL(tile_ranges_kernel, dim3(pc), dim3(256), 0, st, v, pb);
   if (grp_count > 0)
     hipLaunchKernelGGL(schedule_kernel, dim3((pc + 3) / 4), dim3(256), 0, st, v, pb, pc,
-                       grp_begin, grp_count, wgs);
+                       grp_begin, grp_count, SFM_XCD_SWEEP ? std::min(8, wgs) : wgs);
   return hipGetLastError();
 }
 
