@@ -40,53 +40,84 @@ __global__ __launch_bounds__(1024) void scan_pairs_kernel(BatchView v, int32_t p
   }
 }
 
+// One workgroup per pair; a round covers kEmitPer slices of kEmitThreads
+// consecutive queries, whose results are read together with coalesced loads
+// (thread t reads query t of every slice).  Ranks come from a ballot + mbcnt
+// inside each wave and one scan over the (slice, wave) counts of the round,
+// so even the largest pair needs only a few rounds.
+constexpr int kEmitPer = 8;
+constexpr int kEmitWaves = kEmitThreads / 64;
+
 __global__ __launch_bounds__(kEmitThreads) void emit_kernel(BatchView v, int32_t pb,
                                                             const int64_t* offset, int32_t* oq,
                                                             int32_t* om, int32_t* od1,
                                                             int32_t* od2, int32_t* am,
                                                             int32_t* ad1, int32_t* ad2,
                                                             int32_t* ac) {
-  __shared__ int32_t wtot[kEmitThreads / 64];
+  __shared__ int32_t cnt[kEmitPer * kEmitWaves];   // accepted per (slice, wave), then prefix
   __shared__ int32_t run;
   const int32_t p = pb + blockIdx.x;
   const PairDesc P = v.pairs[p];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t out0 = offset[p];
+  const QueryResult* res = v.res + P.q_off;
   if (t == 0) run = 0;
   __syncthreads();
-  for (int32_t base = 0; base < P.na; base += kEmitThreads) {
-    const int32_t i = base + t;
-    QueryResult r;
-    r.match = -1; r.d1 = r.d2 = kDistInf; r.flags = 0;
-    if (i < P.na) r = v.res[P.q_off + i];
-    const bool acc = (r.flags & 1) != 0;
-    if (am && i < P.na) {
-      am[P.q_off + i] = r.match;
-      ad1[P.q_off + i] = r.d1;
-      ad2[P.q_off + i] = r.d2;
-      ac[P.q_off + i] = r.flags >> 1;
+  for (int32_t base = 0; base < P.na; base += kEmitThreads * kEmitPer) {
+    const int32_t rbase = run;   // rows before this round (read before its first barrier)
+    QueryResult r[kEmitPer];
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k) {
+      const int32_t i = base + k * kEmitThreads + t;
+      if (i < P.na) {
+        r[k] = res[i];
+      } else {
+        r[k].match = -1; r[k].d1 = r[k].d2 = kDistInf; r[k].flags = 0;
+      }
     }
-    const unsigned long long m = __ballot(acc);
-    const int32_t pre = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0));
-    if (lane == 0) wtot[wv] = __builtin_popcountll(m);
-    __syncthreads();
-    int32_t before = run;
-    for (int w = 0; w < wv; ++w) before += wtot[w];
-    if (acc) {
-      const int64_t row = out0 + before + pre;
-      oq[row] = i;
-      om[row] = r.match;
-      od1[row] = r.d1;
-      od2[row] = r.d2;
-    }
-    __syncthreads();
-    if (t == 0) {
-      int32_t s = 0;
-      for (int w = 0; w < kEmitThreads / 64; ++w) s += wtot[w];
-      run += s;
+    int32_t pre[kEmitPer];
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k) {
+      const int32_t i = base + k * kEmitThreads + t;
+      if (am && i < P.na) {
+        am[P.q_off + i] = r[k].match;
+        ad1[P.q_off + i] = r[k].d1;
+        ad2[P.q_off + i] = r[k].d2;
+        ac[P.q_off + i] = r[k].flags >> 1;
+      }
+      const unsigned long long m = __ballot((r[k].flags & 1) != 0);
+      pre[k] = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0));
+      if (lane == 0) cnt[k * kEmitWaves + wv] = __builtin_popcountll(m);
     }
     __syncthreads();
+    // Exclusive scan of the kEmitPer * kEmitWaves counts in (slice, wave)
+    // order by the first wave, two entries per lane.
+    if (wv == 0) {
+      static_assert(kEmitPer * kEmitWaves == 128, "two counts per lane");
+      const int32_t c0 = cnt[2 * lane], c1 = cnt[2 * lane + 1];
+      int32_t x = c0 + c1;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      const int32_t ex = x - c0 - c1;
+      cnt[2 * lane] = ex;
+      cnt[2 * lane + 1] = ex + c0;
+      if (lane == 63) run = rbase + x;   // every thread has read rbase already
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k) {
+      if (r[k].flags & 1) {
+        const int64_t row = out0 + rbase + cnt[k * kEmitWaves + wv] + pre[k];
+        const int32_t i = base + k * kEmitThreads + t;
+        oq[row] = i;
+        om[row] = r[k].match;
+        od1[row] = r[k].d1;
+        od2[row] = r[k].d2;
+      }
+    }
+    __syncthreads();   // the next round rewrites cnt
   }
 }
 

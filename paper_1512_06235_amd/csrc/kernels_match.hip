@@ -355,9 +355,13 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
       for (int k = 0; k < kRowLoads; ++k) w[k] = load_row_share(r, b_desc, lane, k);
       r = load_rec(cand, t0 + 4 * kCandTile + own, S1);
       if (t0 < my_e && t0 + kCandTile > my_b) {
+        // Waves in their compute phase issue first (1-2% faster than equal
+        // priority; raising the load phase instead gains nothing).
+        __builtin_amdgcn_s_setprio(2);
         v4i a[4];
         read_a(L, rs, lane, a);
         tile_compute(a, bq, qr, band, L, ms, half, k1, k2, cnt);
+        __builtin_amdgcn_s_setprio(0);
       }
       // Keys hold positions mod 1024: close a chunk every 1024 positions.
       const int32_t t1 = t0 + kCandTile;
