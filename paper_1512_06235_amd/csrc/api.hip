@@ -311,7 +311,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
       HIP_TRY(ctx, prof_mark(ctx, st));
       const int32_t g0 = int32_t(pd[size_t(p)].grp_off), gn = pd[size_t(p)].ngroups;
       const int32_t wgs = match_workgroups(ctx->device, gn);
-      HIP_TRY(ctx, launch_prepare(v, p, 1, g0, gn, wgs, nullptr, st));
+      HIP_TRY(ctx, launch_prepare(v, p, 1, g0, gn, wgs, nullptr, pd[size_t(p)].na, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
       HIP_TRY(ctx, launch_match(v, gn > 0 ? wgs : 0, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
@@ -321,8 +321,10 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
     }
   } else {
     HIP_TRY(ctx, prof_mark(ctx, st));
+    int32_t max_na = 0;
+    for (const PairDesc& pp : pd) max_na = std::max(max_na, pp.na);
     HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, 0, int32_t(L.sum_groups), L.wgs,
-                                reinterpret_cast<const int32_t*>(ctx->ws + L.order), st));
+                                reinterpret_cast<const int32_t*>(ctx->ws + L.order), max_na, st));
     HIP_TRY(ctx, prof_mark(ctx, st));
     HIP_TRY(ctx, launch_match(v, L.sum_groups > 0 ? L.wgs : 0, st));
     HIP_TRY(ctx, prof_mark(ctx, st));

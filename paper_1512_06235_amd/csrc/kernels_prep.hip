@@ -165,6 +165,7 @@ __global__ void geometry_kernel(BatchView v, int32_t pb, int32_t pc) {
   z.accepted = 0;
   z.ties = 0;
   v.counters[p] = z;
+  v.pcost[p] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -453,37 +454,56 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
 
 // Candidate range of every query tile (the union of its queries' bin windows
 // mapped through b's bin starts) and of every group of kGroupTiles
-// consecutive tiles.  One workgroup per pair, one thread per group.
-__global__ __launch_bounds__(256) void tile_ranges_kernel(BatchView v, int32_t pb) {
+// consecutive tiles, with the group record and its schedule cost.  Block
+// (p, c) takes queries [256c, 256c + 256) of pair p: one thread per query,
+// half-wave min/max reductions per tile, one thread per group.
+constexpr int kRangeThreads = 256;
+constexpr int kRangeTiles = kRangeThreads / kQueryTile;
+static_assert(kRangeTiles % kGroupTiles == 0, "a block holds whole groups");
+
+__global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v, int32_t pb) {
+  __shared__ int2 trange[kRangeTiles];
   const int32_t p = pb + blockIdx.x;
   const PairDesc P = v.pairs[p];
-  const ImageDev A = v.images[P.a];
-  const ImageDev B = v.images[P.b];
-  const float band = v.geom[p].band32;
-  long long my_cost = 0;
-  for (int32_t g = threadIdx.x; g < P.ngroups; g += blockDim.x) {
-    TileGroup tg;
+  const int32_t q0 = int32_t(blockIdx.y) * kRangeThreads;
+  if (q0 >= P.na) return;
+  const int t = threadIdx.x, lane = t & 63;
+  const int32_t s = q0 + t;
+  const int2 w = s < P.na ? v.qwin[P.q_off + s] : make_int2(1, 0);
+  int32_t lo = w.x <= w.y ? w.x : 0x7FFFFFFF;
+  int32_t hi = w.x <= w.y ? w.y : -1;
+  for (int o = kQueryTile / 2; o > 0; o >>= 1) {   // stays within the tile's 32 lanes
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
+  if ((t & (kQueryTile - 1)) == 0) {
+    int32_t sb = 0, se = 0;
+    if (lo <= hi) {
+      sb = v.bin_start[P.bin_off + lo];
+      se = v.bin_start[P.bin_off + hi + 1];
+    }
+    trange[t / kQueryTile] = make_int2(sb, se);
+  }
+  __syncthreads();
+  const int32_t tiles_here = min(kRangeTiles, (P.na - q0 + kQueryTile - 1) / kQueryTile);
+  const int32_t groups_here = (tiles_here + kGroupTiles - 1) / kGroupTiles;
+  long long cost = 0;
+  if (t < groups_here) {
+    const int32_t g = int32_t(blockIdx.y) * (kRangeTiles / kGroupTiles) + t;
     const int32_t k0 = g * kGroupTiles;
     const int32_t nt = min(kGroupTiles, P.nblocks - k0);
+    const ImageDev A = v.images[P.a];
+    const ImageDev B = v.images[P.b];
+    TileGroup tg;
+    memset(&tg, 0, sizeof tg);
     int32_t gb = 0x7FFFFFFF, ge = 0;
 #pragma unroll
-    for (int32_t t = 0; t < kGroupTiles; ++t) {
-      int32_t sb = 0, se = 0;
-      if (t < nt) {
-        const int32_t s0 = (k0 + t) * kQueryTile;
-        int32_t lo = 0x7FFFFFFF, hi = -1;
-        for (int s = 0; s < kQueryTile; ++s) {
-          const int2 w = s0 + s < P.na ? v.qwin[P.q_off + s0 + s] : make_int2(1, 0);
-          if (w.x <= w.y) { lo = min(lo, w.x); hi = max(hi, w.y); }
-        }
-        if (lo <= hi) {
-          sb = v.bin_start[P.bin_off + lo];
-          se = v.bin_start[P.bin_off + hi + 1];
-        }
-        if (se > sb) { gb = min(gb, sb); ge = max(ge, se); }
-      }
-      tg.t_begin[t] = sb;
-      tg.t_end[t] = se;
+    for (int32_t k = 0; k < kGroupTiles; ++k) {
+      int2 r = make_int2(0, 0);
+      if (k < nt) r = trange[t * kGroupTiles + k];
+      if (r.y > r.x) { gb = min(gb, r.x); ge = max(ge, r.y); }
+      tg.t_begin[k] = r.x;
+      tg.t_end[k] = r.y;
     }
     tg.pair = p;
     tg.tile0 = k0;
@@ -491,33 +511,26 @@ __global__ __launch_bounds__(256) void tile_ranges_kernel(BatchView v, int32_t p
     tg.na = P.na;
     tg.s_begin = gb <= ge ? gb : 0;
     tg.s_end = gb <= ge ? ge : 0;
-    tg.band = band;
-    tg.pad0 = 0;
+    tg.band = v.geom[p].band32;
     tg.q_off = P.q_off;
     tg.c_off = P.c_off;
     tg.a_desc = A.desc;
     tg.a_norm = A.norm2;
     tg.b_desc = B.desc;
-    tg.pad1 = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) tg.pad2[k] = 0;
     v.groups[P.grp_off + g] = tg;
     // A group costs a fixed start-up plus one pipeline step per 32 positions
     // of its union range (every step of the union has a computing wave).
     const int32_t steps = (tg.s_end - tg.s_begin + kCandTile - 1) / kCandTile;
     const int32_t c = kGroupStartCost + kStepCost * steps;
     v.gcost[P.grp_off + g] = c;
-    my_cost += c;
+    cost = c;
   }
-  // The pair's total cost.
-  __shared__ long long red[256];
-  red[threadIdx.x] = my_cost;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  // The block's groups all sit in the first wave: add their costs to the pair's.
+  if (t < 64) {
+    for (int o = 32; o > 0; o >>= 1) cost += __shfl_xor(cost, o, 64);
+    if (lane == 0 && cost) atomicAdd(reinterpret_cast<unsigned long long*>(&v.pcost[p]),
+                                     (unsigned long long)cost);
   }
-  if (threadIdx.x == 0) v.pcost[p] = red[0];
 }
 
 // Splits the tile groups of pairs [pb, pb + pc) into `wgs` contiguous runs of
@@ -592,11 +605,14 @@ hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_
 #define SFM_XCD_SWEEP 0
 #endif
 hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t grp_begin,
-                          int32_t grp_count, int32_t wgs, const int32_t* order, hipStream_t st) {
+                          int32_t grp_count, int32_t wgs, const int32_t* order,
+                          int32_t max_queries, hipStream_t st) {
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
   hipLaunchKernelGGL(bin_kernel, dim3(pc, 2), dim3(kBinThreads), 0, st, v, pb, order);
-  hipLaunchKernelGGL(tile_ranges_kernel, dim3(pc), dim3(256), 0, st, v, pb);
+  const int32_t qblocks = (max_queries + kRangeThreads - 1) / kRangeThreads;
+  if (qblocks > 0)
+    hipLaunchKernelGGL(tile_ranges_kernel, dim3(pc, qblocks), dim3(kRangeThreads), 0, st, v, pb);
   if (grp_count > 0)
     hipLaunchKernelGGL(schedule_kernel, dim3((pc + 3) / 4), dim3(256), 0, st, v, pb, pc,
                        grp_begin, grp_count, SFM_XCD_SWEEP ? std::min(8, wgs) : wgs);

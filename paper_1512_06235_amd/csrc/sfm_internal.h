@@ -163,10 +163,11 @@ hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_
                            int32_t* bad_flag, hipStream_t st);
 // Preparation of pairs [pair_begin, pair_begin + pair_count), whose tile groups
 // are [grp_begin, grp_begin + grp_count), split over `wgs` match workgroups.
-// `order` (device, may be NULL) lists the pairs in the order binning takes them.
+// `order` (device, may be NULL) lists the pairs in the order binning takes
+// them; `max_queries` is the largest n_a among the pairs.
 hipError_t launch_prepare(const BatchView& v, int32_t pair_begin, int32_t pair_count,
                           int32_t grp_begin, int32_t grp_count, int32_t wgs,
-                          const int32_t* order, hipStream_t st);
+                          const int32_t* order, int32_t max_queries, hipStream_t st);
 // Workgroups the match kernel uses for `groups` tile groups (one resident wave
 // of workgroups at most).
 int32_t match_workgroups(int32_t device, int64_t groups);
