@@ -325,10 +325,35 @@ constexpr int kCacheRounds = 2;
 
 // Counting sort of one side of a pair: the targets of b into CandRec order
 // (and the bin starts), or the queries of a into tile order.
+// Writes one item at its sorted position.
+template <bool kTargets>
+__device__ __forceinline__ void write_sorted(const BatchView& v, const PairDesc& P,
+                                             const PairGeom& g, int32_t pos, int32_t j, float x,
+                                             float y, int32_t nrm) {
+  if (kTargets) {
+    CandRec c;
+    c.x = float(double(x) - g.ox);
+    c.y = float(double(y) - g.oy);
+    c.ncpos = ((uint32_t(nrm) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
+    c.j = j;
+    v.cand[P.c_off + pos] = c;
+  } else {
+    const QueryLine q = query_line(g, x, y);
+    QueryRec rq;
+    rq.a = q.a; rq.b = q.b; rq.c = q.c; rq.i = j;
+    v.qrec[P.q_off + pos] = rq;
+    v.qwin[P.q_off + pos] = make_int2(q.wlo, q.whi);
+  }
+}
+
+// When `perm` is given (the side fits in LDS), pass 2 only records which
+// item lands at each position; a gather pass then writes the outputs in
+// position order, so the stores are coalesced instead of scattered 8- and
+// 16-byte writes that the L2 cannot merge once a batch outgrows it.
 template <bool kTargets>
 __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
                                           const PairGeom& g, const ImageDev& I, int32_t* hist,
-                                          int32_t* wsum, int32_t nh) {
+                                          int32_t* wsum, int32_t nh, uint16_t* perm) {
   constexpr int32_t kStride = kBatch * kBinThreads;
   const int32_t n = kTargets ? P.nb : P.na;
   // The bin of one item (FP64 key of a target, sort key of a query).
@@ -361,9 +386,9 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
       const int32_t j = base + k * kBinThreads;
-      if (j < n) {
+      if (j < n && (!perm || !keep)) {
         px[k] = I.xy[2 * j]; py[k] = I.xy[2 * j + 1];
-        if (kTargets) nrm[k] = I.norm2[j];
+        if (kTargets && !perm) nrm[k] = I.norm2[j];
       }
     }
 #pragma unroll
@@ -372,20 +397,10 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
       if (j >= n) continue;
       const int32_t bin = keep ? keep[k] : item_bin(px[k], py[k]);
       const int32_t pos = atomicAdd(&hist[bin], 1);
-      if (kTargets) {
-        CandRec c;
-        c.x = float(double(px[k]) - g.ox);
-        c.y = float(double(py[k]) - g.oy);
-        c.ncpos = ((uint32_t(nrm[k]) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
-        c.j = j;
-        v.cand[P.c_off + pos] = c;
-      } else {
-        const QueryLine q = query_line(g, px[k], py[k]);
-        QueryRec rq;
-        rq.a = q.a; rq.b = q.b; rq.c = q.c; rq.i = j;
-        v.qrec[P.q_off + pos] = rq;
-        v.qwin[P.q_off + pos] = make_int2(q.wlo, q.whi);
-      }
+      if (perm)
+        perm[pos] = uint16_t(j);
+      else
+        write_sorted<kTargets>(v, P, g, pos, j, px[k], py[k], kTargets ? nrm[k] : 0);
     }
   };
 
@@ -406,12 +421,44 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
   for (int32_t r = 0; r < kCacheRounds; ++r)
     if (r < rounds) place_round(r, keep[r]);
   for (int32_t r = kCacheRounds; r < rounds; ++r) place_round(r, nullptr);
+  if (!perm) return;
+  __syncthreads();
+  // Gather pass: positions in order, kBatch per thread per round.
+  for (int32_t base = threadIdx.x; base < n; base += kStride) {
+    int32_t jj[kBatch], nrm[kBatch];
+    float px[kBatch], py[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t pos = base + k * kBinThreads;
+      if (pos < n) jj[k] = perm[pos];
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t pos = base + k * kBinThreads;
+      if (pos < n) {
+        px[k] = I.xy[2 * jj[k]]; py[k] = I.xy[2 * jj[k] + 1];
+        if (kTargets) nrm[k] = I.norm2[jj[k]];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t pos = base + k * kBinThreads;
+      if (pos < n) write_sorted<kTargets>(v, P, g, pos, jj[k], px[k], py[k], kTargets ? nrm[k] : 0);
+    }
+  }
 }
+
+// LDS of the binning workgroup: the histogram, the scan's wave sums and,
+// when the side fits, the 16-bit permutation of its items.
+constexpr int kBinLdsInts = 16384;
+constexpr int kBinWsum = kBinThreads / 64;
+static_assert(kMaxBins + 2 + kBinWsum <= kBinLdsInts, "histogram fits");
 
 __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t pb,
                                                           const int32_t* order) {
-  __shared__ int32_t hist[kMaxBins + 2];
-  __shared__ int32_t wsum[kBinThreads / 64];
+  __shared__ int32_t lds[kBinLdsInts];
+  int32_t* const wsum = lds + kBinLdsInts - kBinWsum;
+  int32_t* const hist = lds;
   const int32_t p = order ? order[pb + blockIdx.x] : pb + blockIdx.x;
   const PairDesc P = v.pairs[p];
   const PairGeom g = v.geom[p];
@@ -446,10 +493,15 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
 
   for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0;
   __syncthreads();
+  const int32_t n = targets ? P.nb : P.na;
+  const int32_t hist_ints = (nh + 2) & ~1;
+  uint16_t* perm = nullptr;
+  if (hist_ints + (n + 1) / 2 <= kBinLdsInts - kBinWsum)
+    perm = reinterpret_cast<uint16_t*>(lds + hist_ints);
   if (targets)
-    sort_side<true>(v, P, g, I, hist, wsum, nh);
+    sort_side<true>(v, P, g, I, hist, wsum, nh, perm);
   else
-    sort_side<false>(v, P, g, I, hist, wsum, nh);
+    sort_side<false>(v, P, g, I, hist, wsum, nh, perm);
 }
 
 // Candidate range of every query tile (the union of its queries' bin windows
