@@ -230,6 +230,27 @@ int sfm_server_stats(sfm_ctx* ctx, int64_t out[3]);
  * free the slots.  Uncollected results are dropped. */
 int sfm_server_stop(sfm_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Tuning.  Two parameters of the batched form trade evaluated slots against
+ * scheduling and preparation costs (Appendix A steps 1-2 leave them open):
+ *   group_tiles       query tiles of 32 queries (in pencil order) that one
+ *                     match workgroup streams one candidate range for:
+ *                     1, 2 or 4 (default 2);
+ *   features_per_bin  average target features per bin of b's pencil
+ *                     binning, 1..1024 (default 8).
+ * Results do not depend on them.  They apply to later calls on the context. */
+int sfm_set_tuning(sfm_ctx* ctx, int32_t group_tiles, int32_t features_per_bin);
+int sfm_get_tuning(sfm_ctx* ctx, int32_t* group_tiles, int32_t* features_per_bin);
+
+/* Time the batched form on the given batch for every group_tiles in
+ * {1, 2, 4} and features_per_bin in {4, 8, 16} (one warm-up and `repeats`
+ * timed calls each, HIP events on `stream`), keep the fastest setting on the
+ * context, and write the mean milliseconds per call to ms_out[3 * i + j]
+ * (i over group_tiles, j over features_per_bin; ms_out may be NULL).  Uses
+ * scratch outputs it allocates and frees; blocks until done. */
+int sfm_autotune(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                 const sfm_options* opt, void* stream, int32_t repeats, double* ms_out);
+
 /* Human-readable name of a status code (static string). */
 const char* sfm_strerror(int status);
 

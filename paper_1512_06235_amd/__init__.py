@@ -100,6 +100,10 @@ def lib() -> C.CDLL:
         "sfm_server_poll": [vp, C.c_uint64, C.POINTER(sfm_result_view), i32],
         "sfm_server_stats": [vp, C.POINTER(i64)],
         "sfm_server_stop": [vp],
+        "sfm_set_tuning": [vp, i32, i32],
+        "sfm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32)],
+        "sfm_autotune": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options), vp, i32,
+                         C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -119,7 +123,8 @@ def exported_symbols():
             "sfm_guided_match", "sfm_guided_match_plain", "sfm_bruteforce_match", "sfm_sync",
             "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
-            "sfm_server_poll", "sfm_server_stats", "sfm_server_stop"]
+            "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
+            "sfm_get_tuning", "sfm_autotune"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -263,6 +268,34 @@ def sfm_server_stats(ctx) -> dict:
 
 def sfm_server_stop(ctx) -> None:
     _check(ctx, lib().sfm_server_stop(ctx))
+
+
+def sfm_set_tuning(ctx, group_tiles: int, features_per_bin: int) -> None:
+    _check(ctx, lib().sfm_set_tuning(ctx, int(group_tiles), int(features_per_bin)))
+
+
+def sfm_get_tuning(ctx):
+    """(group_tiles, features_per_bin) of the context."""
+    t, f = C.c_int32(), C.c_int32()
+    _check(ctx, lib().sfm_get_tuning(ctx, C.byref(t), C.byref(f)))
+    return t.value, f.value
+
+
+AUTOTUNE_GROUP_TILES = (1, 2, 4)
+AUTOTUNE_FEATURES_PER_BIN = (4, 8, 16)
+
+
+def sfm_autotune(ctx, pairs, F, opt=None, stream=None, repeats: int = 3):
+    """Time every tuning on this batch, keep the fastest; returns
+    {(group_tiles, features_per_bin): ms per call}."""
+    Fh = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(len(pairs), 9))
+    ms = (C.c_double * 9)()
+    st = lib().sfm_autotune(ctx, _pairs(pairs), len(pairs), Fh.ctypes.data,
+                            C.byref(opt if opt is not None else options()),
+                            stream.cuda_stream if stream is not None else None, int(repeats), ms)
+    _check(ctx, st)
+    return {(t, f): ms[3 * i + j] for i, t in enumerate(AUTOTUNE_GROUP_TILES)
+            for j, f in enumerate(AUTOTUNE_FEATURES_PER_BIN)}
 
 
 def options(ratio_num=64, ratio_den=100, accept_single=False, emit_all=False) -> sfm_options:

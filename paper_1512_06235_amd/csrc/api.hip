@@ -16,6 +16,8 @@ using namespace sfm;
 
 struct sfm_ctx {
   int32_t device = 0;
+  int32_t group_tiles = kDefaultGroupTiles;          // query tiles per match workgroup
+  int32_t features_per_bin = kDefaultFeaturesPerBin; // target features per bin of b
   size_t budget = 0;
   std::string last_error;
   std::mutex mu;
@@ -73,14 +75,11 @@ struct Layout {
   int64_t sum_na = 0, sum_nb = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
 };
 
-#ifndef SFM_BIN_DIV
-#define SFM_BIN_DIV 8
-#endif
-int32_t bins_for(int32_t nb) {
-  return std::max<int32_t>(1, std::min<int32_t>(kMaxBins, nb / SFM_BIN_DIV));
+int32_t bins_for(int32_t nb, int32_t features_per_bin) {
+  return std::max<int32_t>(1, std::min<int32_t>(kMaxBins, nb / features_per_bin));
 }
 
-Layout plan(const std::vector<PairDesc>& pd, int32_t device) {
+Layout plan(const std::vector<PairDesc>& pd, int32_t device, int32_t group_tiles) {
   Layout L;
   for (const PairDesc& p : pd) {
     L.sum_na += p.na;
@@ -97,7 +96,7 @@ Layout plan(const std::vector<PairDesc>& pd, int32_t device) {
   L.staged = o;
   L.geom = o; o = align_up(o + P * sizeof(PairGeom));
   L.counters = o; o = align_up(o + P * sizeof(PairCounters));
-  L.wgs = match_workgroups(device, L.sum_groups);
+  L.wgs = match_workgroups(device, group_tiles, L.sum_groups);
   L.wg_start = o; o = align_up(o + size_t(L.wgs + 1) * sizeof(int32_t));
   L.cand = o; o = align_up(o + size_t(L.sum_nb) * sizeof(CandRec));
   L.bins = o; o = align_up(o + size_t(L.sum_bins) * sizeof(int32_t));
@@ -136,9 +135,9 @@ int describe_pairs(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, bool ig
     p.b = s.b;
     p.na = ctx->n_host[size_t(s.a)];
     p.nb = ctx->n_host[size_t(s.b)];
-    p.nbins = ignore_band ? 1 : bins_for(p.nb);
+    p.nbins = ignore_band ? 1 : bins_for(p.nb, ctx->features_per_bin);
     p.nblocks = (p.na + kQueryTile - 1) / kQueryTile;
-    p.ngroups = (p.nblocks + kGroupTiles - 1) / kGroupTiles;
+    p.ngroups = (p.nblocks + ctx->group_tiles - 1) / ctx->group_tiles;
     p.q_off = q;
     p.c_off = c;
     p.bin_off = bo;
@@ -237,7 +236,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
     }
   }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  const Layout L = plan(pd, ctx->device);
+  const Layout L = plan(pd, ctx->device, ctx->group_tiles);
   if (!out->offset) return fail(ctx, SFM_EINVAL, "out->offset is NULL");
   if (out->capacity < L.sum_na) {
     char buf[128];
@@ -300,6 +299,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   v.ratio_den = opt.ratio_den;
   v.accept_single = opt.accept_single ? 1 : 0;
   v.keep_counts = opt.emit_all ? 1 : 0;
+  v.group_tiles = ctx->group_tiles;
   v.groups = reinterpret_cast<TileGroup*>(ctx->ws + L.groups);
 
   int32_t* am = opt.emit_all ? out->all_match : nullptr;
@@ -310,7 +310,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
     for (int32_t p = 0; p < n_pairs; ++p) {
       HIP_TRY(ctx, prof_mark(ctx, st));
       const int32_t g0 = int32_t(pd[size_t(p)].grp_off), gn = pd[size_t(p)].ngroups;
-      const int32_t wgs = match_workgroups(ctx->device, gn);
+      const int32_t wgs = match_workgroups(ctx->device, ctx->group_tiles, gn);
       HIP_TRY(ctx, launch_prepare(v, p, 1, g0, gn, wgs, nullptr, pd[size_t(p)].na, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
       HIP_TRY(ctx, launch_match(v, gn > 0 ? wgs : 0, st));
@@ -484,7 +484,7 @@ int sfm_workspace_size(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, siz
   const int rc = describe_pairs(ctx, pairs, n_pairs, false, pd);
   if (rc) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  *bytes = plan(pd, ctx->device).total;
+  *bytes = plan(pd, ctx->device, ctx->group_tiles).total;
   return SFM_OK;
 }
 
@@ -561,6 +561,103 @@ int sfm_sync(sfm_ctx* ctx, void* stream) {
     return fail(ctx, SFM_EKERNEL, "a kernel raised the device error flag");
   }
   return SFM_OK;
+}
+
+int sfm_set_tuning(sfm_ctx* ctx, int32_t group_tiles, int32_t features_per_bin) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (group_tiles != 1 && group_tiles != 2 && group_tiles != 4)
+    return fail(ctx, SFM_EINVAL, "group_tiles must be 1, 2 or 4");
+  if (features_per_bin < 1 || features_per_bin > 1024)
+    return fail(ctx, SFM_EINVAL, "features_per_bin must be in 1..1024");
+  ctx->group_tiles = group_tiles;
+  ctx->features_per_bin = features_per_bin;
+  return SFM_OK;
+}
+
+int sfm_get_tuning(sfm_ctx* ctx, int32_t* group_tiles, int32_t* features_per_bin) {
+  if (!ctx || !group_tiles || !features_per_bin) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  *group_tiles = ctx->group_tiles;
+  *features_per_bin = ctx->features_per_bin;
+  return SFM_OK;
+}
+
+int sfm_autotune(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                 const sfm_options* opt, void* stream, int32_t repeats, double* ms_out) {
+  if (!ctx) return SFM_EINVAL;
+  if (repeats < 1) return fail(ctx, SFM_EINVAL, "repeats must be >= 1");
+  static const int32_t kTiles[3] = {1, 2, 4};
+  static const int32_t kFpb[3] = {4, 8, 16};
+  int64_t rows = 0;
+  for (int32_t k = 0; k < n_pairs && pairs; ++k) {
+    if (pairs[k].a < 0 || pairs[k].a >= ctx->n_images) return fail(ctx, SFM_EINVAL, "bad pair");
+    rows += ctx->n_host[size_t(pairs[k].a)];
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // Scratch outputs for the trial runs.
+  const size_t r4 = size_t(std::max<int64_t>(rows, 1)) * sizeof(int32_t);
+  int32_t *q = nullptr, *m = nullptr, *d1 = nullptr, *d2 = nullptr;
+  int64_t* off = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = SFM_OK;
+  if (hipMalloc(&q, r4) != hipSuccess || hipMalloc(&m, r4) != hipSuccess ||
+      hipMalloc(&d1, r4) != hipSuccess || hipMalloc(&d2, r4) != hipSuccess ||
+      hipMalloc(&off, size_t(n_pairs + 1) * sizeof(int64_t)) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = fail(ctx, SFM_ENOMEM, "autotune scratch allocation failed");
+  sfm_matches out;
+  memset(&out, 0, sizeof out);
+  out.query = q; out.match = m; out.d1 = d1; out.d2 = d2;
+  out.offset = off; out.capacity = rows;
+  int32_t keep_t, keep_f;
+  {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    keep_t = ctx->group_tiles;
+    keep_f = ctx->features_per_bin;
+  }
+  auto set = [&](int32_t t, int32_t f) {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->group_tiles = t;
+    ctx->features_per_bin = f;
+  };
+  double best = INFINITY;
+  int32_t best_t = keep_t, best_f = keep_f;
+  for (int ti = 0; ti < 3 && rc == SFM_OK; ++ti) {
+    for (int fi = 0; fi < 3 && rc == SFM_OK; ++fi) {
+      set(kTiles[ti], kFpb[fi]);
+      // One untimed run sizes the workspace for this configuration.
+      rc = run_match(ctx, pairs, n_pairs, F, opt, &out, stream, Form::kBatched);
+      if (rc) break;
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = SFM_EHIP; break; }
+      for (int32_t r = 0; r < repeats && rc == SFM_OK; ++r)
+        rc = run_match(ctx, pairs, n_pairs, F, opt, &out, stream, Form::kBatched);
+      if (rc) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = SFM_EHIP;
+        break;
+      }
+      const double per = double(ms) / repeats;
+      if (ms_out) ms_out[3 * ti + fi] = per;
+      if (per < best) { best = per; best_t = kTiles[ti]; best_f = kFpb[fi]; }
+    }
+  }
+  if (st) (void)hipStreamSynchronize(st); else (void)hipDeviceSynchronize();
+  if (rc == SFM_OK)
+    set(best_t, best_f);
+  else
+    set(keep_t, keep_f);
+  if (q) (void)hipFree(q);
+  if (m) (void)hipFree(m);
+  if (d1) (void)hipFree(d1);
+  if (d2) (void)hipFree(d2);
+  if (off) (void)hipFree(off);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return rc;
 }
 
 }  // extern "C"

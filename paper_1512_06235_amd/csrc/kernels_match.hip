@@ -1,7 +1,7 @@
 // Fused candidate test + distance + two-nearest kernel (a4-a6), Appendix A
 // steps 3-4 redesigned for CDNA4.
 //
-// A workgroup of kGroupTiles waves (two) owns a group of consecutive query
+// A workgroup of 1, 2 or 4 waves (default two) owns a group of consecutive query
 // tiles (32 queries each, in pencil order) of one pair, one tile per wave.
 // Their candidate ranges overlap heavily, so the workgroup streams the union
 // range of b's binned features through LDS once, 32 candidates per step:
@@ -39,10 +39,15 @@ typedef unsigned int nv4u __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) nv4u g_nv4u;
 typedef const __attribute__((address_space(1))) int32_t g_i32;
 
-constexpr int kWaves = kGroupTiles;
-constexpr int kRowsPerWave = kCandTile / kWaves;   // rows of a step each wave fetches
-constexpr int kRowLoads = kRowsPerWave / 8;        // 16-B-per-lane loads for them
-static_assert(kRowsPerWave % 8 == 0 && kRowsPerWave <= 64, "waves must split the step by 8 rows");
+// A workgroup of W waves (one query tile each) shares the candidate stream:
+// each wave fetches kCandTile / W rows of every step with (kCandTile / W) / 8
+// loads of 16 bytes per lane.
+template <int W>
+struct Split {
+  static constexpr int kRowsPerWave = kCandTile / W;
+  static constexpr int kRowLoads = kRowsPerWave / 8;
+  static_assert(kRowsPerWave % 8 == 0 && kRowsPerWave <= 64, "waves split a step by 8 rows");
+};
 constexpr int kMetaSlots = 3;
 
 // Band test of eqs. (2)-(3) on centred FP32 coordinates: |a x + b y + c| <= d
@@ -94,7 +99,7 @@ struct GroupLds {
   float x[kMetaSlots][kCandTile];
   float y[kMetaSlots][kCandTile];
   uint32_t nc[kMetaSlots][kCandTile];
-  uint32_t sink[kWaves][3][64];    // targets of the lanes that own no record
+  uint32_t sink[kMaxGroupTiles][3][64];   // targets of the lanes that own no record
 };
 
 // Wave w owns candidates R*w .. R*w+R-1 of every step (R = kRowsPerWave):
@@ -102,10 +107,12 @@ struct GroupLds {
 // metadata (the other lanes write to distinct sink words: no divergent
 // branch, no bank conflict).  Positions past the range get a NaN coordinate,
 // which no band test passes.
+template <int W>
 __device__ __forceinline__ void stage_meta(GroupLds& L, int st, const nv4u& r, int32_t t0,
                                            int32_t c1, int wave, int lane) {
-  const int cand_i = kRowsPerWave * wave + (lane % kRowsPerWave);
-  const bool own = lane < kRowsPerWave;
+  constexpr int R = Split<W>::kRowsPerWave;
+  const int cand_i = R * wave + (lane % R);
+  const bool own = lane < R;
   float* px = own ? &L.x[st][cand_i] : reinterpret_cast<float*>(&L.sink[wave][0][lane]);
   float* py = own ? &L.y[st][cand_i] : reinterpret_cast<float*>(&L.sink[wave][1][lane]);
   uint32_t* pn = own ? &L.nc[st][cand_i] : &L.sink[wave][2][lane];
@@ -123,10 +130,11 @@ __device__ __forceinline__ nv4u load_row_share(const nv4u& r, const uint8_t* des
   return gload16(desc + int64_t(j) * kDescBytes + 16 * (lane & 7));
 }
 
+template <int W>
 __device__ __forceinline__ void store_row_share(GroupLds& L, int st, int wave, int lane, int k,
                                                 const nv4u& rw) {
   const int m = lane >> 3, c = lane & 7;
-  const int row = kRowsPerWave * wave + 8 * k + m;   // row & 7 == m
+  const int row = Split<W>::kRowsPerWave * wave + 8 * k + m;   // row & 7 == m
   *reinterpret_cast<nv4u*>(&L.rows[st][row * kDescBytes + ((c ^ m) << 4)]) = rw;
 }
 
@@ -265,9 +273,11 @@ __device__ __forceinline__ TileGroup load_group(const TileGroup* groups, int32_t
 // One group: up to four query tiles (one per wave) against their union
 // candidate range, streamed through LDS 32 candidates per step with one
 // barrier per step.
-template <bool kKeepCounts>
+template <bool kKeepCounts, int W>
 __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup& G, GroupLds& L,
                                             int wave, int lane, WaveStats& ws) {
+  constexpr int kRowLoads = Split<W>::kRowLoads;
+  constexpr int kRowsPerWave = Split<W>::kRowsPerWave;
   const int col = lane & 31, half = lane >> 5;
   const bool wv = wave < G.ntiles;
   const int32_t blk = G.tile0 + wave;
@@ -275,7 +285,7 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
   // private memory.
   int32_t my_b = 0, my_e = 0;
 #pragma unroll
-  for (int t = 0; t < kGroupTiles; ++t) {
+  for (int t = 0; t < W; ++t) {
     my_b = wave == t ? G.t_begin[t] : my_b;
     my_e = wave == t ? G.t_end[t] : my_e;
   }
@@ -331,11 +341,11 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
     // register with a load in flight would wait for that load).
     const int32_t nsteps = (S1 - S0 + kCandTile - 1) / kCandTile;
     nv4u we[kRowLoads], wo[kRowLoads];
-    stage_meta(L, 0, re, S0, S1, wave, lane);
+    stage_meta<W>(L, 0, re, S0, S1, wave, lane);
 #pragma unroll
     for (int k = 0; k < kRowLoads; ++k) we[k] = load_row_share(re, b_desc, lane, k);
     re = load_rec(cand, S0 + 2 * kCandTile + own, S1);
-    stage_meta(L, 1, ro, S0 + kCandTile, S1, wave, lane);
+    stage_meta<W>(L, 1, ro, S0 + kCandTile, S1, wave, lane);
 #pragma unroll
     for (int k = 0; k < kRowLoads; ++k) wo[k] = load_row_share(ro, b_desc, lane, k);
     ro = load_rec(cand, S0 + 3 * kCandTile + own, S1);
@@ -347,10 +357,10 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
     auto step = [&](int32_t u, int rs, nv4u (&w)[kRowLoads], nv4u& r) {
       const int32_t t0 = S0 + u * kCandTile;
 #pragma unroll
-      for (int k = 0; k < kRowLoads; ++k) store_row_share(L, rs, wave, lane, k, w[k]);
+      for (int k = 0; k < kRowLoads; ++k) store_row_share<W>(L, rs, wave, lane, k, w[k]);
       __syncthreads();
       const int ms2 = ms == 0 ? 2 : ms - 1;   // (u + 2) % 3
-      stage_meta(L, ms2, r, t0 + 2 * kCandTile, S1, wave, lane);
+      stage_meta<W>(L, ms2, r, t0 + 2 * kCandTile, S1, wave, lane);
 #pragma unroll
       for (int k = 0; k < kRowLoads; ++k) w[k] = load_row_share(r, b_desc, lane, k);
       r = load_rec(cand, t0 + 4 * kCandTile + own, S1);
@@ -442,8 +452,8 @@ __device__ __forceinline__ int32_t xcd_contiguous(int32_t g, int32_t G) {
   const int32_t x = g & 7, k = g >> 3, q = G >> 3, r = G & 7;
   return x * q + min(x, r) + k;
 }
-template <bool kKeepCounts>
-__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
+template <bool kKeepCounts, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
 void match_kernel(BatchView v) {
   __shared__ __attribute__((aligned(16))) GroupLds lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -464,7 +474,7 @@ void match_kernel(BatchView v) {
   WaveStats ws = {-1, 0, 0, 0, 0};
   for (int32_t g = g_first; g < g_end; g += w) {
     const TileGroup G = load_group(v.groups, g);
-    match_group<kKeepCounts>(v, G, lds, wave, lane, ws);
+    match_group<kKeepCounts, W>(v, G, lds, wave, lane, ws);
   }
   flush_stats(v, ws, lane);
 }
@@ -472,12 +482,13 @@ void match_kernel(BatchView v) {
 }  // namespace
 
 // Workgroups of the match kernel that fit on a device at once.
+template <int W>
 static int32_t resident_workgroups(int dev) {
   static int32_t cached[64] = {0};
   if (dev < 0 || dev >= 64) return 256;
   if (cached[dev] == 0) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, match_kernel<false>, 64 * kWaves, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, match_kernel<false, W>, 64 * W, 0) !=
             hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         per_cu <= 0 || cus <= 0) {
@@ -489,16 +500,29 @@ static int32_t resident_workgroups(int dev) {
   return cached[dev];
 }
 
-int32_t match_workgroups(int32_t device, int64_t groups) {
-  return int32_t(std::max<int64_t>(1, std::min<int64_t>(groups, resident_workgroups(device))));
+int32_t match_workgroups(int32_t device, int32_t group_tiles, int64_t groups) {
+  const int32_t r = group_tiles == 1   ? resident_workgroups<1>(device)
+                    : group_tiles == 4 ? resident_workgroups<4>(device)
+                                       : resident_workgroups<2>(device);
+  return int32_t(std::max<int64_t>(1, std::min<int64_t>(groups, r)));
+}
+
+template <int W>
+static void launch_match_w(const BatchView& v, int32_t wgs, hipStream_t st) {
+  if (v.keep_counts)
+    hipLaunchKernelGGL((match_kernel<true, W>), dim3(wgs), dim3(64 * W), 0, st, v);
+  else
+    hipLaunchKernelGGL((match_kernel<false, W>), dim3(wgs), dim3(64 * W), 0, st, v);
 }
 
 hipError_t launch_match(const BatchView& v, int32_t wgs, hipStream_t st) {
   if (wgs <= 0) return hipSuccess;
-  if (v.keep_counts)
-    hipLaunchKernelGGL(match_kernel<true>, dim3(wgs), dim3(64 * kWaves), 0, st, v);
+  if (v.group_tiles == 1)
+    launch_match_w<1>(v, wgs, st);
+  else if (v.group_tiles == 4)
+    launch_match_w<4>(v, wgs, st);
   else
-    hipLaunchKernelGGL(match_kernel<false>, dim3(wgs), dim3(64 * kWaves), 0, st, v);
+    launch_match_w<2>(v, wgs, st);
   return hipGetLastError();
 }
 

@@ -505,14 +505,15 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
 }
 
 // Candidate range of every query tile (the union of its queries' bin windows
-// mapped through b's bin starts) and of every group of kGroupTiles
+// mapped through b's bin starts) and of every group of K
 // consecutive tiles, with the group record and its schedule cost.  Block
 // (p, c) takes queries [256c, 256c + 256) of pair p: one thread per query,
 // half-wave min/max reductions per tile, one thread per group.
 constexpr int kRangeThreads = 256;
 constexpr int kRangeTiles = kRangeThreads / kQueryTile;
-static_assert(kRangeTiles % kGroupTiles == 0, "a block holds whole groups");
+static_assert(kRangeTiles % kMaxGroupTiles == 0, "a block holds whole groups");
 
+template <int K>
 __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v, int32_t pb) {
   __shared__ int2 trange[kRangeTiles];
   const int32_t p = pb + blockIdx.x;
@@ -538,21 +539,21 @@ __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v,
   }
   __syncthreads();
   const int32_t tiles_here = min(kRangeTiles, (P.na - q0 + kQueryTile - 1) / kQueryTile);
-  const int32_t groups_here = (tiles_here + kGroupTiles - 1) / kGroupTiles;
+  const int32_t groups_here = (tiles_here + K - 1) / K;
   long long cost = 0;
   if (t < groups_here) {
-    const int32_t g = int32_t(blockIdx.y) * (kRangeTiles / kGroupTiles) + t;
-    const int32_t k0 = g * kGroupTiles;
-    const int32_t nt = min(kGroupTiles, P.nblocks - k0);
+    const int32_t g = int32_t(blockIdx.y) * (kRangeTiles / K) + t;
+    const int32_t k0 = g * K;
+    const int32_t nt = min(K, P.nblocks - k0);
     const ImageDev A = v.images[P.a];
     const ImageDev B = v.images[P.b];
     TileGroup tg;
     memset(&tg, 0, sizeof tg);
     int32_t gb = 0x7FFFFFFF, ge = 0;
 #pragma unroll
-    for (int32_t k = 0; k < kGroupTiles; ++k) {
+    for (int32_t k = 0; k < K; ++k) {
       int2 r = make_int2(0, 0);
-      if (k < nt) r = trange[t * kGroupTiles + k];
+      if (k < nt) r = trange[t * K + k];
       if (r.y > r.x) { gb = min(gb, r.x); ge = max(ge, r.y); }
       tg.t_begin[k] = r.x;
       tg.t_end[k] = r.y;
@@ -663,8 +664,15 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t gr
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
   hipLaunchKernelGGL(bin_kernel, dim3(pc, 2), dim3(kBinThreads), 0, st, v, pb, order);
   const int32_t qblocks = (max_queries + kRangeThreads - 1) / kRangeThreads;
-  if (qblocks > 0)
-    hipLaunchKernelGGL(tile_ranges_kernel, dim3(pc, qblocks), dim3(kRangeThreads), 0, st, v, pb);
+  if (qblocks > 0) {
+    const dim3 grid(pc, qblocks), block(kRangeThreads);
+    if (v.group_tiles == 1)
+      hipLaunchKernelGGL(tile_ranges_kernel<1>, grid, block, 0, st, v, pb);
+    else if (v.group_tiles == 4)
+      hipLaunchKernelGGL(tile_ranges_kernel<4>, grid, block, 0, st, v, pb);
+    else
+      hipLaunchKernelGGL(tile_ranges_kernel<2>, grid, block, 0, st, v, pb);
+  }
   if (grp_count > 0)
     hipLaunchKernelGGL(schedule_kernel, dim3((pc + 3) / 4), dim3(256), 0, st, v, pb, pc,
                        grp_begin, grp_count, SFM_XCD_SWEEP ? std::min(8, wgs) : wgs);

@@ -8,10 +8,9 @@ namespace sfm {
 
 constexpr int kDescBytes = 128;
 constexpr int kQueryTile = 32;          // queries per wave work item (MFMA N)
-#ifndef SFM_GROUP_TILES
-#define SFM_GROUP_TILES 2
-#endif
-constexpr int kGroupTiles = SFM_GROUP_TILES;  // query tiles (waves) sharing one candidate stream
+constexpr int kMaxGroupTiles = 4;       // query tiles (waves) sharing one candidate stream, at most
+constexpr int kDefaultGroupTiles = 2;   // the default (1, 2 or 4)
+constexpr int kDefaultFeaturesPerBin = 8;
 constexpr int kCandTile = 32;           // candidates per MFMA step (MFMA M)
 constexpr int kChunk = 1024;            // candidate positions one key encodes
 constexpr int kPosBits = 10;            // log2(kChunk)
@@ -44,7 +43,7 @@ struct PairDesc {
   int64_t bin_off;          // into bin arrays (prefix of nbins + 1)
   int64_t blk_off;          // into per-block arrays and the work-item space
   int64_t grp_off;          // into the tile-group table
-  int32_t ngroups;          // ceil(nblocks / kGroupTiles)
+  int32_t ngroups;          // ceil(nblocks / group tiles)
   int32_t pad2;
   double band;              // d, pixels (may be +inf)
   int32_t ignore_band;      // exhaustive matching
@@ -101,7 +100,7 @@ struct PairCounters {
   uint32_t ties;            // chunks that needed the tie-break pass
 };
 
-// Up to kGroupTiles consecutive query tiles of one pair and the union of
+// Up to kMaxGroupTiles consecutive query tiles of one pair and the union of
 // their candidate ranges; one workgroup streams the union through LDS.  The
 // record holds everything the match kernel needs about the pair (128 bytes,
 // read with scalar loads).
@@ -115,8 +114,8 @@ struct TileGroup {
   const int32_t* a_norm;
   const uint8_t* b_desc;
   int64_t pad1;
-  int32_t t_begin[kGroupTiles], t_end[kGroupTiles];   // per tile candidate range
-  int32_t pad2[8 - 2 * kGroupTiles + 4];
+  int32_t t_begin[kMaxGroupTiles], t_end[kMaxGroupTiles];   // per tile candidate range
+  int32_t pad2[4];
 };
 static_assert(sizeof(TileGroup) == 128, "TileGroup is read as eight 16-byte words");
 
@@ -142,6 +141,7 @@ struct BatchView {
   int32_t ratio_num, ratio_den;
   int32_t accept_single;
   int32_t keep_counts;
+  int32_t group_tiles;      // tiles per group = waves per match workgroup (1, 2 or 4)
 };
 
 }  // namespace sfm
@@ -170,7 +170,7 @@ hipError_t launch_prepare(const BatchView& v, int32_t pair_begin, int32_t pair_c
                           const int32_t* order, int32_t max_queries, hipStream_t st);
 // Workgroups the match kernel uses for `groups` tile groups (one resident wave
 // of workgroups at most).
-int32_t match_workgroups(int32_t device, int64_t groups);
+int32_t match_workgroups(int32_t device, int32_t group_tiles, int64_t groups);
 // Matches the groups that the last preparation split over `wgs` workgroups.
 hipError_t launch_match(const BatchView& v, int32_t wgs, hipStream_t st);
 hipError_t launch_emit(const BatchView& v, int32_t pair_begin, int32_t pair_count,
