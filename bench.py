@@ -231,6 +231,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tuning (2 tiles per group, 8 features per bin)")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
     ap.add_argument("--serving-rates", default="1000,5000",
                     help="offered pair requests per second, comma-separated")
@@ -278,8 +280,18 @@ def main():
     out = m.buffers(pairs)
     opt = sfm.options()
 
+    batch = sfm.PairBatch(pairs, Fs)   # marshalled once, reused by every call
+
     def step():
-        sfm.sfm_guided_match(m.ctx, pairs, Fs, out, opt, stream)
+        sfm.sfm_guided_match(m.ctx, batch, None, out, opt, stream)
+
+    tuning = None
+    if not args.no_autotune:
+        log("bench: autotuning group size and bin width on the batch")
+        times = sfm.sfm_autotune(m.ctx, batch, None, opt, stream, repeats=3)
+        best = sfm.sfm_get_tuning(m.ctx)
+        tuning = {"group_tiles": best[0], "features_per_bin": best[1],
+                  "ms_per_call": {f"{t}x{f}": round(v, 4) for (t, f), v in times.items()}}
 
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -305,8 +317,8 @@ def main():
     if args.plain_steps > 0:
         log(f"bench: timing {args.plain_steps} plain per-pair steps")
         plain_out = m.buffers(pairs)
-        sfm.sfm_guided_match_plain(m.ctx, pairs, Fs, plain_out, opt, stream)
-        plain_elapsed = timed(lambda: sfm.sfm_guided_match_plain(m.ctx, pairs, Fs, plain_out, opt,
+        sfm.sfm_guided_match_plain(m.ctx, batch, None, plain_out, opt, stream)
+        plain_elapsed = timed(lambda: sfm.sfm_guided_match_plain(m.ctx, batch, None, plain_out, opt,
                                                                  stream), args.plain_steps, stream)
         sfm.sfm_sync(m.ctx, stream)
         assert int(plain_out.offset[-1]) == matches
@@ -358,6 +370,7 @@ def main():
                    "slots_per_step": stats["slots"],
                    "useful_slot_fraction": comparisons / max(1, stats["slots"]),
                    "tie_passes": stats["tie_passes"]},
+        "tuning": tuning,
         "plain_form": plain,
         "phases_ms_per_step": {"prepare": prep_ms / max(1, nrec), "match": match_ms / max(1, nrec),
                                "emit": emit_ms / max(1, nrec)},

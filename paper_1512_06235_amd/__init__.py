@@ -166,11 +166,33 @@ def sfm_register_images(ctx, images) -> None:
     _check(ctx, lib().sfm_register_images(ctx, arr, len(images)))
 
 
+_PAIR_DTYPE = np.dtype([("a", "<i4"), ("b", "<i4"), ("band_px", "<f8")])
+assert _PAIR_DTYPE.itemsize == C.sizeof(sfm_pair)
+
+
+class PairBatch:
+    """Pairs and their fundamental matrices marshalled once for repeated calls:
+    a host sfm_pair[n] and double[9n] that every matching call can take as is."""
+
+    def __init__(self, pairs, F=None):
+        n = len(pairs)
+        self.n = n
+        self.host = np.zeros(max(1, n), dtype=_PAIR_DTYPE)
+        if n:
+            arr = np.asarray(pairs, dtype=np.float64).reshape(n, 3)
+            self.host["a"][:n] = arr[:, 0].astype(np.int32)
+            self.host["b"][:n] = arr[:, 1].astype(np.int32)
+            self.host["band_px"][:n] = arr[:, 2]
+        self.F = None if F is None else np.ascontiguousarray(
+            np.asarray(F, dtype=np.float64).reshape(n, 9))
+        self.c_pairs = self.host.ctypes.data_as(C.POINTER(sfm_pair))
+
+    def __len__(self):
+        return self.n
+
+
 def _pairs(pairs):
-    arr = (sfm_pair * max(1, len(pairs)))()
-    for k, (a, b, band) in enumerate(pairs):
-        arr[k] = sfm_pair(int(a), int(b), float(band))
-    return arr
+    return pairs.c_pairs if isinstance(pairs, PairBatch) else PairBatch(pairs).c_pairs
 
 
 def sfm_workspace_size(ctx, pairs) -> int:
@@ -180,12 +202,15 @@ def sfm_workspace_size(ctx, pairs) -> int:
 
 
 def _call(fn_name, ctx, pairs, F, out: "MatchBuffers", opt: sfm_options, stream):
-    Fh = None
-    if F is not None:
-        Fh = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(len(pairs), 9))
-    st = getattr(lib(), fn_name)(ctx, _pairs(pairs), len(pairs),
-                                 Fh.ctypes.data if Fh is not None else None,
-                                 C.byref(opt), C.byref(out.c_struct()),
+    """pairs: list of (a, b, band_px) or a PairBatch (then F may be None to use
+    the batch's matrices)."""
+    if isinstance(pairs, PairBatch) and (F is None or F is pairs.F):
+        batch = pairs
+    else:
+        batch = PairBatch(pairs, F)
+    st = getattr(lib(), fn_name)(ctx, batch.c_pairs, batch.n,
+                                 batch.F.ctypes.data if batch.F is not None else None,
+                                 C.byref(opt), C.byref(out.c_struct_cached()),
                                  stream.cuda_stream if stream is not None else None)
     _check(ctx, st)
 
@@ -288,9 +313,9 @@ AUTOTUNE_FEATURES_PER_BIN = (4, 8, 16)
 def sfm_autotune(ctx, pairs, F, opt=None, stream=None, repeats: int = 3):
     """Time every tuning on this batch, keep the fastest; returns
     {(group_tiles, features_per_bin): ms per call}."""
-    Fh = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(len(pairs), 9))
+    batch = pairs if isinstance(pairs, PairBatch) and F is None else PairBatch(pairs, F)
     ms = (C.c_double * 9)()
-    st = lib().sfm_autotune(ctx, _pairs(pairs), len(pairs), Fh.ctypes.data,
+    st = lib().sfm_autotune(ctx, batch.c_pairs, batch.n, batch.F.ctypes.data,
                             C.byref(opt if opt is not None else options()),
                             stream.cuda_stream if stream is not None else None, int(repeats), ms)
     _check(ctx, st)
@@ -324,6 +349,11 @@ class MatchBuffers:
             self.all_d1 = torch.empty(cap, **i32)
             self.all_d2 = torch.empty(cap, **i32)
             self.all_count = torch.empty(cap, **i32)
+
+    def c_struct_cached(self) -> sfm_matches:
+        if getattr(self, "_c", None) is None:
+            self._c = self.c_struct()
+        return self._c
 
     def c_struct(self) -> sfm_matches:
         ea = self.emit_all
