@@ -312,16 +312,18 @@ __device__ void block_exclusive_scan(int32_t* cnt, int32_t n, int32_t* wsum) {
 }
 
 // ---------------------------------------------------------------------------
-// a2 + a3: one workgroup per (pair, image).  blockIdx.y = 0 bins the targets
-// of b, blockIdx.y = 1 lines up and tiles the queries of a.  Counting sort:
+// a2 + a3: one workgroup per (pair, image): one bins the targets of b, the
+// other lines up and tiles the queries of a.  Counting sort:
 // pass 1 counts bins in LDS, a scan gives bin starts, pass 2 scatters.  The
 // bins of the first kCacheRounds rounds of items stay in registers between
 // the passes, so their FP64 keys are computed once.  `order` (may be NULL)
 // maps blockIdx.x to the pair, largest pairs first.
 // ---------------------------------------------------------------------------
-constexpr int kBinThreads = 1024;
+// 512 threads at 128 VGPRs fit two binning workgroups per CU (1,024 fit
+// one), which overlaps one pair's barrier phases with another's work.
+constexpr int kBinThreads = 512;
 constexpr int kBatch = 8;   // items per thread per round; their loads are issued together
-constexpr int kCacheRounds = 2;
+constexpr int kCacheRounds = 3;
 
 // Counting sort of one side of a pair: the targets of b into CandRec order
 // (and the bin starts), or the queries of a into tile order.
@@ -459,10 +461,14 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
   __shared__ int32_t lds[kBinLdsInts];
   int32_t* const wsum = lds + kBinLdsInts - kBinWsum;
   int32_t* const hist = lds;
-  const int32_t p = order ? order[pb + blockIdx.x] : pb + blockIdx.x;
+  // Workgroup 2k + 1 sorts the targets and 2k the queries of the k-th pair
+  // in `order`: both sides of the largest pairs are dispatched first, the
+  // costlier query side ahead of its targets.
+  const int32_t rank = blockIdx.x >> 1;
+  const int32_t p = order ? order[pb + rank] : pb + rank;
   const PairDesc P = v.pairs[p];
   const PairGeom g = v.geom[p];
-  const bool targets = blockIdx.y == 0;
+  const bool targets = (blockIdx.x & 1) != 0;
   const int32_t nh = targets ? g.nbins : g.nbins + 1;
   const ImageDev I = v.images[targets ? P.b : P.a];
 
@@ -662,7 +668,7 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t gr
                           int32_t max_queries, hipStream_t st) {
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
-  hipLaunchKernelGGL(bin_kernel, dim3(pc, 2), dim3(kBinThreads), 0, st, v, pb, order);
+  hipLaunchKernelGGL(bin_kernel, dim3(2 * pc), dim3(kBinThreads), 0, st, v, pb, order);
   const int32_t qblocks = (max_queries + kRangeThreads - 1) / kRangeThreads;
   if (qblocks > 0) {
     const dim3 grid(pc, qblocks), block(kRangeThreads);
