@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
 INT8_PEAK_TOPS = 5000.0    # MI355X dense int8 MFMA, vendor figure
 MATCH_SOURCE = os.path.join(ROOT, "paper_1512_06235_amd", "csrc", "kernels_match.hip")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "match_kernel_500pair_arc_traffic.txt")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "match_kernel_500pair_arc_traffic_{}.txt")
 
 
 def log(msg):
@@ -53,15 +53,19 @@ def source_digest(path=MATCH_SOURCE):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(tuning):
     """HBM bytes per match-kernel launch from the committed counter summary,
-    or None when there is none or the kernel source changed since."""
+    or None when there is none, the kernel source changed since, or the
+    counters were taken with another tuning (group_tiles x features_per_bin)."""
+    tag = f"{tuning[0]}x{tuning[1]}"
     try:
-        fields = dict(line.split(":", 1) for line in open(TRAFFIC_SUMMARY) if ":" in line)
+        fields = dict(line.split(":", 1) for line in open(TRAFFIC_SUMMARY.format(tag)) if ":" in line)
     except OSError:
         return None
     fields = {k.strip(): v.strip() for k, v in fields.items()}
     if fields.get("kernel_source_sha256") != source_digest():
+        return None
+    if fields.get("tuning") != tag:
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -107,7 +111,8 @@ def summarize_trace(directory, command):
     return "\n".join(out) + "\n"
 
 
-def summarize_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_mib, commands):
+def summarize_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_mib, commands,
+                      tuning="2x8"):
     """HBM bytes per match-kernel launch: FETCH_SIZE and WRITE_SIZE (KiB per
     dispatch), each scaled by what the same counter reads for a device copy of
     known size."""
@@ -119,10 +124,12 @@ def summarize_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_mi
     nbytes_kib = cal_mib * 1024.0
     f_factor = nbytes_kib / cfetch[copy_key][0]
     w_factor = nbytes_kib / cwrite[copy_key][0]
-    kf, nf = fetch["match_kernel<false>"]
-    kw, nw = write["match_kernel<false>"]
+    # The match kernel instantiation the run used (most dispatches).
+    key = max((k for k in fetch if k.startswith("match_kernel<")), key=lambda k: fetch[k][1])
+    kf, nf = fetch[key]
+    kw, nw = write[key]
     hbm = (kf * f_factor + kw * w_factor) * 1024.0
-    lines = ["HBM traffic of match_kernel, 500-pair arc-scene batch (rocprofv3 --pmc)",
+    lines = [f"HBM traffic of {key}, 500-pair arc-scene batch (rocprofv3 --pmc)",
              *[f"command_{i}: {c}" for i, c in enumerate(commands)], "",
              f"copy_kernel: {copy_key}",
              f"copy_bytes: {int(cal_mib) << 20}",
@@ -133,6 +140,7 @@ def summarize_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_mi
              f"match_fetch_kib_per_dispatch: {kf:.0f}  (dispatches: {nf})",
              f"match_write_kib_per_dispatch: {kw:.0f}  (dispatches: {nw})",
              f"hbm_bytes_per_launch: {hbm:.0f}",
+             f"tuning: {tuning}",
              f"kernel_source_sha256: {source_digest()}"]
     return "\n".join(lines) + "\n"
 
@@ -233,6 +241,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tuning (2 tiles per group, 8 features per bin)")
+    ap.add_argument("--tuning", default=None, metavar="TILESxFEATURES",
+                    help="use this tuning instead of autotuning, e.g. 2x4")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
     ap.add_argument("--serving-rates", default="1000,5000",
                     help="offered pair requests per second, comma-separated")
@@ -240,9 +250,9 @@ def main():
                     help="only run a device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DIR", "COMMAND"),
                     help="print a summary of a rocprofv3 --kernel-trace --stats csv run")
-    ap.add_argument("--summarize-traffic", nargs=6,
+    ap.add_argument("--summarize-traffic", nargs=7,
                     metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR", "CAL_MIB",
-                             "COMMANDS"),
+                             "TUNING", "COMMANDS"),
                     help="print the HBM traffic summary of rocprofv3 --pmc runs "
                          "(COMMANDS: the four commands, joined by ' || ')")
     args = ap.parse_args()
@@ -250,8 +260,8 @@ def main():
         print(summarize_trace(*args.summarize_trace), end="")
         return
     if args.summarize_traffic:
-        f, w, cf, cw, mib, cmds = args.summarize_traffic
-        print(summarize_traffic(f, w, cf, cw, float(mib), cmds.split(" || ")), end="")
+        f, w, cf, cw, mib, tun, cmds = args.summarize_traffic
+        print(summarize_traffic(f, w, cf, cw, float(mib), cmds.split(" || "), tun), end="")
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); pairs are independent, "
@@ -286,7 +296,11 @@ def main():
         sfm.sfm_guided_match(m.ctx, batch, None, out, opt, stream)
 
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        t, f = (int(x) for x in args.tuning.lower().split("x"))
+        sfm.sfm_set_tuning(m.ctx, t, f)
+        tuning = {"group_tiles": t, "features_per_bin": f, "ms_per_call": None}
+    elif not args.no_autotune:
         log("bench: autotuning group size and bin width on the batch")
         times = sfm.sfm_autotune(m.ctx, batch, None, opt, stream, repeats=3)
         best = sfm.sfm_get_tuning(m.ctx)
@@ -376,7 +390,8 @@ def main():
                                "emit": emit_ms / max(1, nrec)},
         "roofline": {"bound": "hbm", "kernel": "match_kernel", "achieved": achieved_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(), "bytes_per_launch": bytes_launch,
+                     "traffic": measured_traffic(sfm.sfm_get_tuning(m.ctx)),
+                     "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": match_s * 1e3,
                      "int8_mfma_frac": 256.0 * comparisons / match_s / 1e12 / INT8_PEAK_TOPS},
         "serving": serve,
