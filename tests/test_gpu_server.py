@@ -141,3 +141,89 @@ def test_server_open_loop(sfm, ring):
     say(f"  {len(res)} requests: p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
     assert all(r["status"] == sfm.SFM_OK for r in res)
     assert np.all(lat > 0)
+
+
+@pytest.mark.parametrize("max_batch_pairs,max_inflight", [(1, 1), (3, 4), (64, 8)])
+def test_server_configurations(sfm, ring, max_batch_pairs, max_inflight):
+    """Batch and slot limits change batching, never results."""
+    images, pairs, Fs = ring
+    m = sfm.Matcher().register(images)
+    ref = m.match(pairs, Fs, form="batched")
+    cap = max(m.n_features(a) for a, _, _ in pairs)
+    sfm.sfm_server_start(m.ctx, max_batch_pairs=max_batch_pairs, max_inflight=max_inflight)
+    try:
+        tickets = [sfm.sfm_server_submit(m.ctx, p, F) for p, F in zip(pairs, Fs)]
+        res = collect(sfm, m.ctx, tickets, cap)
+        stats = sfm.sfm_server_stats(m.ctx)
+    finally:
+        sfm.sfm_server_stop(m.ctx)
+    assert stats["launches"] >= (len(pairs) + max_batch_pairs - 1) // max_batch_pairs
+    for k, r in enumerate(res):
+        q, mt, d1, d2 = ref.pair(k)
+        assert r["status"] == sfm.SFM_OK
+        assert np.array_equal(r["query"], q) and np.array_equal(r["match"], mt)
+        assert np.array_equal(r["d1"], d1) and np.array_equal(r["d2"], d2)
+
+
+def test_server_capacity_and_empty_images(sfm, ring):
+    """A request larger than a slot fails alone with SFM_ECAPACITY; pairs with
+    an empty image succeed with no matches; the rest are unaffected."""
+    images, pairs, Fs = ring
+    empty = (np.zeros((0, 2), np.float32), np.zeros((0, 128), np.uint8))
+    m = sfm.Matcher().register(images + [empty])
+    e = len(images)
+    small = min(m.n_features(a) for a, _, _ in pairs)
+    big = max(range(len(pairs)), key=lambda k: m.n_features(pairs[k][0]))
+    ok = min(range(len(pairs)), key=lambda k: m.n_features(pairs[k][0]))
+    sfm.sfm_server_start(m.ctx, max_batch_pairs=4, max_batch_queries=small)
+    try:
+        t_big = sfm.sfm_server_submit(m.ctx, pairs[big], Fs[big])
+        t_ok = sfm.sfm_server_submit(m.ctx, pairs[ok], Fs[ok])
+        t_e1 = sfm.sfm_server_submit(m.ctx, (e, 0, 4.0), Fs[0])
+        t_e2 = sfm.sfm_server_submit(m.ctx, (0, e, 4.0), Fs[0])
+        r_big = sfm.sfm_server_poll(m.ctx, t_big, small, timeout_ms=60_000)
+        r_ok = sfm.sfm_server_poll(m.ctx, t_ok, small, timeout_ms=60_000)
+        r_e1 = sfm.sfm_server_poll(m.ctx, t_e1, small, timeout_ms=60_000)
+        r_e2 = sfm.sfm_server_poll(m.ctx, t_e2, small, timeout_ms=60_000)
+    finally:
+        sfm.sfm_server_stop(m.ctx)
+    if m.n_features(pairs[big][0]) > small:
+        assert r_big["status"] == sfm.SFM_ECAPACITY
+    assert r_ok["status"] == sfm.SFM_OK
+    q, mt, _, _ = m.match([pairs[ok]], Fs[ok:ok + 1], form="batched").pair(0)
+    assert np.array_equal(r_ok["query"], q) and np.array_equal(r_ok["match"], mt)
+    for r in (r_e1, r_e2):
+        assert r["status"] == sfm.SFM_OK and r["query"].size == 0 and r["n_comparisons"] == 0
+
+
+def test_server_concurrent_clients(sfm, ring):
+    """Four client threads submit and collect at once."""
+    import threading
+    images, pairs, Fs = ring
+    m = sfm.Matcher().register(images)
+    ref = m.match(pairs, Fs, form="batched")
+    cap = max(m.n_features(a) for a, _, _ in pairs)
+    errors = []
+    sfm.sfm_server_start(m.ctx, max_batch_pairs=16, max_inflight=2)
+
+    def client(offset):
+        try:
+            for k in range(offset, len(pairs), 4):
+                t = sfm.sfm_server_submit(m.ctx, pairs[k], Fs[k])
+                r = sfm.sfm_server_poll(m.ctx, t, cap, timeout_ms=60_000)
+                q, mt, d1, d2 = ref.pair(k)
+                if not (r["status"] == sfm.SFM_OK and np.array_equal(r["query"], q)
+                        and np.array_equal(r["match"], mt)):
+                    errors.append(k)
+        except Exception as exc:   # surfaced below
+            errors.append(repr(exc))
+
+    threads = [threading.Thread(target=client, args=(i,)) for i in range(4)]
+    try:
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(timeout=120)
+    finally:
+        sfm.sfm_server_stop(m.ctx)
+    assert not errors, errors
