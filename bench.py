@@ -201,6 +201,76 @@ def serving(sfm, rates, duration_s, log_fn):
     return out
 
 
+def stress_serving(sfm, log_fn, n_requests=20_000, burst=2_000):
+    """Stress serving: the 1,000-camera scene (8k-40k features per image,
+    descriptors resident), 20,000 covisible-pair requests with bands drawn from
+    2-8 px, released in bursts of 2,000, each burst once the server has
+    admitted the previous one.  The same requests then run in the plain form
+    (one pair per launch) for the served-vs-plain ratio."""
+    import scenes
+    t = time.time()
+    log_fn("bench: stress scene (1,000 cameras, 8k-40k features)")
+    sc = scenes.make_config_c5()
+    scenes.materialize(sc, workers=16,
+                       progress=lambda k, n: log_fn(f"bench:   {k}/{n} images ({time.time() - t:.0f} s)"))
+    reqs = scenes.stress_requests(sc, n_requests)
+    Fs = np.stack([sc.F(a, b) for a, b, _ in reqs])
+    images = [(sc.image(k).xy, sc.image(k).desc) for k in range(sc.n_images)]
+    m = sfm.Matcher(device=0).register(images)
+    cap = max(m.n_features(a) for a, _, _ in reqs)
+    bursts = [(s, min(s + burst, len(reqs))) for s in range(0, len(reqs), burst)]
+    sfm.sfm_server_start(m.ctx, max_batch_pairs=256, max_inflight=2)
+    try:
+        for tk in sfm.sfm_server_submit_batch(m.ctx, reqs[:256], Fs[:256]):   # warm-up
+            sfm.sfm_server_poll(m.ctx, int(tk), cap)
+        s0 = sfm.sfm_server_stats(m.ctx)
+        log_fn(f"bench: serving {len(reqs)} requests in {len(bursts)} bursts")
+        tickets = []
+        for s, e in bursts:
+            tickets += [int(x) for x in sfm.sfm_server_submit_batch(m.ctx, reqs[s:e], Fs[s:e])]
+            while sfm.sfm_server_stats(m.ctx)["launched"] - s0["launched"] < len(tickets):
+                time.sleep(0.0002)
+        res = [sfm.sfm_server_poll(m.ctx, tk, cap, timeout_ms=120_000) for tk in tickets]
+        s1 = sfm.sfm_server_stats(m.ctx)
+    finally:
+        sfm.sfm_server_stop(m.ctx)
+    assert all(r is not None and r["status"] == sfm.SFM_OK for r in res)
+    t0 = min(r["arrival_ns"] for r in res)
+    span = (max(r["done_ns"] for r in res) - t0) / 1e9
+    lat = np.array([(r["done_ns"] - r["arrival_ns"]) / 1e6 for r in res])
+    cmp_total = sum(r["n_comparisons"] for r in res)
+    served = cmp_total / span
+    log_fn("bench: the same requests in the plain form")
+    stream = torch_stream()
+    opt = sfm.options()
+    plain_s = 0.0
+    for s, e in bursts:
+        b = sfm.PairBatch(reqs[s:e], Fs[s:e])
+        o = m.buffers(reqs[s:e])
+        plain_s += timed(lambda: sfm.sfm_guided_match_plain(m.ctx, b, None, o, opt, stream), 1,
+                         stream)
+        assert int(o.n_comparisons[:e - s].sum()) == sum(r["n_comparisons"] for r in res[s:e])
+        del o
+    m.close()
+    nbytes = algorithmic_bytes(images, reqs)
+    return {"workload": "20,000 covisible-pair requests in 10 bursts of 2,000, 1,000 cameras on "
+                        "10 rings, 8k-40k features per image, band 2-8 px per request",
+            "images": len(images), "requests": len(res), "comparisons": int(cmp_total),
+            "wall_ms": round(span * 1e3, 3), "comparisons_per_s": served,
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "launches": int(s1["launches"] - s0["launches"]),
+            "algorithmic_gb_per_s": nbytes / span / 1e9,
+            "hbm_frac": nbytes / span / 1e9 / HBM_PEAK_GBS,
+            "plain_ms": round(plain_s * 1e3, 3), "plain_comparisons_per_s": cmp_total / plain_s,
+            "speedup_served_vs_plain": plain_s / span}
+
+
+def torch_stream():
+    import torch
+    return torch.cuda.current_stream(torch.device("cuda", 0))
+
+
 def timed(fn, steps, stream):
     import torch
     torch.cuda.synchronize()
@@ -239,6 +309,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the 20,000-request stress-serving run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tuning (2 tiles per group, 8 features per bin)")
     ap.add_argument("--tuning", default=None, metavar="TILESxFEATURES",
@@ -366,6 +438,10 @@ def main():
         serve = serving(sfm, [float(r) for r in args.serving_rates.split(",")],
                         args.serving_seconds, log)
 
+    stress = None
+    if not args.no_stress:
+        stress = stress_serving(sfm, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
@@ -395,6 +471,7 @@ def main():
                      "avg_launch_ms": match_s * 1e3,
                      "int8_mfma_frac": 256.0 * comparisons / match_s / 1e12 / INT8_PEAK_TOPS},
         "serving": serve,
+        "stress_serving": stress,
         "context_bruteforce": context,
         "cpu_baseline": cpu,
     }

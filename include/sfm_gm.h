@@ -216,6 +216,16 @@ int sfm_server_start(sfm_ctx* ctx, const sfm_server_cfg* cfg);
 int sfm_server_submit(sfm_ctx* ctx, const sfm_pair* pair, const double* F, int64_t arrival_ns,
                       uint64_t* ticket);
 
+/* Submit n requests at once (a burst that the visibility filter emits
+ * together): pairs[0..n) with F (host, n * 9 doubles, as in
+ * sfm_guided_match), all arriving at arrival_ns (<= 0: now).  Every request
+ * is checked first; if any is invalid nothing is queued and SFM_EINVAL is
+ * returned.  Otherwise all n enter the queue together, in order, and
+ * tickets[k] (host, n entries, caller-owned) identifies pairs[k].  n = 0 is a
+ * no-op. */
+int sfm_server_submit_batch(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n, const double* F,
+                            int64_t arrival_ns, uint64_t* tickets);
+
 /* Collect a request's result into *out, waiting up to timeout_ms
  * (0: do not wait, < 0: wait for ever).  SFM_ETIMEOUT: not ready yet;
  * SFM_ENOTFOUND: unknown or already collected ticket; SFM_ECAPACITY: out

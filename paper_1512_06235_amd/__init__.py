@@ -97,6 +97,7 @@ def lib() -> C.CDLL:
         "sfm_last_error": [vp, C.c_char_p, sz],
         "sfm_server_start": [vp, C.POINTER(sfm_server_cfg)],
         "sfm_server_submit": [vp, C.POINTER(sfm_pair), vp, i64, C.POINTER(C.c_uint64)],
+        "sfm_server_submit_batch": [vp, C.POINTER(sfm_pair), i32, vp, i64, vp],
         "sfm_server_poll": [vp, C.c_uint64, C.POINTER(sfm_result_view), i32],
         "sfm_server_stats": [vp, C.POINTER(i64)],
         "sfm_server_stop": [vp],
@@ -123,7 +124,7 @@ def exported_symbols():
             "sfm_guided_match", "sfm_guided_match_plain", "sfm_bruteforce_match", "sfm_sync",
             "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
-            "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
+            "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
             "sfm_get_tuning", "sfm_autotune"]
 
 
@@ -271,6 +272,19 @@ def sfm_server_submit(ctx, pair, F, arrival_ns: int = 0) -> int:
     return t.value
 
 
+def sfm_server_submit_batch(ctx, pairs, F=None, arrival_ns: int = 0) -> np.ndarray:
+    """Submit a burst of requests at once; returns their tickets (uint64[n]).
+    `pairs` may be a PairBatch holding its F."""
+    b = pairs if isinstance(pairs, PairBatch) else PairBatch(pairs, F)
+    Fh = b.F if F is None else np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(-1, 9))
+    if Fh is None or Fh.shape[0] != b.n:
+        raise ValueError("one F per pair is required")
+    tickets = np.zeros(max(1, b.n), dtype=np.uint64)
+    _check(ctx, lib().sfm_server_submit_batch(ctx, b.c_pairs, b.n, Fh.ctypes.data,
+                                              int(arrival_ns), tickets.ctypes.data))
+    return tickets[:b.n]
+
+
 def sfm_server_poll(ctx, ticket: int, capacity: int, timeout_ms: int = -1):
     """The request's result as a dict with host arrays, or None on SFM_ETIMEOUT."""
     bufs = [np.empty(max(1, int(capacity)), dtype=np.int32) for _ in range(4)]
@@ -280,8 +294,10 @@ def sfm_server_poll(ctx, ticket: int, capacity: int, timeout_ms: int = -1):
         return None
     _check(ctx, st)
     n = int(v.n_matches)
-    return {"status": int(v.status), "query": bufs[0][:n], "match": bufs[1][:n],
-            "d1": bufs[2][:n], "d2": bufs[3][:n], "n_comparisons": int(v.n_comparisons),
+    # Copies of the filled rows, so a held result does not pin `capacity` rows.
+    return {"status": int(v.status), "query": bufs[0][:n].copy(), "match": bufs[1][:n].copy(),
+            "d1": bufs[2][:n].copy(), "d2": bufs[3][:n].copy(),
+            "n_comparisons": int(v.n_comparisons),
             "arrival_ns": int(v.arrival_ns), "done_ns": int(v.done_ns)}
 
 

@@ -360,30 +360,41 @@ int sfm_server_start(sfm_ctx* ctx, const sfm_server_cfg* cfg_in) {
 
 int sfm_server_submit(sfm_ctx* ctx, const sfm_pair* pair, const double* F, int64_t arrival_ns,
                       uint64_t* ticket) {
-  if (!ctx || !pair || !F || !ticket) return SFM_EINVAL;
+  return sfm_server_submit_batch(ctx, pair, 1, F, arrival_ns, ticket);
+}
+
+int sfm_server_submit_batch(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n, const double* F,
+                            int64_t arrival_ns, uint64_t* tickets) {
+  if (!ctx || n < 0 || (n > 0 && (!pairs || !F || !tickets))) return SFM_EINVAL;
   Server* S = find_server(ctx);
   if (!S) return SFM_EBUSY;
   const int32_t n_images = ctx_n_images(ctx);
-  if (pair->a < 0 || pair->a >= n_images || pair->b < 0 || pair->b >= n_images ||
-      !(pair->band_px >= 0.0))
-    return SFM_EINVAL;
-  bool nonzero = false;
-  for (int k = 0; k < 9; ++k) {
-    if (!std::isfinite(F[k])) return SFM_EINVAL;
-    nonzero |= F[k] != 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    const sfm_pair& p = pairs[i];
+    if (p.a < 0 || p.a >= n_images || p.b < 0 || p.b >= n_images || !(p.band_px >= 0.0))
+      return SFM_EINVAL;
+    bool nonzero = false;
+    for (int k = 0; k < 9; ++k) {
+      const double f = F[int64_t(i) * 9 + k];
+      if (!std::isfinite(f)) return SFM_EINVAL;
+      nonzero |= f != 0.0;
+    }
+    if (!nonzero) return SFM_EINVAL;
   }
-  if (!nonzero) return SFM_EINVAL;
-  Request r;
-  r.pair = *pair;
-  memcpy(r.F, F, sizeof r.F);
-  r.arrival_ns = arrival_ns > 0 ? arrival_ns : now_ns();
+  const int64_t t = arrival_ns > 0 ? arrival_ns : now_ns();
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->stopping) return SFM_EBUSY;
-  r.ticket = S->next_ticket++;
-  *ticket = r.ticket;
-  S->outstanding.insert(r.ticket);
-  S->queue.push_back(r);
-  S->cv_work.notify_one();
+  for (int32_t i = 0; i < n; ++i) {
+    Request r;
+    r.pair = pairs[i];
+    memcpy(r.F, F + int64_t(i) * 9, sizeof r.F);
+    r.arrival_ns = t;
+    r.ticket = S->next_ticket++;
+    tickets[i] = r.ticket;
+    S->outstanding.insert(r.ticket);
+    S->queue.push_back(r);
+  }
+  if (n > 0) S->cv_work.notify_one();
   return SFM_OK;
 }
 

@@ -10,4 +10,5 @@ from .generator import (  # noqa: F401
     look_at_camera, fundamental_from_poses, make_pair_scene, make_config_c1,
     make_config_c2, make_multiview_scene, make_config_c3, make_config_c4,
     make_config_c5, sample_pairs_by_angle, covisible_pairs, poisson_arrivals,
+    materialize, stress_requests,
 )

@@ -309,6 +309,30 @@ def covisible_pairs(scene: MultiViewScene, min_shared: int = 8, top_k: int = 30)
     return out
 
 
+def materialize(scene: MultiViewScene, workers: int = 8, progress=None) -> None:
+    """Generate every image of a multi-view scene into its cache with a
+    thread pool.  Each image draws from its own seeded generator, so the
+    bytes do not depend on the order or the number of workers."""
+    from concurrent.futures import ThreadPoolExecutor
+    todo = [i for i in range(scene.n_images) if i not in scene._cache]
+    with ThreadPoolExecutor(max(1, int(workers))) as ex:
+        for k, _ in enumerate(ex.map(scene.image, todo)):
+            if progress is not None and (k + 1) % 200 == 0:
+                progress(k + 1, len(todo))
+
+
+def stress_requests(scene: MultiViewScene, n_requests: int = 20_000, band_lo: float = 2.0,
+                    band_hi: float = 8.0, seed: int = 1):
+    """Stress-serving requests: n_requests distinct covisible pairs (top 30
+    per image, >= 8 shared points) in a seeded random order, each with its own
+    band half-width drawn uniformly from [band_lo, band_hi] px."""
+    pool = covisible_pairs(scene)
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(pool), size=min(n_requests, len(pool)), replace=False)
+    bands = rng.uniform(band_lo, band_hi, size=pick.shape[0])
+    return [(pool[k][0], pool[k][1], float(d)) for k, d in zip(pick, bands)]
+
+
 def poisson_arrivals(rate_per_s: float, duration_s: float, seed: int = 0) -> np.ndarray:
     """Arrival times (s) of an open-loop Poisson stream."""
     rng = np.random.default_rng(seed)

@@ -96,6 +96,14 @@ def test_server_errors(sfm, ring):
         with pytest.raises(sfm.SfmError) as e:
             sfm.sfm_server_poll(m.ctx, 10**9, 16, timeout_ms=0)
         assert e.value.status == sfm.SFM_ENOTFOUND
+        # A burst with one bad request queues nothing; an empty burst is a no-op.
+        before = sfm.sfm_server_stats(m.ctx)
+        with pytest.raises(sfm.SfmError) as e:
+            sfm.sfm_server_submit_batch(m.ctx, [pairs[0], (0, 1, -2.0), pairs[1]], Fs[:3])
+        assert e.value.status == sfm.SFM_EINVAL
+        assert sfm.sfm_server_submit_batch(m.ctx, [], np.zeros((0, 9))).size == 0
+        after = sfm.sfm_server_stats(m.ctx)
+        assert after["launched"] + after["waiting"] == before["launched"] + before["waiting"]
         t = sfm.sfm_server_submit(m.ctx, pairs[0], Fs[0])
         # Too small a buffer: reported, and the result stays collectable.
         with pytest.raises(sfm.SfmError) as e:
@@ -194,6 +202,28 @@ def test_server_capacity_and_empty_images(sfm, ring):
     assert np.array_equal(r_ok["query"], q) and np.array_equal(r_ok["match"], mt)
     for r in (r_e1, r_e2):
         assert r["status"] == sfm.SFM_OK and r["query"].size == 0 and r["n_comparisons"] == 0
+
+
+def test_server_burst_submit(sfm, ring):
+    """A burst submitted in one call: consecutive tickets, one arrival time,
+    results equal the batched form."""
+    images, pairs, Fs = ring
+    m = sfm.Matcher().register(images)
+    ref = m.match(pairs, Fs, form="batched")
+    cap = max(m.n_features(a) for a, _, _ in pairs)
+    sfm.sfm_server_start(m.ctx, max_batch_pairs=7, max_inflight=3)
+    try:
+        tickets = sfm.sfm_server_submit_batch(m.ctx, pairs, Fs)
+        res = collect(sfm, m.ctx, [int(t) for t in tickets], cap)
+    finally:
+        sfm.sfm_server_stop(m.ctx)
+    assert np.array_equal(np.diff(tickets.astype(np.int64)), np.ones(len(pairs) - 1))
+    assert len({r["arrival_ns"] for r in res}) == 1
+    for k, r in enumerate(res):
+        q, mt, d1, d2 = ref.pair(k)
+        assert r["status"] == sfm.SFM_OK
+        assert np.array_equal(r["query"], q) and np.array_equal(r["match"], mt)
+        assert np.array_equal(r["d1"], d1) and np.array_equal(r["d2"], d2)
 
 
 def test_server_concurrent_clients(sfm, ring):
