@@ -45,10 +45,16 @@ struct Request {
 
 struct Result {
   int32_t status = SFM_OK;
-  std::vector<int32_t> query, match, d1, d2;
+  int64_t n = 0;                   // accepted rows
+  std::vector<int32_t> rows;       // query[n] | match[n] | d1[n] | d2[n]
   int64_t n_comparisons = 0;
   int64_t arrival_ns = 0, done_ns = 0;
 };
+
+// Launches with at least this many accepted rows copy them into the
+// requests' results on several threads.
+constexpr int64_t kParallelCopyRows = int64_t(1) << 18;
+constexpr int kCopyThreads = 4;
 
 // Device outputs of one launch and their pinned host mirrors.
 struct Slot {
@@ -213,10 +219,37 @@ void worker_main(Server* Sp) {
   }
 }
 
-// Waits for launches in order, copies their rows and hands out results.
+// Results [k0, k1) of one launch from the host mirrors of its rows.
+void fill_results(const Slot& s, const std::vector<Request>& reqs, const std::vector<int64_t>& off,
+                  const std::vector<int64_t>& ncmp, int64_t t, size_t k0, size_t k1,
+                  std::vector<Result>& out) {
+  for (size_t k = k0; k < k1; ++k) {
+    Result& res = out[k];
+    const int64_t b = off[k], n = off[k + 1] - off[k];
+    res.status = SFM_OK;
+    res.n = n;
+    res.rows.resize(size_t(4 * n));
+    int32_t* dst = res.rows.data();
+    memcpy(dst, s.hq + b, size_t(n) * sizeof(int32_t));
+    memcpy(dst + n, s.hm + b, size_t(n) * sizeof(int32_t));
+    memcpy(dst + 2 * n, s.hd1 + b, size_t(n) * sizeof(int32_t));
+    memcpy(dst + 3 * n, s.hd2 + b, size_t(n) * sizeof(int32_t));
+    res.n_comparisons = ncmp[k];
+    res.arrival_ns = reqs[k].arrival_ns;
+    res.done_ns = t;
+  }
+}
+
+// Waits for launches in order and hands out their results.  Once a launch's
+// rows are in the slot's host mirrors, the slot's device buffers go back to
+// the worker (its offsets and counts were copied out first), so the next
+// launch runs while this thread copies the rows into the requests' results,
+// outside the lock and on several threads for large launches.  The mirrors
+// are rewritten only by this thread's own copy of a later launch.
 void completer_main(Server* Sp) {
   Server& S = *Sp;
   (void)hipSetDevice(S.device);
+  std::vector<int64_t> off, ncmp;
   for (;;) {
     int slot_id;
     {
@@ -227,12 +260,12 @@ void completer_main(Server* Sp) {
     }
     Slot& s = S.slots[size_t(slot_id)];
     int32_t rc = s.status;
-    int64_t total = 0;
+    const size_t n = s.reqs.size();
+    if (rc == SFM_OK && hipEventSynchronize(s.meta) != hipSuccess) rc = SFM_EHIP;
     if (rc == SFM_OK) {
-      if (hipEventSynchronize(s.meta) != hipSuccess) rc = SFM_EHIP;
-    }
-    if (rc == SFM_OK) {
-      total = s.hoffset[s.reqs.size()];
+      off.assign(s.hoffset, s.hoffset + n + 1);
+      ncmp.assign(s.hncmp, s.hncmp + n);
+      const int64_t total = off[n];
       if (total > 0) {
         const size_t b = size_t(total) * sizeof(int32_t);
         if (hipMemcpyAsync(s.hq, s.q, b, hipMemcpyDeviceToHost, S.copy) != hipSuccess ||
@@ -245,28 +278,37 @@ void completer_main(Server* Sp) {
       }
     }
     const int64_t t = now_ns();
-    std::lock_guard<std::mutex> lk(S.mu);
-    if (rc != SFM_OK) {
-      fail_batch(S, s.reqs, rc);
-    } else {
-      for (size_t k = 0; k < s.reqs.size(); ++k) {
-        const Request& r = s.reqs[k];
-        Result& res = S.results[r.ticket];
-        const int64_t b = s.hoffset[k], e = s.hoffset[k + 1];
-        res.status = SFM_OK;
-        res.query.assign(s.hq + b, s.hq + e);
-        res.match.assign(s.hm + b, s.hm + e);
-        res.d1.assign(s.hd1 + b, s.hd1 + e);
-        res.d2.assign(s.hd2 + b, s.hd2 + e);
-        res.n_comparisons = s.hncmp[k];
-        res.arrival_ns = r.arrival_ns;
-        res.done_ns = t;
-      }
-      s.reqs.clear();
+    std::vector<Request> reqs = std::move(s.reqs);
+    s.reqs.clear();
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      S.inflight.pop_front();
+      S.free_slots.push_back(slot_id);
+      if (rc != SFM_OK) fail_batch(S, reqs, rc);
+      S.cv_work.notify_all();
+      S.cv_done.notify_all();
     }
-    S.inflight.pop_front();
-    S.free_slots.push_back(slot_id);
-    S.cv_work.notify_all();
+    if (rc != SFM_OK) continue;
+    std::vector<Result> out(n);
+    if (off[n] < kParallelCopyRows || n < 2) {
+      fill_results(s, reqs, off, ncmp, t, 0, n, out);
+    } else {
+      // Contiguous runs of requests with about equal rows per thread.
+      std::vector<size_t> cut(kCopyThreads + 1, n);
+      cut[0] = 0;
+      for (int i = 1; i < kCopyThreads; ++i)
+        cut[i] = size_t(std::lower_bound(off.begin(), off.end(), off[n] * i / kCopyThreads) -
+                        off.begin());
+      for (int i = 1; i <= kCopyThreads; ++i) cut[i] = std::max(std::min(cut[i], n), cut[i - 1]);
+      std::vector<std::thread> helpers;
+      for (int i = 1; i < kCopyThreads; ++i)
+        helpers.emplace_back(fill_results, std::cref(s), std::cref(reqs), std::cref(off),
+                             std::cref(ncmp), t, cut[i], cut[i + 1], std::ref(out));
+      fill_results(s, reqs, off, ncmp, t, cut[0], cut[1], out);
+      for (std::thread& h : helpers) h.join();
+    }
+    std::lock_guard<std::mutex> lk(S.mu);
+    for (size_t k = 0; k < n; ++k) S.results[reqs[k].ticket] = std::move(out[k]);
     S.cv_done.notify_all();
   }
 }
@@ -414,7 +456,7 @@ int sfm_server_poll(sfm_ctx* ctx, uint64_t ticket, sfm_result_view* out, int32_t
     }
   }
   Result& res = S->results[ticket];
-  const int64_t n = int64_t(res.query.size());
+  const int64_t n = res.n;
   out->status = res.status;
   out->n_matches = n;
   out->n_comparisons = res.n_comparisons;
@@ -423,10 +465,11 @@ int sfm_server_poll(sfm_ctx* ctx, uint64_t ticket, sfm_result_view* out, int32_t
   if (res.status == SFM_OK && n > 0) {
     if (out->capacity < n || !out->query || !out->match || !out->d1 || !out->d2)
       return SFM_ECAPACITY;   // the result stays collectable with a larger buffer
-    memcpy(out->query, res.query.data(), size_t(n) * sizeof(int32_t));
-    memcpy(out->match, res.match.data(), size_t(n) * sizeof(int32_t));
-    memcpy(out->d1, res.d1.data(), size_t(n) * sizeof(int32_t));
-    memcpy(out->d2, res.d2.data(), size_t(n) * sizeof(int32_t));
+    const int32_t* r = res.rows.data();
+    memcpy(out->query, r, size_t(n) * sizeof(int32_t));
+    memcpy(out->match, r + n, size_t(n) * sizeof(int32_t));
+    memcpy(out->d1, r + 2 * n, size_t(n) * sizeof(int32_t));
+    memcpy(out->d2, r + 3 * n, size_t(n) * sizeof(int32_t));
   }
   S->results.erase(ticket);
   S->outstanding.erase(ticket);

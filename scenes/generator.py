@@ -21,6 +21,7 @@ This is input preparation: the matcher receives F and never builds it.
 """
 from __future__ import annotations
 
+import threading
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -31,6 +32,10 @@ FOCAL = 1000.0
 PRINCIPAL = (512.0, 384.0)
 DESC_DIM = 128
 
+# numpy's BLAS gives wrong results when several threads call it at once, so
+# the matrix products that image generation makes run one at a time.
+_BLAS_LOCK = threading.Lock()
+
 
 @dataclass
 class Camera:
@@ -40,7 +45,8 @@ class Camera:
 
     @property
     def center(self) -> np.ndarray:
-        return -self.R.T @ self.t
+        with _BLAS_LOCK:
+            return -self.R.T @ self.t
 
 
 @dataclass
@@ -74,8 +80,9 @@ def look_at_camera(center, target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0)) -> Camera
 
 def project(cam: Camera, X: np.ndarray):
     """Pixel coordinates and camera depth of world points X (n, 3)."""
-    Xc = X @ cam.R.T + cam.t
-    uvw = Xc @ cam.K.T
+    with _BLAS_LOCK:
+        Xc = X @ cam.R.T + cam.t
+        uvw = Xc @ cam.K.T
     with np.errstate(divide="ignore", invalid="ignore"):
         xy = uvw[:, :2] / uvw[:, 2:3]
     return xy, Xc[:, 2]
