@@ -89,6 +89,29 @@ def test_c3_sample_batched_vs_plain(sfm, oracle_lib):
         assert np.array_equal(a[:n].numpy(), b[:n].numpy()), k
 
 
+def test_c3_full_batch_as_benchmarked(sfm, oracle_lib):
+    """The whole 500-pair batch in the launch configuration bench.py times
+    (one batched call on a PairBatch, default tuning, no per-query outputs):
+    every pair against the oracle."""
+    import bench
+    import torch
+    images, pairs, Fs, _ = bench.c3_workload()
+    m = sfm.Matcher().register(images)
+    out = m.buffers(pairs)
+    batch = sfm.PairBatch(pairs, Fs)
+    st = torch.cuda.current_stream()
+    sfm.sfm_guided_match(m.ctx, batch, None, out, sfm.options(), st)
+    sfm.sfm_sync(m.ctx, st)
+    say(f"  500-pair batch: {int(out.offset[-1])} matches, tuning {sfm.sfm_get_tuning(m.ctx)}")
+    ores = oracle_lib.match(images, pairs, Fs)
+    clean, bl = compare_all(out, ores, len(pairs))
+    say(f"  500-pair batch: {clean} queries exact, {bl} borderline")
+    # With ~90 in-band candidates per query, ~4% of queries have one within
+    # 1e-3 px of either band edge; those are excused, all others are exact.
+    assert clean > 0.94 * (clean + bl)
+    m.close()
+
+
 def test_bruteforce_equals_infinite_band(sfm, oracle_lib):
     xy_a, desc_a, xy_b, desc_b, F = random_pair(1500, 1800, seed=21)
     imgs = [(xy_a, desc_a), (xy_b, desc_b)]

@@ -6,7 +6,8 @@ request from 2-8 px, so both the sizes and the bands of a launch are uneven.
 
 Every served result must equal the batched form on the same burst (rows and
 comparison counts); a sample equals the pair run alone (plain form), and the
-smallest requests equal the oracle on non-borderline queries."""
+two smallest requests and six random ones equal the oracle on non-borderline
+queries."""
 import time
 
 import numpy as np
@@ -107,9 +108,12 @@ def test_stress_bursts_equal_batched_alone_and_oracle(sfm, oracle_lib, stress):
         assert np.array_equal(r["query"], q) and np.array_equal(r["match"], mt)
         assert np.array_equal(r["d1"], d1) and np.array_equal(r["d2"], d2)
 
-    # The two smallest requests against the oracle (non-borderline queries).
+    # The two smallest requests and six drawn at random against the oracle
+    # (non-borderline queries).
     sizes = [images[a][0].shape[0] * images[b][0].shape[0] for a, b, _ in reqs]
-    for k in np.argsort(sizes)[:2]:
+    picks = list(np.argsort(sizes)[:2]) + list(np.random.default_rng(4).choice(len(reqs), 6,
+                                                                             replace=False))
+    for k in picks:
         a, b, band = reqs[k]
         o = oracle_lib.match([images[a], images[b]], [(0, 1, band)], Fs[k:k + 1]).pair(0)
         clean = o["borderline"] == 0
