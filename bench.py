@@ -399,6 +399,16 @@ def main():
     bytes_launch = algorithmic_bytes(images, pairs)
     achieved_gbs = bytes_launch / match_s / 1e9
 
+    # The same steps with the kernels replayed from a captured HIP graph.
+    sfm.sfm_set_graph_replay(m.ctx, True)
+    step()
+    sfm.sfm_sync(m.ctx, stream)
+    graph_elapsed = timed(step, args.steps, stream)
+    sfm.sfm_sync(m.ctx, stream)
+    sfm.sfm_set_graph_replay(m.ctx, False)
+    assert int(out.n_comparisons[:len(pairs)].sum()) == comparisons
+    assert int(out.offset[-1]) == matches
+
     plain = None
     if args.plain_steps > 0:
         log(f"bench: timing {args.plain_steps} plain per-pair steps")
@@ -462,6 +472,7 @@ def main():
                    "tie_passes": stats["tie_passes"]},
         "tuning": tuning,
         "plain_form": plain,
+        "graph_replay_ms_per_step": graph_elapsed / args.steps * 1e3,
         "phases_ms_per_step": {"prepare": prep_ms / max(1, nrec), "match": match_ms / max(1, nrec),
                                "emit": emit_ms / max(1, nrec)},
         "roofline": {"bound": "hbm", "kernel": "match_kernel", "achieved": achieved_gbs,

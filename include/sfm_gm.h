@@ -252,6 +252,18 @@ int sfm_server_stop(sfm_ctx* ctx);
 int sfm_set_tuning(sfm_ctx* ctx, int32_t group_tiles, int32_t features_per_bin);
 int sfm_get_tuning(sfm_ctx* ctx, int32_t* group_tiles, int32_t* features_per_bin);
 
+/* Graph replay of the batched form (enable != 0; default off).  The kernels
+ * of a call are captured into a HIP graph for its launch layout (pairs,
+ * feature counts, workspace, outputs, options and tuning) and the graph is
+ * replayed by later calls with the same layout; any other layout captures
+ * anew.  The copy of the pairs and F into the workspace stays a stream copy.
+ * Results are identical to stream launches.  Measured on MI355X for the
+ * 500-pair batch, replay and launching the seven kernels on the stream are
+ * within 3% of each other either way, so it is off by default; it serves
+ * callers that replay one batch shape.  Disabling frees the graph.
+ * Profiling (sfm_set_profiling) uses stream launches. */
+int sfm_set_graph_replay(sfm_ctx* ctx, int32_t enable);
+
 /* Time the batched form on the given batch for every group_tiles in
  * {1, 2, 4} and features_per_bin in {4, 8, 16} (one warm-up and `repeats`
  * timed calls each, HIP events on `stream`), keep the fastest setting on the

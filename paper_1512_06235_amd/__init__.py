@@ -102,6 +102,7 @@ def lib() -> C.CDLL:
         "sfm_server_stats": [vp, C.POINTER(i64)],
         "sfm_server_stop": [vp],
         "sfm_set_tuning": [vp, i32, i32],
+        "sfm_set_graph_replay": [vp, i32],
         "sfm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32)],
         "sfm_autotune": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options), vp, i32,
                          C.POINTER(C.c_double)],
@@ -125,7 +126,7 @@ def exported_symbols():
             "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
             "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
-            "sfm_get_tuning", "sfm_autotune"]
+            "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -309,6 +310,10 @@ def sfm_server_stats(ctx) -> dict:
 
 def sfm_server_stop(ctx) -> None:
     _check(ctx, lib().sfm_server_stop(ctx))
+
+
+def sfm_set_graph_replay(ctx, enable: bool) -> None:
+    _check(ctx, lib().sfm_set_graph_replay(ctx, 1 if enable else 0))
 
 
 def sfm_set_tuning(ctx, group_tiles: int, features_per_bin: int) -> None:

@@ -45,6 +45,13 @@ struct sfm_ctx {
   bool profiling = false;
   std::vector<hipEvent_t> prof_events;
   std::vector<hipEvent_t> prof_pool;
+
+  // Graph replay of the batched form (sfm_set_graph_replay): the kernels of
+  // one launch layout captured once and replayed while the layout repeats.
+  bool graph_replay = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::vector<char> graph_key;
 };
 
 namespace {
@@ -187,6 +194,53 @@ int ensure_pinned(sfm_ctx* ctx, size_t bytes) {
 
 enum class Form { kBatched, kPlain, kExhaustive };
 
+// Everything the batched form's kernels take: a graph captured for one Key
+// is valid for every call with the same Key.
+struct GraphKey {
+  BatchView v;
+  sfm_matches out;
+  int32_t n_pairs, sum_groups, wgs, max_na;
+  const int32_t* order;
+};
+
+// Enqueues the batched form's kernels on `st` by replaying the graph of this
+// key, capturing (on a private stream) and instantiating it first when the
+// key differs from the last one.  The staging copy stays outside the graph,
+// so the host may prepare the next call while this one runs.
+int replay_batched(sfm_ctx* ctx, const GraphKey& key, int32_t* am, int32_t* ad1, int32_t* ad2,
+                   int32_t* ac, hipStream_t st) {
+  const char* kb = reinterpret_cast<const char*>(&key);
+  if (!ctx->graph || ctx->graph_key.size() != sizeof key ||
+      memcmp(ctx->graph_key.data(), kb, sizeof key) != 0) {
+    if (ctx->graph) HIP_TRY(ctx, hipGraphExecDestroy(ctx->graph));
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+    if (!ctx->cap_stream)
+      HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = ctx->cap_stream;
+    const BatchView& v = key.v;
+    const sfm_matches& out = key.out;
+    HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const hipError_t e1 = launch_prepare(v, 0, key.n_pairs, 0, key.sum_groups, key.wgs, key.order,
+                                         key.max_na, cs);
+    const hipError_t e2 = launch_match(v, key.sum_groups > 0 ? key.wgs : 0, cs);
+    const hipError_t e3 = launch_emit(v, 0, key.n_pairs, out.offset, out.query, out.match, out.d1,
+                                      out.d2, out.n_comparisons, am, ad1, ad2, ac, cs);
+    hipGraph_t g = nullptr;
+    HIP_TRY(ctx, hipStreamEndCapture(cs, &g));
+    const hipError_t ei = (e1 != hipSuccess)   ? e1
+                          : (e2 != hipSuccess) ? e2
+                          : (e3 != hipSuccess) ? e3
+                                               : hipGraphInstantiate(&ctx->graph, g, nullptr,
+                                                                     nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(ctx, ei);
+    ctx->graph_key.assign(kb, kb + sizeof key);
+  }
+  HIP_TRY(ctx, hipGraphLaunch(ctx->graph, st));
+  return SFM_OK;
+}
+
 // Records an event on `st` when profiling is enabled.
 hipError_t prof_mark(sfm_ctx* ctx, hipStream_t st) {
   if (!ctx->profiling) return hipSuccess;
@@ -279,6 +333,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   HIP_TRY(ctx, hipEventRecord(ctx->staging_done, st));
 
   BatchView v;
+  memset(&v, 0, sizeof v);   // padding too: graph keys compare the bytes
   v.images = ctx->images_dev;
   v.pairs = reinterpret_cast<const PairDesc*>(ctx->ws + L.pairs);
   v.F = reinterpret_cast<const double*>(ctx->ws + L.F);
@@ -319,6 +374,20 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
                                out->n_comparisons, am, ad1, ad2, ac, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
     }
+  } else if (ctx->graph_replay && !ctx->profiling && form == Form::kBatched) {
+    GraphKey key;
+    memset(&key, 0, sizeof key);
+    key.v = v;
+    key.out = *out;
+    key.n_pairs = n_pairs;
+    key.sum_groups = int32_t(L.sum_groups);
+    key.wgs = L.wgs;
+    for (const PairDesc& pp : pd) key.max_na = std::max(key.max_na, pp.na);
+    key.order = reinterpret_cast<const int32_t*>(ctx->ws + L.order);
+    if (!opt.emit_all) {
+      key.out.all_match = key.out.all_d1 = key.out.all_d2 = key.out.all_count = nullptr;
+    }
+    if ((rc = replay_batched(ctx, key, am, ad1, ad2, ac, st))) return rc;
   } else {
     HIP_TRY(ctx, prof_mark(ctx, st));
     int32_t max_na = 0;
@@ -416,6 +485,8 @@ int sfm_destroy(sfm_ctx* ctx) {
   for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
   if (ctx->work_done) (void)hipEventDestroy(ctx->work_done);
+  if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return SFM_OK;
 }
@@ -572,6 +643,19 @@ int sfm_set_tuning(sfm_ctx* ctx, int32_t group_tiles, int32_t features_per_bin) 
     return fail(ctx, SFM_EINVAL, "features_per_bin must be in 1..1024");
   ctx->group_tiles = group_tiles;
   ctx->features_per_bin = features_per_bin;
+  return SFM_OK;
+}
+
+int sfm_set_graph_replay(sfm_ctx* ctx, int32_t enable) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  ctx->graph_replay = enable != 0;
+  if (!ctx->graph_replay && ctx->graph) {
+    if (ctx->has_work) HIP_TRY(ctx, hipEventSynchronize(ctx->work_done));
+    HIP_TRY(ctx, hipGraphExecDestroy(ctx->graph));
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+  }
   return SFM_OK;
 }
 

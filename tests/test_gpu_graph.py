@@ -1,0 +1,109 @@
+"""Graph replay of the batched form (sfm_set_graph_replay) through the C ABI.
+
+The graph of one launch layout is replayed several times, with eager work on
+the same stream and host synchronisations between the replays; before every
+replay the outputs are overwritten with garbage, and after it they must equal
+the stream-launched result exactly.  A second layout in between forces a new
+capture; switching back captures the first again."""
+import numpy as np
+import pytest
+
+import scenes
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("offset", "query", "match", "d1", "d2", "n_comparisons",
+          "all_match", "all_d1", "all_d2", "all_count")
+
+
+@pytest.fixture(scope="module")
+def sfm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1512_06235_amd as sfm
+    sfm.lib()
+    return sfm
+
+
+def _snapshot(out, n_pairs):
+    n = int(out.offset[n_pairs])
+    snap = {}
+    for k in FIELDS:
+        t = getattr(out, k)
+        snap[k] = t[:n].cpu().numpy().copy() if k in ("query", "match", "d1", "d2") \
+            else t.cpu().numpy().copy()
+    return snap
+
+
+def _poison(out):
+    for k in FIELDS:
+        getattr(out, k).fill_(-7)
+
+
+def test_graph_replay_equals_stream_launches(sfm):
+    import torch
+    scene, pairs = scenes.make_config_c3()
+    used = sorted({a for a, _, _ in pairs[:60]} | {b for _, b, _ in pairs[:60]})
+    remap = {k: i for i, k in enumerate(used)}
+    m = sfm.Matcher().register([(scene.image(k).xy, scene.image(k).desc) for k in used])
+    sp = [(remap[a], remap[b], band) for a, b, band in pairs[:60]]
+    Fs = np.stack([scene.F(a, b) for a, b, _ in pairs[:60]])
+    A = sfm.PairBatch(sp[:40], Fs[:40])
+    B = sfm.PairBatch(sp[40:], Fs[40:])
+    st = torch.cuda.current_stream()
+    opt = sfm.options(emit_all=True)
+    outA, outB = m.buffers(sp[:40], emit_all=True), m.buffers(sp[40:], emit_all=True)
+
+    sfm.sfm_guided_match(m.ctx, A, None, outA, opt, st)
+    sfm.sfm_sync(m.ctx, st)
+    refA = _snapshot(outA, 40)
+    sfm.sfm_guided_match(m.ctx, B, None, outB, opt, st)
+    sfm.sfm_sync(m.ctx, st)
+    refB = _snapshot(outB, 20)
+    assert int(outA.offset[40]) > 0 and int(outB.offset[20]) > 0
+
+    def check(out, n, ref, what):
+        got = _snapshot(out, n)
+        for k in FIELDS:
+            assert np.array_equal(got[k], ref[k]), f"{what}: {k} differs"
+
+    sfm.sfm_set_graph_replay(m.ctx, True)
+    x = torch.randn(1 << 20, device="cuda")
+    for rep in range(4):
+        _poison(outA)
+        sfm.sfm_guided_match(m.ctx, A, None, outA, opt, st)
+        y = (x * 2.0 + 1.0).sum()          # eager work after the replay, same stream
+        sfm.sfm_sync(m.ctx, st)
+        assert torch.isfinite(y).item()
+        check(outA, 40, refA, f"replay {rep}")
+    _poison(outB)
+    sfm.sfm_guided_match(m.ctx, B, None, outB, opt, st)   # another layout: new capture
+    sfm.sfm_sync(m.ctx, st)
+    check(outB, 20, refB, "second layout")
+    for rep in range(2):
+        _poison(outA)
+        sfm.sfm_guided_match(m.ctx, A, None, outA, opt, st)
+        sfm.sfm_sync(m.ctx, st)
+        check(outA, 40, refA, f"first layout again, replay {rep}")
+    # Without per-query outputs (the benchmark's configuration).
+    fast = sfm.options()
+    outC = m.buffers(sp[:40])
+    sfm.sfm_set_graph_replay(m.ctx, False)
+    sfm.sfm_guided_match(m.ctx, A, None, outC, fast, st)
+    sfm.sfm_sync(m.ctx, st)
+    n = int(outC.offset[40])
+    ref = [t[:n].cpu().numpy().copy() for t in (outC.query, outC.match, outC.d1, outC.d2)]
+    sfm.sfm_set_graph_replay(m.ctx, True)
+    for rep in range(3):
+        for t in (outC.query, outC.match, outC.d1, outC.d2, outC.offset):
+            t.fill_(-7)
+        sfm.sfm_guided_match(m.ctx, A, None, outC, fast, st)
+        sfm.sfm_sync(m.ctx, st)
+        assert int(outC.offset[40]) == n
+        got = [t[:n].cpu().numpy() for t in (outC.query, outC.match, outC.d1, outC.d2)]
+        assert all(np.array_equal(a, b) for a, b in zip(got, ref)), f"fast form, replay {rep}"
+    sfm.sfm_set_graph_replay(m.ctx, False)
+    say(f"  graph replays equal stream launches ({n} matches)")
+    m.close()
