@@ -32,13 +32,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def c3_workload():
+def arc_batch_workload():
     import scenes
-    scene, pairs = scenes.make_config_c3()
+    scene, pairs = scenes.make_arc_batch()
     used = sorted({a for a, _, _ in pairs} | {b for _, b, _ in pairs})
     images = [(scene.image(k).xy, scene.image(k).desc) for k in range(scene.n_images)]
     Fs = np.stack([scene.F(a, b) for a, b, _ in pairs])
     return images, pairs, Fs, len(used)
+
+
+def unique_bytes(images, pairs):
+    """The same bytes with every image counted once, however many pairs use
+    it: the floor if the pairs of one image shared its reads."""
+    used = {a for a, _, _ in pairs} | {b for _, b, _ in pairs}
+    return sum(136 * images[k][0].shape[0] for k in used)
 
 
 def algorithmic_bytes(images, pairs):
@@ -151,7 +158,7 @@ def serving(sfm, rates, duration_s, log_fn):
     sfm_server_*.  Latency: scheduled arrival to rows in pinned host memory."""
     import scenes
     log_fn("bench: serving scene (300 cameras, 4k-25k features)")
-    sc = scenes.make_config_c4()
+    sc = scenes.make_three_rings()
     images = [(sc.image(k).xy, sc.image(k).desc) for k in range(sc.n_images)]
     pairs = [(a, b, 4.0) for a, b in scenes.covisible_pairs(sc)]
     Fs = np.stack([sc.F(a, b) for a, b, _ in pairs])
@@ -210,7 +217,7 @@ def stress_serving(sfm, log_fn, n_requests=20_000, burst=2_000):
     import scenes
     t = time.time()
     log_fn("bench: stress scene (1,000 cameras, 8k-40k features)")
-    sc = scenes.make_config_c5()
+    sc = scenes.make_ten_rings()
     scenes.materialize(sc, workers=16,
                        progress=lambda k, n: log_fn(f"bench:   {k}/{n} images ({time.time() - t:.0f} s)"))
     reqs = scenes.stress_requests(sc, n_requests)
@@ -357,7 +364,7 @@ def main():
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
     log("bench: generating the 500-pair arc-scene batch")
-    images, pairs, Fs, n_used = c3_workload()
+    images, pairs, Fs, n_used = arc_batch_workload()
     m = sfm.Matcher(device=0).register(images)
     out = m.buffers(pairs)
     opt = sfm.options()
@@ -426,7 +433,7 @@ def main():
     if not args.no_context:
         import scenes
         log("bench: 16k-feature pair, guided vs exhaustive")
-        s2 = scenes.make_config_c2()
+        s2 = scenes.make_two_view_16k()
         m2 = sfm.Matcher(device=0).register([(im.xy, im.desc) for im in s2.images])
         o2 = m2.buffers(s2.pairs)
         g2 = lambda: sfm.sfm_guided_match(m2.ctx, s2.pairs, [s2.F], o2, opt, stream)  # noqa
@@ -480,7 +487,9 @@ def main():
                      "traffic": measured_traffic(sfm.sfm_get_tuning(m.ctx)),
                      "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": match_s * 1e3,
-                     "int8_mfma_frac": 256.0 * comparisons / match_s / 1e12 / INT8_PEAK_TOPS},
+                     "int8_mfma_frac": 256.0 * comparisons / match_s / 1e12 / INT8_PEAK_TOPS,
+                     "unique_bytes_per_launch": unique_bytes(images, pairs),
+                     "unique_frac": unique_bytes(images, pairs) / match_s / 1e9 / HBM_PEAK_GBS},
         "serving": serve,
         "stress_serving": stress,
         "context_bruteforce": context,

@@ -7,8 +7,8 @@ same bytes from it.
 """
 from .generator import (  # noqa: F401
     IMG_W, IMG_H, FOCAL, Camera, Image, PairScene, MultiViewScene,
-    look_at_camera, fundamental_from_poses, make_pair_scene, make_config_c1,
-    make_config_c2, make_multiview_scene, make_config_c3, make_config_c4,
-    make_config_c5, sample_pairs_by_angle, covisible_pairs, poisson_arrivals,
+    look_at_camera, fundamental_from_poses, make_pair_scene, make_two_view_2k,
+    make_two_view_16k, make_multiview_scene, make_arc_batch, make_three_rings,
+    make_ten_rings, sample_pairs_by_angle, covisible_pairs, poisson_arrivals,
     materialize, stress_requests,
 )

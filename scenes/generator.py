@@ -178,12 +178,12 @@ def make_pair_scene(n_points: int, n_features: int, sep_deg: float = 15.0,
                      band_px)
 
 
-def make_config_c1(seed: int = 0) -> PairScene:
+def make_two_view_2k(seed: int = 0) -> PairScene:
     """One pair: 1,500 points, 2 cameras 15 deg apart, 2,000 features each."""
     return make_pair_scene(1500, 2000, seed=seed)
 
 
-def make_config_c2(seed: int = 0) -> PairScene:
+def make_two_view_16k(seed: int = 0) -> PairScene:
     """One large pair: 16,000 features per image, about 40% true (6,400 points)."""
     return make_pair_scene(6400, 16000, seed=seed)
 
@@ -256,7 +256,7 @@ def _ring(n: int, radius: float, elev_deg: float, az0: float = 0.0, span: float 
             for a in az]
 
 
-def make_config_c3(seed: int = 0):
+def make_arc_batch(seed: int = 0):
     """60 cameras on a 180 deg arc (radius 20), 2k-20k features, 500 pairs 5-30 deg apart."""
     centers = _ring(60, 20.0, 0.0, az0=-90.0, span=180.0, endpoint=True)
     scene = make_multiview_scene(centers, 2000, 20000, seed=seed)
@@ -265,7 +265,7 @@ def make_config_c3(seed: int = 0):
     return scene, [(a, b, 4.0) for a, b in pairs]
 
 
-def make_config_c4(seed: int = 0):
+def make_three_rings(seed: int = 0):
     """300 cameras on 3 rings x 100 (elevations -15/0/+15), 4k-25k features."""
     centers = []
     for el in (-15.0, 0.0, 15.0):
@@ -273,7 +273,7 @@ def make_config_c4(seed: int = 0):
     return make_multiview_scene(centers, 4000, 25000, seed=seed)
 
 
-def make_config_c5(seed: int = 0):
+def make_ten_rings(seed: int = 0):
     """1,000 cameras on 10 rings x 100 (elevations -30..+30, radii 18-26), 8k-40k features."""
     centers = []
     for el, r in zip(np.linspace(-30.0, 30.0, 10), np.linspace(18.0, 26.0, 10)):

@@ -51,7 +51,7 @@ def random_pair(n_a, n_b, seed, F=None, spread=1.0):
     desc_a = np.clip(rng.normal(64, 30 * spread, (n_a, 128)), 0, 127).astype(np.uint8)
     desc_b = np.clip(rng.normal(64, 30 * spread, (n_b, 128)), 0, 127).astype(np.uint8)
     if F is None:
-        F = scenes.make_config_c1().F
+        F = scenes.make_two_view_2k().F
     return xy_a, desc_a, xy_b, desc_b, np.asarray(F, np.float64)
 
 

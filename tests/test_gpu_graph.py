@@ -44,7 +44,7 @@ def _poison(out):
 
 def test_graph_replay_equals_stream_launches(sfm):
     import torch
-    scene, pairs = scenes.make_config_c3()
+    scene, pairs = scenes.make_arc_batch()
     used = sorted({a for a, _, _ in pairs[:60]} | {b for _, b, _ in pairs[:60]})
     remap = {k: i for i, k in enumerate(used)}
     m = sfm.Matcher().register([(scene.image(k).xy, scene.image(k).desc) for k in used])

@@ -40,33 +40,33 @@ def test_hand_fixture_gpu(sfm):
 
 
 @pytest.mark.parametrize("form", ["batched", "plain"])
-def test_c1_parity(sfm, oracle_lib, form):
-    s = scenes.make_config_c1()
+def test_two_view_2k_parity(sfm, oracle_lib, form):
+    s = scenes.make_two_view_2k()
     imgs = [(im.xy, im.desc) for im in s.images]
     _, out, ores = run_both(sfm, oracle_lib, imgs, s.pairs, [s.F], form)
     clean, bl = compare_all(out, ores, 1)
-    say(f"  C1 {form}: {clean} queries exact, {bl} borderline, comparisons {int(ores.n_comparisons[0])}")
+    say(f"  2-view 2k {form}: {clean} queries exact, {bl} borderline, comparisons {int(ores.n_comparisons[0])}")
     assert clean > 1900
 
 
-def test_c2_parity_and_fp32_error(sfm, oracle_lib):
+def test_two_view_16k_parity_and_fp32_error(sfm, oracle_lib):
     """Full 16k x 16k pair.  Also re-checks with a 1e-4 px borderline margin:
     every query whose candidates all lie more than 1e-4 px from the band edge
     must match exactly, which bounds the FP32 distance error by 1e-4 px on
     the candidates that lie between 1e-4 and 1e-3 px from the edge."""
-    s = scenes.make_config_c2()
+    s = scenes.make_two_view_16k()
     imgs = [(im.xy, im.desc) for im in s.images]
     m, out, ores = run_both(sfm, oracle_lib, imgs, s.pairs, [s.F])
     clean, bl = compare_all(out, ores, 1)
-    say(f"  C2: {clean} exact, {bl} borderline (1e-3 px)")
+    say(f"  2-view 16k: {clean} exact, {bl} borderline (1e-3 px)")
     tight = oracle_lib.match(imgs, s.pairs, [s.F], borderline_px=1e-4)
     clean4, bl4 = compare_all(out, tight, 1)
-    say(f"  C2: {clean4} exact, {bl4} borderline (1e-4 px)")
+    say(f"  2-view 16k: {clean4} exact, {bl4} borderline (1e-4 px)")
     assert bl4 < bl or bl == 0
 
 
-def test_c3_sample_batched_vs_plain(sfm, oracle_lib):
-    scene, pairs = scenes.make_config_c3()
+def test_arc_batch_sample_batched_vs_plain(sfm, oracle_lib):
+    scene, pairs = scenes.make_arc_batch()
     rng = np.random.default_rng(5)
     sel = sorted(rng.choice(len(pairs), size=24, replace=False))
     sub = [pairs[k] for k in sel]
@@ -79,23 +79,23 @@ def test_c3_sample_batched_vs_plain(sfm, oracle_lib):
     ores = oracle_lib.match(imgs, sp, Fs)
     outs = {}
     for form in ("batched", "plain"):
-        say(f"  C3 sample {form}")
+        say(f"  arc batch sample {form}")
         outs[form] = m.match(sp, Fs, form=form, emit_all=True)
         clean, bl = compare_all(outs[form], ores, len(sp))
-        say(f"  C3 {form}: {clean} exact, {bl} borderline")
+        say(f"  arc batch sample {form}: {clean} exact, {bl} borderline")
     for k in ("query", "match", "d1", "d2", "offset", "n_comparisons", "all_count"):
         a, b = getattr(outs["batched"], k).cpu(), getattr(outs["plain"], k).cpu()
         n = int(outs["batched"].offset[-1]) if k in ("query", "match", "d1", "d2") else a.shape[0]
         assert np.array_equal(a[:n].numpy(), b[:n].numpy()), k
 
 
-def test_c3_full_batch_as_benchmarked(sfm, oracle_lib):
+def test_arc_batch_full_as_benchmarked(sfm, oracle_lib):
     """The whole 500-pair batch in the launch configuration bench.py times
     (one batched call on a PairBatch, default tuning, no per-query outputs):
     every pair against the oracle."""
     import bench
     import torch
-    images, pairs, Fs, _ = bench.c3_workload()
+    images, pairs, Fs, _ = bench.arc_batch_workload()
     m = sfm.Matcher().register(images)
     out = m.buffers(pairs)
     batch = sfm.PairBatch(pairs, Fs)
@@ -158,7 +158,7 @@ def test_epipole_positions(sfm, oracle_lib, e):
 
 
 def test_scaled_f_and_options(sfm, oracle_lib):
-    s = scenes.make_config_c1()
+    s = scenes.make_two_view_2k()
     imgs = [(im.xy, im.desc) for im in s.images]
     Fs = [s.F * -3.7, s.F * 1e-6]
     pairs = [(0, 1, 4.0), (0, 1, 6.5)]
@@ -168,7 +168,7 @@ def test_scaled_f_and_options(sfm, oracle_lib):
 
 
 def test_determinism(sfm):
-    s = scenes.make_config_c2()
+    s = scenes.make_two_view_16k()
     m = sfm.Matcher().register([(im.xy, im.desc) for im in s.images])
     a = m.match(s.pairs, [s.F], emit_all=True)
     b = m.match(s.pairs, [s.F], emit_all=True)
@@ -182,7 +182,7 @@ def test_determinism(sfm):
 
 def test_fast_path_equals_counting_path(sfm):
     """Without emit_all the kernel skips per-query counts; outputs must not change."""
-    scene, pairs = scenes.make_config_c3()
+    scene, pairs = scenes.make_arc_batch()
     sub = pairs[:10]
     used = sorted({a for a, _, _ in sub} | {b for _, b, _ in sub})
     remap = {k: i for i, k in enumerate(used)}

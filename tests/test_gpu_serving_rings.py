@@ -25,9 +25,9 @@ def sfm():
     return sfm
 
 
-def test_c4_open_loop_equals_batched_and_oracle(sfm, oracle_lib):
+def test_three_rings_open_loop_equals_batched_and_oracle(sfm, oracle_lib):
     t = time.time()
-    sc = scenes.make_config_c4()
+    sc = scenes.make_three_rings()
     scenes.materialize(sc, workers=16)
     pool = [(a, b, 4.0) for a, b in scenes.covisible_pairs(sc)]
     images = [(sc.image(k).xy, sc.image(k).desc) for k in range(sc.n_images)]

@@ -35,7 +35,7 @@ def sfm():
 @pytest.fixture(scope="module")
 def stress(sfm):
     t = time.time()
-    sc = scenes.make_config_c5()
+    sc = scenes.make_ten_rings()
     say(f"  stress scene: {sc.n_images} cameras, generating images")
     scenes.materialize(sc, workers=16,
                        progress=lambda k, n: say(f"    {k}/{n} images ({time.time() - t:.0f} s)"))

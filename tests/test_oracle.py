@@ -199,14 +199,14 @@ def test_infinite_band_is_exhaustive_matching(oracle_lib):
 
 
 def test_zero_band_on_noisy_data_is_empty(oracle_lib):
-    s = scenes.make_config_c1()
+    s = scenes.make_two_view_2k()
     r = oracle_lib.match([(im.xy, im.desc) for im in s.images], [(0, 1, 0.0)], [s.F])
     assert r.n_comparisons[0] == 0 and r.n_accepted[0] == 0
 
 
-def test_planted_match_recovery_c1(oracle_lib):
+def test_planted_match_recovery_two_view(oracle_lib):
     """Recall of in-band true correspondences and precision of accepted matches."""
-    s = scenes.make_config_c1()
+    s = scenes.make_two_view_2k()
     A, B = s.images
     r = oracle_lib.match([(A.xy, A.desc), (B.xy, B.desc)], s.pairs, [s.F])
     q, m, d1, d2 = r.matches(0)
@@ -224,7 +224,7 @@ def test_planted_match_recovery_c1(oracle_lib):
 def test_repetitive_structure_guided_keeps_match(oracle_lib):
     """A near-duplicate of the true partner placed outside the band fails the
     ratio test of exhaustive matching but not guided matching (Section 6.2.3)."""
-    s = scenes.make_config_c1()
+    s = scenes.make_two_view_2k()
     A, B = s.images
     pos_b = {int(g): k for k, g in enumerate(B.gt) if g >= 0}
     i = next(k for k, g in enumerate(A.gt) if g >= 0 and int(g) in pos_b)

@@ -15,7 +15,7 @@ def _planted(scene, a=0, b=1):
 
 def test_f_direction_noise_free_correspondences():
     """x_b^T F x_a = 0 for exact projections, in the a -> b direction (eq. 1)."""
-    s = scenes.make_config_c1()
+    s = scenes.make_two_view_2k()
     X = s.points[:200]
     xa, za = project(s.cams[0], X)
     xb, zb = project(s.cams[1], X)
@@ -32,7 +32,7 @@ def test_f_direction_noise_free_correspondences():
 
 
 def test_f_rank_two_and_epipole():
-    s = scenes.make_config_c1()
+    s = scenes.make_two_view_2k()
     sv = np.linalg.svd(s.F, compute_uv=False)
     assert sv[2] <= 1e-12 * sv[0]
     # The epipole of image b is the projection of camera a's centre.
@@ -47,7 +47,7 @@ def test_f_rank_two_and_epipole():
 
 
 def test_descriptor_model_and_counts():
-    s = scenes.make_config_c1()
+    s = scenes.make_two_view_2k()
     for im in s.images:
         assert im.n == 2000
         assert im.desc.dtype == np.uint8 and im.desc.max() <= 127
@@ -67,7 +67,7 @@ def test_descriptor_model_and_counts():
 
 
 def test_keypoint_noise_statistics():
-    s = scenes.make_config_c2()
+    s = scenes.make_two_view_16k()
     A = s.images[0]
     t = A.gt >= 0
     xy_p, _ = project(s.cams[0], s.points[A.gt[t]])
@@ -78,16 +78,16 @@ def test_keypoint_noise_statistics():
 
 
 def test_seeds_reproducible():
-    a = scenes.make_config_c1(seed=0)
-    b = scenes.make_config_c1(seed=0)
-    c = scenes.make_config_c1(seed=1)
+    a = scenes.make_two_view_2k(seed=0)
+    b = scenes.make_two_view_2k(seed=0)
+    c = scenes.make_two_view_2k(seed=1)
     assert np.array_equal(a.images[0].desc, b.images[0].desc)
     assert np.array_equal(a.images[1].xy, b.images[1].xy)
     assert not np.array_equal(a.images[0].desc, c.images[0].desc)
 
 
 def test_multiview_visibility_and_pairs():
-    scene, pairs = scenes.make_config_c3()
+    scene, pairs = scenes.make_arc_batch()
     assert scene.n_images == 60 and len(pairs) == 500
     assert scene.n_features.min() >= 2000 and scene.n_features.max() <= 20000
     im = scene.image(3)
