@@ -186,6 +186,11 @@ typedef struct {
                                   a single larger request fails with SFM_ECAPACITY */
   sfm_options opt;             /* emit_all must be 0 */
 } sfm_server_cfg;
+/* Admission: a launch takes waiting requests in arrival order while it stays
+ * within max_batch_pairs and max_batch_queries and its workspace (an upper
+ * bound from the pairs' feature counts) within the context's workspace budget
+ * (sfm_create); the next request waits for the next launch.  A request whose
+ * workspace alone exceeds the budget fails with SFM_ECAPACITY. */
 
 typedef struct {
   int32_t* query;              /* host, caller-owned, capacity rows: accepted matches */

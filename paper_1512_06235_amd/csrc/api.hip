@@ -416,6 +416,25 @@ int32_t ctx_n_images(const sfm_ctx* ctx) { return ctx->n_images; }
 int32_t ctx_image_size(const sfm_ctx* ctx, int32_t image) {
   return image >= 0 && image < ctx->n_images ? ctx->n_host[size_t(image)] : 0;
 }
+// The per-pair terms of plan(), each section counted without its alignment
+// (which ctx_call_bytes covers), so sums over pairs bound plan().total.
+size_t ctx_request_bytes(const sfm_ctx* ctx, int32_t a, int32_t b) {
+  const size_t na = size_t(ctx_image_size(ctx, a)), nb = size_t(ctx_image_size(ctx, b));
+  const size_t nbins = size_t(bins_for(int32_t(nb), ctx->features_per_bin));
+  const size_t nblocks = (na + kQueryTile - 1) / kQueryTile;
+  const size_t ngroups = (nblocks + size_t(ctx->group_tiles) - 1) / size_t(ctx->group_tiles);
+  return sizeof(PairDesc) + 9 * sizeof(double) + sizeof(int32_t) + sizeof(PairGeom) +
+         sizeof(PairCounters) + sizeof(long long) + nb * sizeof(CandRec) +
+         (nbins + 1) * sizeof(int32_t) +
+         na * (sizeof(QueryRec) + sizeof(QueryResult) + sizeof(int2)) +
+         ngroups * (sizeof(TileGroup) + sizeof(int32_t));
+}
+// The alignment of plan()'s sections and the schedule table at its largest.
+size_t ctx_call_bytes(const sfm_ctx* ctx) {
+  const int32_t wgs = match_workgroups(ctx->device, ctx->group_tiles, int64_t(1) << 40);
+  return 16 * kAlign + size_t(wgs + 1) * sizeof(int32_t);
+}
+size_t ctx_budget(const sfm_ctx* ctx) { return ctx->budget; }
 }  // namespace sfm
 
 extern "C" {

@@ -164,12 +164,19 @@ void worker_main(Server* Sp) {
       if (S.queue.empty()) return;   // stopping, everything launched
       slot_id = S.free_slots.front();
       S.free_slots.pop_front();
+      // Admission in arrival order while the launch stays within the pair
+      // and query caps and its workspace within the context's budget.
       int64_t queries = 0;
+      size_t bytes = ctx_call_bytes(S.ctx);
+      const size_t budget = ctx_budget(S.ctx);
       while (!S.queue.empty() && int32_t(batch.size()) < S.cfg.max_batch_pairs) {
         const Request& r = S.queue.front();
         const int64_t na = ctx_image_size(S.ctx, r.pair.a);
-        if (!batch.empty() && queries + na > S.cfg.max_batch_queries) break;
+        const size_t rb = ctx_request_bytes(S.ctx, r.pair.a, r.pair.b);
+        if (!batch.empty() && (queries + na > S.cfg.max_batch_queries || bytes + rb > budget))
+          break;
         queries += na;
+        bytes += rb;
         batch.push_back(r);
         S.queue.pop_front();
       }

@@ -155,6 +155,12 @@ namespace sfm {
 int32_t ctx_device(const sfm_ctx* ctx);
 int32_t ctx_n_images(const sfm_ctx* ctx);
 int32_t ctx_image_size(const sfm_ctx* ctx, int32_t image);
+// Workspace admission for the serving loop: an upper bound on the bytes one
+// pair adds to a batched call's workspace, the bytes every call needs
+// besides its pairs, and the context's workspace budget.
+size_t ctx_request_bytes(const sfm_ctx* ctx, int32_t a, int32_t b);
+size_t ctx_call_bytes(const sfm_ctx* ctx);
+size_t ctx_budget(const sfm_ctx* ctx);
 void server_release(sfm_ctx* ctx);
 
 // Host launchers (one translation unit each).

@@ -226,6 +226,46 @@ def test_server_burst_submit(sfm, ring):
         assert np.array_equal(r["d1"], d1) and np.array_equal(r["d2"], d2)
 
 
+def test_server_admission_by_workspace_budget(sfm, ring):
+    """A context whose workspace budget holds about three requests: a burst of
+    every pair is split into launches that fit, none fails, and the results
+    equal the batched form on a context with the default budget."""
+    images, pairs, Fs = ring
+    ref_m = sfm.Matcher().register(images)
+    ref = ref_m.match(pairs, Fs, form="batched")
+    sizes = [sfm.sfm_workspace_size(ref_m.ctx, [p]) for p in pairs]
+    per = max(sizes)
+    m = sfm.Matcher(workspace_budget_bytes=3 * per).register(images)
+    cap = max(m.n_features(a) for a, _, _ in pairs)
+    sfm.sfm_server_start(m.ctx, max_batch_pairs=256, max_inflight=2)
+    try:
+        tickets = sfm.sfm_server_submit_batch(m.ctx, pairs, Fs)
+        res = collect(sfm, m.ctx, [int(t) for t in tickets], cap)
+        stats = sfm.sfm_server_stats(m.ctx)
+    finally:
+        sfm.sfm_server_stop(m.ctx)
+    say(f"  budget {3 * per} B: {len(pairs)} requests in {stats['launches']} launches")
+    # Every launch fitted the budget (none failed), so the burst took at
+    # least about its summed workspace over the budget.
+    assert stats["launches"] >= max(2, sum(sizes) // (3 * per) // 2)
+    for k, r in enumerate(res):
+        q, mt, d1, d2 = ref.pair(k)
+        assert r["status"] == sfm.SFM_OK, (k, r["status"])
+        assert np.array_equal(r["query"], q) and np.array_equal(r["match"], mt)
+        assert np.array_equal(r["d1"], d1) and np.array_equal(r["d2"], d2)
+    # A request larger than the whole budget fails alone.
+    small = sfm.Matcher(workspace_budget_bytes=per // 4).register(images)
+    sfm.sfm_server_start(small.ctx, max_batch_pairs=8)
+    try:
+        t = sfm.sfm_server_submit(small.ctx, pairs[0], Fs[0])
+        r = sfm.sfm_server_poll(small.ctx, t, cap, timeout_ms=60_000)
+    finally:
+        sfm.sfm_server_stop(small.ctx)
+    assert r["status"] == sfm.SFM_ECAPACITY
+    for mm in (m, small, ref_m):
+        mm.close()
+
+
 def test_server_concurrent_clients(sfm, ring):
     """Four client threads submit and collect at once."""
     import threading
