@@ -235,7 +235,9 @@ int sfm_server_submit_batch(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n, cons
  * (0: do not wait, < 0: wait for ever).  SFM_ETIMEOUT: not ready yet;
  * SFM_ENOTFOUND: unknown or already collected ticket; SFM_ECAPACITY: out
  * cannot hold its n_matches rows (out->n_matches says how many; the result
- * stays collectable).  A collected result is released. */
+ * stays collectable); SFM_EBUSY: no server runs, or it was stopped while this
+ * call waited.  A collected result is released.  Polls, submissions and a
+ * stop may run on different threads at once. */
 int sfm_server_poll(sfm_ctx* ctx, uint64_t ticket, sfm_result_view* out, int32_t timeout_ms);
 
 /* out[0] launches so far, out[1] requests launched, out[2] requests waiting. */

@@ -18,7 +18,9 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
+#include <system_error>
 #include <thread>
 #include <unordered_map>
 #include <unordered_set>
@@ -86,15 +88,18 @@ struct Server {
   uint64_t next_ticket = 1;
   bool stopping = false;
   bool worker_done = false;          // the worker has launched everything and exited
+  bool closed = false;               // stopped: threads joined, slots freed
   int64_t launches = 0, launched_pairs = 0;
 
   std::thread worker, completer;
 };
 
+// Servers are shared: a caller that found one keeps it alive until its call
+// returns, even if another thread stops it meanwhile.
 std::mutex g_servers_mu;
-std::unordered_map<sfm_ctx*, Server*> g_servers;
+std::unordered_map<sfm_ctx*, std::shared_ptr<Server>> g_servers;
 
-Server* find_server(sfm_ctx* ctx) {
+std::shared_ptr<Server> find_server(sfm_ctx* ctx) {
   std::lock_guard<std::mutex> lk(g_servers_mu);
   auto it = g_servers.find(ctx);
   return it == g_servers.end() ? nullptr : it->second;
@@ -308,10 +313,19 @@ void completer_main(Server* Sp) {
                         off.begin());
       for (int i = 1; i <= kCopyThreads; ++i) cut[i] = std::max(std::min(cut[i], n), cut[i - 1]);
       std::vector<std::thread> helpers;
-      for (int i = 1; i < kCopyThreads; ++i)
-        helpers.emplace_back(fill_results, std::cref(s), std::cref(reqs), std::cref(off),
-                             std::cref(ncmp), t, cut[i], cut[i + 1], std::ref(out));
+      int i = 1;
+      for (; i < kCopyThreads; ++i) {
+        try {
+          helpers.emplace_back(fill_results, std::cref(s), std::cref(reqs), std::cref(off),
+                               std::cref(ncmp), t, cut[size_t(i)], cut[size_t(i) + 1],
+                               std::ref(out));
+        } catch (const std::system_error&) {
+          break;   // no thread to spare: this thread copies the rest
+        }
+      }
       fill_results(s, reqs, off, ncmp, t, cut[0], cut[1], out);
+      for (; i < kCopyThreads; ++i)
+        fill_results(s, reqs, off, ncmp, t, cut[size_t(i)], cut[size_t(i) + 1], out);
       for (std::thread& h : helpers) h.join();
     }
     std::lock_guard<std::mutex> lk(S.mu);
@@ -340,13 +354,16 @@ void shutdown(Server* S) {
   for (Slot& s : S->slots) free_slot(s);
   if (S->stream) (void)hipStreamDestroy(S->stream);
   if (S->copy) (void)hipStreamDestroy(S->copy);
-  delete S;
+  S->stream = S->copy = nullptr;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->closed = true;
+  S->cv_done.notify_all();   // pollers still waiting return SFM_EBUSY
 }
 
 }  // namespace
 
 void server_release(sfm_ctx* ctx) {
-  Server* S = nullptr;
+  std::shared_ptr<Server> S;
   {
     std::lock_guard<std::mutex> lk(g_servers_mu);
     auto it = g_servers.find(ctx);
@@ -354,7 +371,7 @@ void server_release(sfm_ctx* ctx) {
     S = it->second;
     g_servers.erase(it);
   }
-  shutdown(S);
+  shutdown(S.get());
 }
 
 }  // namespace sfm
@@ -380,20 +397,20 @@ int sfm_server_start(sfm_ctx* ctx, const sfm_server_cfg* cfg_in) {
       cfg.max_batch_queries < 1 || cfg.opt.ratio_den <= 0 || cfg.opt.ratio_num < 0 ||
       cfg.opt.emit_all)
     return SFM_EINVAL;
-  Server* S = new Server();
+  std::shared_ptr<Server> S = std::make_shared<Server>();
   S->ctx = ctx;
   S->device = ctx_device(ctx);
   S->cfg = cfg;
   if (hipSetDevice(S->device) != hipSuccess ||
       hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) != hipSuccess) {
-    shutdown(S);
+    shutdown(S.get());
     return SFM_EHIP;
   }
   S->slots.resize(size_t(cfg.max_inflight));
   for (int k = 0; k < cfg.max_inflight; ++k) {
     if (!alloc_slot(S->slots[size_t(k)], cfg.max_batch_queries, cfg.max_batch_pairs)) {
-      shutdown(S);
+      shutdown(S.get());
       return SFM_ENOMEM;
     }
     S->free_slots.push_back(k);
@@ -402,8 +419,8 @@ int sfm_server_start(sfm_ctx* ctx, const sfm_server_cfg* cfg_in) {
     std::lock_guard<std::mutex> lk(g_servers_mu);
     g_servers[ctx] = S;
   }
-  S->worker = std::thread(worker_main, S);
-  S->completer = std::thread(completer_main, S);
+  S->worker = std::thread(worker_main, S.get());
+  S->completer = std::thread(completer_main, S.get());
   return SFM_OK;
 }
 
@@ -415,7 +432,7 @@ int sfm_server_submit(sfm_ctx* ctx, const sfm_pair* pair, const double* F, int64
 int sfm_server_submit_batch(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n, const double* F,
                             int64_t arrival_ns, uint64_t* tickets) {
   if (!ctx || n < 0 || (n > 0 && (!pairs || !F || !tickets))) return SFM_EINVAL;
-  Server* S = find_server(ctx);
+  std::shared_ptr<Server> S = find_server(ctx);
   if (!S) return SFM_EBUSY;
   const int32_t n_images = ctx_n_images(ctx);
   for (int32_t i = 0; i < n; ++i) {
@@ -449,18 +466,20 @@ int sfm_server_submit_batch(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n, cons
 
 int sfm_server_poll(sfm_ctx* ctx, uint64_t ticket, sfm_result_view* out, int32_t timeout_ms) {
   if (!ctx || !out) return SFM_EINVAL;
-  Server* S = find_server(ctx);
+  std::shared_ptr<Server> S = find_server(ctx);
   if (!S) return SFM_EBUSY;
   std::unique_lock<std::mutex> lk(S->mu);
   if (!S->outstanding.count(ticket)) return SFM_ENOTFOUND;
   auto ready = [&] { return S->results.count(ticket) != 0; };
+  auto done = [&] { return ready() || S->closed; };
   if (!ready()) {
-    if (timeout_ms == 0) return SFM_ETIMEOUT;
+    if (timeout_ms == 0) return S->closed ? SFM_EBUSY : SFM_ETIMEOUT;
     if (timeout_ms < 0) {
-      S->cv_done.wait(lk, ready);
-    } else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
+      S->cv_done.wait(lk, done);
+    } else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)) {
       return SFM_ETIMEOUT;
     }
+    if (!ready()) return SFM_EBUSY;   // the server was stopped meanwhile
   }
   Result& res = S->results[ticket];
   const int64_t n = res.n;
@@ -485,7 +504,7 @@ int sfm_server_poll(sfm_ctx* ctx, uint64_t ticket, sfm_result_view* out, int32_t
 
 int sfm_server_stats(sfm_ctx* ctx, int64_t out[3]) {
   if (!ctx || !out) return SFM_EINVAL;
-  Server* S = find_server(ctx);
+  std::shared_ptr<Server> S = find_server(ctx);
   if (!S) return SFM_EBUSY;
   std::lock_guard<std::mutex> lk(S->mu);
   out[0] = S->launches;

@@ -266,6 +266,36 @@ def test_server_admission_by_workspace_budget(sfm, ring):
         mm.close()
 
 
+def test_server_stop_while_polling(sfm, ring):
+    """A thread blocked in poll while another stops the server gets either its
+    result or SFM_EBUSY, never a crash; stop drains what was submitted."""
+    import threading
+    images, pairs, Fs = ring
+    m = sfm.Matcher().register(images)
+    cap = max(m.n_features(a) for a, _, _ in pairs)
+    outcomes = []
+    for trial in range(3):
+        sfm.sfm_server_start(m.ctx, max_batch_pairs=4, max_inflight=1)
+        tickets = [int(t) for t in sfm.sfm_server_submit_batch(m.ctx, pairs, Fs)]
+
+        def poller():
+            for t in tickets:
+                try:
+                    r = sfm.sfm_server_poll(m.ctx, t, cap, timeout_ms=-1)
+                    outcomes.append(r["status"])
+                except sfm.SfmError as e:
+                    outcomes.append(e.status)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        sfm.sfm_server_stop(m.ctx)
+        th.join(timeout=60)
+        assert not th.is_alive()
+    assert set(outcomes) <= {sfm.SFM_OK, sfm.SFM_EBUSY}
+    say(f"  {outcomes.count(sfm.SFM_OK)} collected, {outcomes.count(sfm.SFM_EBUSY)} after stop")
+    m.close()
+
+
 def test_server_concurrent_clients(sfm, ring):
     """Four client threads submit and collect at once."""
     import threading
