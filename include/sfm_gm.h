@@ -271,6 +271,37 @@ int sfm_get_tuning(sfm_ctx* ctx, int32_t* group_tiles, int32_t* features_per_bin
  * Profiling (sfm_set_profiling) uses stream launches. */
 int sfm_set_graph_replay(sfm_ctx* ctx, int32_t enable);
 
+/* ---------------------------------------------------------------------------
+ * Candidate images (Section 6.1): which image pairs to match.  The covisible
+ * points of images i and j are the coarse-model points both observe; image
+ * q's candidates are the images sharing more than `threshold` points with it
+ * (the paper's T = 8), ranked by that count (ties: lower index), at most
+ * top_k of them (the paper keeps about 10% of the images).  The unique
+ * unordered pairs over all queries are the pairs to match.
+ *
+ * Input (device, caller-owned): the points each image observes, as CSR:
+ * image i observes vis_pts[vis_off[i] .. vis_off[i + 1]), point ids in
+ * 0..n_points-1, each at most once per image; nnz = vis_off[n_images].
+ * n_images <= 4096 (one row of counts lives in LDS).  A point id out of
+ * range, or ranges inconsistent with nnz, raise the device error flag
+ * (SFM_EKERNEL at sfm_sync); the outputs are then unspecified.
+ * Outputs (device, caller-owned), per image q in rank order:
+ * cand[q * top_k + r] and n_shared[q * top_k + r] for r < n_cand[q], -1 and 0
+ * after.  If pairs is not NULL, the unique pairs (i, j), i < j, ascending, go
+ * to pairs[2 p], pairs[2 p + 1] (room for n_images * top_k pairs) and their
+ * number to *n_pairs.  Asynchronous on `stream`; uses the context's workspace
+ * (4 (3 n_points + nnz) bytes and a bit per image pair). */
+typedef struct {
+  int32_t* cand;        /* n_images * top_k */
+  int32_t* n_shared;    /* n_images * top_k */
+  int32_t* n_cand;      /* n_images */
+  int32_t* pairs;       /* optional: 2 * n_images * top_k */
+  int64_t* n_pairs;     /* 1; needed with pairs */
+} sfm_candidates;
+int sfm_candidate_images(sfm_ctx* ctx, const int32_t* vis_off, const int32_t* vis_pts,
+                         int64_t nnz, int32_t n_images, int32_t n_points, int32_t threshold,
+                         int32_t top_k, const sfm_candidates* out, void* stream);
+
 /* Time the batched form on the given batch for every group_tiles in
  * {1, 2, 4} and features_per_bin in {4, 8, 16} (one warm-up and `repeats`
  * timed calls each, HIP events on `stream`), keep the fastest setting on the

@@ -54,6 +54,11 @@ class sfm_matches(C.Structure):
                 ("all_d1", C.c_void_p), ("all_d2", C.c_void_p), ("all_count", C.c_void_p)]
 
 
+class sfm_candidates(C.Structure):
+    _fields_ = [("cand", C.c_void_p), ("n_shared", C.c_void_p), ("n_cand", C.c_void_p),
+                ("pairs", C.c_void_p), ("n_pairs", C.c_void_p)]
+
+
 class sfm_server_cfg(C.Structure):
     _fields_ = [("max_batch_pairs", C.c_int32), ("max_inflight", C.c_int32),
                 ("max_batch_queries", C.c_int64), ("opt", sfm_options)]
@@ -103,6 +108,8 @@ def lib() -> C.CDLL:
         "sfm_server_stop": [vp],
         "sfm_set_tuning": [vp, i32, i32],
         "sfm_set_graph_replay": [vp, i32],
+        "sfm_candidate_images": [vp, vp, vp, i64, i32, i32, i32, i32, C.POINTER(sfm_candidates),
+                                 vp],
         "sfm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32)],
         "sfm_autotune": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options), vp, i32,
                          C.POINTER(C.c_double)],
@@ -126,7 +133,7 @@ def exported_symbols():
             "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
             "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
-            "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay"]
+            "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay", "sfm_candidate_images"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -310,6 +317,51 @@ def sfm_server_stats(ctx) -> dict:
 
 def sfm_server_stop(ctx) -> None:
     _check(ctx, lib().sfm_server_stop(ctx))
+
+
+class CandidateBuffers:
+    """Device outputs of sfm_candidate_images for n_images images, top_k each."""
+
+    def __init__(self, n_images: int, top_k: int, device="cuda:0", with_pairs: bool = True):
+        import torch
+        self.n_images, self.top_k = int(n_images), int(top_k)
+        n = max(1, self.n_images * self.top_k)
+        self.cand = torch.full((n,), -1, dtype=torch.int32, device=device)
+        self.n_shared = torch.zeros(n, dtype=torch.int32, device=device)
+        self.n_cand = torch.zeros(max(1, self.n_images), dtype=torch.int32, device=device)
+        self.pairs = torch.zeros(2 * n, dtype=torch.int32, device=device) if with_pairs else None
+        self.n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def c_struct(self):
+        return sfm_candidates(self.cand.data_ptr(), self.n_shared.data_ptr(),
+                              self.n_cand.data_ptr(),
+                              self.pairs.data_ptr() if self.pairs is not None else None,
+                              self.n_pairs.data_ptr())
+
+    def lists(self):
+        """Host lists per image q of (candidate, shared count) in rank order."""
+        cand = self.cand.cpu().numpy().reshape(-1)
+        shared = self.n_shared.cpu().numpy().reshape(-1)
+        nc = self.n_cand.cpu().numpy()
+        k = self.top_k
+        return [[(int(cand[q * k + r]), int(shared[q * k + r])) for r in range(int(nc[q]))]
+                for q in range(self.n_images)]
+
+    def unique_pairs(self):
+        n = int(self.n_pairs.cpu()[0])
+        return self.pairs[:2 * n].cpu().numpy().reshape(n, 2)
+
+
+def sfm_candidate_images(ctx, vis_off, vis_pts, n_points: int, threshold: int, top_k: int,
+                         out: "CandidateBuffers", stream=None) -> None:
+    """vis_off (int32[n_images + 1]) and vis_pts (int32[nnz]) are device tensors."""
+    n_images = int(vis_off.shape[0]) - 1
+    nnz = int(vis_pts.shape[0])
+    s = out.c_struct()
+    _check(ctx, lib().sfm_candidate_images(ctx, vis_off.data_ptr(), vis_pts.data_ptr(), nnz,
+                                           n_images, int(n_points), int(threshold), int(top_k),
+                                           C.byref(s),
+                                           stream.cuda_stream if stream is not None else None))
 
 
 def sfm_set_graph_replay(ctx, enable: bool) -> None:

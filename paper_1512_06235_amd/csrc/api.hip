@@ -665,6 +665,70 @@ int sfm_set_tuning(sfm_ctx* ctx, int32_t group_tiles, int32_t features_per_bin) 
   return SFM_OK;
 }
 
+int sfm_candidate_images(sfm_ctx* ctx, const int32_t* vis_off, const int32_t* vis_pts,
+                         int64_t nnz, int32_t n_images, int32_t n_points, int32_t threshold,
+                         int32_t top_k, const sfm_candidates* out, void* stream) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (!out) return fail(ctx, SFM_EINVAL, "out is NULL");
+  if (n_images < 0 || n_images > kMaxCovisImages)
+    return fail(ctx, SFM_EINVAL, "n_images must be in 0..4096");
+  if (n_points < 0 || int64_t(n_points) + 1 > covis_scan_limit())
+    return fail(ctx, SFM_EINVAL, "n_points out of range");
+  if (nnz < 0 || nnz > INT32_MAX) return fail(ctx, SFM_EINVAL, "nnz must be in 0..2^31-1");
+  if (threshold < 0 || top_k < 0) return fail(ctx, SFM_EINVAL, "threshold and top_k must be >= 0");
+  if (n_images > 0 && (!vis_off || !out->n_cand))
+    return fail(ctx, SFM_EINVAL, "vis_off and n_cand are required");
+  if (nnz > 0 && !vis_pts) return fail(ctx, SFM_EINVAL, "vis_pts is NULL");
+  if (n_images > 0 && top_k > 0 && (!out->cand || !out->n_shared))
+    return fail(ctx, SFM_EINVAL, "cand and n_shared are required");
+  if (out->pairs && !out->n_pairs) return fail(ctx, SFM_EINVAL, "pairs needs n_pairs");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const size_t np1 = size_t(n_points) + 1, ni1 = size_t(n_images) + 1;
+  const size_t words = (size_t(n_images) + 31) / 32;
+  const size_t nsums = (std::max(np1, ni1) + 8191) / 8192 + 1;
+  size_t o = 0;
+  const size_t o_count = o; o = align_up(o + np1 * 4);
+  const size_t o_off = o; o = align_up(o + np1 * 4);
+  const size_t o_cursor = o; o = align_up(o + np1 * 4);
+  const size_t o_imgs = o; o = align_up(o + std::max<size_t>(size_t(nnz), 1) * 4);
+  const size_t o_sums = o; o = align_up(o + nsums * 4);
+  const size_t o_rc = o; o = align_up(o + ni1 * 4);
+  const size_t o_ro = o; o = align_up(o + ni1 * 4);
+  const size_t o_bits = o; o = align_up(o + std::max<size_t>(size_t(n_images) * words, 1) * 4);
+  int rc = ensure_workspace(ctx, o);
+  if (rc) return rc;
+  if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
+  CovisArgs a;
+  a.vis_off = vis_off;
+  a.vis_pts = vis_pts;
+  a.nnz = nnz;
+  a.n_images = n_images;
+  a.n_points = n_points;
+  a.threshold = threshold;
+  a.top_k = top_k;
+  a.pt_count = reinterpret_cast<int32_t*>(ctx->ws + o_count);
+  a.pt_off = reinterpret_cast<int32_t*>(ctx->ws + o_off);
+  a.cursor = reinterpret_cast<int32_t*>(ctx->ws + o_cursor);
+  a.pt_imgs = reinterpret_cast<int32_t*>(ctx->ws + o_imgs);
+  a.sums = reinterpret_cast<int32_t*>(ctx->ws + o_sums);
+  a.row_count = reinterpret_cast<int32_t*>(ctx->ws + o_rc);
+  a.row_off = reinterpret_cast<int32_t*>(ctx->ws + o_ro);
+  a.bits = reinterpret_cast<uint32_t*>(ctx->ws + o_bits);
+  a.cand = out->cand;
+  a.n_shared = out->n_shared;
+  a.n_cand = out->n_cand;
+  a.pairs = out->pairs;
+  a.n_pairs = out->n_pairs;
+  a.err = ctx->err_dev;
+  HIP_TRY(ctx, launch_candidates(a, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
+  ctx->has_work = true;
+  ctx->last_pairs = 0;
+  return SFM_OK;
+}
+
 int sfm_set_graph_replay(sfm_ctx* ctx, int32_t enable) {
   if (!ctx) return SFM_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);

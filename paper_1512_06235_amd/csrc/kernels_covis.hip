@@ -1,0 +1,343 @@
+// Candidate images from point-camera covisibility (Section 6.1).
+//
+// For images i and j of the coarse model, the covisible points are the
+// points both observe, P_cv(i, j) = Points(i) ∩ Points(j).  Image q's
+// candidates are the images sharing more than T points with it, ranked by
+// |P_cv(q, i)| (ties: lower index), at most k of them; the unique unordered
+// pairs over all queries are what the matcher then runs.
+//
+// GPU form:
+//   1. transpose the visibility (points of each image) into the observers of
+//      each point: a counting sort by point id (count, scan, scatter);
+//   2. one workgroup per query image q histograms, in LDS, the other
+//      observers of every point q sees: row[j] = |P_cv(q, j)| for all j at once;
+//      a bitonic sort of the packed keys (count, ~j) in LDS ranks the row and
+//      the first k with count > T are the candidates;
+//   3. the unique pairs: a bit per (i, j), i < j, set by every candidate,
+//      then counted per row, scanned, and written in ascending order with a
+//      popcount prefix per row.
+#include <algorithm>
+
+#include "sfm_internal.h"
+
+namespace sfm {
+namespace {
+
+constexpr int kCovisThreads = 1024;
+constexpr int kScanPer = 8;                          // items per thread of one scan block
+constexpr int kScanBlock = kCovisThreads * kScanPer; // items per scan block
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t n, int32_t value) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = value;
+}
+
+// The [begin, end) range of image i's points, clamped to [0, nnz).
+__device__ __forceinline__ void image_range(const int32_t* vis_off, int32_t i, int64_t nnz,
+                                            int64_t& b, int64_t& e) {
+  b = min(max(int64_t(vis_off[i]), int64_t(0)), nnz);
+  e = min(max(int64_t(vis_off[i + 1]), b), nnz);
+}
+
+// Pass 1 of the transpose: observers per point.  One block per image.
+__global__ __launch_bounds__(256) void covis_count_kernel(const int32_t* vis_off,
+                                                          const int32_t* vis_pts, int64_t nnz,
+                                                          int32_t n_points, int32_t* pt_count,
+                                                          int32_t* err) {
+  int64_t b, e;
+  image_range(vis_off, blockIdx.x, nnz, b, e);
+  for (int64_t s = b + threadIdx.x; s < e; s += blockDim.x) {
+    const int32_t p = vis_pts[s];
+    if (p < 0 || p >= n_points) {
+      *err = 1;
+      continue;
+    }
+    atomicAdd(&pt_count[p], 1);
+  }
+}
+
+// Exclusive scan of one block of kScanBlock items; block sums to `sums`.
+__global__ __launch_bounds__(kCovisThreads) void scan_block_kernel(const int32_t* in,
+                                                                   int32_t* out, int64_t n,
+                                                                   int32_t* sums) {
+  __shared__ int32_t wtot[kCovisThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t base = int64_t(blockIdx.x) * kScanBlock + int64_t(t) * kScanPer;
+  int32_t v[kScanPer];
+  int32_t run = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0;
+    run += v[k];
+  }
+  int32_t x = run;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wtot[wv] = x;
+  __syncthreads();
+  int32_t before = 0;
+  for (int w = 0; w < wv; ++w) before += wtot[w];
+  int32_t acc = before + x - run;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) out[base + k] = acc;
+    acc += v[k];
+  }
+  if (t == kCovisThreads - 1) sums[blockIdx.x] = before + x;
+}
+
+// In place exclusive scan of the block sums (one block; at most kScanBlock).
+__global__ __launch_bounds__(kCovisThreads) void scan_sums_kernel(int32_t* sums, int32_t nb) {
+  __shared__ int32_t wtot[kCovisThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int32_t v[kScanPer];
+  int32_t run = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int32_t i = t * kScanPer + k;
+    v[k] = i < nb ? sums[i] : 0;
+    run += v[k];
+  }
+  int32_t x = run;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wtot[wv] = x;
+  __syncthreads();
+  int32_t before = 0;
+  for (int w = 0; w < wv; ++w) before += wtot[w];
+  int32_t acc = before + x - run;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int32_t i = t * kScanPer + k;
+    if (i < nb) sums[i] = acc;
+    acc += v[k];
+  }
+}
+
+// Adds each block's offset; also writes a copy (the scatter cursors).
+__global__ __launch_bounds__(256) void scan_add_kernel(int32_t* out, int64_t n,
+                                                       const int32_t* sums, int32_t* copy) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t v = out[i] + sums[i / kScanBlock];
+    out[i] = v;
+    if (copy) copy[i] = v;
+  }
+}
+
+// Pass 2 of the transpose: image i into the observer list of each of its
+// points.  Positions past nnz (inconsistent input) raise the error flag.
+__global__ __launch_bounds__(256) void covis_scatter_kernel(const int32_t* vis_off,
+                                                            const int32_t* vis_pts, int64_t nnz,
+                                                            int32_t n_points, int32_t* cursor,
+                                                            int32_t* pt_imgs, int32_t* err) {
+  int64_t b, e;
+  image_range(vis_off, blockIdx.x, nnz, b, e);
+  for (int64_t s = b + threadIdx.x; s < e; s += blockDim.x) {
+    const int32_t p = vis_pts[s];
+    if (p < 0 || p >= n_points) continue;
+    const int32_t pos = atomicAdd(&cursor[p], 1);
+    if (pos < 0 || int64_t(pos) >= nnz) {
+      *err = 1;
+      continue;
+    }
+    pt_imgs[pos] = int32_t(blockIdx.x);
+  }
+}
+
+// One block per query image q: |P_cv(q, j)| for every j in LDS, then the
+// ranked candidates.  Keys pack (count, 2^32 - 1 - j) so a descending sort
+// ranks by count, then by lower index; keys of non-candidates are 0.
+__global__ __launch_bounds__(kCovisThreads) void covis_rows_kernel(
+    const int32_t* vis_off, const int32_t* vis_pts, int64_t nnz, int32_t n_images,
+    int32_t n_points, const int32_t* pt_off, const int32_t* pt_imgs, int32_t threshold,
+    int32_t top_k, int32_t nsort, int32_t* cand, int32_t* n_shared, int32_t* n_cand) {
+  __shared__ uint32_t row[kMaxCovisImages];
+  __shared__ unsigned long long keys[kMaxCovisImages];
+  __shared__ int32_t taken;
+  const int32_t q = blockIdx.x;
+  const int t = threadIdx.x;
+  for (int32_t j = t; j < n_images; j += kCovisThreads) row[j] = 0;
+  if (t == 0) taken = top_k;
+  __syncthreads();
+  int64_t b, e;
+  image_range(vis_off, q, nnz, b, e);
+  for (int64_t s = b + t; s < e; s += kCovisThreads) {
+    const int32_t p = vis_pts[s];
+    if (p < 0 || p >= n_points) continue;
+    // Offsets past nnz only arise from inconsistent input (the scatter
+    // raised the error flag); reads stay inside pt_imgs.
+    const int64_t o0 = max(int64_t(pt_off[p]), int64_t(0));
+    const int64_t o1 = min(int64_t(pt_off[p + 1]), nnz);
+    for (int64_t o = o0; o < o1; ++o) {
+      const int32_t j = pt_imgs[o];
+      if (j != q && j >= 0 && j < n_images) atomicAdd(&row[j], 1u);
+    }
+  }
+  __syncthreads();
+  for (int32_t j = t; j < nsort; j += kCovisThreads) {
+    const uint32_t c = j < n_images ? row[j] : 0u;
+    keys[j] = (j < n_images && j != q && c > uint32_t(threshold))
+                  ? ((unsigned long long)c << 32) | (0xFFFFFFFFull - uint32_t(j))
+                  : 0ull;
+  }
+  __syncthreads();
+  // Bitonic sort, descending, of nsort (a power of two) keys.
+  for (int32_t size = 2; size <= nsort; size <<= 1) {
+    for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int32_t i = t; i < nsort / 2; i += kCovisThreads) {
+        const int32_t lo = 2 * i - (i & (stride - 1));
+        const int32_t hi = lo + stride;
+        const bool desc = (lo & size) == 0;
+        const unsigned long long a = keys[lo], c = keys[hi];
+        if ((a < c) == desc) {
+          keys[lo] = c;
+          keys[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int32_t r = t; r < top_k; r += kCovisThreads) {
+    const unsigned long long key = r < nsort ? keys[r] : 0ull;
+    const int64_t at = int64_t(q) * top_k + r;
+    if (key != 0ull) {
+      cand[at] = int32_t(0xFFFFFFFFull - (key & 0xFFFFFFFFull));
+      n_shared[at] = int32_t(key >> 32);
+    } else {
+      cand[at] = -1;
+      n_shared[at] = 0;
+      if (r == 0 || (r - 1 < nsort && keys[r - 1] != 0ull)) taken = r;
+    }
+  }
+  __syncthreads();
+  if (t == 0) n_cand[q] = taken;
+}
+
+// Sets bit (min(q, c), max(q, c)) for every candidate c of every q.
+__global__ __launch_bounds__(256) void pair_mark_kernel(int32_t n_images, int32_t top_k,
+                                                        const int32_t* cand,
+                                                        const int32_t* n_cand, uint32_t* bits,
+                                                        int32_t words) {
+  const int64_t total = int64_t(n_images) * top_k;
+  for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
+       x += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t q = int32_t(x / top_k), r = int32_t(x % top_k);
+    if (r >= n_cand[q]) continue;
+    const int32_t c = cand[x];
+    if (c < 0 || c >= n_images || c == q) continue;
+    const int32_t i = min(q, c), j = max(q, c);
+    atomicOr(&bits[int64_t(i) * words + (j >> 5)], 1u << (j & 31));
+  }
+}
+
+// Pairs per row i (set bits), one block per row.
+__global__ __launch_bounds__(256) void pair_count_kernel(const uint32_t* bits, int32_t words,
+                                                         int32_t* row_count) {
+  __shared__ int32_t tot;
+  if (threadIdx.x == 0) tot = 0;
+  __syncthreads();
+  int32_t c = 0;
+  for (int32_t w = threadIdx.x; w < words; w += blockDim.x)
+    c += __builtin_popcount(bits[int64_t(blockIdx.x) * words + w]);
+  atomicAdd(&tot, c);
+  __syncthreads();
+  if (threadIdx.x == 0) row_count[blockIdx.x] = tot;
+}
+
+// Writes row i's pairs (i, j) in ascending j from its offset; one block per
+// row, one thread per word (words <= kMaxCovisImages / 32 = 128).
+__global__ __launch_bounds__(128) void pair_write_kernel(const uint32_t* bits, int32_t words,
+                                                         const int32_t* row_off, int32_t n_images,
+                                                         int32_t* pairs, int64_t* n_pairs) {
+  __shared__ int32_t pre[128];
+  const int32_t i = blockIdx.x;
+  const int w = threadIdx.x;
+  const uint32_t word = w < words ? bits[int64_t(i) * words + w] : 0u;
+  pre[w] = __builtin_popcount(word);
+  __syncthreads();
+  if (w == 0) {
+    int32_t acc = 0;
+    for (int k = 0; k < 128; ++k) {
+      const int32_t c = pre[k];
+      pre[k] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  int64_t at = int64_t(row_off[i]) + pre[w];
+  uint32_t m = word;
+  while (m) {
+    const int bit = __builtin_ctz(m);
+    m &= m - 1;
+    pairs[2 * at] = i;
+    pairs[2 * at + 1] = 32 * w + bit;
+    ++at;
+  }
+  if (i == n_images - 1 && w == 0) *n_pairs = int64_t(row_off[n_images]);
+}
+
+int32_t grid_for(int64_t n, int32_t per_block) {
+  return int32_t(std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, 65535)));
+}
+
+// Exclusive scan of in[0..n) into out (n <= kScanBlock^2); `copy` may be NULL.
+void launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, int32_t* copy,
+                 hipStream_t st) {
+  const int32_t nb = int32_t((n + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(kCovisThreads), 0, st, in, out, n, sums);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kCovisThreads), 0, st, sums, nb);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, out, n, sums,
+                     copy);
+}
+
+}  // namespace
+
+int64_t covis_scan_limit() { return int64_t(kScanBlock) * kScanBlock; }
+
+hipError_t launch_candidates(const CovisArgs& a, hipStream_t st) {
+  const int64_t np1 = int64_t(a.n_points) + 1;
+  // Observers of every point: counts, exclusive offsets (pt_off[n_points] =
+  // nnz of valid entries), scatter cursors.
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(np1, 256)), dim3(256), 0, st, a.pt_count,
+                     np1, 0);
+  if (a.n_images > 0)
+    hipLaunchKernelGGL(covis_count_kernel, dim3(a.n_images), dim3(256), 0, st, a.vis_off,
+                       a.vis_pts, a.nnz, a.n_points, a.pt_count, a.err);
+  launch_scan(a.pt_count, a.pt_off, np1, a.sums, a.cursor, st);
+  if (a.n_images > 0) {
+    hipLaunchKernelGGL(covis_scatter_kernel, dim3(a.n_images), dim3(256), 0, st, a.vis_off,
+                       a.vis_pts, a.nnz, a.n_points, a.cursor, a.pt_imgs, a.err);
+    int32_t nsort = 1;
+    while (nsort < a.n_images) nsort <<= 1;
+    hipLaunchKernelGGL(covis_rows_kernel, dim3(a.n_images), dim3(kCovisThreads), 0, st,
+                       a.vis_off, a.vis_pts, a.nnz, a.n_images, a.n_points, a.pt_off, a.pt_imgs,
+                       a.threshold, a.top_k, nsort, a.cand, a.n_shared, a.n_cand);
+  }
+  if (a.pairs && a.n_images > 0 && a.top_k > 0) {
+    const int32_t words = (a.n_images + 31) / 32;
+    const int64_t nbits = int64_t(a.n_images) * words;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(nbits, 256)), dim3(256), 0, st,
+                       reinterpret_cast<int32_t*>(a.bits), nbits, 0);
+    hipLaunchKernelGGL(pair_mark_kernel, dim3(grid_for(int64_t(a.n_images) * a.top_k, 256)),
+                       dim3(256), 0, st, a.n_images, a.top_k, a.cand, a.n_cand, a.bits, words);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(int64_t(a.n_images) + 1, 256)), dim3(256),
+                       0, st, a.row_count, int64_t(a.n_images) + 1, 0);
+    hipLaunchKernelGGL(pair_count_kernel, dim3(a.n_images), dim3(256), 0, st, a.bits, words,
+                       a.row_count);
+    launch_scan(a.row_count, a.row_off, int64_t(a.n_images) + 1, a.sums, nullptr, st);
+    hipLaunchKernelGGL(pair_write_kernel, dim3(a.n_images), dim3(128), 0, st, a.bits, words,
+                       a.row_off, a.n_images, a.pairs, a.n_pairs);
+  } else if (a.pairs && a.n_pairs) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st,
+                       reinterpret_cast<int32_t*>(a.n_pairs), 2, 0);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sfm

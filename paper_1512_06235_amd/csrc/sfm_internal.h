@@ -155,6 +155,27 @@ namespace sfm {
 int32_t ctx_device(const sfm_ctx* ctx);
 int32_t ctx_n_images(const sfm_ctx* ctx);
 int32_t ctx_image_size(const sfm_ctx* ctx, int32_t image);
+// Candidate images from covisibility (kernels_covis.hip).  One query image's
+// row of covisible counts and its sort keys live in LDS: at most this many
+// images per call.
+constexpr int kMaxCovisImages = 4096;
+struct CovisArgs {
+  const int32_t* vis_off;   // points of image i: vis_pts[vis_off[i] .. vis_off[i + 1])
+  const int32_t* vis_pts;
+  int64_t nnz;
+  int32_t n_images, n_points, threshold, top_k;
+  // Workspace: observers per point (counts, offsets, cursors, image ids),
+  // scan block sums, pair bits and per-row pair counts and offsets.
+  int32_t *pt_count, *pt_off, *cursor, *pt_imgs, *sums, *row_count, *row_off;
+  uint32_t* bits;
+  // Outputs.
+  int32_t *cand, *n_shared, *n_cand, *pairs;
+  int64_t* n_pairs;
+  int32_t* err;
+};
+hipError_t launch_candidates(const CovisArgs& a, hipStream_t st);
+int64_t covis_scan_limit();   // longest array the two-level scan handles
+
 // Workspace admission for the serving loop: an upper bound on the bytes one
 // pair adds to a batched call's workspace, the bytes every call needs
 // besides its pairs, and the context's workspace budget.

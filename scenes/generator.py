@@ -316,6 +316,25 @@ def covisible_pairs(scene: MultiViewScene, min_shared: int = 8, top_k: int = 30)
     return out
 
 
+def visibility_lists(scene: MultiViewScene):
+    """The coarse-model visibility: per image, the sorted ids of the 3D points
+    its true features observe."""
+    out = []
+    for i in range(scene.n_images):
+        g = scene.image(i).gt
+        out.append(np.unique(g[g >= 0]).astype(np.int32))
+    return out
+
+
+def visibility_csr(vis_lists):
+    """The lists as CSR arrays: offsets int32[n + 1] and point ids int32[nnz]."""
+    off = np.zeros(len(vis_lists) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(p) for p in vis_lists])
+    pts = np.concatenate([np.asarray(p, dtype=np.int32) for p in vis_lists]) \
+        if len(vis_lists) else np.zeros(0, np.int32)
+    return off.astype(np.int32), pts.astype(np.int32)
+
+
 def materialize(scene: MultiViewScene, workers: int = 8, progress=None) -> None:
     """Generate every image of a multi-view scene into its cache with a
     thread pool.  Each image draws from its own seeded generator, so the
