@@ -224,6 +224,7 @@ def stress_serving(sfm, log_fn, n_requests=20_000, burst=2_000):
     Fs = np.stack([sc.F(a, b) for a, b, _ in reqs])
     images = [(sc.image(k).xy, sc.image(k).desc) for k in range(sc.n_images)]
     m = sfm.Matcher(device=0).register(images)
+    cands = candidate_selection(sfm, m, sc, log_fn)
     cap = max(m.n_features(a) for a, _, _ in reqs)
     bursts = [(s, min(s + burst, len(reqs))) for s in range(0, len(reqs), burst)]
     sfm.sfm_server_start(m.ctx, max_batch_pairs=256, max_inflight=2)
@@ -260,7 +261,8 @@ def stress_serving(sfm, log_fn, n_requests=20_000, burst=2_000):
         del o
     m.close()
     nbytes = algorithmic_bytes(images, reqs)
-    return {"workload": "20,000 covisible-pair requests in 10 bursts of 2,000, 1,000 cameras on "
+    return {"candidate_images": cands,
+            "workload": "20,000 covisible-pair requests in 10 bursts of 2,000, 1,000 cameras on "
                         "10 rings, 8k-40k features per image, band 2-8 px per request",
             "images": len(images), "requests": len(res), "comparisons": int(cmp_total),
             "wall_ms": round(span * 1e3, 3), "comparisons_per_s": served,
@@ -271,6 +273,41 @@ def stress_serving(sfm, log_fn, n_requests=20_000, burst=2_000):
             "hbm_frac": nbytes / span / 1e9 / HBM_PEAK_GBS,
             "plain_ms": round(plain_s * 1e3, 3), "plain_comparisons_per_s": cmp_total / plain_s,
             "speedup_served_vs_plain": plain_s / span}
+
+
+def candidate_selection(sfm, m, sc, log_fn, threshold=8, top_k=100, reps=10):
+    """Candidate images of every image of the scene (more than 8 covisible
+    points, top 10%) from its coarse-model visibility: GPU time per call
+    (HIP events around `reps` calls), and the oracle's time on the host."""
+    import scenes
+    import torch
+    lists = scenes.visibility_lists(sc)
+    off, pts = scenes.visibility_csr(lists)
+    d_off, d_pts = torch.as_tensor(off).cuda(), torch.as_tensor(pts).cuda()
+    out = sfm.CandidateBuffers(len(lists), top_k)
+    st = torch_stream()
+    run = lambda: sfm.sfm_candidate_images(m.ctx, d_off, d_pts, sc.points.shape[0],  # noqa
+                                           threshold, top_k, out, st)
+    run()
+    sfm.sfm_sync(m.ctx, st)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        run()
+    e1.record(st)
+    sfm.sfm_sync(m.ctx, st)
+    gpu_ms = e0.elapsed_time(e1) / reps
+    n_pairs = int(out.n_pairs.cpu()[0])
+    res = {"workload": f"{len(lists)} images, more than {threshold} covisible points, top {top_k}",
+           "observations": int(pts.shape[0]), "unique_pairs": n_pairs, "gpu_ms": gpu_ms,
+           "observations_per_s": pts.shape[0] / (gpu_ms / 1e3)}
+    # Inputs for the host baseline of the same step (timed in the CPU leg).
+    CANDIDATE_INPUTS.update(lists=lists, n_points=sc.points.shape[0], threshold=threshold,
+                            top_k=top_k, n_pairs=n_pairs)
+    return res
+
+
+CANDIDATE_INPUTS = {}
 
 
 def torch_stream():
@@ -301,7 +338,19 @@ def cpu_baseline(images, pairs, Fs, budget_s):
         cmp += int(r.n_comparisons.sum())
         done += len(sub)
         chunk = min(32, chunk * 2)
-    return {"value": cmp / t_used, "unit": "comparisons/s", "cores": oracle.threads_used(),
+    cand = None
+    if CANDIDATE_INPUTS:
+        import oracle.covis
+        c = CANDIDATE_INPUTS
+        t = time.perf_counter()
+        _, upairs = oracle.covis.candidate_images(c["lists"], c["n_points"], c["threshold"],
+                                                  c["top_k"])
+        cand = {"candidate_images_ms": (time.perf_counter() - t) * 1e3,
+                "unique_pairs_equal_gpu": len(upairs) == c["n_pairs"],
+                "sample": "candidate images of the whole 1,000-image scene (sparse product and "
+                          "selection, one host thread)"}
+    return {"candidate_images": cand,
+            "value": cmp / t_used, "unit": "comparisons/s", "cores": oracle.threads_used(),
             "kind": "oracle", "sample": f"first {done} of {len(pairs)} pairs of the same batch, "
             f"{cmp} comparisons in {t_used:.1f} s"}
 

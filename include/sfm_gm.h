@@ -290,7 +290,8 @@ int sfm_set_graph_replay(sfm_ctx* ctx, int32_t enable);
  * after.  If pairs is not NULL, the unique pairs (i, j), i < j, ascending, go
  * to pairs[2 p], pairs[2 p + 1] (room for n_images * top_k pairs) and their
  * number to *n_pairs.  Asynchronous on `stream`; uses the context's workspace
- * (4 (3 n_points + nnz) bytes and a bit per image pair). */
+ * (about 4 (3 n_points + nnz) bytes and a bit per image pair; see
+ * sfm_set_covis_method for the other method). */
 typedef struct {
   int32_t* cand;        /* n_images * top_k */
   int32_t* n_shared;    /* n_images * top_k */
@@ -301,6 +302,15 @@ typedef struct {
 int sfm_candidate_images(sfm_ctx* ctx, const int32_t* vis_off, const int32_t* vis_pts,
                          int64_t nnz, int32_t n_images, int32_t n_points, int32_t threshold,
                          int32_t top_k, const sfm_candidates* out, void* stream);
+
+/* How sfm_candidate_images counts covisible points (the results are the
+ * same): 1 = a histogram of every image's co-observers (work grows with the
+ * sum over points of their observers squared: short tracks), 2 = a bit matrix
+ * of images x points and popcounts of row ANDs (work grows with images^2 x
+ * points / 32: dense visibility), 0 = choose from nnz, n_images and n_points
+ * (default).  Method 2 also needs n_images * (n_points / 8 + 4 n_images)
+ * bytes of workspace. */
+int sfm_set_covis_method(sfm_ctx* ctx, int32_t method);
 
 /* Time the batched form on the given batch for every group_tiles in
  * {1, 2, 4} and features_per_bin in {4, 8, 16} (one warm-up and `repeats`

@@ -108,6 +108,7 @@ def lib() -> C.CDLL:
         "sfm_server_stop": [vp],
         "sfm_set_tuning": [vp, i32, i32],
         "sfm_set_graph_replay": [vp, i32],
+        "sfm_set_covis_method": [vp, i32],
         "sfm_candidate_images": [vp, vp, vp, i64, i32, i32, i32, i32, C.POINTER(sfm_candidates),
                                  vp],
         "sfm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32)],
@@ -133,7 +134,8 @@ def exported_symbols():
             "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
             "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
-            "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay", "sfm_candidate_images"]
+            "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay", "sfm_candidate_images",
+            "sfm_set_covis_method"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -362,6 +364,10 @@ def sfm_candidate_images(ctx, vis_off, vis_pts, n_points: int, threshold: int, t
                                            n_images, int(n_points), int(threshold), int(top_k),
                                            C.byref(s),
                                            stream.cuda_stream if stream is not None else None))
+
+
+def sfm_set_covis_method(ctx, method: int) -> None:
+    _check(ctx, lib().sfm_set_covis_method(ctx, int(method)))
 
 
 def sfm_set_graph_replay(ctx, enable: bool) -> None:

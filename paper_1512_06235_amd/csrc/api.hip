@@ -49,6 +49,7 @@ struct sfm_ctx {
   // Graph replay of the batched form (sfm_set_graph_replay): the kernels of
   // one launch layout captured once and replayed while the layout repeats.
   bool graph_replay = false;
+  int32_t covis_method = 0;   // candidate images: 0 choose, 1 point histogram, 2 bit matrix
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph = nullptr;
   std::vector<char> graph_key;
@@ -687,16 +688,31 @@ int sfm_candidate_images(sfm_ctx* ctx, const int32_t* vis_off, const int32_t* vi
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const size_t np1 = size_t(n_points) + 1, ni1 = size_t(n_images) + 1;
   const size_t words = (size_t(n_images) + 31) / 32;
+  const size_t pwords = (size_t(n_points) + 31) / 32;
   const size_t nsums = (std::max(np1, ni1) + 8191) / 8192 + 1;
+  // The two exact methods: observers per point and an LDS histogram per image
+  // (work ~ sum over points of observers^2, at least nnz^2 / n_points), or
+  // the bit-matrix product (n^2 / 2 pairs of pwords words, ~20x cheaper per
+  // unit).  Dense visibility favours the product, short tracks the histogram.
+  bool use_gram = ctx->covis_method == 2;
+  if (ctx->covis_method == 0 && n_images > 0 && n_points > 0) {
+    const double hist = double(nnz) * double(nnz) / double(n_points);
+    const double prod = double(n_images) * double(n_images) * double(pwords) / 2.0 / 20.0;
+    use_gram = prod < hist;
+  }
   size_t o = 0;
   const size_t o_count = o; o = align_up(o + np1 * 4);
   const size_t o_off = o; o = align_up(o + np1 * 4);
   const size_t o_cursor = o; o = align_up(o + np1 * 4);
-  const size_t o_imgs = o; o = align_up(o + std::max<size_t>(size_t(nnz), 1) * 4);
+  const size_t o_imgs = o; o = align_up(o + (use_gram ? 1 : std::max<size_t>(size_t(nnz), 1)) * 4);
   const size_t o_sums = o; o = align_up(o + nsums * 4);
   const size_t o_rc = o; o = align_up(o + ni1 * 4);
   const size_t o_ro = o; o = align_up(o + ni1 * 4);
   const size_t o_bits = o; o = align_up(o + std::max<size_t>(size_t(n_images) * words, 1) * 4);
+  const size_t o_bitset = o;
+  o = align_up(o + (use_gram ? std::max<size_t>(size_t(n_images) * pwords, 1) : 1) * 4);
+  const size_t o_gram = o;
+  o = align_up(o + (use_gram ? std::max<size_t>(size_t(n_images) * size_t(n_images), 1) : 1) * 4);
   int rc = ensure_workspace(ctx, o);
   if (rc) return rc;
   if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
@@ -716,6 +732,8 @@ int sfm_candidate_images(sfm_ctx* ctx, const int32_t* vis_off, const int32_t* vi
   a.row_count = reinterpret_cast<int32_t*>(ctx->ws + o_rc);
   a.row_off = reinterpret_cast<int32_t*>(ctx->ws + o_ro);
   a.bits = reinterpret_cast<uint32_t*>(ctx->ws + o_bits);
+  a.bitset = reinterpret_cast<uint32_t*>(ctx->ws + o_bitset);
+  a.gram = use_gram ? reinterpret_cast<int32_t*>(ctx->ws + o_gram) : nullptr;
   a.cand = out->cand;
   a.n_shared = out->n_shared;
   a.n_cand = out->n_cand;
@@ -726,6 +744,14 @@ int sfm_candidate_images(sfm_ctx* ctx, const int32_t* vis_off, const int32_t* vi
   HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
   ctx->has_work = true;
   ctx->last_pairs = 0;
+  return SFM_OK;
+}
+
+int sfm_set_covis_method(sfm_ctx* ctx, int32_t method) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (method < 0 || method > 2) return fail(ctx, SFM_EINVAL, "method must be 0, 1 or 2");
+  ctx->covis_method = method;
   return SFM_OK;
 }
 

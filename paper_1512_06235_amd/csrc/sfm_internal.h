@@ -168,6 +168,9 @@ struct CovisArgs {
   // scan block sums, pair bits and per-row pair counts and offsets.
   int32_t *pt_count, *pt_off, *cursor, *pt_imgs, *sums, *row_count, *row_off;
   uint32_t* bits;
+  // Bit-matrix path (when gram is not NULL): image bitsets, n x n counts.
+  uint32_t* bitset;
+  int32_t* gram;
   // Outputs.
   int32_t *cand, *n_shared, *n_cand, *pairs;
   int64_t* n_pairs;

@@ -1,7 +1,8 @@
 """Candidate images (sfm_candidate_images) through the C ABI against the
 oracle: bit-exact ranked lists, shared counts and unique pairs, on random
 edge cases and on the three-ring (300 images) and ten-ring (1,000 images)
-scenes' coarse-model visibility."""
+scenes' coarse-model visibility, with each counting method (co-observer
+histogram, bit-matrix product) and the automatic choice."""
 import numpy as np
 import pytest
 
@@ -43,8 +44,10 @@ def _check(sfm, m, lists, npts, T, k):
     return ref_pairs
 
 
-def test_random_and_edge_cases(sfm):
+@pytest.mark.parametrize("method", [1, 2, 0])
+def test_random_and_edge_cases(sfm, method):
     m = sfm.Matcher()
+    sfm.sfm_set_covis_method(m.ctx, method)
     rng = np.random.default_rng(21)
     for trial in range(12):
         n = int(rng.integers(1, 70))
@@ -62,13 +65,18 @@ def test_random_and_edge_cases(sfm):
     m.close()
 
 
-def test_bad_inputs(sfm):
+@pytest.mark.parametrize("method", [1, 2])
+def test_bad_inputs(sfm, method):
     m = sfm.Matcher()
+    sfm.sfm_set_covis_method(m.ctx, method)
     with pytest.raises(sfm.SfmError) as e:
         _run(sfm, m, [np.zeros(0, np.int32)] * 4097, 10, 8, 2)
     assert e.value.status == sfm.SFM_EINVAL
     with pytest.raises(sfm.SfmError) as e:
         _run(sfm, m, [np.arange(5, dtype=np.int32)] * 3, 10, -1, 2)
+    assert e.value.status == sfm.SFM_EINVAL
+    with pytest.raises(sfm.SfmError) as e:
+        sfm.sfm_set_covis_method(m.ctx, 3)
     assert e.value.status == sfm.SFM_EINVAL
     # A point id past n_points: the kernels' own checks raise the error flag.
     with pytest.raises(sfm.SfmError) as e:
@@ -79,14 +87,15 @@ def test_bad_inputs(sfm):
     m.close()
 
 
-@pytest.mark.parametrize("rings,top_k", [(3, 30), (10, 100)])
-def test_scenes(sfm, rings, top_k):
+@pytest.mark.parametrize("rings,top_k,method", [(3, 30, 1), (3, 30, 2), (10, 100, 1), (10, 100, 2)])
+def test_scenes(sfm, rings, top_k, method):
     sc = scenes.make_three_rings() if rings == 3 else scenes.make_ten_rings()
     scenes.materialize(sc, workers=16)
     lists = scenes.visibility_lists(sc)
     npts = sc.points.shape[0]
     m = sfm.Matcher()
+    sfm.sfm_set_covis_method(m.ctx, method)
     pairs = _check(sfm, m, lists, npts, 8, top_k)
     say(f"  {sc.n_images} images, {sum(len(p) for p in lists)} observations, "
-        f"top {top_k}: {len(pairs)} unique pairs, bit-exact")
+        f"top {top_k}, method {method}: {len(pairs)} unique pairs, bit-exact")
     m.close()
