@@ -312,6 +312,33 @@ int sfm_candidate_images(sfm_ctx* ctx, const int32_t* vis_off, const int32_t* vi
  * bytes of workspace. */
 int sfm_set_covis_method(sfm_ctx* ctx, int32_t method);
 
+/* ---------------------------------------------------------------------------
+ * Track merging and triangulation (Section 6.3).
+ *
+ * sfm_tracks: the tracks are the connected components of the match graph,
+ * whose nodes are observations (a feature of an image; the caller numbers
+ * them 0..n_nodes-1, e.g. an image's first node plus the feature index) and
+ * whose edges are accepted matches: edges[2 k], edges[2 k + 1] (device,
+ * n_edges pairs of node ids).  label[i] (device, n_nodes, caller-owned)
+ * receives the smallest node id of i's component, whatever the order of the
+ * edges.  A node id out of range raises the device error flag (SFM_EKERNEL at
+ * sfm_sync).  No workspace.  Asynchronous on `stream`.
+ *
+ * sfm_triangulate: for every track root r (label[r] == r), the least-squares
+ * point of its observations: node i was seen at node_xy[2 i], node_xy[2 i + 1]
+ * (pixels) in image node_image[i], whose camera is the row-major 3 x 4 matrix
+ * P[12 image ..] (x ~ P (X, 1)); each observation gives the two linear
+ * equations (x p3 - p1).(X, 1) = 0, (y p3 - p2).(X, 1) = 0, solved by the
+ * FP64 normal equations.  X[3 r ..] (device, 3 n_nodes doubles) receives the
+ * point, NaN for tracks of one observation or a singular system;
+ * n_obs[r] its number of observations, 0 for non-roots.  Uses 80 n_nodes
+ * bytes of workspace.  Asynchronous on `stream`. */
+int sfm_tracks(sfm_ctx* ctx, int64_t n_nodes, const int32_t* edges, int64_t n_edges,
+               int32_t* label, void* stream);
+int sfm_triangulate(sfm_ctx* ctx, int64_t n_nodes, const int32_t* label, const int32_t* node_image,
+                    const float* node_xy, const double* P, int32_t n_images, double* X,
+                    int32_t* n_obs, void* stream);
+
 /* Time the batched form on the given batch for every group_tiles in
  * {1, 2, 4} and features_per_bin in {4, 8, 16} (one warm-up and `repeats`
  * timed calls each, HIP events on `stream`), keep the fastest setting on the

@@ -109,6 +109,8 @@ def lib() -> C.CDLL:
         "sfm_set_tuning": [vp, i32, i32],
         "sfm_set_graph_replay": [vp, i32],
         "sfm_set_covis_method": [vp, i32],
+        "sfm_tracks": [vp, i64, vp, i64, vp, vp],
+        "sfm_triangulate": [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp],
         "sfm_candidate_images": [vp, vp, vp, i64, i32, i32, i32, i32, C.POINTER(sfm_candidates),
                                  vp],
         "sfm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32)],
@@ -135,7 +137,7 @@ def exported_symbols():
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
             "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
             "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay", "sfm_candidate_images",
-            "sfm_set_covis_method"]
+            "sfm_set_covis_method", "sfm_tracks", "sfm_triangulate"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -364,6 +366,24 @@ def sfm_candidate_images(ctx, vis_off, vis_pts, n_points: int, threshold: int, t
                                            n_images, int(n_points), int(threshold), int(top_k),
                                            C.byref(s),
                                            stream.cuda_stream if stream is not None else None))
+
+
+def sfm_tracks(ctx, n_nodes: int, edges, label, stream=None) -> None:
+    """edges: device int32 tensor (n_edges, 2) of node ids; label: device int32[n_nodes]."""
+    n_edges = int(edges.shape[0]) if edges is not None else 0
+    _check(ctx, lib().sfm_tracks(ctx, int(n_nodes), edges.data_ptr() if n_edges else None,
+                                 n_edges, label.data_ptr() if n_nodes else None,
+                                 stream.cuda_stream if stream is not None else None))
+
+
+def sfm_triangulate(ctx, label, node_image, node_xy, P, X, n_obs, stream=None) -> None:
+    """Device tensors: label, node_image int32[n]; node_xy float32[n, 2];
+    P float64[n_images, 3, 4]; X float64[n, 3]; n_obs int32[n]."""
+    n = int(label.shape[0])
+    _check(ctx, lib().sfm_triangulate(ctx, n, label.data_ptr(), node_image.data_ptr(),
+                                      node_xy.data_ptr(), P.data_ptr(), int(P.shape[0]),
+                                      X.data_ptr(), n_obs.data_ptr(),
+                                      stream.cuda_stream if stream is not None else None))
 
 
 def sfm_set_covis_method(ctx, method: int) -> None:

@@ -747,6 +747,46 @@ int sfm_candidate_images(sfm_ctx* ctx, const int32_t* vis_off, const int32_t* vi
   return SFM_OK;
 }
 
+int sfm_tracks(sfm_ctx* ctx, int64_t n_nodes, const int32_t* edges, int64_t n_edges,
+               int32_t* label, void* stream) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (n_nodes < 0 || n_nodes > INT32_MAX) return fail(ctx, SFM_EINVAL, "n_nodes out of range");
+  if (n_edges < 0) return fail(ctx, SFM_EINVAL, "n_edges < 0");
+  if (n_nodes > 0 && !label) return fail(ctx, SFM_EINVAL, "label is NULL");
+  if (n_edges > 0 && !edges) return fail(ctx, SFM_EINVAL, "edges is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
+  HIP_TRY(ctx, launch_tracks(n_nodes, edges, n_edges, label, ctx->err_dev, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
+  ctx->has_work = true;
+  ctx->last_pairs = 0;
+  return SFM_OK;
+}
+
+int sfm_triangulate(sfm_ctx* ctx, int64_t n_nodes, const int32_t* label, const int32_t* node_image,
+                    const float* node_xy, const double* P, int32_t n_images, double* X,
+                    int32_t* n_obs, void* stream) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (n_nodes < 0 || n_nodes > INT32_MAX) return fail(ctx, SFM_EINVAL, "n_nodes out of range");
+  if (n_images < 0) return fail(ctx, SFM_EINVAL, "n_images < 0");
+  if (n_nodes > 0 && (!label || !node_image || !node_xy || !X || !n_obs || (n_images > 0 && !P)))
+    return fail(ctx, SFM_EINVAL, "a pointer is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int rc = ensure_workspace(ctx, align_up(size_t(std::max<int64_t>(n_nodes, 1)) * 10 * sizeof(double)));
+  if (rc) return rc;
+  if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
+  HIP_TRY(ctx, launch_triangulate(n_nodes, label, node_image, node_xy, P, n_images,
+                                  reinterpret_cast<double*>(ctx->ws), X, n_obs, ctx->err_dev, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
+  ctx->has_work = true;
+  ctx->last_pairs = 0;
+  return SFM_OK;
+}
+
 int sfm_set_covis_method(sfm_ctx* ctx, int32_t method) {
   if (!ctx) return SFM_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);

@@ -179,6 +179,14 @@ struct CovisArgs {
 hipError_t launch_candidates(const CovisArgs& a, hipStream_t st);
 int64_t covis_scan_limit();   // longest array the two-level scan handles
 
+// Tracks and triangulation (kernels_tracks.hip).
+hipError_t launch_tracks(int64_t n_nodes, const int32_t* edges, int64_t n_edges, int32_t* label,
+                         int32_t* err, hipStream_t st);
+hipError_t launch_triangulate(int64_t n_nodes, const int32_t* label, const int32_t* node_image,
+                              const float* node_xy, const double* P, int32_t n_images,
+                              double* acc, double* X, int32_t* n_obs, int32_t* err,
+                              hipStream_t st);
+
 // Workspace admission for the serving loop: an upper bound on the bytes one
 // pair adds to a batched call's workspace, the bytes every call needs
 // besides its pairs, and the context's workspace budget.
