@@ -308,6 +308,56 @@ def candidate_selection(sfm, m, sc, log_fn, threshold=8, top_k=100, reps=10):
 
 
 CANDIDATE_INPUTS = {}
+TRACK_INPUTS = {}
+
+
+def track_building(sfm, m, images, pairs, out, log_fn, reps=10):
+    """Tracks and triangulation of the batch's accepted matches: the match
+    graph of all 500 pairs (nodes = features of the 60 images), GPU time per
+    sfm_tracks + sfm_triangulate (HIP events around `reps` calls)."""
+    import scenes
+    import torch
+    log_fn("bench: tracks and triangulation of the batch's matches")
+    sc, _ = scenes.make_arc_batch()
+    off = np.concatenate([[0], np.cumsum([xy.shape[0] for xy, _ in images])])
+    o = out.offset.cpu().numpy()
+    q = out.query[:int(o[len(pairs)])].cpu().numpy()
+    mt = out.match[:int(o[len(pairs)])].cpu().numpy()
+    edges = []
+    for k, (a, b, _) in enumerate(pairs):
+        s0, s1 = int(o[k]), int(o[k + 1])
+        edges.append(np.stack([off[a] + q[s0:s1], off[b] + mt[s0:s1]], axis=1))
+    edges = np.concatenate(edges).astype(np.int32)
+    n = int(off[-1])
+    node_image = np.repeat(np.arange(len(images)), np.diff(off)).astype(np.int32)
+    node_xy = np.concatenate([xy for xy, _ in images]).astype(np.float32)
+    P = np.stack([c.K @ np.hstack([c.R, c.t[:, None]]) for c in sc.cams])
+    d = {k: torch.as_tensor(v).cuda() for k, v in
+         (("edges", edges), ("img", node_image), ("xy", node_xy), ("P", P))}
+    label = torch.empty(n, dtype=torch.int32, device="cuda")
+    X = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    n_obs = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch_stream()
+
+    def run():
+        sfm.sfm_tracks(m.ctx, n, d["edges"], label, st)
+        sfm.sfm_triangulate(m.ctx, label, d["img"], d["xy"], d["P"], X, n_obs, st)
+
+    run()
+    sfm.sfm_sync(m.ctx, st)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        run()
+    e1.record(st)
+    sfm.sfm_sync(m.ctx, st)
+    nobs = n_obs.cpu().numpy()
+    TRACK_INPUTS.update(n=n, edges=edges, node_image=node_image, node_xy=node_xy, P=P,
+                        label=label.cpu().numpy())
+    return {"workload": "match graph of the 500-pair batch (features of 60 images)",
+            "observations": n, "matches": int(edges.shape[0]),
+            "tracks": int((nobs >= 2).sum()), "longest": int(nobs.max()),
+            "gpu_ms": e0.elapsed_time(e1) / reps}
 
 
 def torch_stream():
@@ -338,6 +388,24 @@ def cpu_baseline(images, pairs, Fs, budget_s):
         cmp += int(r.n_comparisons.sum())
         done += len(sub)
         chunk = min(32, chunk * 2)
+    trk = None
+    if TRACK_INPUTS:
+        import oracle.tracks
+        c = TRACK_INPUTS
+        t = time.perf_counter()
+        lab = oracle.tracks.tracks(c["n"], c["edges"])
+        t_tracks = time.perf_counter() - t
+        sample = np.flatnonzero(np.isin(lab, np.unique(lab)[:20_000]))
+        where = np.full(c["n"], -1, dtype=np.int64)
+        where[sample] = np.arange(sample.size)        # roots are in the sample with their tracks
+        t = time.perf_counter()
+        oracle.tracks.triangulate(where[lab[sample]], c["node_image"][sample],
+                                  c["node_xy"][sample], c["P"])
+        t_tri = time.perf_counter() - t
+        trk = {"tracks_ms": t_tracks * 1e3, "labels_equal_gpu": bool(np.array_equal(lab, c["label"])),
+               "triangulate_ms_per_1k_tracks": t_tri * 1e3 / 20.0,
+               "sample": "all tracks of the batch's match graph; triangulation of the first "
+                         "20,000 tracks (one host thread)"}
     cand = None
     if CANDIDATE_INPUTS:
         import oracle.covis
@@ -349,7 +417,7 @@ def cpu_baseline(images, pairs, Fs, budget_s):
                 "unique_pairs_equal_gpu": len(upairs) == c["n_pairs"],
                 "sample": "candidate images of the whole 1,000-image scene (sparse product and "
                           "selection, one host thread)"}
-    return {"candidate_images": cand,
+    return {"candidate_images": cand, "tracks": trk,
             "value": cmp / t_used, "unit": "comparisons/s", "cores": oracle.threads_used(),
             "kind": "oracle", "sample": f"first {done} of {len(pairs)} pairs of the same batch, "
             f"{cmp} comparisons in {t_used:.1f} s"}
@@ -478,6 +546,8 @@ def main():
         plain = {"value": plain_value, "ms_per_step": plain_elapsed / args.plain_steps * 1e3,
                  "speedup_batched_vs_plain": value / plain_value}
 
+    tracks = track_building(sfm, m, images, pairs, out, log)
+
     context = None
     if not args.no_context:
         import scenes
@@ -541,6 +611,7 @@ def main():
                      "unique_frac": unique_bytes(images, pairs) / match_s / 1e9 / HBM_PEAK_GBS},
         "serving": serve,
         "stress_serving": stress,
+        "tracks": tracks,
         "context_bruteforce": context,
         "cpu_baseline": cpu,
     }
