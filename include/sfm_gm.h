@@ -32,6 +32,11 @@
  * registered images, per-feature squared norms and a workspace it grows on
  * demand up to the budget given to sfm_create().
  *
+ * Around the matcher, the library also selects the image pairs to match
+ * from the coarse model's point-camera visibility (Section 6.1,
+ * sfm_candidate_images) and merges the accepted matches of all pairs into
+ * tracks and triangulates them (Section 6.3, sfm_tracks, sfm_triangulate).
+ *
  * Streams.  Matching calls enqueue their work on the given HIP stream
  * (hipStream_t passed as void*, NULL = the default stream) and return without
  * waiting.  Errors found on the host return immediately; an error raised on
