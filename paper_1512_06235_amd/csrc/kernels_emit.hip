@@ -35,7 +35,7 @@ __global__ __launch_bounds__(1024) void scan_pairs_kernel(BatchView v, int32_t p
     for (int w = 0; w < wv; ++w) before += wtot[w];
     if (k < pc) offset[pb + k + 1] = before + x;
     __syncthreads();
-    if (t == blockDim.x - 1) carry = before + x;
+    if (t == int(blockDim.x) - 1) carry = before + x;
     __syncthreads();
   }
 }
