@@ -10,5 +10,5 @@ from .generator import (  # noqa: F401
     look_at_camera, fundamental_from_poses, make_pair_scene, make_two_view_2k,
     make_two_view_16k, make_multiview_scene, make_arc_batch, make_three_rings,
     make_ten_rings, sample_pairs_by_angle, covisible_pairs, poisson_arrivals,
-    materialize, stress_requests, visibility_lists, visibility_csr,
+    materialize, stress_requests, visibility_lists, visibility_csr, by_scale,
 )

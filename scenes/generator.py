@@ -54,6 +54,7 @@ class Image:
     xy: np.ndarray     # float32 (n, 2), pixel coordinates
     desc: np.ndarray   # uint8 (n, 128), values 0..127
     gt: np.ndarray     # int32 (n,), 3D point id or -1 for a distractor
+    scale: np.ndarray = None   # float32 (n,): the feature's scale (multi-view scenes)
 
     @property
     def n(self) -> int:
@@ -227,11 +228,26 @@ class MultiViewScene:
         n = int(self.n_features[i])
         n_true = int(round(self.true_frac * n))
         img = _assemble_image(rng, self.cams[i], self.points, self.base, order, n, n_true)
+        # Scale: a true feature takes its point's saliency (the images keep their
+        # most salient visible points, so large scales repeat across views, as
+        # high-scale SIFT does); a distractor a uniform draw of its own.
+        srng = np.random.default_rng([self.seed, 11, i])
+        scale = srng.uniform(0.0, 1.0, size=img.gt.shape[0])
+        true = img.gt >= 0
+        scale[true] = self.saliency[img.gt[true]]
+        img.scale = scale.astype(np.float32)
         self._cache[i] = img
         return img
 
     def F(self, a: int, b: int) -> np.ndarray:
         return fundamental_from_poses(self.cams[a], self.cams[b])
+
+
+def by_scale(img: Image) -> Image:
+    """The image with its features listed in decreasing scale (ties keep their
+    order), the order a feature extractor emits them in."""
+    order = np.argsort(-img.scale, kind="stable")
+    return Image(img.xy[order], img.desc[order], img.gt[order], img.scale[order])
 
 
 def make_multiview_scene(cam_centers, n_lo: int, n_hi: int, n_points: int = 200_000,
