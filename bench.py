@@ -32,9 +32,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+WORKLOAD_SCENE = {}
+
+
 def arc_batch_workload():
     import scenes
     scene, pairs = scenes.make_arc_batch()
+    WORKLOAD_SCENE["arc"] = scene
     used = sorted({a for a, _, _ in pairs} | {b for _, b, _ in pairs})
     images = [(scene.image(k).xy, scene.image(k).desc) for k in range(scene.n_images)]
     Fs = np.stack([scene.F(a, b) for a, b, _ in pairs])
@@ -360,6 +364,39 @@ def track_building(sfm, m, images, pairs, out, log_fn, reps=10):
             "gpu_ms": e0.elapsed_time(e1) / reps}
 
 
+PREEMPTIVE_INPUTS = {}
+
+
+def coarse_matching(sfm, scene, log_fn, reps=5):
+    """Staged coarse matching (Section 4) of all 1,770 unordered pairs of the
+    arc scene's 60 images, features listed by decreasing scale: wall time per
+    call.  The call is host-synchronous (stage 1, the host reads its counts,
+    stage 2 for the pairs with more than 4 matches, merge), so the time
+    includes its two host round trips."""
+    import scenes
+    log_fn("bench: staged coarse matching of all pairs of the scene")
+    imgs = [scenes.by_scale(scene.image(k)) for k in range(scene.n_images)]
+    pairs = [(a, b, 0.0) for a in range(len(imgs)) for b in range(a + 1, len(imgs))]
+    m = sfm.Matcher(device=0).register([(im.xy, im.desc) for im in imgs])
+    out = m.buffers(pairs)
+    batch = sfm.PairBatch(pairs)
+    st = torch_stream()
+    stages = sfm.sfm_preemptive_match(m.ctx, batch, out, stream=st)
+    t = timed(lambda: sfm.sfm_preemptive_match(m.ctx, batch, out, stream=st), reps, st) / reps
+    cmp = int(out.n_comparisons[:len(pairs)].sum())
+    full = sum(imgs[a].n * imgs[b].n for a, b, _ in pairs)
+    PREEMPTIVE_INPUTS.update(images=[(im.xy, im.desc, im.scale) for im in imgs], pairs=pairs)
+    res = {"workload": f"all {len(pairs)} unordered pairs of the 60-view arc scene, 2k-20k "
+                       "features per image; 10% of a's features vs 20% of b's, next 10% after "
+                       "more than 4 matches",
+           "ms_per_call": t * 1e3, "comparisons": cmp, "comparisons_per_s": cmp / t,
+           "pairs_per_s": len(pairs) / t, "matches": int(out.offset[len(pairs)]),
+           "pairs_with_stage_2": int((stages == 2).sum()),
+           "fraction_of_all_feature_comparisons": cmp / full}
+    m.close()
+    return res
+
+
 def torch_stream():
     import torch
     return torch.cuda.current_stream(torch.device("cuda", 0))
@@ -406,6 +443,18 @@ def cpu_baseline(images, pairs, Fs, budget_s):
                "triangulate_ms_per_1k_tracks": t_tri * 1e3 / 20.0,
                "sample": "all tracks of the batch's match graph; triangulation of the first "
                          "20,000 tracks (one host thread)"}
+    coarse = None
+    if PREEMPTIVE_INPUTS:
+        import oracle.preemptive
+        c = PREEMPTIVE_INPUTS
+        sample = c["pairs"][:40]
+        t = time.perf_counter()
+        r = oracle.preemptive.preemptive_match(c["images"], sample)
+        dt = time.perf_counter() - t
+        ncmp = sum(x["n_comparisons"] for x in r)
+        coarse = {"pairs_per_s": len(sample) / dt, "comparisons_per_s": ncmp / dt,
+                  "cores": oracle.threads_used(),
+                  "sample": f"first {len(sample)} pairs of the staged coarse workload"}
     cand = None
     if CANDIDATE_INPUTS:
         import oracle.covis
@@ -417,7 +466,7 @@ def cpu_baseline(images, pairs, Fs, budget_s):
                 "unique_pairs_equal_gpu": len(upairs) == c["n_pairs"],
                 "sample": "candidate images of the whole 1,000-image scene (sparse product and "
                           "selection, one host thread)"}
-    return {"candidate_images": cand, "tracks": trk,
+    return {"candidate_images": cand, "tracks": trk, "coarse_matching": coarse,
             "value": cmp / t_used, "unit": "comparisons/s", "cores": oracle.threads_used(),
             "kind": "oracle", "sample": f"first {done} of {len(pairs)} pairs of the same batch, "
             f"{cmp} comparisons in {t_used:.1f} s"}
@@ -547,6 +596,7 @@ def main():
                  "speedup_batched_vs_plain": value / plain_value}
 
     tracks = track_building(sfm, m, images, pairs, out, log)
+    coarse = coarse_matching(sfm, WORKLOAD_SCENE["arc"], log)
 
     context = None
     if not args.no_context:
@@ -612,6 +662,7 @@ def main():
         "serving": serve,
         "stress_serving": stress,
         "tracks": tracks,
+        "coarse_matching": coarse,
         "context_bruteforce": context,
         "cpu_baseline": cpu,
     }

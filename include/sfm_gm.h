@@ -155,6 +155,42 @@ int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
 int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                          const sfm_options* opt, const sfm_matches* out, void* stream);
 
+/* Staged matching of coarse features (Section 4, the hybrid scheme modelled
+ * on preemptive matching).  Each registered image must list its features in
+ * decreasing scale, so that a prefix is its highest-scale part.  For a pair
+ * (a, b) with n_a, n_b features:
+ *   - if n_a or n_b is below cfg.small_image, all features of a are matched
+ *     against all of b in one stage;
+ *   - otherwise stage 1 matches the first q = ceil(n_a * query_pct / 100)
+ *     features of a against the first r = ceil(n_b * target_pct / 100) of b;
+ *     stage 2 matches the next min(q, n_a - q) features of a against the same
+ *     r, and runs only when stage 1 accepted more than cfg.min_matches and,
+ *     with cfg.enough > 0, fewer than cfg.enough (enough matches for the
+ *     geometry: the pair stops early).
+ * Every stage is exhaustive 2-NN matching with the ratio test of `opt`
+ * (band_px of the pairs is ignored; emit_all must be 0).  Rows of a pair are
+ * its stage-1 rows then its stage-2 rows, in ascending query index of a (the
+ * registered indexing); n_comparisons sums both stages.  out->capacity must
+ * be >= the sum over pairs of the queries their stages take (sum of n_a
+ * always suffices).  stages (optional, host int32[n_pairs]) receives 0 for a
+ * pair matched whole, 1 when only stage 1 ran, 2 when both ran.
+ * Host-synchronous: the host reads stage 1's counts to choose the stage-2
+ * pairs, and the call returns once `out` is written.  Default cfg (NULL):
+ * query_pct 10, target_pct 20, min_matches 4, enough 0, small_image 1000.
+ * SFM_EINVAL: bad index, cfg or options; SFM_ECAPACITY: out->capacity or the
+ * workspace budget is too small; SFM_EKERNEL: a device error flag. */
+typedef struct {
+  int32_t query_pct;     /* 10 */
+  int32_t target_pct;    /* 20 */
+  int32_t min_matches;   /* 4 */
+  int32_t enough;        /* 0: no early stop */
+  int32_t small_image;   /* 1000 */
+  int32_t pad;
+} sfm_preemptive_cfg;
+int sfm_preemptive_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
+                         const sfm_preemptive_cfg* cfg, const sfm_options* opt,
+                         const sfm_matches* out, int32_t* stages, void* stream);
+
 /* Wait for the context's work on `stream`, then report a device error flag
  * raised since the last sfm_sync (SFM_EKERNEL) or a HIP error (SFM_EHIP). */
 int sfm_sync(sfm_ctx* ctx, void* stream);

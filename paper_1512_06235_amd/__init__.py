@@ -64,6 +64,12 @@ class sfm_server_cfg(C.Structure):
                 ("max_batch_queries", C.c_int64), ("opt", sfm_options)]
 
 
+class sfm_preemptive_cfg(C.Structure):
+    _fields_ = [("query_pct", C.c_int32), ("target_pct", C.c_int32),
+                ("min_matches", C.c_int32), ("enough", C.c_int32),
+                ("small_image", C.c_int32), ("pad", C.c_int32)]
+
+
 class sfm_result_view(C.Structure):
     _fields_ = [("query", C.c_void_p), ("match", C.c_void_p), ("d1", C.c_void_p),
                 ("d2", C.c_void_p), ("capacity", C.c_int64), ("n_matches", C.c_int64),
@@ -95,6 +101,8 @@ def lib() -> C.CDLL:
                                    C.POINTER(sfm_matches), vp],
         "sfm_bruteforce_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
                                  C.POINTER(sfm_matches), vp],
+        "sfm_preemptive_match": [vp, C.POINTER(sfm_pair), i32, C.POINTER(sfm_preemptive_cfg),
+                                 C.POINTER(sfm_options), C.POINTER(sfm_matches), vp, vp],
         "sfm_sync": [vp, vp],
         "sfm_set_profiling": [vp, i32],
         "sfm_phase_times": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
@@ -137,7 +145,7 @@ def exported_symbols():
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
             "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
             "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay", "sfm_candidate_images",
-            "sfm_set_covis_method", "sfm_tracks", "sfm_triangulate"]
+            "sfm_set_covis_method", "sfm_tracks", "sfm_triangulate", "sfm_preemptive_match"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -238,6 +246,26 @@ def sfm_guided_match_plain(ctx, pairs, F, out, opt, stream=None):
 
 def sfm_bruteforce_match(ctx, pairs, F, out, opt, stream=None):
     _call("sfm_bruteforce_match", ctx, pairs, F, out, opt, stream)
+
+
+def preemptive_cfg(query_pct=10, target_pct=20, min_matches=4, enough=0,
+                   small_image=1000) -> sfm_preemptive_cfg:
+    return sfm_preemptive_cfg(int(query_pct), int(target_pct), int(min_matches), int(enough),
+                              int(small_image), 0)
+
+
+def sfm_preemptive_match(ctx, pairs, out, opt=None, cfg=None, stream=None) -> np.ndarray:
+    """Staged coarse matching; returns the stages each pair ran (0 whole, 1, 2).
+    pairs: list of (a, b) or (a, b, band) (the band is ignored) or a PairBatch."""
+    if not isinstance(pairs, PairBatch):
+        pairs = PairBatch([(p[0], p[1], 0.0) for p in pairs], None)
+    stages = np.zeros(max(1, pairs.n), np.int32)
+    st = lib().sfm_preemptive_match(
+        ctx, pairs.c_pairs, pairs.n, C.byref(cfg if cfg is not None else preemptive_cfg()),
+        C.byref(opt if opt is not None else options()), C.byref(out.c_struct_cached()),
+        stages.ctypes.data, stream.cuda_stream if stream is not None else None)
+    _check(ctx, st)
+    return stages[:pairs.n]
 
 
 def sfm_sync(ctx, stream=None) -> None:

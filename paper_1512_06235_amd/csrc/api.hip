@@ -41,6 +41,10 @@ struct sfm_ctx {
   int32_t last_pairs = 0;              // pairs of the last matching call
   size_t last_counters = 0;            // workspace offset of its counters
 
+  // Staged matching: view table, per-stage rows and merge plan.
+  char* stage_buf = nullptr;
+  size_t stage_cap = 0;
+
   // Phase timing: 4 events per record (start, after prepare, after match, end).
   bool profiling = false;
   std::vector<hipEvent_t> prof_events;
@@ -118,18 +122,30 @@ Layout plan(const std::vector<PairDesc>& pd, int32_t device, int32_t group_tiles
   return L;
 }
 
-int describe_pairs(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, bool ignore_band,
-                   std::vector<PairDesc>& pd) {
+// The images pairs refer to: the registered ones, or views of them (a run of
+// consecutive features of one image) built for a staged match.
+struct ImageTable {
+  const ImageDev* dev;   // device table
+  const int32_t* n;      // host copy of the feature counts
+  int32_t count;
+};
+
+ImageTable registered(const sfm_ctx* ctx) {
+  return ImageTable{ctx->images_dev, ctx->n_host.data(), ctx->n_images};
+}
+
+int describe_pairs(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int32_t n_pairs,
+                   bool ignore_band, std::vector<PairDesc>& pd) {
   if (n_pairs < 0) return fail(ctx, SFM_EINVAL, "n_pairs < 0");
   if (n_pairs > 0 && !pairs) return fail(ctx, SFM_EINVAL, "pairs is NULL");
   pd.resize(size_t(n_pairs));
   int64_t q = 0, c = 0, bo = 0, blk = 0, grp = 0;
   for (int32_t k = 0; k < n_pairs; ++k) {
     const sfm_pair& s = pairs[k];
-    if (s.a < 0 || s.a >= ctx->n_images || s.b < 0 || s.b >= ctx->n_images) {
+    if (s.a < 0 || s.a >= tab.count || s.b < 0 || s.b >= tab.count) {
       char buf[128];
       snprintf(buf, sizeof buf, "pair %d: image index out of range (a=%d b=%d, %d registered)", k,
-               s.a, s.b, ctx->n_images);
+               s.a, s.b, tab.count);
       return fail(ctx, SFM_EINVAL, buf);
     }
     if (!ignore_band && !(s.band_px >= 0.0)) {
@@ -141,8 +157,8 @@ int describe_pairs(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, bool ig
     memset(&p, 0, sizeof p);
     p.a = s.a;
     p.b = s.b;
-    p.na = ctx->n_host[size_t(s.a)];
-    p.nb = ctx->n_host[size_t(s.b)];
+    p.na = tab.n[s.a];
+    p.nb = tab.n[s.b];
     p.nbins = ignore_band ? 1 : bins_for(p.nb, ctx->features_per_bin);
     p.nblocks = (p.na + kQueryTile - 1) / kQueryTile;
     p.ngroups = (p.nblocks + ctx->group_tiles - 1) / ctx->group_tiles;
@@ -257,10 +273,10 @@ hipError_t prof_mark(sfm_ctx* ctx, hipStream_t st) {
   return hipEventRecord(e, st);
 }
 
-int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
-              const sfm_options* opt_in, const sfm_matches* out, void* stream, Form form) {
-  if (!ctx) return SFM_EINVAL;
-  std::lock_guard<std::mutex> lock(ctx->mu);
+// One matching call over the images of `tab`; the caller holds ctx->mu.
+int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int32_t n_pairs,
+                 const double* F, const sfm_options* opt_in, const sfm_matches* out, void* stream,
+                 Form form) {
   if (!out) return fail(ctx, SFM_EINVAL, "out is NULL");
   sfm_options opt = {64, 100, 0, 0};
   if (opt_in) opt = *opt_in;
@@ -268,7 +284,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
     return fail(ctx, SFM_EINVAL, "ratio_den must be > 0 and ratio_num >= 0");
   const bool exhaustive = form == Form::kExhaustive;
   std::vector<PairDesc> pd;
-  int rc = describe_pairs(ctx, pairs, n_pairs, exhaustive, pd);
+  int rc = describe_pairs(ctx, tab, pairs, n_pairs, exhaustive, pd);
   if (rc) return rc;
   if (!exhaustive) {
     if (n_pairs > 0 && !F) return fail(ctx, SFM_EINVAL, "F is NULL");
@@ -335,7 +351,7 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
 
   BatchView v;
   memset(&v, 0, sizeof v);   // padding too: graph keys compare the bytes
-  v.images = ctx->images_dev;
+  v.images = tab.dev;
   v.pairs = reinterpret_cast<const PairDesc*>(ctx->ws + L.pairs);
   v.F = reinterpret_cast<const double*>(ctx->ws + L.F);
   v.geom = reinterpret_cast<PairGeom*>(ctx->ws + L.geom);
@@ -407,6 +423,13 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   ctx->last_pairs = n_pairs;
   ctx->last_counters = L.counters;
   return SFM_OK;
+}
+
+int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+              const sfm_options* opt, const sfm_matches* out, void* stream, Form form) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  return match_locked(ctx, registered(ctx), pairs, n_pairs, F, opt, out, stream, form);
 }
 
 }  // namespace
@@ -499,6 +522,7 @@ int sfm_destroy(sfm_ctx* ctx) {
   (void)hipDeviceSynchronize();
   free_registration(ctx);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->stage_buf) (void)hipFree(ctx->stage_buf);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->err_dev) (void)hipFree(ctx->err_dev);
   for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
@@ -572,7 +596,7 @@ int sfm_workspace_size(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, siz
   if (!ctx || !bytes) return SFM_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   std::vector<PairDesc> pd;
-  const int rc = describe_pairs(ctx, pairs, n_pairs, false, pd);
+  const int rc = describe_pairs(ctx, registered(ctx), pairs, n_pairs, false, pd);
   if (rc) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   *bytes = plan(pd, ctx->device, ctx->group_tiles).total;
@@ -593,6 +617,173 @@ int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
 int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                          const sfm_options* opt, const sfm_matches* out, void* stream) {
   return run_match(ctx, pairs, n_pairs, F, opt, out, stream, Form::kExhaustive);
+}
+
+int sfm_preemptive_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
+                         const sfm_preemptive_cfg* cfg_in, const sfm_options* opt_in,
+                         const sfm_matches* out, int32_t* stages, void* stream) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  sfm_preemptive_cfg cfg = {10, 20, 4, 0, 1000, 0};
+  if (cfg_in) cfg = *cfg_in;
+  if (cfg.query_pct < 1 || cfg.query_pct > 100 || cfg.target_pct < 1 || cfg.target_pct > 100 ||
+      cfg.min_matches < 0 || cfg.enough < 0 || cfg.small_image < 0)
+    return fail(ctx, SFM_EINVAL,
+                "cfg: query_pct and target_pct must be in 1..100, the counts >= 0");
+  sfm_options opt = {64, 100, 0, 0};
+  if (opt_in) opt = *opt_in;
+  if (opt.emit_all) return fail(ctx, SFM_EINVAL, "emit_all is not available for staged matching");
+  if (!out || !out->offset) return fail(ctx, SFM_EINVAL, "out or out->offset is NULL");
+  if (n_pairs < 0 || n_pairs > INT32_MAX / 3 || (n_pairs > 0 && !pairs))
+    return fail(ctx, SFM_EINVAL, "bad pair list");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+
+  // Views per pair k: 3k = stage-1 queries, 3k+1 = targets, 3k+2 = stage-2 queries.
+  const size_t P = size_t(n_pairs);
+  std::vector<int32_t> spec(9 * P), vn(3 * P);
+  std::vector<uint8_t> whole(P);
+  int64_t cap1 = 0, cap2 = 0;
+  for (size_t k = 0; k < P; ++k) {
+    const sfm_pair& s = pairs[k];
+    if (s.a < 0 || s.a >= ctx->n_images || s.b < 0 || s.b >= ctx->n_images) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "pair %zu: image index out of range (a=%d b=%d, %d registered)",
+               k, s.a, s.b, ctx->n_images);
+      return fail(ctx, SFM_EINVAL, buf);
+    }
+    const int64_t na = ctx->n_host[size_t(s.a)], nb = ctx->n_host[size_t(s.b)];
+    whole[k] = na < cfg.small_image || nb < cfg.small_image;
+    const int64_t q = whole[k] ? na : (na * cfg.query_pct + 99) / 100;
+    const int64_t r = whole[k] ? nb : (nb * cfg.target_pct + 99) / 100;
+    const int64_t q2 = whole[k] ? 0 : std::min(q, na - q);
+    const int32_t v[9] = {s.a, 0, int32_t(q), s.b, 0, int32_t(r), s.a, int32_t(q), int32_t(q2)};
+    std::copy(v, v + 9, spec.begin() + 9 * k);
+    vn[3 * k] = int32_t(q);
+    vn[3 * k + 1] = int32_t(r);
+    vn[3 * k + 2] = int32_t(q2);
+    cap1 += q;
+    cap2 += q2;
+  }
+  if (out->capacity < cap1 + cap2) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "output capacity %lld < %lld queries", (long long)out->capacity,
+             (long long)(cap1 + cap2));
+    return fail(ctx, SFM_ECAPACITY, buf);
+  }
+  if (cap1 + cap2 > 0 && (!out->query || !out->match || !out->d1 || !out->d2))
+    return fail(ctx, SFM_EINVAL, "output arrays are NULL");
+  if (n_pairs == 0) {
+    HIP_TRY(ctx, hipMemsetAsync(out->offset, 0, sizeof(int64_t), st));
+    return SFM_OK;
+  }
+
+  // Stage buffer: views, spec, both stages' rows and counts, merge plan.
+  size_t o = 0;
+  const size_t o_views = o; o = align_up(o + 3 * P * sizeof(ImageDev));
+  const size_t o_spec = o; o = align_up(o + 9 * P * sizeof(int32_t));
+  const size_t o_merge = o; o = align_up(o + P * sizeof(StageMerge));
+  size_t o_off[2], o_cmp[2], o_rows[2];
+  const int64_t caps[2] = {cap1, cap2};
+  for (int t = 0; t < 2; ++t) {
+    o_off[t] = o; o = align_up(o + (P + 1) * sizeof(int64_t));
+    o_cmp[t] = o; o = align_up(o + P * sizeof(int64_t));
+    o_rows[t] = o; o = align_up(o + 4 * size_t(std::max<int64_t>(caps[t], 1)) * sizeof(int32_t));
+  }
+  if (o > ctx->budget) return fail(ctx, SFM_ECAPACITY, "staged matching exceeds the budget");
+  if (o > ctx->stage_cap) {
+    if (ctx->has_work) HIP_TRY(ctx, hipEventSynchronize(ctx->work_done));
+    if (ctx->stage_buf) HIP_TRY(ctx, hipFree(ctx->stage_buf));
+    ctx->stage_buf = nullptr;
+    ctx->stage_cap = 0;
+    HIP_TRY(ctx, hipMalloc(&ctx->stage_buf, o + o / 4));
+    ctx->stage_cap = o + o / 4;
+  }
+  char* B = ctx->stage_buf;
+  if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
+  ImageDev* views = reinterpret_cast<ImageDev*>(B + o_views);
+  HIP_TRY(ctx, hipMemcpyAsync(B + o_spec, spec.data(), spec.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, launch_make_views(ctx->images_dev, reinterpret_cast<const int32_t*>(B + o_spec),
+                                 int32_t(3 * P), views, st));
+  const ImageTable tab{views, vn.data(), int32_t(3 * P)};
+  sfm_matches so[2];
+  StageRows rows[2];
+  for (int t = 0; t < 2; ++t) {
+    int32_t* r = reinterpret_cast<int32_t*>(B + o_rows[t]);
+    const size_t c = size_t(std::max<int64_t>(caps[t], 1));
+    memset(&so[t], 0, sizeof so[t]);
+    so[t].query = r;
+    so[t].match = r + c;
+    so[t].d1 = r + 2 * c;
+    so[t].d2 = r + 3 * c;
+    so[t].capacity = caps[t];
+    so[t].offset = reinterpret_cast<int64_t*>(B + o_off[t]);
+    so[t].n_comparisons = reinterpret_cast<int64_t*>(B + o_cmp[t]);
+    rows[t] = StageRows{so[t].query, so[t].match, so[t].d1, so[t].d2, so[t].n_comparisons};
+  }
+
+  // Stage 1 (or the whole pair), then the counts back on the host.
+  std::vector<sfm_pair> sp(P);
+  for (size_t k = 0; k < P; ++k) sp[k] = sfm_pair{int32_t(3 * k), int32_t(3 * k + 1), 0.0};
+  int rc = match_locked(ctx, tab, sp.data(), n_pairs, nullptr, &opt, &so[0], stream,
+                        Form::kExhaustive);
+  if (rc) return rc;
+  std::vector<int64_t> off1(P + 1), off2(P + 1, 0);
+  HIP_TRY(ctx, hipMemcpyAsync(off1.data(), so[0].offset, (P + 1) * sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+
+  // Stage 2 for the pairs whose first stage found more than min_matches.
+  std::vector<int32_t> in2(P, -1);
+  sp.clear();
+  for (size_t k = 0; k < P; ++k) {
+    const int64_t c = off1[k + 1] - off1[k];
+    if (whole[k] || vn[3 * k + 2] == 0 || c <= cfg.min_matches || (cfg.enough > 0 && c >= cfg.enough))
+      continue;
+    in2[k] = int32_t(sp.size());
+    sp.push_back(sfm_pair{int32_t(3 * k + 2), int32_t(3 * k + 1), 0.0});
+  }
+  if (!sp.empty()) {
+    rc = match_locked(ctx, tab, sp.data(), int32_t(sp.size()), nullptr, &opt, &so[1], stream,
+                      Form::kExhaustive);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipMemcpyAsync(off2.data(), so[1].offset, (sp.size() + 1) * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+  }
+
+  // Merge: each pair's stage-1 rows, then its stage-2 rows.
+  std::vector<StageMerge> plan_h(P);
+  std::vector<int64_t> final_off(P + 1, 0);
+  for (size_t k = 0; k < P; ++k) {
+    StageMerge& m = plan_h[k];
+    m.src1 = off1[k];
+    m.n1 = int32_t(off1[k + 1] - off1[k]);
+    m.s2 = in2[k];
+    m.src2 = m.s2 >= 0 ? off2[size_t(m.s2)] : 0;
+    m.n2 = m.s2 >= 0 ? int32_t(off2[size_t(m.s2) + 1] - off2[size_t(m.s2)]) : 0;
+    m.shift = vn[3 * k];
+    m.dst = final_off[k];
+    final_off[k + 1] = final_off[k] + m.n1 + m.n2;
+    if (stages) stages[k] = whole[k] ? 0 : (m.s2 >= 0 ? 2 : 1);
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(B + o_merge, plan_h.data(), P * sizeof(StageMerge),
+                              hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(out->offset, final_off.data(), (P + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, launch_merge_stages(reinterpret_cast<const StageMerge*>(B + o_merge), n_pairs,
+                                   rows[0], rows[1], out->query, out->match, out->d1, out->d2,
+                                   out->n_comparisons, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  int32_t flag = 0;
+  HIP_TRY(ctx, hipMemcpy(&flag, ctx->err_dev, sizeof flag, hipMemcpyDeviceToHost));
+  if (flag) {
+    HIP_TRY(ctx, hipMemset(ctx->err_dev, 0, sizeof(int32_t)));
+    return fail(ctx, SFM_EKERNEL, "a kernel raised the device error flag");
+  }
+  return SFM_OK;
 }
 
 int sfm_set_profiling(sfm_ctx* ctx, int32_t enable) {

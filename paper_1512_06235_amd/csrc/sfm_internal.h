@@ -187,6 +187,26 @@ hipError_t launch_triangulate(int64_t n_nodes, const int32_t* label, const int32
                               double* acc, double* X, int32_t* n_obs, int32_t* err,
                               hipStream_t st);
 
+// Staged (preemptive) matching (kernels_stage.hip).
+// A view is a run of consecutive features of one registered image: spec holds
+// (image, first feature, count) per view, checked on the host.
+hipError_t launch_make_views(const ImageDev* images, const int32_t* spec, int32_t n_views,
+                             ImageDev* views, hipStream_t st);
+// Rows of one pair's two stages, placed one after the other at dst.
+struct StageMerge {
+  int64_t src1, src2, dst;
+  int32_t n1, n2;
+  int32_t shift;   // added to a second-stage query index (the first stage's query count)
+  int32_t s2;      // the pair's index in the second stage, -1 if it had none
+};
+struct StageRows {
+  const int32_t *q, *m, *d1, *d2;
+  const int64_t* n_cmp;
+};
+hipError_t launch_merge_stages(const StageMerge* merge, int32_t n_pairs, StageRows one,
+                               StageRows two, int32_t* out_q, int32_t* out_m, int32_t* out_d1,
+                               int32_t* out_d2, int64_t* out_cmp, hipStream_t st);
+
 // Workspace admission for the serving loop: an upper bound on the bytes one
 // pair adds to a batched call's workspace, the bytes every call needs
 // besides its pairs, and the context's workspace budget.
