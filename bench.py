@@ -397,6 +397,36 @@ def coarse_matching(sfm, scene, log_fn, reps=5):
     return res
 
 
+GRID_INPUTS = {}
+
+
+def grid_search(sfm, m, images, pairs, Fs, exact_out, stream, reps=10):
+    """The paper's grid search (Section 6.2.1) on the same batch with d equal
+    to each pair's band: time per call and agreement with the exact band."""
+    out = m.buffers(pairs)
+    batch = sfm.PairBatch(pairs, Fs)
+    opt = sfm.options()
+    run = lambda: sfm.sfm_grid_match(m.ctx, batch, None, out, opt, stream)  # noqa: E731
+    run()
+    sfm.sfm_sync(m.ctx, stream)
+    t = timed(run, reps, stream) / reps
+    sfm.sfm_sync(m.ctx, stream)
+    cmp = int(out.n_comparisons[:len(pairs)].sum())
+    o_g, o_e = out.offset.cpu().numpy(), exact_out.offset.cpu().numpy()
+    qg, mg = out.query.cpu().numpy(), out.match.cpu().numpy()
+    qe, me = exact_out.query.cpu().numpy(), exact_out.match.cpu().numpy()
+    both = 0
+    for p in range(len(pairs)):
+        g = set(zip(qg[o_g[p]:o_g[p + 1]].tolist(), mg[o_g[p]:o_g[p + 1]].tolist()))
+        e = set(zip(qe[o_e[p]:o_e[p + 1]].tolist(), me[o_e[p]:o_e[p + 1]].tolist()))
+        both += len(g & e)
+    GRID_INPUTS.update(images=images, pair=pairs[0], F=Fs[0])
+    return {"workload": "the same 500-pair batch, cells 2d x 2d with d = the band (4 px)",
+            "ms_per_step": t * 1e3, "comparisons": cmp, "comparisons_per_s": cmp / t,
+            "matches": int(o_g[len(pairs)]), "exact_band_matches": int(o_e[len(pairs)]),
+            "exact_matches_also_found": both / max(1, int(o_e[len(pairs)]))}
+
+
 def torch_stream():
     import torch
     return torch.cuda.current_stream(torch.device("cuda", 0))
@@ -455,6 +485,17 @@ def cpu_baseline(images, pairs, Fs, budget_s):
         coarse = {"pairs_per_s": len(sample) / dt, "comparisons_per_s": ncmp / dt,
                   "cores": oracle.threads_used(),
                   "sample": f"first {len(sample)} pairs of the staged coarse workload"}
+    grid = None
+    if GRID_INPUTS:
+        import oracle.grid
+        c = GRID_INPUTS
+        a, b, d = c["pair"]
+        qs = np.arange(min(400, c["images"][a][0].shape[0]))
+        t = time.perf_counter()
+        oracle.grid.grid_match(c["images"], [c["pair"]], [c["F"]], queries=[qs])
+        dt = time.perf_counter() - t
+        grid = {"queries_per_s": len(qs) / dt,
+                "sample": f"first {len(qs)} queries of the batch's first pair (one host thread)"}
     cand = None
     if CANDIDATE_INPUTS:
         import oracle.covis
@@ -467,6 +508,7 @@ def cpu_baseline(images, pairs, Fs, budget_s):
                 "sample": "candidate images of the whole 1,000-image scene (sparse product and "
                           "selection, one host thread)"}
     return {"candidate_images": cand, "tracks": trk, "coarse_matching": coarse,
+            "grid_search": grid,
             "value": cmp / t_used, "unit": "comparisons/s", "cores": oracle.threads_used(),
             "kind": "oracle", "sample": f"first {done} of {len(pairs)} pairs of the same batch, "
             f"{cmp} comparisons in {t_used:.1f} s"}
@@ -597,6 +639,8 @@ def main():
 
     tracks = track_building(sfm, m, images, pairs, out, log)
     coarse = coarse_matching(sfm, WORKLOAD_SCENE["arc"], log)
+    log("bench: grid search of Section 6.2.1 on the batch")
+    grid = grid_search(sfm, m, images, pairs, Fs, out, stream)
 
     context = None
     if not args.no_context:
@@ -663,6 +707,7 @@ def main():
         "stress_serving": stress,
         "tracks": tracks,
         "coarse_matching": coarse,
+        "grid_search": grid,
         "context_bruteforce": context,
         "cpu_baseline": cpu,
     }

@@ -155,6 +155,26 @@ int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
 int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                          const sfm_options* opt, const sfm_matches* out, void* stream);
 
+/* Grid-based approximate candidate search (Section 6.2.1, eqs. 4-9; the
+ * paper's own search, kept as an alternative to the exact band).  band_px of
+ * each pair is the cell parameter d > 0 (finite): b's features are binned
+ * into four grids of 2d x 2d cells shifted by (0,0), (d,0), (0,d), (d,d); the
+ * query's line (x_b^T F x_a = 0) is cut by the bounding box of b's keypoints
+ * at A (first crossing on the edges x = min, x = max, y = min, y = max) and B
+ * (the crossing farthest from A); K + 1 points p_k = (k A + (K - k) B) / K,
+ * K the smallest integer with K d >= |AB|, each select the centre-most of the
+ * four cells holding them (lower grid on ties); C' is the set of features in
+ * the selected cells.  The two nearest of C' and the ratio test of `opt`
+ * decide the match; outputs as sfm_guided_match (n_comparisons = sum of
+ * |C'|).  C' approximates the band: it may include features up to 2d from
+ * the line's sample points and miss band members near cell corners.
+ * Limits: n_b <= 65536 per pair; at most 2^22 cells per grid (SFM_ECAPACITY);
+ * a query whose C' exceeds 4096 features raises the device error flag
+ * (SFM_EKERNEL at sfm_sync) and keeps the first 4096 found.
+ * SFM_EINVAL: bad index, d, F or options. */
+int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                   const sfm_options* opt, const sfm_matches* out, void* stream);
+
 /* Staged matching of coarse features (Section 4, the hybrid scheme modelled
  * on preemptive matching).  Each registered image must list its features in
  * decreasing scale, so that a prefix is its highest-scale part.  For a pair

@@ -101,6 +101,8 @@ def lib() -> C.CDLL:
                                    C.POINTER(sfm_matches), vp],
         "sfm_bruteforce_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
                                  C.POINTER(sfm_matches), vp],
+        "sfm_grid_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
+                           C.POINTER(sfm_matches), vp],
         "sfm_preemptive_match": [vp, C.POINTER(sfm_pair), i32, C.POINTER(sfm_preemptive_cfg),
                                  C.POINTER(sfm_options), C.POINTER(sfm_matches), vp, vp],
         "sfm_sync": [vp, vp],
@@ -145,7 +147,8 @@ def exported_symbols():
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
             "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
             "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay", "sfm_candidate_images",
-            "sfm_set_covis_method", "sfm_tracks", "sfm_triangulate", "sfm_preemptive_match"]
+            "sfm_set_covis_method", "sfm_tracks", "sfm_triangulate", "sfm_preemptive_match",
+            "sfm_grid_match"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -266,6 +269,11 @@ def sfm_preemptive_match(ctx, pairs, out, opt=None, cfg=None, stream=None) -> np
         stages.ctypes.data, stream.cuda_stream if stream is not None else None)
     _check(ctx, st)
     return stages[:pairs.n]
+
+
+def sfm_grid_match(ctx, pairs, F, out, opt, stream=None):
+    """The grid search of Section 6.2.1; band_px of each pair is the cell parameter d."""
+    _call("sfm_grid_match", ctx, pairs, F, out, opt, stream)
 
 
 def sfm_sync(ctx, stream=None) -> None:
@@ -550,6 +558,8 @@ class Matcher:
             sfm_guided_match_plain(self.ctx, pairs, F, out, opt, stream)
         elif form == "bruteforce":
             sfm_bruteforce_match(self.ctx, pairs, F, out, opt, stream)
+        elif form == "grid":
+            sfm_grid_match(self.ctx, pairs, F, out, opt, stream)
         else:
             raise ValueError(form)
         if sync:

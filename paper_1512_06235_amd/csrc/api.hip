@@ -25,6 +25,7 @@ struct sfm_ctx {
   // Registered images.
   int32_t n_images = 0;
   std::vector<int32_t> n_host;
+  std::vector<float> bbox_host;        // 4 per image: min x, min y, max x, max y
   ImageDev* images_dev = nullptr;
   int32_t* norm2_dev = nullptr;
   int64_t* norm_off_dev = nullptr;
@@ -273,6 +274,29 @@ hipError_t prof_mark(sfm_ctx* ctx, hipStream_t st) {
   return hipEventRecord(e, st);
 }
 
+// Every pair's F must be finite and not all zero.
+int check_F(sfm_ctx* ctx, const double* F, int32_t n_pairs) {
+  if (n_pairs > 0 && !F) return fail(ctx, SFM_EINVAL, "F is NULL");
+  for (int32_t k = 0; k < n_pairs; ++k) {
+    bool nonzero = false;
+    for (int t = 0; t < 9; ++t) {
+      const double f = F[9 * size_t(k) + size_t(t)];
+      if (!std::isfinite(f)) {
+        char buf[64];
+        snprintf(buf, sizeof buf, "pair %d: F is not finite", k);
+        return fail(ctx, SFM_EINVAL, buf);
+      }
+      nonzero |= f != 0.0;
+    }
+    if (!nonzero) {
+      char buf[64];
+      snprintf(buf, sizeof buf, "pair %d: F is all zero", k);
+      return fail(ctx, SFM_EINVAL, buf);
+    }
+  }
+  return SFM_OK;
+}
+
 // One matching call over the images of `tab`; the caller holds ctx->mu.
 int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int32_t n_pairs,
                  const double* F, const sfm_options* opt_in, const sfm_matches* out, void* stream,
@@ -286,26 +310,7 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
   std::vector<PairDesc> pd;
   int rc = describe_pairs(ctx, tab, pairs, n_pairs, exhaustive, pd);
   if (rc) return rc;
-  if (!exhaustive) {
-    if (n_pairs > 0 && !F) return fail(ctx, SFM_EINVAL, "F is NULL");
-    for (int32_t k = 0; k < n_pairs; ++k) {
-      bool nonzero = false;
-      for (int t = 0; t < 9; ++t) {
-        const double f = F[9 * size_t(k) + size_t(t)];
-        if (!std::isfinite(f)) {
-          char buf[64];
-          snprintf(buf, sizeof buf, "pair %d: F is not finite", k);
-          return fail(ctx, SFM_EINVAL, buf);
-        }
-        nonzero |= f != 0.0;
-      }
-      if (!nonzero) {
-        char buf[64];
-        snprintf(buf, sizeof buf, "pair %d: F is all zero", k);
-        return fail(ctx, SFM_EINVAL, buf);
-      }
-    }
-  }
+  if (!exhaustive && (rc = check_F(ctx, F, n_pairs))) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const Layout L = plan(pd, ctx->device, ctx->group_tiles);
   if (!out->offset) return fail(ctx, SFM_EINVAL, "out->offset is NULL");
@@ -513,6 +518,7 @@ static void free_registration(sfm_ctx* ctx) {
   ctx->norm_off_dev = nullptr;
   ctx->n_images = 0;
   ctx->n_host.clear();
+  ctx->bbox_host.clear();
 }
 
 int sfm_destroy(sfm_ctx* ctx) {
@@ -586,9 +592,19 @@ int sfm_register_images(sfm_ctx* ctx, const sfm_image* images, int32_t n_images)
     free_registration(ctx);
     return fail(ctx, SFM_EINVAL, "a descriptor byte exceeds 127 or a keypoint is not finite");
   }
+  e = hipMemcpy(host.data(), ctx->images_dev, host.size() * sizeof(ImageDev),
+                hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    free_registration(ctx);
+    return hip_fail(ctx, e, "image registration");
+  }
   ctx->n_images = n_images;
   ctx->n_host.resize(size_t(n_images));
-  for (int32_t k = 0; k < n_images; ++k) ctx->n_host[size_t(k)] = images[k].n;
+  ctx->bbox_host.resize(4 * size_t(n_images));
+  for (int32_t k = 0; k < n_images; ++k) {
+    ctx->n_host[size_t(k)] = images[k].n;
+    for (int c = 0; c < 4; ++c) ctx->bbox_host[4 * size_t(k) + size_t(c)] = host[size_t(k)].bbox[c];
+  }
   return SFM_OK;
 }
 
@@ -617,6 +633,144 @@ int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
 int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                          const sfm_options* opt, const sfm_matches* out, void* stream) {
   return run_match(ctx, pairs, n_pairs, F, opt, out, stream, Form::kExhaustive);
+}
+
+int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                   const sfm_options* opt_in, const sfm_matches* out, void* stream) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (!out || !out->offset) return fail(ctx, SFM_EINVAL, "out or out->offset is NULL");
+  sfm_options opt = {64, 100, 0, 0};
+  if (opt_in) opt = *opt_in;
+  if (opt.ratio_den <= 0 || opt.ratio_num < 0)
+    return fail(ctx, SFM_EINVAL, "ratio_den must be > 0 and ratio_num >= 0");
+  std::vector<PairDesc> pd;
+  int rc = describe_pairs(ctx, registered(ctx), pairs, n_pairs, false, pd);
+  if (rc) return rc;
+  if ((rc = check_F(ctx, F, n_pairs))) return rc;
+  const size_t P = size_t(n_pairs);
+  std::vector<GridPair> gp(P);
+  int64_t sum_na = 0, cells = 0, items = 0;
+  for (size_t k = 0; k < P; ++k) {
+    const sfm_pair& s = pairs[k];
+    if (!(s.band_px > 0.0) || !std::isfinite(s.band_px)) {
+      char buf[96];
+      snprintf(buf, sizeof buf, "pair %zu: the grid needs a finite d > 0 (got %g)", k, s.band_px);
+      return fail(ctx, SFM_EINVAL, buf);
+    }
+    GridPair& g = gp[k];
+    memset(&g, 0, sizeof g);
+    g.a = s.a;
+    g.b = s.b;
+    g.na = pd[k].na;
+    g.nb = pd[k].nb;
+    if (g.nb > kGridMaxTargets) {
+      char buf[96];
+      snprintf(buf, sizeof buf, "pair %zu: %d target features exceed the grid limit %d", k, g.nb,
+               kGridMaxTargets);
+      return fail(ctx, SFM_ECAPACITY, buf);
+    }
+    g.d = s.band_px;
+    for (int c = 0; c < 4; ++c) g.box[c] = double(ctx->bbox_host[4 * size_t(s.b) + size_t(c)]);
+    g.q_off = sum_na;
+    g.item_off = items;
+    const double two_d = 2.0 * g.d;
+    for (int t = 0; t < 4; ++t) {
+      const double sx = (t & 1) ? g.d : 0.0, sy = (t & 2) ? g.d : 0.0;
+      const double fx0 = std::floor((g.box[0] - sx) / two_d), fx1 = std::floor((g.box[2] - sx) / two_d);
+      const double fy0 = std::floor((g.box[1] - sy) / two_d), fy1 = std::floor((g.box[3] - sy) / two_d);
+      const double ncx = fx1 - fx0 + 1.0, ncy = fy1 - fy0 + 1.0;
+      if (!(ncx * ncy <= double(kGridMaxCells)) || std::fabs(fx0) > 1e9 || std::fabs(fy0) > 1e9) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "pair %zu: d = %g makes more than %lld cells per grid", k, g.d,
+                 (long long)kGridMaxCells);
+        return fail(ctx, SFM_ECAPACITY, buf);
+      }
+      g.cx0[t] = int32_t(fx0);
+      g.cy0[t] = int32_t(fy0);
+      g.ncx[t] = int32_t(ncx);
+      g.ncy[t] = int32_t(ncy);
+      g.cell_off[t] = cells;
+      cells += int64_t(ncx) * int64_t(ncy) + 1;
+    }
+    sum_na += g.na;
+    items += 4 * int64_t(g.nb);
+  }
+  if (out->capacity < sum_na) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "output capacity %lld < %lld queries", (long long)out->capacity,
+             (long long)sum_na);
+    return fail(ctx, SFM_ECAPACITY, buf);
+  }
+  if (sum_na > 0 && (!out->query || !out->match || !out->d1 || !out->d2))
+    return fail(ctx, SFM_EINVAL, "output arrays are NULL");
+  if (opt.emit_all && sum_na > 0 &&
+      (!out->all_match || !out->all_d1 || !out->all_d2 || !out->all_count))
+    return fail(ctx, SFM_EINVAL, "emit_all needs all_match, all_d1, all_d2 and all_count");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (n_pairs == 0) {
+    HIP_TRY(ctx, hipMemsetAsync(out->offset, 0, sizeof(int64_t), st));
+    return SFM_OK;
+  }
+  // Workspace: staged part (grid pairs, pair descriptors, F), then tables.
+  size_t o = 0;
+  const size_t o_gp = o; o = align_up(o + P * sizeof(GridPair));
+  const size_t o_pd = o; o = align_up(o + P * sizeof(PairDesc));
+  const size_t o_F = o; o = align_up(o + P * 9 * sizeof(double));
+  const size_t staged = o;
+  const size_t o_start = o; o = align_up(o + size_t(cells) * sizeof(int32_t));
+  const size_t o_cur = o; o = align_up(o + size_t(cells) * sizeof(int32_t));
+  const size_t o_items = o; o = align_up(o + size_t(std::max<int64_t>(items, 1)) * sizeof(int32_t));
+  const size_t o_res = o; o = align_up(o + size_t(std::max<int64_t>(sum_na, 1)) * sizeof(QueryResult));
+  const size_t o_cnt = o; o = align_up(o + P * sizeof(PairCounters));
+  if ((rc = ensure_workspace(ctx, o))) return rc;
+  if ((rc = ensure_pinned(ctx, staged))) return rc;
+  if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
+  HIP_TRY(ctx, hipEventSynchronize(ctx->staging_done));
+  memcpy(ctx->pinned + o_gp, gp.data(), P * sizeof(GridPair));
+  memcpy(ctx->pinned + o_pd, pd.data(), P * sizeof(PairDesc));
+  memcpy(ctx->pinned + o_F, F, P * 9 * sizeof(double));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->ws, ctx->pinned, staged, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->staging_done, st));
+  HIP_TRY(ctx, hipMemsetAsync(ctx->ws + o_cnt, 0, P * sizeof(PairCounters), st));
+
+  GridView gv;
+  memset(&gv, 0, sizeof gv);
+  gv.images = ctx->images_dev;
+  gv.pairs = reinterpret_cast<const GridPair*>(ctx->ws + o_gp);
+  gv.F = reinterpret_cast<const double*>(ctx->ws + o_F);
+  gv.cell_start = reinterpret_cast<int32_t*>(ctx->ws + o_start);
+  gv.cursor = reinterpret_cast<int32_t*>(ctx->ws + o_cur);
+  gv.items = reinterpret_cast<int32_t*>(ctx->ws + o_items);
+  gv.res = reinterpret_cast<QueryResult*>(ctx->ws + o_res);
+  gv.counters = reinterpret_cast<PairCounters*>(ctx->ws + o_cnt);
+  gv.err = ctx->err_dev;
+  gv.n_pairs = n_pairs;
+  gv.ratio_num = opt.ratio_num;
+  gv.ratio_den = opt.ratio_den;
+  gv.accept_single = opt.accept_single ? 1 : 0;
+  gv.keep_counts = opt.emit_all ? 1 : 0;
+  HIP_TRY(ctx, launch_grid(gv, sum_na, st));
+
+  // Ordered emission reads only the pair descriptors, results and counters.
+  BatchView v;
+  memset(&v, 0, sizeof v);
+  v.pairs = reinterpret_cast<const PairDesc*>(ctx->ws + o_pd);
+  v.res = gv.res;
+  v.counters = gv.counters;
+  v.n_pairs = n_pairs;
+  int32_t* am = opt.emit_all ? out->all_match : nullptr;
+  int32_t* ad1 = opt.emit_all ? out->all_d1 : nullptr;
+  int32_t* ad2 = opt.emit_all ? out->all_d2 : nullptr;
+  int32_t* ac = opt.emit_all ? out->all_count : nullptr;
+  HIP_TRY(ctx, launch_emit(v, 0, n_pairs, out->offset, out->query, out->match, out->d1, out->d2,
+                           out->n_comparisons, am, ad1, ad2, ac, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
+  ctx->has_work = true;
+  ctx->last_pairs = n_pairs;
+  ctx->last_counters = o_cnt;
+  return SFM_OK;
 }
 
 int sfm_preemptive_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,

@@ -1,0 +1,264 @@
+// Grid-based approximate candidate search (Section 6.2.1, eqs. 4-9, and the
+// GPU steps 1, 3 and 4 of Appendix A).
+//
+// b's features are binned once per pair into four grids of 2d x 2d cells,
+// shifted by (0,0), (d,0), (0,d) and (d,d).  A query's line is cut by b's
+// keypoint box at A and B; K + 1 equidistant points are taken between them
+// (K the smallest integer with K d >= |AB|), and each point selects the
+// centre-most of the four cells that contain it.  C' is the union of the
+// features of the selected cells, made a set with a per-query bitmap in LDS;
+// the two nearest of C' by exact squared L2 and the ratio test decide the
+// match.  C' approximates the band of eq. (2): it can hold features up to 2d
+// (per axis) from a sample point and miss band members near a cell corner.
+//
+// Every floating-point decision (crossings, sample points, cells, centre
+// distances) is IEEE double with no contraction, in a fixed order, so the
+// result is reproducible bit for bit by a plain implementation of the same
+// steps.
+#include <algorithm>
+#include <cmath>
+
+#include "sfm_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace sfm {
+namespace {
+
+constexpr int kBinThreads = 256;
+
+__device__ __forceinline__ double grid_shift(int g, double d, int axis) {
+  return ((g >> axis) & 1) ? d : 0.0;
+}
+
+// Cell of (x, y) in grid g of pair P, as an index into its table; -1 outside.
+__device__ __forceinline__ int64_t cell_of(const GridPair& P, int g, double x, double y) {
+  const double two_d = 2.0 * P.d;
+  const double sx = grid_shift(g, P.d, 0), sy = grid_shift(g, P.d, 1);
+  const int64_t cx = int64_t(floor((x - sx) / two_d)) - P.cx0[g];
+  const int64_t cy = int64_t(floor((y - sy) / two_d)) - P.cy0[g];
+  if (cx < 0 || cx >= P.ncx[g] || cy < 0 || cy >= P.ncy[g]) return -1;
+  return cy * P.ncx[g] + cx;
+}
+
+__device__ __forceinline__ int32_t load_count(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One workgroup per (pair, grid): count per cell, scan, scatter.  Features
+// of one cell land in any order; C' is a set, so the order never matters.
+__global__ __launch_bounds__(kBinThreads) void grid_bin_kernel(GridView v) {
+  __shared__ int64_t part[kBinThreads];
+  const int32_t p = blockIdx.x >> 2, g = blockIdx.x & 3;
+  const GridPair P = v.pairs[p];
+  const ImageDev B = v.images[P.b];
+  const int64_t ncell = int64_t(P.ncx[g]) * P.ncy[g];
+  int32_t* start = v.cell_start + P.cell_off[g];
+  int32_t* cur = v.cursor + P.cell_off[g];
+  int32_t* items = v.items + P.item_off + int64_t(g) * P.nb;
+  const int t = threadIdx.x;
+  for (int64_t c = t; c < ncell; c += kBinThreads) cur[c] = 0;
+  __syncthreads();
+  for (int32_t j = t; j < P.nb; j += kBinThreads) {
+    const int64_t c = cell_of(P, g, double(B.xy[2 * j]), double(B.xy[2 * j + 1]));
+    if (c < 0) {
+      *v.err = 1;
+      continue;
+    }
+    atomicAdd(&cur[c], 1);
+  }
+  __syncthreads();
+  // Exclusive scan: each thread owns a contiguous run of cells.
+  const int64_t chunk = (ncell + kBinThreads - 1) / kBinThreads;
+  const int64_t c0 = std::min<int64_t>(ncell, chunk * t), c1 = std::min<int64_t>(ncell, c0 + chunk);
+  int64_t sum = 0;
+  for (int64_t c = c0; c < c1; ++c) sum += load_count(&cur[c]);
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < kBinThreads; o <<= 1) {
+    const int64_t add = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  int64_t run = part[t] - sum;
+  for (int64_t c = c0; c < c1; ++c) {
+    const int32_t n = load_count(&cur[c]);
+    start[c] = int32_t(run);
+    __hip_atomic_store(&cur[c], int32_t(run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    run += n;
+  }
+  if (t == kBinThreads - 1) start[ncell] = int32_t(part[t]);
+  __syncthreads();
+  for (int32_t j = t; j < P.nb; j += kBinThreads) {
+    const int64_t c = cell_of(P, g, double(B.xy[2 * j]), double(B.xy[2 * j + 1]));
+    if (c < 0) continue;
+    items[atomicAdd(&cur[c], 1)] = j;
+  }
+}
+
+__device__ __forceinline__ unsigned long long wave_min(unsigned long long x) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(x, o, 64);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+// One wave per query.
+__global__ __launch_bounds__(64) void grid_query_kernel(GridView v, int64_t total) {
+  __shared__ uint32_t bitmap[kGridMaxTargets / 32];
+  __shared__ int32_t cand[kGridMaxCand];
+  __shared__ int32_t ncand;
+  const int64_t gq = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+  if (gq >= total) return;
+  // The pair holding query gq: the last pair whose first query is <= gq.
+  int32_t lo = 0, hi = v.n_pairs - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (v.pairs[mid].q_off <= gq) lo = mid; else hi = mid - 1;
+  }
+  const GridPair P = v.pairs[lo];
+  const int32_t i = int32_t(gq - P.q_off);
+  const int lane = threadIdx.x;
+  const int32_t words = (P.nb + 31) >> 5;
+  for (int32_t w = lane; w < words; w += 64) bitmap[w] = 0;
+  if (lane == 0) ncand = 0;
+  __syncthreads();
+
+  const ImageDev A = v.images[P.a], B = v.images[P.b];
+  const double xa = double(A.xy[2 * i]), ya = double(A.xy[2 * i + 1]);
+  const double* F = v.F + 9 * int64_t(lo);
+  const double la = F[0] * xa + F[1] * ya + F[2];
+  const double lb = F[3] * xa + F[4] * ya + F[5];
+  const double lc = F[6] * xa + F[7] * ya + F[8];
+  // Crossings with the box, on x = x0, x = x1, y = y0, y = y1 in that order.
+  const double x0 = P.box[0], y0 = P.box[1], x1 = P.box[2], y1 = P.box[3];
+  double hx[4], hy[4];
+  int nh = 0;
+  if (lb != 0.0) {
+    const double ya0 = -(la * x0 + lc) / lb;
+    if (y0 <= ya0 && ya0 <= y1) { hx[nh] = x0; hy[nh] = ya0; ++nh; }
+    const double ya1 = -(la * x1 + lc) / lb;
+    if (y0 <= ya1 && ya1 <= y1) { hx[nh] = x1; hy[nh] = ya1; ++nh; }
+  }
+  if (la != 0.0) {
+    const double xb0 = -(lb * y0 + lc) / la;
+    if (x0 <= xb0 && xb0 <= x1) { hx[nh] = xb0; hy[nh] = y0; ++nh; }
+    const double xb1 = -(lb * y1 + lc) / la;
+    if (x0 <= xb1 && xb1 <= x1) { hx[nh] = xb1; hy[nh] = y1; ++nh; }
+  }
+  if (nh > 0 && P.nb > 0) {
+    const double xA = hx[0], yA = hy[0];
+    double xB = xA, yB = yA, far = -1.0;
+    for (int h = 0; h < nh; ++h) {
+      const double dx = hx[h] - xA, dy = hy[h] - yA;
+      const double r = dx * dx + dy * dy;
+      if (r > far) { xB = hx[h]; yB = hy[h]; far = r; }
+    }
+    const double dx = xB - xA, dy = yB - yA;
+    const double len2 = dx * dx + dy * dy;
+    const double d2 = P.d * P.d;
+    int64_t K = int64_t(ceil(sqrt(len2) / P.d));
+    while (K > 0 && double((K - 1) * (K - 1)) * d2 >= len2) --K;
+    while (double(K * K) * d2 < len2) ++K;
+    const double two_d = 2.0 * P.d;
+    for (int64_t k = lane; k <= K; k += 64) {
+      double px = xA, py = yA;
+      if (K > 0) {
+        const double kd = double(k), rd = double(K - k), Kd = double(K);
+        px = (kd * xA + rd * xB) / Kd;
+        py = (kd * yA + rd * yB) / Kd;
+      }
+      // Centre-most of the four cells holding the point (lower grid on ties).
+      int gsel = 0;
+      double best = INFINITY, bcx = 0.0, bcy = 0.0;
+      for (int g = 0; g < 4; ++g) {
+        const double sx = grid_shift(g, P.d, 0), sy = grid_shift(g, P.d, 1);
+        const double cx = floor((px - sx) / two_d), cy = floor((py - sy) / two_d);
+        const double ex = px - (cx * two_d + sx + P.d);
+        const double ey = py - (cy * two_d + sy + P.d);
+        const double r = ex * ex + ey * ey;
+        if (r < best) { best = r; gsel = g; bcx = cx; bcy = cy; }
+      }
+      const int64_t cx = int64_t(bcx) - P.cx0[gsel], cy = int64_t(bcy) - P.cy0[gsel];
+      if (cx < 0 || cx >= P.ncx[gsel] || cy < 0 || cy >= P.ncy[gsel]) continue;
+      const int32_t* start = v.cell_start + P.cell_off[gsel];
+      const int32_t* items = v.items + P.item_off + int64_t(gsel) * P.nb;
+      const int64_t c = cy * P.ncx[gsel] + cx;
+      for (int32_t s = start[c], e = start[c + 1]; s < e; ++s) {
+        const int32_t j = items[s];
+        const uint32_t bit = 1u << (j & 31);
+        if (atomicOr(&bitmap[j >> 5], bit) & bit) continue;
+        const int32_t slot = atomicAdd(&ncand, 1);
+        if (slot < kGridMaxCand) cand[slot] = j;
+      }
+    }
+  }
+  __syncthreads();
+  int32_t n = ncand;
+  if (n > kGridMaxCand) {
+    if (lane == 0) *v.err = 1;
+    n = kGridMaxCand;
+  }
+
+  // Two nearest of C': packed keys (D << 32 | j) order by distance, then index.
+  uint32_t q[32];
+  const uint4* qd = reinterpret_cast<const uint4*>(A.desc + 128 * int64_t(i));
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    const uint4 u = qd[w];
+    q[4 * w] = u.x; q[4 * w + 1] = u.y; q[4 * w + 2] = u.z; q[4 * w + 3] = u.w;
+  }
+  const int32_t qn = A.norm2[i];
+  unsigned long long b1 = ~0ull, b2 = ~0ull;
+  for (int32_t s = lane; s < n; s += 64) {
+    const int32_t j = cand[s];
+    const uint4* bd = reinterpret_cast<const uint4*>(B.desc + 128 * int64_t(j));
+    uint32_t dot = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      const uint4 u = bd[w];
+      dot = __builtin_amdgcn_udot4(q[4 * w], u.x, dot, false);
+      dot = __builtin_amdgcn_udot4(q[4 * w + 1], u.y, dot, false);
+      dot = __builtin_amdgcn_udot4(q[4 * w + 2], u.z, dot, false);
+      dot = __builtin_amdgcn_udot4(q[4 * w + 3], u.w, dot, false);
+    }
+    const int32_t D = qn + B.norm2[j] - 2 * int32_t(dot);
+    const unsigned long long key = (static_cast<unsigned long long>(uint32_t(D)) << 32) | uint32_t(j);
+    if (key < b1) { b2 = b1; b1 = key; } else if (key < b2) { b2 = key; }
+  }
+  const unsigned long long m1 = wave_min(b1);
+  const unsigned long long m2 = wave_min(b1 == m1 ? b2 : b1);
+  if (lane == 0) {
+    QueryResult r;
+    r.match = n > 0 ? int32_t(uint32_t(m1)) : -1;
+    r.d1 = n > 0 ? int32_t(m1 >> 32) : kDistInf;
+    r.d2 = n > 1 ? int32_t(m2 >> 32) : kDistInf;
+    bool accept = false;
+    if (n >= 2)
+      accept = int64_t(v.ratio_den) * r.d1 < int64_t(v.ratio_num) * r.d2;
+    else if (n == 1)
+      accept = v.accept_single != 0;
+    r.flags = (accept ? 1 : 0) | (v.keep_counts ? (n << 1) : 0);
+    v.res[P.q_off + i] = r;
+    atomicAdd(&v.counters[lo].comparisons, static_cast<unsigned long long>(n));
+    if (accept) atomicAdd(&v.counters[lo].accepted, 1u);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_grid(const GridView& v, int64_t total_queries, hipStream_t st) {
+  if (v.n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grid_bin_kernel, dim3(4 * v.n_pairs), dim3(kBinThreads), 0, st, v);
+  if (total_queries > 0) {
+    const int64_t gx = std::min<int64_t>(total_queries, 1 << 20);
+    const int64_t gy = (total_queries + gx - 1) / gx;
+    hipLaunchKernelGGL(grid_query_kernel, dim3(uint32_t(gx), uint32_t(gy)), dim3(64), 0, st, v,
+                       total_queries);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sfm

@@ -187,6 +187,42 @@ hipError_t launch_triangulate(int64_t n_nodes, const int32_t* label, const int32
                               double* acc, double* X, int32_t* n_obs, int32_t* err,
                               hipStream_t st);
 
+// Grid-based approximate candidate search (kernels_grid.hip).
+constexpr int32_t kGridMaxTargets = 65536;            // features of b (one LDS bit each)
+constexpr int32_t kGridMaxCand = 4096;                // |C'| per query (LDS slots)
+constexpr int64_t kGridMaxCells = int64_t(1) << 22;   // cells of one grid of one pair
+
+// Per pair, filled on the host: the four grids over b's keypoint box.
+struct GridPair {
+  int32_t a, b, na, nb;
+  int64_t q_off;            // into per-query results
+  int64_t item_off;         // into the binned feature lists (4 nb per pair)
+  int64_t cell_off[4];      // into the cell tables (cells + 1 per grid)
+  int32_t cx0[4], cy0[4];   // first cell of each grid
+  int32_t ncx[4], ncy[4];   // cells of each grid
+  double d;                 // cell parameter: cells are 2d x 2d, grids shifted by d
+  double box[4];            // min x, min y, max x, max y of b's keypoints
+};
+
+struct GridView {
+  const ImageDev* images;
+  const GridPair* pairs;
+  const double* F;          // 9 per pair, as given
+  int32_t* cell_start;      // per grid: cells + 1 starts
+  int32_t* cursor;          // per grid: counts, then fill positions
+  int32_t* items;           // feature indices of b ordered by cell, per grid
+  QueryResult* res;
+  PairCounters* counters;
+  int32_t* err;
+  int32_t n_pairs;
+  int32_t ratio_num, ratio_den;
+  int32_t accept_single;
+  int32_t keep_counts;
+};
+// Bins b's features into the four grids of every pair, then finds C', the
+// two nearest candidates and the ratio test for every query.
+hipError_t launch_grid(const GridView& v, int64_t total_queries, hipStream_t st);
+
 // Staged (preemptive) matching (kernels_stage.hip).
 // A view is a run of consecutive features of one registered image: spec holds
 // (image, first feature, count) per view, checked on the host.

@@ -1,0 +1,138 @@
+"""The grid search of Section 6.2.1 (sfm_grid_match) against the oracle.
+
+Every floating-point decision of the grid search is IEEE double in a fixed
+order on both sides, so each query's C' size, nearest index, D1, D2 and
+decision must equal the oracle's exactly."""
+import numpy as np
+import pytest
+
+import scenes
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sfm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1512_06235_amd as sfm
+    sfm.lib()
+    return sfm
+
+
+def _per_query(out, q_off, p):
+    s, e = int(q_off[p]), int(q_off[p + 1])
+    return {"match": out.all_match[s:e].cpu().numpy(), "d1": out.all_d1[s:e].cpu().numpy(),
+            "d2": out.all_d2[s:e].cpu().numpy(), "count": out.all_count[s:e].cpu().numpy()}
+
+
+def _check(out, images, pairs, Fs, want, queries=None):
+    q_off = np.concatenate([[0], np.cumsum([images[a][0].shape[0] for a, _, _ in pairs])])
+    for p in range(len(pairs)):
+        g = _per_query(out, q_off, p)
+        w = want[p]
+        qs = np.arange(images[pairs[p][0]][0].shape[0]) if queries is None else queries[p]
+        for k in ("match", "d1", "d2", "count"):
+            bad = np.nonzero(g[k][qs] != w[k])[0]
+            assert bad.size == 0, f"pair {p}: {k} differs on {bad.size} queries, first {qs[bad[:5]]}"
+        q, _, _, _ = out.pair(p)
+        if queries is None:
+            assert np.array_equal(q, np.nonzero(w["accept"])[0]), f"pair {p}: accepted set"
+        else:
+            acc = np.zeros(images[pairs[p][0]][0].shape[0], bool)
+            acc[q] = True
+            assert np.array_equal(acc[qs], w["accept"]), f"pair {p}: accepted set"
+
+
+def test_grid_two_view_equals_oracle(sfm):
+    from oracle.grid import grid_match
+    sc = scenes.make_two_view_2k()
+    images = [(im.xy, im.desc) for im in sc.images]
+    m = sfm.Matcher().register(images)
+    for d in (2.0, 4.0, 7.5):
+        pairs = [(0, 1, d)]
+        out = m.match(pairs, [sc.F], form="grid", emit_all=True)
+        want = grid_match(images, pairs, [sc.F])
+        _check(out, images, pairs, [sc.F], want)
+        say(f"  two-view d={d}: {int(out.offset[1])} matches, mean |C'| "
+            f"{want[0]['count'].mean():.1f}")
+    m.close()
+
+
+def test_grid_batch_equals_oracle(sfm):
+    """Pairs of a 12-view arc with several d, an empty target image and
+    ragged sizes."""
+    from oracle.grid import grid_match
+    centers = [(20 * np.sin(a), 0.0, 20 * np.cos(a)) for a in np.deg2rad(np.linspace(-30, 30, 8))]
+    scene = scenes.make_multiview_scene(centers, 700, 2500, seed=9)
+    images = [(scene.image(k).xy, scene.image(k).desc) for k in range(8)]
+    images.append((np.zeros((0, 2), np.float32), np.zeros((0, 128), np.uint8)))
+    pairs = [(0, 1, 4.0), (1, 0, 2.5), (2, 5, 6.0), (3, 4, 4.0), (6, 7, 3.0), (7, 2, 9.0),
+             (0, 8, 4.0), (4, 3, 1.5)]
+    Fs = np.stack([scene.F(a, b) if b < 8 else scene.F(a, 1) for a, b, _ in pairs])
+    m = sfm.Matcher().register(images)
+    out = m.match(pairs, Fs, form="grid", emit_all=True)
+    want = grid_match(images, pairs, Fs)
+    _check(out, images, pairs, Fs, want)
+    n = int(out.offset[len(pairs)])
+    say(f"  batch of {len(pairs)} pairs: {n} matches")
+    m.close()
+
+
+def test_grid_full_batch_sampled_and_recall(sfm):
+    """The 500-pair batch with d = 4: 200 queries of five pairs against the
+    oracle; agreement with the exact band on every pair."""
+    import bench
+    from oracle.grid import grid_match
+    images, pairs, Fs, _ = bench.arc_batch_workload()
+    m = sfm.Matcher().register(images)
+    out = m.match(pairs, Fs, form="grid", emit_all=True)
+    exact = m.match(pairs, Fs, form="batched")
+    sample = [0, 7, 123, 311, 499]
+    rng = np.random.default_rng(3)
+    qsel = [np.sort(rng.choice(images[pairs[p][0]][0].shape[0], 200, replace=False))
+            for p in sample]
+    want = grid_match(images, [pairs[p] for p in sample], Fs[sample], queries=qsel)
+    q_off = np.concatenate([[0], np.cumsum([images[a][0].shape[0] for a, _, _ in pairs])])
+    for t, p in enumerate(sample):
+        g = _per_query(out, q_off, p)
+        for k in ("match", "d1", "d2", "count"):
+            assert np.array_equal(g[k][qsel[t]], want[t][k]), f"pair {p}: {k} differs"
+    # Agreement with the exact band: matches found by both, per pair summed.
+    both = total_exact = total_grid = 0
+    for p in range(len(pairs)):
+        qe, me, _, _ = exact.pair(p)
+        qg, mg, _, _ = out.pair(p)
+        e = set(zip(qe.tolist(), me.tolist()))
+        gset = set(zip(qg.tolist(), mg.tolist()))
+        both += len(e & gset)
+        total_exact += len(e)
+        total_grid += len(gset)
+    say(f"  grid d=4 vs exact band 4: {total_grid} vs {total_exact} matches, "
+        f"{both / max(1, total_exact):.3f} of the exact ones found")
+    assert both / total_exact > 0.8
+    m.close()
+
+
+def test_grid_errors(sfm):
+    sc = scenes.make_two_view_2k()
+    images = [(im.xy, im.desc) for im in sc.images]
+    rng = np.random.default_rng(0)
+    big = (rng.uniform(0, 1000, size=(70000, 2)).astype(np.float32),
+           rng.integers(0, 128, size=(70000, 128), dtype=np.uint8))
+    m = sfm.Matcher().register(images + [big])
+    for d, status in ((0.0, sfm.SFM_EINVAL), (float("inf"), sfm.SFM_EINVAL),
+                      (0.05, sfm.SFM_ECAPACITY)):
+        with pytest.raises(sfm.SfmError) as e:
+            m.match([(0, 1, d)], [sc.F], form="grid")
+        assert e.value.status == status
+    with pytest.raises(sfm.SfmError) as e:
+        m.match([(0, 2, 4.0)], [sc.F], form="grid")
+    assert e.value.status == sfm.SFM_ECAPACITY
+    out = m.match([], np.zeros((0, 3, 3)), form="grid")
+    assert int(out.offset[0]) == 0
+    out = m.match([(0, 1, 4.0)], [sc.F], form="grid")      # still usable
+    assert int(out.offset[1]) > 0
+    m.close()
