@@ -85,12 +85,22 @@ __global__ __launch_bounds__(256) void uf_union_kernel(int32_t* parent, const in
   }
 }
 
-// Final labels in place: every node points straight at its root (a write of
-// an ancestor, like the halving writes of concurrent finds).
+// Root of x without writing: the labelling pass below must not use the
+// halving find, whose writes (an ancestor read before another thread stored
+// its node's root) could replace a finished label by a non-root ancestor.
+__device__ __forceinline__ int32_t uf_root(const int32_t* parent, int32_t x) {
+  int32_t cur = x, next;
+  while (cur > (next = load_link(&parent[cur]))) cur = next;
+  return cur;
+}
+
+// Final labels in place: every node points straight at its root.  Each
+// thread writes only its own node, and only a root, so concurrent walks see
+// either the old ancestor or the root and every label ends as the root.
 __global__ __launch_bounds__(256) void uf_label_kernel(int32_t* parent, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x)
-    store_link(&parent[i], uf_find(parent, int32_t(i)));
+    store_link(&parent[i], uf_root(parent, int32_t(i)));
 }
 
 // Per observation: its two equations' contributions to the normal equations

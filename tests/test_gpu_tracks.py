@@ -125,3 +125,48 @@ def test_bad_edges_raise(sfm, graph):
         sfm.sfm_tracks(m.ctx, n, bad, label)
         sfm.sfm_sync(m.ctx)
     assert e.value.status == sfm.SFM_EKERNEL
+
+
+def test_tracks_large_graphs_equal_oracle(sfm):
+    """Graphs large enough for many concurrent finds: the 500-pair batch's
+    match graph and a million nodes in long shuffled chains.  The labelling
+    pass once let a path-halving write replace a finished label with a
+    non-root ancestor on the batch's graph."""
+    import torch
+    import bench
+    images, pairs, Fs, _ = bench.arc_batch_workload()
+    m = sfm.Matcher().register(images)
+    out = m.match(pairs, Fs, form="batched")
+    off = np.concatenate([[0], np.cumsum([xy.shape[0] for xy, _ in images])])
+    edges = []
+    for k, (a, b, _) in enumerate(pairs):
+        q, mt, _, _ = out.pair(k)
+        edges.append(np.stack([off[a] + q, off[b] + mt], axis=1))
+    batch_edges = np.concatenate(edges).astype(np.int32)
+    rng = np.random.default_rng(11)
+    n2 = 1_000_000
+    perm = rng.permutation(n2).astype(np.int32)
+    cuts = np.sort(rng.choice(np.arange(1, n2), size=2_000, replace=False))
+    chain = np.ones(n2 - 1, bool)
+    chain[cuts - 1] = False                      # no edge across a cut
+    e2 = np.stack([perm[:-1][chain], perm[1:][chain]], axis=1)
+    seg = np.searchsorted(cuts, np.arange(n2), side="right")
+    a = rng.integers(0, n2, size=200_000)
+    starts = np.concatenate([[0], cuts])
+    ends = np.concatenate([cuts, [n2]])
+    b = starts[seg[a]] + (rng.integers(0, 1 << 30, size=a.size) % (ends[seg[a]] - starts[seg[a]]))
+    e2 = np.concatenate([e2, np.stack([perm[a], perm[b]], axis=1)])
+    e2 = e2[rng.permutation(e2.shape[0])].astype(np.int32)
+    for n, e, what in ((int(off[-1]), batch_edges, "batch graph"), (n2, e2, "chains")):
+        ref = tr.tracks(n, e)
+        d_edges = torch.as_tensor(e).cuda()
+        label = torch.empty(n, dtype=torch.int32, device="cuda")
+        for rep in range(3):
+            label.fill_(-1)
+            sfm.sfm_tracks(m.ctx, n, d_edges, label)
+            sfm.sfm_sync(m.ctx)
+            got = label.cpu().numpy()
+            bad = np.nonzero(got != ref)[0]
+            assert bad.size == 0, f"{what}, run {rep}: {bad.size} labels differ, first {bad[:5]}"
+        say(f"  {what}: {n} nodes, {e.shape[0]} edges, {np.unique(ref).size} components")
+    m.close()
