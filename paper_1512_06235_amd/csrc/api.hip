@@ -718,6 +718,15 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   const size_t o_gp = o; o = align_up(o + P * sizeof(GridPair));
   const size_t o_pd = o; o = align_up(o + P * sizeof(PairDesc));
   const size_t o_F = o; o = align_up(o + P * 9 * sizeof(double));
+  std::vector<int2> blocks;
+  int32_t max_nb = 0;
+  for (size_t k = 0; k < P; ++k) {
+    for (int32_t q0 = 0; q0 < gp[k].na; q0 += kGridQueriesPerBlock)
+      blocks.push_back(make_int2(int32_t(k), q0));
+    max_nb = std::max(max_nb, gp[k].nb);
+  }
+  if (blocks.size() > size_t(INT32_MAX)) return fail(ctx, SFM_ECAPACITY, "too many queries");
+  const size_t o_blk = o; o = align_up(o + std::max<size_t>(blocks.size(), 1) * sizeof(int2));
   const size_t staged = o;
   const size_t o_start = o; o = align_up(o + size_t(cells) * sizeof(int32_t));
   const size_t o_cur = o; o = align_up(o + size_t(cells) * sizeof(int32_t));
@@ -731,6 +740,7 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   memcpy(ctx->pinned + o_gp, gp.data(), P * sizeof(GridPair));
   memcpy(ctx->pinned + o_pd, pd.data(), P * sizeof(PairDesc));
   memcpy(ctx->pinned + o_F, F, P * 9 * sizeof(double));
+  memcpy(ctx->pinned + o_blk, blocks.data(), blocks.size() * sizeof(int2));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->ws, ctx->pinned, staged, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipEventRecord(ctx->staging_done, st));
   HIP_TRY(ctx, hipMemsetAsync(ctx->ws + o_cnt, 0, P * sizeof(PairCounters), st));
@@ -743,6 +753,8 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   gv.cell_start = reinterpret_cast<int32_t*>(ctx->ws + o_start);
   gv.cursor = reinterpret_cast<int32_t*>(ctx->ws + o_cur);
   gv.items = reinterpret_cast<int32_t*>(ctx->ws + o_items);
+  gv.blocks = reinterpret_cast<const int2*>(ctx->ws + o_blk);
+  gv.bitmap_words = std::max(1, (max_nb + 31) / 32);
   gv.res = reinterpret_cast<QueryResult*>(ctx->ws + o_res);
   gv.counters = reinterpret_cast<PairCounters*>(ctx->ws + o_cnt);
   gv.err = ctx->err_dev;
@@ -751,7 +763,7 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   gv.ratio_den = opt.ratio_den;
   gv.accept_single = opt.accept_single ? 1 : 0;
   gv.keep_counts = opt.emit_all ? 1 : 0;
-  HIP_TRY(ctx, launch_grid(gv, sum_na, st));
+  HIP_TRY(ctx, launch_grid(gv, int64_t(blocks.size()), st));
 
   // Ordered emission reads only the pair descriptors, results and counters.
   BatchView v;

@@ -32,13 +32,15 @@ __device__ __forceinline__ double grid_shift(int g, double d, int axis) {
 }
 
 // Cell of (x, y) in grid g of pair P, as an index into its table; -1 outside.
-__device__ __forceinline__ int64_t cell_of(const GridPair& P, int g, double x, double y) {
-  const double two_d = 2.0 * P.d;
-  const double sx = grid_shift(g, P.d, 0), sy = grid_shift(g, P.d, 1);
-  const int64_t cx = int64_t(floor((x - sx) / two_d)) - P.cx0[g];
-  const int64_t cy = int64_t(floor((y - sy) / two_d)) - P.cy0[g];
-  if (cx < 0 || cx >= P.ncx[g] || cy < 0 || cy >= P.ncy[g]) return -1;
-  return cy * P.ncx[g] + cx;
+// (The pair record stays in global memory: indexing its per-grid arrays
+// with a run-time grid number would otherwise put a copy in scratch.)
+__device__ __forceinline__ int64_t cell_of(const GridPair* P, int g, double x, double y) {
+  const double two_d = 2.0 * P->d;
+  const double sx = grid_shift(g, P->d, 0), sy = grid_shift(g, P->d, 1);
+  const int64_t cx = int64_t(floor((x - sx) / two_d)) - P->cx0[g];
+  const int64_t cy = int64_t(floor((y - sy) / two_d)) - P->cy0[g];
+  if (cx < 0 || cx >= P->ncx[g] || cy < 0 || cy >= P->ncy[g]) return -1;
+  return cy * P->ncx[g] + cx;
 }
 
 __device__ __forceinline__ int32_t load_count(const int32_t* p) {
@@ -50,16 +52,17 @@ __device__ __forceinline__ int32_t load_count(const int32_t* p) {
 __global__ __launch_bounds__(kBinThreads) void grid_bin_kernel(GridView v) {
   __shared__ int64_t part[kBinThreads];
   const int32_t p = blockIdx.x >> 2, g = blockIdx.x & 3;
-  const GridPair P = v.pairs[p];
-  const ImageDev B = v.images[P.b];
-  const int64_t ncell = int64_t(P.ncx[g]) * P.ncy[g];
-  int32_t* start = v.cell_start + P.cell_off[g];
-  int32_t* cur = v.cursor + P.cell_off[g];
-  int32_t* items = v.items + P.item_off + int64_t(g) * P.nb;
+  const GridPair* P = v.pairs + p;
+  const ImageDev B = v.images[P->b];
+  const int32_t nb = P->nb;
+  const int64_t ncell = int64_t(P->ncx[g]) * P->ncy[g];
+  int32_t* start = v.cell_start + P->cell_off[g];
+  int32_t* cur = v.cursor + P->cell_off[g];
+  int32_t* items = v.items + P->item_off + int64_t(g) * nb;
   const int t = threadIdx.x;
   for (int64_t c = t; c < ncell; c += kBinThreads) cur[c] = 0;
   __syncthreads();
-  for (int32_t j = t; j < P.nb; j += kBinThreads) {
+  for (int32_t j = t; j < nb; j += kBinThreads) {
     const int64_t c = cell_of(P, g, double(B.xy[2 * j]), double(B.xy[2 * j + 1]));
     if (c < 0) {
       *v.err = 1;
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(kBinThreads) void grid_bin_kernel(GridView v) {
   }
   if (t == kBinThreads - 1) start[ncell] = int32_t(part[t]);
   __syncthreads();
-  for (int32_t j = t; j < P.nb; j += kBinThreads) {
+  for (int32_t j = t; j < nb; j += kBinThreads) {
     const int64_t c = cell_of(P, g, double(B.xy[2 * j]), double(B.xy[2 * j + 1]));
     if (c < 0) continue;
     items[atomicAdd(&cur[c], 1)] = j;
@@ -105,64 +108,50 @@ __device__ __forceinline__ unsigned long long wave_min(unsigned long long x) {
   return x;
 }
 
-// One wave per query.
-__global__ __launch_bounds__(64) void grid_query_kernel(GridView v, int64_t total) {
-  __shared__ uint32_t bitmap[kGridMaxTargets / 32];
-  __shared__ int32_t cand[kGridMaxCand];
-  __shared__ int32_t ncand;
-  const int64_t gq = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
-  if (gq >= total) return;
-  // The pair holding query gq: the last pair whose first query is <= gq.
-  int32_t lo = 0, hi = v.n_pairs - 1;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi + 1) >> 1;
-    if (v.pairs[mid].q_off <= gq) lo = mid; else hi = mid - 1;
-  }
-  const GridPair P = v.pairs[lo];
-  const int32_t i = int32_t(gq - P.q_off);
+// C' of query i of pair pr into the LDS list `cand` (count in *ncand; the
+// bitmap, one bit per feature of b, is clear on entry).  Lanes take the
+// sample points k = lane, lane + 64, ...
+__device__ __forceinline__ void grid_collect(const GridView& v, const GridPair* P, int32_t pr,
+                                             const ImageDev& A, int32_t i, uint32_t* bitmap,
+                                             int32_t* cand, int32_t* ncand) {
   const int lane = threadIdx.x;
-  const int32_t words = (P.nb + 31) >> 5;
-  for (int32_t w = lane; w < words; w += 64) bitmap[w] = 0;
-  if (lane == 0) ncand = 0;
-  __syncthreads();
-
-  const ImageDev A = v.images[P.a], B = v.images[P.b];
   const double xa = double(A.xy[2 * i]), ya = double(A.xy[2 * i + 1]);
-  const double* F = v.F + 9 * int64_t(lo);
+  const double* F = v.F + 9 * int64_t(pr);
   const double la = F[0] * xa + F[1] * ya + F[2];
   const double lb = F[3] * xa + F[4] * ya + F[5];
   const double lc = F[6] * xa + F[7] * ya + F[8];
-  // Crossings with the box, on x = x0, x = x1, y = y0, y = y1 in that order.
-  const double x0 = P.box[0], y0 = P.box[1], x1 = P.box[2], y1 = P.box[3];
-  double hx[4], hy[4];
+  // Crossings with the box, on x = x0, x = x1, y = y0, y = y1 in that order:
+  // A is the first, B the first of those farthest from A.
+  const double x0 = P->box[0], y0 = P->box[1], x1 = P->box[2], y1 = P->box[3];
   int nh = 0;
+  double xA = 0.0, yA = 0.0, xB = 0.0, yB = 0.0, far = -1.0;
+  auto hit = [&](double x, double y) {
+    if (nh++ == 0) { xA = x; yA = y; }
+    const double dx = x - xA, dy = y - yA;
+    const double r = dx * dx + dy * dy;
+    if (r > far) { xB = x; yB = y; far = r; }
+  };
   if (lb != 0.0) {
     const double ya0 = -(la * x0 + lc) / lb;
-    if (y0 <= ya0 && ya0 <= y1) { hx[nh] = x0; hy[nh] = ya0; ++nh; }
+    if (y0 <= ya0 && ya0 <= y1) hit(x0, ya0);
     const double ya1 = -(la * x1 + lc) / lb;
-    if (y0 <= ya1 && ya1 <= y1) { hx[nh] = x1; hy[nh] = ya1; ++nh; }
+    if (y0 <= ya1 && ya1 <= y1) hit(x1, ya1);
   }
   if (la != 0.0) {
     const double xb0 = -(lb * y0 + lc) / la;
-    if (x0 <= xb0 && xb0 <= x1) { hx[nh] = xb0; hy[nh] = y0; ++nh; }
+    if (x0 <= xb0 && xb0 <= x1) hit(xb0, y0);
     const double xb1 = -(lb * y1 + lc) / la;
-    if (x0 <= xb1 && xb1 <= x1) { hx[nh] = xb1; hy[nh] = y1; ++nh; }
+    if (x0 <= xb1 && xb1 <= x1) hit(xb1, y1);
   }
-  if (nh > 0 && P.nb > 0) {
-    const double xA = hx[0], yA = hy[0];
-    double xB = xA, yB = yA, far = -1.0;
-    for (int h = 0; h < nh; ++h) {
-      const double dx = hx[h] - xA, dy = hy[h] - yA;
-      const double r = dx * dx + dy * dy;
-      if (r > far) { xB = hx[h]; yB = hy[h]; far = r; }
-    }
+  if (nh == 0 || P->nb == 0) return;
+  {
     const double dx = xB - xA, dy = yB - yA;
     const double len2 = dx * dx + dy * dy;
-    const double d2 = P.d * P.d;
-    int64_t K = int64_t(ceil(sqrt(len2) / P.d));
+    const double d2 = P->d * P->d;
+    int64_t K = int64_t(ceil(sqrt(len2) / P->d));
     while (K > 0 && double((K - 1) * (K - 1)) * d2 >= len2) --K;
     while (double(K * K) * d2 < len2) ++K;
-    const double two_d = 2.0 * P.d;
+    const double two_d = 2.0 * P->d;
     for (int64_t k = lane; k <= K; k += 64) {
       double px = xA, py = yA;
       if (K > 0) {
@@ -174,35 +163,35 @@ __global__ __launch_bounds__(64) void grid_query_kernel(GridView v, int64_t tota
       int gsel = 0;
       double best = INFINITY, bcx = 0.0, bcy = 0.0;
       for (int g = 0; g < 4; ++g) {
-        const double sx = grid_shift(g, P.d, 0), sy = grid_shift(g, P.d, 1);
+        const double sx = grid_shift(g, P->d, 0), sy = grid_shift(g, P->d, 1);
         const double cx = floor((px - sx) / two_d), cy = floor((py - sy) / two_d);
-        const double ex = px - (cx * two_d + sx + P.d);
-        const double ey = py - (cy * two_d + sy + P.d);
+        const double ex = px - (cx * two_d + sx + P->d);
+        const double ey = py - (cy * two_d + sy + P->d);
         const double r = ex * ex + ey * ey;
         if (r < best) { best = r; gsel = g; bcx = cx; bcy = cy; }
       }
-      const int64_t cx = int64_t(bcx) - P.cx0[gsel], cy = int64_t(bcy) - P.cy0[gsel];
-      if (cx < 0 || cx >= P.ncx[gsel] || cy < 0 || cy >= P.ncy[gsel]) continue;
-      const int32_t* start = v.cell_start + P.cell_off[gsel];
-      const int32_t* items = v.items + P.item_off + int64_t(gsel) * P.nb;
-      const int64_t c = cy * P.ncx[gsel] + cx;
+      const int64_t cx = int64_t(bcx) - P->cx0[gsel], cy = int64_t(bcy) - P->cy0[gsel];
+      if (cx < 0 || cx >= P->ncx[gsel] || cy < 0 || cy >= P->ncy[gsel]) continue;
+      const int32_t* start = v.cell_start + P->cell_off[gsel];
+      const int32_t* items = v.items + P->item_off + int64_t(gsel) * P->nb;
+      const int64_t c = cy * P->ncx[gsel] + cx;
       for (int32_t s = start[c], e = start[c + 1]; s < e; ++s) {
         const int32_t j = items[s];
         const uint32_t bit = 1u << (j & 31);
         if (atomicOr(&bitmap[j >> 5], bit) & bit) continue;
-        const int32_t slot = atomicAdd(&ncand, 1);
+        const int32_t slot = atomicAdd(ncand, 1);
         if (slot < kGridMaxCand) cand[slot] = j;
       }
     }
   }
-  __syncthreads();
-  int32_t n = ncand;
-  if (n > kGridMaxCand) {
-    if (lane == 0) *v.err = 1;
-    n = kGridMaxCand;
-  }
+}
 
-  // Two nearest of C': packed keys (D << 32 | j) order by distance, then index.
+// Two nearest of C' and the ratio test for query i of pair pr.
+__device__ __forceinline__ void grid_decide(const GridView& v, int64_t q_off, int32_t pr,
+                                            const ImageDev& A, const ImageDev& B, int32_t i,
+                                            const int32_t* cand, int32_t n) {
+  const int lane = threadIdx.x;
+  // Packed keys (D << 32 | j) order by distance, then index.
   uint32_t q[32];
   const uint4* qd = reinterpret_cast<const uint4*>(A.desc + 128 * int64_t(i));
 #pragma unroll
@@ -241,22 +230,52 @@ __global__ __launch_bounds__(64) void grid_query_kernel(GridView v, int64_t tota
     else if (n == 1)
       accept = v.accept_single != 0;
     r.flags = (accept ? 1 : 0) | (v.keep_counts ? (n << 1) : 0);
-    v.res[P.q_off + i] = r;
-    atomicAdd(&v.counters[lo].comparisons, static_cast<unsigned long long>(n));
-    if (accept) atomicAdd(&v.counters[lo].accepted, 1u);
+    v.res[q_off + i] = r;
+    atomicAdd(&v.counters[pr].comparisons, static_cast<unsigned long long>(n));
+    if (accept) atomicAdd(&v.counters[pr].accepted, 1u);
+  }
+}
+
+// One wave per workgroup, taking up to kGridQueriesPerBlock consecutive
+// queries of one pair (an entry of the host's block table) one after the
+// other.  LDS: a bitmap with one bit per feature of the largest b of the
+// call, then kGridMaxCand candidate slots and their count.
+__global__ __launch_bounds__(64) void grid_query_kernel(GridView v) {
+  extern __shared__ uint32_t lds[];
+  const int2 blk = v.blocks[blockIdx.x];
+  const int32_t pr = blk.x;
+  const GridPair* P = v.pairs + pr;
+  const ImageDev A = v.images[P->a], B = v.images[P->b];
+  const int64_t q_off = P->q_off;
+  uint32_t* bitmap = lds;
+  int32_t* cand = reinterpret_cast<int32_t*>(lds + v.bitmap_words);
+  int32_t* ncand = cand + kGridMaxCand;
+  const int32_t words = (P->nb + 31) >> 5;
+  const int32_t i_end = min(P->na, blk.y + kGridQueriesPerBlock);
+  for (int32_t i = blk.y; i < i_end; ++i) {
+    for (int32_t w = threadIdx.x; w < words; w += 64) bitmap[w] = 0;
+    if (threadIdx.x == 0) *ncand = 0;
+    __syncthreads();
+    grid_collect(v, P, pr, A, i, bitmap, cand, ncand);
+    __syncthreads();
+    int32_t n = *ncand;
+    if (n > kGridMaxCand) {
+      if (threadIdx.x == 0) *v.err = 1;
+      n = kGridMaxCand;
+    }
+    grid_decide(v, q_off, pr, A, B, i, cand, n);
+    __syncthreads();   // the next query clears the bitmap and the list
   }
 }
 
 }  // namespace
 
-hipError_t launch_grid(const GridView& v, int64_t total_queries, hipStream_t st) {
+hipError_t launch_grid(const GridView& v, int64_t n_blocks, hipStream_t st) {
   if (v.n_pairs <= 0) return hipSuccess;
   hipLaunchKernelGGL(grid_bin_kernel, dim3(4 * v.n_pairs), dim3(kBinThreads), 0, st, v);
-  if (total_queries > 0) {
-    const int64_t gx = std::min<int64_t>(total_queries, 1 << 20);
-    const int64_t gy = (total_queries + gx - 1) / gx;
-    hipLaunchKernelGGL(grid_query_kernel, dim3(uint32_t(gx), uint32_t(gy)), dim3(64), 0, st, v,
-                       total_queries);
+  if (n_blocks > 0) {
+    const size_t lds = sizeof(uint32_t) * (size_t(v.bitmap_words) + kGridMaxCand + 1);
+    hipLaunchKernelGGL(grid_query_kernel, dim3(uint32_t(n_blocks)), dim3(64), lds, st, v);
   }
   return hipGetLastError();
 }

@@ -189,7 +189,8 @@ hipError_t launch_triangulate(int64_t n_nodes, const int32_t* label, const int32
 
 // Grid-based approximate candidate search (kernels_grid.hip).
 constexpr int32_t kGridMaxTargets = 65536;            // features of b (one LDS bit each)
-constexpr int32_t kGridMaxCand = 4096;                // |C'| per query (LDS slots)
+constexpr int32_t kGridMaxCand = 2048;                // |C'| per query (LDS slots)
+constexpr int32_t kGridQueriesPerBlock = 16;          // queries one workgroup takes in turn
 constexpr int64_t kGridMaxCells = int64_t(1) << 22;   // cells of one grid of one pair
 
 // Per pair, filled on the host: the four grids over b's keypoint box.
@@ -211,6 +212,7 @@ struct GridView {
   int32_t* cell_start;      // per grid: cells + 1 starts
   int32_t* cursor;          // per grid: counts, then fill positions
   int32_t* items;           // feature indices of b ordered by cell, per grid
+  const int2* blocks;       // per query workgroup: (pair, first query)
   QueryResult* res;
   PairCounters* counters;
   int32_t* err;
@@ -218,10 +220,12 @@ struct GridView {
   int32_t ratio_num, ratio_den;
   int32_t accept_single;
   int32_t keep_counts;
+  int32_t bitmap_words;     // ceil(largest n_b of the call / 32)
 };
 // Bins b's features into the four grids of every pair, then finds C', the
-// two nearest candidates and the ratio test for every query.
-hipError_t launch_grid(const GridView& v, int64_t total_queries, hipStream_t st);
+// two nearest candidates and the ratio test for every query (n_blocks
+// entries of the block table).
+hipError_t launch_grid(const GridView& v, int64_t n_blocks, hipStream_t st);
 
 // Staged (preemptive) matching (kernels_stage.hip).
 // A view is a run of consecutive features of one registered image: spec holds
