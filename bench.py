@@ -524,6 +524,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-coarse", action="store_true", help="skip staged coarse matching")
+    ap.add_argument("--no-grid", action="store_true", help="skip the grid search")
     ap.add_argument("--no-stress", action="store_true",
                     help="skip the 20,000-request stress-serving run")
     ap.add_argument("--no-autotune", action="store_true",
@@ -638,9 +640,11 @@ def main():
                  "speedup_batched_vs_plain": value / plain_value}
 
     tracks = track_building(sfm, m, images, pairs, out, log)
-    coarse = coarse_matching(sfm, WORKLOAD_SCENE["arc"], log)
-    log("bench: grid search of Section 6.2.1 on the batch")
-    grid = grid_search(sfm, m, images, pairs, Fs, out, stream)
+    coarse = None if args.no_coarse else coarse_matching(sfm, WORKLOAD_SCENE["arc"], log)
+    grid = None
+    if not args.no_grid:
+        log("bench: grid search of Section 6.2.1 on the batch")
+        grid = grid_search(sfm, m, images, pairs, Fs, out, stream)
 
     context = None
     if not args.no_context:
