@@ -40,9 +40,8 @@ import numpy as np
 SHIFTS = ((0, 0), (1, 0), (0, 1), (1, 1))   # in units of d
 
 
-def line_points(F, xa: float, ya: float, box, d: float):
-    """The sample points of eqs. (4)-(5) on the line of (xa, ya), as two float
-    arrays (empty without a crossing)."""
+def crossings(F, xa: float, ya: float, box):
+    """(A, B) of the line of (xa, ya) with the box, or None without a crossing."""
     F = [float(v) for v in np.asarray(F, dtype=np.float64).reshape(9)]
     a = F[0] * xa + F[1] * ya + F[2]
     b = F[3] * xa + F[4] * ya + F[5]
@@ -60,7 +59,7 @@ def line_points(F, xa: float, ya: float, box, d: float):
             if x0 <= x <= x1:
                 hits.append((x, ye))
     if not hits:
-        return np.zeros(0), np.zeros(0)
+        return None
     xA, yA = hits[0]
     xB, yB, best = xA, yA, -1.0
     for x, y in hits:
@@ -68,6 +67,16 @@ def line_points(F, xa: float, ya: float, box, d: float):
         r = dx * dx + dy * dy
         if r > best:
             xB, yB, best = x, y, r
+    return (xA, yA), (xB, yB)
+
+
+def line_points(F, xa: float, ya: float, box, d: float):
+    """The sample points of eqs. (4)-(5) on the line of (xa, ya), as two float
+    arrays (empty without a crossing)."""
+    ab = crossings(F, xa, ya, box)
+    if ab is None:
+        return np.zeros(0), np.zeros(0)
+    (xA, yA), (xB, yB) = ab
     dx, dy = xB - xA, yB - yA
     len2 = dx * dx + dy * dy
     d2 = d * d
@@ -82,13 +91,18 @@ def line_points(F, xa: float, ya: float, box, d: float):
     return (k * xA + (K - k) * xB) / K, (k * yA + (K - k) * yB) / K
 
 
+def keypoint_box(xy_b):
+    xy_b = np.asarray(xy_b, dtype=np.float32).reshape(-1, 2)
+    return (float(xy_b[:, 0].min()), float(xy_b[:, 1].min()),
+            float(xy_b[:, 0].max()), float(xy_b[:, 1].max()))
+
+
 def grid_candidates(xy_b, F, xa: float, ya: float, d: float) -> np.ndarray:
     """C' of one query: ascending feature indices of b."""
     xy_b = np.asarray(xy_b, dtype=np.float32).reshape(-1, 2)
     if xy_b.shape[0] == 0:
         return np.zeros(0, np.int64)
-    box = (float(xy_b[:, 0].min()), float(xy_b[:, 1].min()),
-           float(xy_b[:, 0].max()), float(xy_b[:, 1].max()))
+    box = keypoint_box(xy_b)
     px, py = line_points(F, float(xa), float(ya), box, d)
     if px.size == 0:
         return np.zeros(0, np.int64)
@@ -140,20 +154,64 @@ def two_nearest(q_desc, b_desc, cand, ratio_num=64, ratio_den=100, accept_single
     return j, d1, d2, n, ratio_den * d1 < ratio_num * d2
 
 
+def query_groups(xy_a, xy_b, F, tol_px=2.0):
+    """The 2-px grouping of Section 6.2.2 (App. A step 2): the queries sorted by
+    their line's crossings (A.x, A.y, B.x, B.y, then query index; lines without
+    a crossing last), and a new group wherever a line's A or B lies more than
+    tol_px from the previous line's (a line without a crossing is a group of
+    its own).  Returns the sorted query order and the start of every group in
+    it."""
+    n = xy_a.shape[0]
+    if n == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    if np.asarray(xy_b).reshape(-1, 2).shape[0] == 0:
+        ab = [None] * n
+    else:
+        box = keypoint_box(xy_b)
+        ab = [crossings(F, float(xy_a[i, 0]), float(xy_a[i, 1]), box) for i in range(n)]
+    inf = float("inf")
+    keys = np.array([(inf, inf, inf, inf) if c is None else (c[0][0], c[0][1], c[1][0], c[1][1])
+                     for c in ab], dtype=np.float64).reshape(n, 4)
+    order = np.lexsort((np.arange(n), keys[:, 3], keys[:, 2], keys[:, 1], keys[:, 0]))
+    tol2 = tol_px * tol_px
+    starts = [0]
+    for s in range(1, n):
+        cur, prev = ab[order[s]], ab[order[s - 1]]
+        if cur is None or prev is None:
+            starts.append(s)
+            continue
+        (ax, ay), (bx, by) = cur
+        (px, py), (qx, qy) = prev
+        dA = (ax - px) * (ax - px) + (ay - py) * (ay - py)
+        dB = (bx - qx) * (bx - qx) + (by - qy) * (by - qy)
+        if dA > tol2 or dB > tol2:
+            starts.append(s)
+    return order, np.array(starts, np.int64)
+
+
 def grid_match(images, pairs, Fs, queries=None, ratio_num=64, ratio_den=100,
-               accept_single=False):
+               accept_single=False, group_px=None):
     """images: list of (xy, desc); pairs: list of (a, b, d); Fs (n_pairs, 3, 3).
     Per pair a dict of per-query arrays (match, d1, d2, count, accept) over
-    the queries listed in queries[p] (default: all of a)."""
+    the queries listed in queries[p] (default: all of a).  With group_px, the
+    queries are grouped as in query_groups and every query takes the C' of
+    its group's first line."""
     out = []
     for p, (a, b, d) in enumerate(pairs):
         xa, da = images[int(a)]
         xb, db = images[int(b)]
         qs = np.arange(xa.shape[0]) if queries is None else np.asarray(queries[p])
+        leader = np.arange(xa.shape[0])
+        if group_px is not None:
+            order, starts = query_groups(xa, xb, Fs[p], group_px)
+            ends = np.append(starts[1:], len(order))
+            for s0, s1 in zip(starts, ends):
+                leader[order[s0:s1]] = order[s0]
         res = {k: np.zeros(len(qs), np.int64) for k in ("match", "d1", "d2", "count")}
         res["accept"] = np.zeros(len(qs), bool)
         for t, i in enumerate(qs):
-            cand = grid_candidates(xb, Fs[p], float(xa[i, 0]), float(xa[i, 1]), float(d))
+            li = leader[i]
+            cand = grid_candidates(xb, Fs[p], float(xa[li, 0]), float(xa[li, 1]), float(d))
             m, d1, d2, n, acc = two_nearest(da[i], db, cand, ratio_num, ratio_den, accept_single)
             res["match"][t], res["d1"][t], res["d2"][t], res["count"][t] = m, d1, d2, n
             res["accept"][t] = acc

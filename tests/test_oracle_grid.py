@@ -88,3 +88,43 @@ def test_two_nearest_rules():
     assert two_nearest(q, b, np.array([], np.int64))[:4] == (-1, 2**31 - 1, 2**31 - 1, 0)
     assert two_nearest(q, b, np.array([3]))[4] is False
     assert two_nearest(q, b, np.array([3]), accept_single=True)[4] is True
+
+
+def test_query_groups_by_hand():
+    """Horizontal lines y = y_a (F maps (x, y, 1) to (0, 1, -y)) cross the box
+    x in [0, 100] at A = (0, y), B = (100, y).  Sorted by y, a new group starts
+    where y jumps by more than 2 px from the previous line: the chain 10, 11.5,
+    13 stays one group although its ends are 3 px apart."""
+    from oracle.grid import query_groups
+    F = np.zeros((3, 3))
+    F[1, 2] = 1.0
+    F[2, 1] = -1.0
+    ys = np.array([20.0, 10.0, 13.0, 21.0, 11.5, 40.0, 500.0, 10.0], np.float32)
+    xy_a = np.column_stack([np.zeros_like(ys), ys]).astype(np.float32)
+    xy_b = np.array([[0.0, 0.0], [100.0, 100.0]], np.float32)
+    order, starts = query_groups(xy_a, xy_b, F)
+    # y = 500 misses the box [0, 100]^2: last, a group of its own.
+    assert order.tolist() == [1, 7, 4, 2, 0, 3, 5, 6]
+    assert starts.tolist() == [0, 4, 6, 7]
+    order0, starts0 = query_groups(xy_a, xy_b, F, tol_px=0.0)
+    assert starts0.tolist() == [0, 2, 3, 4, 5, 6, 7]          # only the duplicate y = 10 shares
+
+
+def test_grouped_queries_share_the_leaders_candidates():
+    from oracle.grid import grid_match, query_groups
+    rng = np.random.default_rng(5)
+    n = 600
+    xy = np.column_stack([rng.uniform(0, 300, n), rng.uniform(0, 200, n)]).astype(np.float32)
+    desc = rng.integers(0, 128, size=(n, 128), dtype=np.uint8)
+    # A pencil through a point far to the left: nearby queries give nearby lines.
+    F = np.array([[0.0, -1.0, 100.0], [1.0, 0.0, 1500.0], [-100.0, -1500.0, 0.0]])
+    imgs = [(xy, desc), (xy, desc)]
+    plain = grid_match(imgs, [(0, 1, 3.0)], [F])[0]
+    grouped = grid_match(imgs, [(0, 1, 3.0)], [F], group_px=2.0)[0]
+    order, starts = query_groups(xy, xy, F)
+    ends = np.append(starts[1:], n)
+    assert len(starts) < n                                  # some groups hold several queries
+    for s0, s1 in zip(starts, ends):
+        lead = order[s0]
+        assert grouped["count"][lead] == plain["count"][lead]
+        assert np.all(grouped["count"][order[s0:s1]] == plain["count"][lead])
