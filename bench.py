@@ -420,11 +420,32 @@ def grid_search(sfm, m, images, pairs, Fs, exact_out, stream, reps=10):
         g = set(zip(qg[o_g[p]:o_g[p + 1]].tolist(), mg[o_g[p]:o_g[p + 1]].tolist()))
         e = set(zip(qe[o_e[p]:o_e[p + 1]].tolist(), me[o_e[p]:o_e[p + 1]].tolist()))
         both += len(g & e)
+    n_exact = max(1, int(o_e[len(pairs)]))
+    res = {"workload": "the same 500-pair batch, cells 2d x 2d with d = the band (4 px)",
+           "ms_per_step": t * 1e3, "comparisons": cmp, "comparisons_per_s": cmp / t,
+           "matches": int(o_g[len(pairs)]), "exact_band_matches": int(o_e[len(pairs)]),
+           "exact_matches_also_found": both / n_exact,
+           "queries": int(sum(images[a][0].shape[0] for a, _, _ in pairs))}
+    # The same with the 2-px query grouping of Section 6.2.2, against the
+    # previous line (App. A's stencil) and against the group's first line.
+    for name, lead in (("grouped_2px_previous", False), ("grouped_2px_leader", True)):
+        sfm.sfm_set_grid_grouping(m.ctx, 2.0, lead)
+        run()
+        sfm.sfm_sync(m.ctx, stream)
+        tg = timed(run, reps, stream) / reps
+        groups = sfm.sfm_grid_groups(m.ctx)
+        og = out.offset.cpu().numpy()
+        qg2, mg2 = out.query.cpu().numpy(), out.match.cpu().numpy()
+        both_g = 0
+        for p in range(len(pairs)):
+            g = set(zip(qg2[og[p]:og[p + 1]].tolist(), mg2[og[p]:og[p + 1]].tolist()))
+            e = set(zip(qe[o_e[p]:o_e[p + 1]].tolist(), me[o_e[p]:o_e[p + 1]].tolist()))
+            both_g += len(g & e)
+        res[name] = {"ms_per_step": tg * 1e3, "groups": groups, "matches": int(og[len(pairs)]),
+                     "exact_matches_also_found": both_g / n_exact}
+    sfm.sfm_set_grid_grouping(m.ctx, 0.0)
     GRID_INPUTS.update(images=images, pair=pairs[0], F=Fs[0])
-    return {"workload": "the same 500-pair batch, cells 2d x 2d with d = the band (4 px)",
-            "ms_per_step": t * 1e3, "comparisons": cmp, "comparisons_per_s": cmp / t,
-            "matches": int(o_g[len(pairs)]), "exact_band_matches": int(o_e[len(pairs)]),
-            "exact_matches_also_found": both / max(1, int(o_e[len(pairs)]))}
+    return res
 
 
 def torch_stream():

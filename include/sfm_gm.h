@@ -175,6 +175,19 @@ int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, c
 int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                    const sfm_options* opt, const sfm_matches* out, void* stream);
 
+/* Query grouping for sfm_grid_match (Section 6.2.2, App. A step 2); px = 0
+ * (the default) turns it off, px = 2 is the paper's setting.  With grouping,
+ * the queries of each pair are sorted by their line's crossings with b's box
+ * (A.x, A.y, B.x, B.y, then query index; lines without a crossing last), a
+ * new group starts where A or B lies more than px from the previous line's
+ * (to_leader = 0, App. A's stencil) or from the group's first line's
+ * (to_leader = 1), or where either line has no crossing; every query of a
+ * group takes the C' of the group's first line.  A grouped call is host-synchronous: the host
+ * reads the group count before the last launch.  sfm_grid_groups reports the
+ * groups of the last grouped call.  SFM_EINVAL: px negative or not finite. */
+int sfm_set_grid_grouping(sfm_ctx* ctx, double px, int32_t to_leader);
+int sfm_grid_groups(sfm_ctx* ctx, int64_t* n_groups);
+
 /* Staged matching of coarse features (Section 4, the hybrid scheme modelled
  * on preemptive matching).  Each registered image must list its features in
  * decreasing scale, so that a prefix is its highest-scale part.  For a pair

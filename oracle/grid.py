@@ -154,12 +154,13 @@ def two_nearest(q_desc, b_desc, cand, ratio_num=64, ratio_den=100, accept_single
     return j, d1, d2, n, ratio_den * d1 < ratio_num * d2
 
 
-def query_groups(xy_a, xy_b, F, tol_px=2.0):
+def query_groups(xy_a, xy_b, F, tol_px=2.0, to_leader=False):
     """The 2-px grouping of Section 6.2.2 (App. A step 2): the queries sorted by
     their line's crossings (A.x, A.y, B.x, B.y, then query index; lines without
     a crossing last), and a new group wherever a line's A or B lies more than
-    tol_px from the previous line's (a line without a crossing is a group of
-    its own).  Returns the sorted query order and the start of every group in
+    tol_px from the previous line's (App. A's stencil), or with to_leader from
+    the group's first line's (a line without a crossing is a group of its
+    own).  Returns the sorted query order and the start of every group in
     it."""
     n = xy_a.shape[0]
     if n == 0:
@@ -176,7 +177,7 @@ def query_groups(xy_a, xy_b, F, tol_px=2.0):
     tol2 = tol_px * tol_px
     starts = [0]
     for s in range(1, n):
-        cur, prev = ab[order[s]], ab[order[s - 1]]
+        cur, prev = ab[order[s]], ab[order[starts[-1] if to_leader else s - 1]]
         if cur is None or prev is None:
             starts.append(s)
             continue
@@ -190,7 +191,7 @@ def query_groups(xy_a, xy_b, F, tol_px=2.0):
 
 
 def grid_match(images, pairs, Fs, queries=None, ratio_num=64, ratio_den=100,
-               accept_single=False, group_px=None):
+               accept_single=False, group_px=None, to_leader=False):
     """images: list of (xy, desc); pairs: list of (a, b, d); Fs (n_pairs, 3, 3).
     Per pair a dict of per-query arrays (match, d1, d2, count, accept) over
     the queries listed in queries[p] (default: all of a).  With group_px, the
@@ -203,7 +204,7 @@ def grid_match(images, pairs, Fs, queries=None, ratio_num=64, ratio_den=100,
         qs = np.arange(xa.shape[0]) if queries is None else np.asarray(queries[p])
         leader = np.arange(xa.shape[0])
         if group_px is not None:
-            order, starts = query_groups(xa, xb, Fs[p], group_px)
+            order, starts = query_groups(xa, xb, Fs[p], group_px, to_leader)
             ends = np.append(starts[1:], len(order))
             for s0, s1 in zip(starts, ends):
                 leader[order[s0:s1]] = order[s0]

@@ -103,6 +103,8 @@ def lib() -> C.CDLL:
                                  C.POINTER(sfm_matches), vp],
         "sfm_grid_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
                            C.POINTER(sfm_matches), vp],
+        "sfm_set_grid_grouping": [vp, C.c_double, i32],
+        "sfm_grid_groups": [vp, C.POINTER(i64)],
         "sfm_preemptive_match": [vp, C.POINTER(sfm_pair), i32, C.POINTER(sfm_preemptive_cfg),
                                  C.POINTER(sfm_options), C.POINTER(sfm_matches), vp, vp],
         "sfm_sync": [vp, vp],
@@ -148,7 +150,7 @@ def exported_symbols():
             "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
             "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay", "sfm_candidate_images",
             "sfm_set_covis_method", "sfm_tracks", "sfm_triangulate", "sfm_preemptive_match",
-            "sfm_grid_match"]
+            "sfm_grid_match", "sfm_set_grid_grouping", "sfm_grid_groups"]
 
 
 # --- C names, marshalling only ------------------------------------------------------------
@@ -274,6 +276,18 @@ def sfm_preemptive_match(ctx, pairs, out, opt=None, cfg=None, stream=None) -> np
 def sfm_grid_match(ctx, pairs, F, out, opt, stream=None):
     """The grid search of Section 6.2.1; band_px of each pair is the cell parameter d."""
     _call("sfm_grid_match", ctx, pairs, F, out, opt, stream)
+
+
+def sfm_set_grid_grouping(ctx, px: float, to_leader: bool = False) -> None:
+    """Group queries whose lines cross b's box within px (0 = off) of the
+    previous line's crossings, or of the group's first line's, in sfm_grid_match."""
+    _check(ctx, lib().sfm_set_grid_grouping(ctx, float(px), int(bool(to_leader))))
+
+
+def sfm_grid_groups(ctx) -> int:
+    n = C.c_int64()
+    _check(ctx, lib().sfm_grid_groups(ctx, C.byref(n)))
+    return n.value
 
 
 def sfm_sync(ctx, stream=None) -> None:

@@ -55,6 +55,9 @@ struct sfm_ctx {
   // one launch layout captured once and replayed while the layout repeats.
   bool graph_replay = false;
   int32_t covis_method = 0;   // candidate images: 0 choose, 1 point histogram, 2 bit matrix
+  double grid_group_px = 0.0; // grid search: query grouping distance (0 = off)
+  int32_t grid_group_leader = 0;  // grouping against the group's first line
+  int64_t last_groups = 0;    // query groups of the last grouped grid call
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph = nullptr;
   std::vector<char> graph_key;
@@ -727,7 +730,19 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   }
   if (blocks.size() > size_t(INT32_MAX)) return fail(ctx, SFM_ECAPACITY, "too many queries");
   const size_t o_blk = o; o = align_up(o + std::max<size_t>(blocks.size(), 1) * sizeof(int2));
+  const bool grouped = ctx->grid_group_px > 0.0 && sum_na > 0;
+  if (grouped && sum_na > INT32_MAX / 4) return fail(ctx, SFM_ECAPACITY, "too many queries");
+  const size_t N = size_t(sum_na);
+  const size_t o_seg = o; o = align_up(o + 2 * P * sizeof(int32_t));
   const size_t staged = o;
+  size_t temp_bytes = 0;
+  if (grouped) HIP_TRY(ctx, grid_group_temp_bytes(int32_t(N), n_pairs, &temp_bytes));
+  const size_t o_cross = o; o = align_up(o + (grouped ? N * 4 * sizeof(double) : 0));
+  const size_t o_hit = o; o = align_up(o + (grouped ? N * sizeof(int32_t) : 0));
+  const size_t o_key = o; o = align_up(o + (grouped ? 2 * N * sizeof(unsigned long long) : 0));
+  const size_t o_val = o; o = align_up(o + (grouped ? 2 * N * sizeof(int32_t) : 0));
+  const size_t o_sten = o; o = align_up(o + (grouped ? 3 * N * sizeof(int32_t) : 0));
+  const size_t o_temp = o; o = align_up(o + temp_bytes);
   const size_t o_start = o; o = align_up(o + size_t(cells) * sizeof(int32_t));
   const size_t o_cur = o; o = align_up(o + size_t(cells) * sizeof(int32_t));
   const size_t o_items = o; o = align_up(o + size_t(std::max<int64_t>(items, 1)) * sizeof(int32_t));
@@ -741,6 +756,13 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   memcpy(ctx->pinned + o_pd, pd.data(), P * sizeof(PairDesc));
   memcpy(ctx->pinned + o_F, F, P * 9 * sizeof(double));
   memcpy(ctx->pinned + o_blk, blocks.data(), blocks.size() * sizeof(int2));
+  {
+    int32_t* seg = reinterpret_cast<int32_t*>(ctx->pinned + o_seg);
+    for (size_t k = 0; k < P; ++k) {
+      seg[k] = int32_t(gp[k].q_off);
+      seg[P + k] = int32_t(gp[k].q_off + gp[k].na);
+    }
+  }
   HIP_TRY(ctx, hipMemcpyAsync(ctx->ws, ctx->pinned, staged, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipEventRecord(ctx->staging_done, st));
   HIP_TRY(ctx, hipMemsetAsync(ctx->ws + o_cnt, 0, P * sizeof(PairCounters), st));
@@ -763,7 +785,39 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   gv.ratio_den = opt.ratio_den;
   gv.accept_single = opt.accept_single ? 1 : 0;
   gv.keep_counts = opt.emit_all ? 1 : 0;
-  HIP_TRY(ctx, launch_grid(gv, int64_t(blocks.size()), st));
+  if (!grouped) {
+    HIP_TRY(ctx, launch_grid(gv, int64_t(blocks.size()), st));
+  } else {
+    // Grouping (Section 6.2.2): sort, stencil and scan on the device; the
+    // host reads the group count to size the last launch.
+    HIP_TRY(ctx, launch_grid(gv, 0, st));
+    GroupView g;
+    memset(&g, 0, sizeof g);
+    g.cross = reinterpret_cast<double*>(ctx->ws + o_cross);
+    g.hit = reinterpret_cast<int32_t*>(ctx->ws + o_hit);
+    g.key[0] = reinterpret_cast<unsigned long long*>(ctx->ws + o_key);
+    g.key[1] = g.key[0] + N;
+    g.val[0] = reinterpret_cast<int32_t*>(ctx->ws + o_val);
+    g.val[1] = g.val[0] + N;
+    g.seg_begin = reinterpret_cast<const int32_t*>(ctx->ws + o_seg);
+    g.seg_end = g.seg_begin + P;
+    g.stencil = reinterpret_cast<int32_t*>(ctx->ws + o_sten);
+    g.gid = g.stencil + N;
+    g.gstart = g.gid + N;
+    g.temp = ctx->ws + o_temp;
+    g.temp_bytes = temp_bytes;
+    g.n = int32_t(N);
+    g.tol2 = ctx->grid_group_px * ctx->grid_group_px;
+    g.to_leader = ctx->grid_group_leader;
+    HIP_TRY(ctx, launch_grid_group_prepare(gv, g, st));
+    int32_t n_groups = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&n_groups, g.gid + (N - 1), sizeof(int32_t), hipMemcpyDeviceToHost,
+                                st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (n_groups < 1 || size_t(n_groups) > N) return fail(ctx, SFM_EKERNEL, "bad group count");
+    HIP_TRY(ctx, launch_grid_groups(gv, g, n_groups, st));
+    ctx->last_groups = n_groups;
+  }
 
   // Ordered emission reads only the pair descriptors, results and counters.
   BatchView v;
@@ -782,6 +836,22 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   ctx->has_work = true;
   ctx->last_pairs = n_pairs;
   ctx->last_counters = o_cnt;
+  return SFM_OK;
+}
+
+int sfm_set_grid_grouping(sfm_ctx* ctx, double px, int32_t to_leader) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (!(px >= 0.0) || !std::isfinite(px)) return fail(ctx, SFM_EINVAL, "px must be finite and >= 0");
+  ctx->grid_group_px = px;
+  ctx->grid_group_leader = to_leader ? 1 : 0;
+  return SFM_OK;
+}
+
+int sfm_grid_groups(sfm_ctx* ctx, int64_t* n_groups) {
+  if (!ctx || !n_groups) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  *n_groups = ctx->last_groups;
   return SFM_OK;
 }
 

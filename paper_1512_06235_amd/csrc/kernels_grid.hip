@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <hipcub/hipcub.hpp>
+
 #include "sfm_internal.h"
 
 #pragma clang fp contract(off)
@@ -108,23 +110,20 @@ __device__ __forceinline__ unsigned long long wave_min(unsigned long long x) {
   return x;
 }
 
-// C' of query i of pair pr into the LDS list `cand` (count in *ncand; the
-// bitmap, one bit per feature of b, is clear on entry).  Lanes take the
-// sample points k = lane, lane + 64, ...
-__device__ __forceinline__ void grid_collect(const GridView& v, const GridPair* P, int32_t pr,
-                                             const ImageDev& A, int32_t i, uint32_t* bitmap,
-                                             int32_t* cand, int32_t* ncand) {
-  const int lane = threadIdx.x;
+// The line of query i of pair pr cut by b's keypoint box: crossings on the
+// edges x = x0, x = x1, y = y0, y = y1 in that order; A is the first, B the
+// first of those farthest from A.  False without a crossing.
+__device__ __forceinline__ bool line_crossings(const GridView& v, const GridPair* P, int32_t pr,
+                                               const ImageDev& A, int32_t i, double& xA,
+                                               double& yA, double& xB, double& yB) {
   const double xa = double(A.xy[2 * i]), ya = double(A.xy[2 * i + 1]);
   const double* F = v.F + 9 * int64_t(pr);
   const double la = F[0] * xa + F[1] * ya + F[2];
   const double lb = F[3] * xa + F[4] * ya + F[5];
   const double lc = F[6] * xa + F[7] * ya + F[8];
-  // Crossings with the box, on x = x0, x = x1, y = y0, y = y1 in that order:
-  // A is the first, B the first of those farthest from A.
   const double x0 = P->box[0], y0 = P->box[1], x1 = P->box[2], y1 = P->box[3];
   int nh = 0;
-  double xA = 0.0, yA = 0.0, xB = 0.0, yB = 0.0, far = -1.0;
+  double far = -1.0;
   auto hit = [&](double x, double y) {
     if (nh++ == 0) { xA = x; yA = y; }
     const double dx = x - xA, dy = y - yA;
@@ -143,7 +142,19 @@ __device__ __forceinline__ void grid_collect(const GridView& v, const GridPair* 
     const double xb1 = -(lb * y1 + lc) / la;
     if (x0 <= xb1 && xb1 <= x1) hit(xb1, y1);
   }
-  if (nh == 0 || P->nb == 0) return;
+  return nh > 0;
+}
+
+// C' of query i of pair pr into the LDS list `cand` (count in *ncand; the
+// bitmap, one bit per feature of b, is clear on entry).  Lanes take the
+// sample points k = lane, lane + 64, ...
+__device__ __forceinline__ void grid_collect(const GridView& v, const GridPair* P, int32_t pr,
+                                             const ImageDev& A, int32_t i, uint32_t* bitmap,
+                                             int32_t* cand, int32_t* ncand) {
+  const int lane = threadIdx.x;
+  double xA = 0.0, yA = 0.0, xB = 0.0, yB = 0.0;
+  const bool crosses = line_crossings(v, P, pr, A, i, xA, yA, xB, yB);
+  if (!crosses || P->nb == 0) return;
   {
     const double dx = xB - xA, dy = yB - yA;
     const double len2 = dx * dx + dy * dy;
@@ -268,7 +279,179 @@ __global__ __launch_bounds__(64) void grid_query_kernel(GridView v) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Query grouping: queries whose lines cross b's box within tol of the
+// previous line's crossings (in sorted order) share the first line's C'.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int32_t pair_of(const int32_t* seg_begin, int32_t n_pairs, int32_t t) {
+  int32_t lo = 0, hi = n_pairs - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (seg_begin[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Unsigned key with the order of the double (-0 first made +0).
+__device__ __forceinline__ unsigned long long sortable(double x) {
+  x = x + 0.0;
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ __launch_bounds__(256) void grid_cross_kernel(GridView v, GroupView g) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n) return;
+  const int32_t pr = pair_of(g.seg_begin, v.n_pairs, t);
+  const GridPair* P = v.pairs + pr;
+  const ImageDev A = v.images[P->a];
+  double xA = 0.0, yA = 0.0, xB = 0.0, yB = 0.0;
+  const bool crosses = line_crossings(v, P, pr, A, int32_t(t - P->q_off), xA, yA, xB, yB);
+  g.cross[4 * int64_t(t)] = xA;
+  g.cross[4 * int64_t(t) + 1] = yA;
+  g.cross[4 * int64_t(t) + 2] = xB;
+  g.cross[4 * int64_t(t) + 3] = yB;
+  g.hit[t] = crosses ? 1 : 0;
+  g.val[0][t] = t;
+}
+
+// key[t] = component c of the crossings of position val[t]; lines without a
+// crossing sort last.
+__global__ __launch_bounds__(256) void grid_key_kernel(GroupView g, int c, const int32_t* val,
+                                                       unsigned long long* key) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n) return;
+  const int32_t s = val[t];
+  key[t] = g.hit[s] ? sortable(g.cross[4 * int64_t(s) + c]) : ~0ull;
+}
+
+__global__ __launch_bounds__(256) void grid_stencil_kernel(GridView v, GroupView g) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n) return;
+  const int32_t pr = pair_of(g.seg_begin, v.n_pairs, t);
+  int32_t start = 1;
+  if (t > g.seg_begin[pr]) {
+    const int32_t s = g.val[0][t], q = g.val[0][t - 1];
+    if (g.hit[s] && g.hit[q]) {
+      const double* a = g.cross + 4 * int64_t(s);
+      const double* b = g.cross + 4 * int64_t(q);
+      const double dA = (a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]);
+      const double dB = (a[2] - b[2]) * (a[2] - b[2]) + (a[3] - b[3]) * (a[3] - b[3]);
+      start = (dA > g.tol2 || dB > g.tol2) ? 1 : 0;
+    }
+  }
+  g.stencil[t] = start;
+}
+
+// The same decision against the group's first line: a walk along each
+// pair's sorted queries, one thread per pair.
+__global__ __launch_bounds__(64) void grid_stencil_leader_kernel(GridView v, GroupView g) {
+  const int32_t pr = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pr >= v.n_pairs) return;
+  const int32_t* order = g.val[0];
+  int32_t lead = -1;
+  for (int32_t t = g.seg_begin[pr]; t < g.seg_end[pr]; ++t) {
+    const int32_t s = order[t];
+    int32_t start = 1;
+    if (lead >= 0 && g.hit[s] && g.hit[lead]) {
+      const double* a = g.cross + 4 * int64_t(s);
+      const double* b = g.cross + 4 * int64_t(lead);
+      const double dA = (a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]);
+      const double dB = (a[2] - b[2]) * (a[2] - b[2]) + (a[3] - b[3]) * (a[3] - b[3]);
+      start = (dA > g.tol2 || dB > g.tol2) ? 1 : 0;
+    }
+    if (start) lead = s;
+    g.stencil[t] = start;
+  }
+}
+
+__global__ __launch_bounds__(256) void grid_gstart_kernel(GroupView g) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < g.n && g.stencil[t]) g.gstart[g.gid[t] - 1] = t;
+}
+
+__global__ __launch_bounds__(64) void grid_group_query_kernel(GridView v, GroupView g,
+                                                              int32_t n_groups) {
+  extern __shared__ uint32_t lds[];
+  const int32_t gi = blockIdx.x;
+  const int32_t t0 = g.gstart[gi], t1 = gi + 1 < n_groups ? g.gstart[gi + 1] : g.n;
+  const int32_t pr = pair_of(g.seg_begin, v.n_pairs, t0);
+  const GridPair* P = v.pairs + pr;
+  const ImageDev A = v.images[P->a], B = v.images[P->b];
+  const int64_t q_off = P->q_off;
+  const int32_t* order = g.val[0];
+  uint32_t* bitmap = lds;
+  int32_t* cand = reinterpret_cast<int32_t*>(lds + v.bitmap_words);
+  int32_t* ncand = cand + kGridMaxCand;
+  const int32_t words = (P->nb + 31) >> 5;
+  for (int32_t w = threadIdx.x; w < words; w += 64) bitmap[w] = 0;
+  if (threadIdx.x == 0) *ncand = 0;
+  __syncthreads();
+  grid_collect(v, P, pr, A, int32_t(order[t0] - q_off), bitmap, cand, ncand);
+  __syncthreads();
+  int32_t n = *ncand;
+  if (n > kGridMaxCand) {
+    if (threadIdx.x == 0) *v.err = 1;
+    n = kGridMaxCand;
+  }
+  for (int32_t t = t0; t < t1; ++t) grid_decide(v, q_off, pr, A, B, int32_t(order[t] - q_off), cand, n);
+}
+
+int32_t blocks256(int32_t n) { return (n + 255) / 256; }
+
 }  // namespace
+
+hipError_t grid_group_temp_bytes(int32_t n, int32_t n_pairs, size_t* bytes) {
+  size_t sort_bytes = 0, scan_bytes = 0;
+  hipError_t e = hipcub::DeviceSegmentedRadixSort::SortPairs(
+      nullptr, sort_bytes, static_cast<const unsigned long long*>(nullptr),
+      static_cast<unsigned long long*>(nullptr), static_cast<const int32_t*>(nullptr),
+      static_cast<int32_t*>(nullptr), n, n_pairs, static_cast<const int32_t*>(nullptr),
+      static_cast<const int32_t*>(nullptr));
+  if (e != hipSuccess) return e;
+  e = hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, static_cast<const int32_t*>(nullptr),
+                                       static_cast<int32_t*>(nullptr), n);
+  *bytes = std::max(sort_bytes, scan_bytes);
+  return e;
+}
+
+hipError_t launch_grid_group_prepare(const GridView& v, const GroupView& g, hipStream_t st) {
+  if (g.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grid_cross_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, v, g);
+  // Least significant component first; each pass is a stable sort.
+  int cur = 0;
+  for (int c = 3; c >= 0; --c) {
+    hipLaunchKernelGGL(grid_key_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, g, c,
+                       g.val[cur], g.key[0]);
+    size_t bytes = g.temp_bytes;
+    hipError_t e = hipcub::DeviceSegmentedRadixSort::SortPairs(
+        g.temp, bytes, g.key[0], g.key[1], g.val[cur], g.val[1 - cur], g.n, v.n_pairs,
+        g.seg_begin, g.seg_end, 0, 64, st);
+    if (e != hipSuccess) return e;
+    cur = 1 - cur;
+  }
+  // Four passes end in val[0].
+  if (g.to_leader)
+    hipLaunchKernelGGL(grid_stencil_leader_kernel, dim3((v.n_pairs + 63) / 64), dim3(64), 0, st,
+                       v, g);
+  else
+    hipLaunchKernelGGL(grid_stencil_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, v, g);
+  size_t bytes = g.temp_bytes;
+  hipError_t e = hipcub::DeviceScan::InclusiveSum(g.temp, bytes, g.stencil, g.gid, g.n, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(grid_gstart_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_groups(const GridView& v, const GroupView& g, int32_t n_groups,
+                              hipStream_t st) {
+  if (n_groups <= 0) return hipSuccess;
+  const size_t lds = sizeof(uint32_t) * (size_t(v.bitmap_words) + kGridMaxCand + 1);
+  hipLaunchKernelGGL(grid_group_query_kernel, dim3(uint32_t(n_groups)), dim3(64), lds, st, v, g,
+                     n_groups);
+  return hipGetLastError();
+}
 
 hipError_t launch_grid(const GridView& v, int64_t n_blocks, hipStream_t st) {
   if (v.n_pairs <= 0) return hipSuccess;

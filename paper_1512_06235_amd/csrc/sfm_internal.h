@@ -224,8 +224,35 @@ struct GridView {
 };
 // Bins b's features into the four grids of every pair, then finds C', the
 // two nearest candidates and the ratio test for every query (n_blocks
-// entries of the block table).
+// entries of the block table; 0 = binning only).
 hipError_t launch_grid(const GridView& v, int64_t n_blocks, hipStream_t st);
+
+// Query grouping (Section 6.2.2): buffers over the n query positions of a
+// call (position = the pair's first query + query index).
+struct GroupView {
+  double* cross;                 // 4 per position: A.x, A.y, B.x, B.y
+  int32_t* hit;                  // 1 if the line crosses b's box
+  unsigned long long* key[2];    // sort keys, ping-pong
+  int32_t* val[2];               // positions in sorted order, ping-pong (result in val[0])
+  const int32_t* seg_begin;      // per pair: first position
+  const int32_t* seg_end;        // per pair: one past the last
+  int32_t* stencil;              // 1 where a group starts
+  int32_t* gid;                  // inclusive scan of the stencil
+  int32_t* gstart;               // per group: its first sorted position
+  void* temp;                    // library sort / scan storage
+  size_t temp_bytes;
+  int32_t n;
+  int32_t to_leader;             // compare with the group's first line, not the previous one
+  double tol2;                   // squared grouping distance (px^2)
+};
+hipError_t grid_group_temp_bytes(int32_t n, int32_t n_pairs, size_t* bytes);
+// Crossings, the lexicographic sort of (A.x, A.y, B.x, B.y) within each pair,
+// the stencil, its scan and the group starts; gid[n - 1] is the group count.
+hipError_t launch_grid_group_prepare(const GridView& v, const GroupView& g, hipStream_t st);
+// One wave per group: C' of the group's first line, then every member's
+// two nearest and ratio test.
+hipError_t launch_grid_groups(const GridView& v, const GroupView& g, int32_t n_groups,
+                              hipStream_t st);
 
 // Staged (preemptive) matching (kernels_stage.hip).
 // A view is a run of consecutive features of one registered image: spec holds

@@ -136,3 +136,38 @@ def test_grid_errors(sfm):
     out = m.match([(0, 1, 4.0)], [sc.F], form="grid")      # still usable
     assert int(out.offset[1]) > 0
     m.close()
+
+
+def test_grid_grouped_equals_oracle(sfm):
+    """The 2-px query grouping of Section 6.2.2: per-query results and the
+    number of groups equal the oracle's, on the two-view pair and a ragged
+    batch; grouping off again gives the ungrouped results."""
+    from oracle.grid import grid_match, query_groups
+    sc = scenes.make_two_view_2k()
+    centers = [(20 * np.sin(a), 0.0, 20 * np.cos(a)) for a in np.deg2rad(np.linspace(-30, 30, 6))]
+    scene = scenes.make_multiview_scene(centers, 700, 2500, seed=4)
+    images = [(im.xy, im.desc) for im in sc.images]
+    images += [(scene.image(k).xy, scene.image(k).desc) for k in range(6)]
+    images.append((np.zeros((0, 2), np.float32), np.zeros((0, 128), np.uint8)))
+    pairs = [(0, 1, 4.0), (2, 3, 4.0), (4, 7, 3.0), (5, 2, 6.0), (6, 5, 4.0), (2, 8, 4.0),
+             (3, 4, 2.5)]
+    Fs = [sc.F] + [scene.F(a - 2, b - 2 if b < 8 else 1) for a, b, _ in pairs[1:]]
+    Fs = np.stack(Fs)
+    m = sfm.Matcher().register(images)
+    with pytest.raises(sfm.SfmError):
+        sfm.sfm_set_grid_grouping(m.ctx, -1.0)
+    for px, lead in ((2.0, False), (0.5, False), (2.0, True)):
+        sfm.sfm_set_grid_grouping(m.ctx, px, lead)
+        out = m.match(pairs, Fs, form="grid", emit_all=True)
+        want = grid_match(images, pairs, Fs, group_px=px, to_leader=lead)
+        _check(out, images, pairs, Fs, want)
+        groups = sum(len(query_groups(images[a][0], images[b][0], Fs[p], px, lead)[1])
+                     for p, (a, b, _) in enumerate(pairs))
+        assert sfm.sfm_grid_groups(m.ctx) == groups
+        nq = sum(images[a][0].shape[0] for a, _, _ in pairs)
+        say(f"  grouped px={px} to_leader={lead}: {groups} groups for {nq} queries, "
+            f"{int(out.offset[len(pairs)])} matches")
+    sfm.sfm_set_grid_grouping(m.ctx, 0.0)
+    out = m.match(pairs, Fs, form="grid", emit_all=True)
+    _check(out, images, pairs, Fs, grid_match(images, pairs, Fs))
+    m.close()

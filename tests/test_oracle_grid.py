@@ -108,6 +108,9 @@ def test_query_groups_by_hand():
     assert starts.tolist() == [0, 4, 6, 7]
     order0, starts0 = query_groups(xy_a, xy_b, F, tol_px=0.0)
     assert starts0.tolist() == [0, 2, 3, 4, 5, 6, 7]          # only the duplicate y = 10 shares
+    # Against the group's first line instead: 13 is 3 px from 10, a new group.
+    _, starts1 = query_groups(xy_a, xy_b, F, to_leader=True)
+    assert starts1.tolist() == [0, 3, 4, 6, 7]
 
 
 def test_grouped_queries_share_the_leaders_candidates():
