@@ -345,24 +345,46 @@ __global__ __launch_bounds__(256) void grid_stencil_kernel(GridView v, GroupView
 }
 
 // The same decision against the group's first line: a walk along each
-// pair's sorted queries, one thread per pair.
+// pair's sorted queries.  One wave per pair loads 64 positions at a time into
+// LDS; its first lane then walks them in order, carrying the leader.
 __global__ __launch_bounds__(64) void grid_stencil_leader_kernel(GridView v, GroupView g) {
-  const int32_t pr = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pr >= v.n_pairs) return;
+  __shared__ double cx[64][4];
+  __shared__ int32_t hs[64], out[64];
+  const int32_t pr = blockIdx.x;
+  const int lane = threadIdx.x;
   const int32_t* order = g.val[0];
-  int32_t lead = -1;
-  for (int32_t t = g.seg_begin[pr]; t < g.seg_end[pr]; ++t) {
-    const int32_t s = order[t];
-    int32_t start = 1;
-    if (lead >= 0 && g.hit[s] && g.hit[lead]) {
-      const double* a = g.cross + 4 * int64_t(s);
-      const double* b = g.cross + 4 * int64_t(lead);
-      const double dA = (a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]);
-      const double dB = (a[2] - b[2]) * (a[2] - b[2]) + (a[3] - b[3]) * (a[3] - b[3]);
-      start = (dA > g.tol2 || dB > g.tol2) ? 1 : 0;
+  const int32_t begin = g.seg_begin[pr], end = g.seg_end[pr];
+  bool have_lead = false, lead_hit = false;
+  double L0 = 0.0, L1 = 0.0, L2 = 0.0, L3 = 0.0;
+  for (int32_t base = begin; base < end; base += 64) {
+    const int32_t t = base + lane;
+    if (t < end) {
+      const int32_t s = order[t];
+      hs[lane] = g.hit[s];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cx[lane][c] = g.cross[4 * int64_t(s) + c];
     }
-    if (start) lead = s;
-    g.stencil[t] = start;
+    __syncthreads();
+    if (lane == 0) {
+      const int32_t cnt = min(64, end - base);
+      for (int32_t k = 0; k < cnt; ++k) {
+        int32_t start = 1;
+        if (have_lead && hs[k] && lead_hit) {
+          const double dA = (cx[k][0] - L0) * (cx[k][0] - L0) + (cx[k][1] - L1) * (cx[k][1] - L1);
+          const double dB = (cx[k][2] - L2) * (cx[k][2] - L2) + (cx[k][3] - L3) * (cx[k][3] - L3);
+          start = (dA > g.tol2 || dB > g.tol2) ? 1 : 0;
+        }
+        if (start) {
+          have_lead = true;
+          lead_hit = hs[k] != 0;
+          L0 = cx[k][0]; L1 = cx[k][1]; L2 = cx[k][2]; L3 = cx[k][3];
+        }
+        out[k] = start;
+      }
+    }
+    __syncthreads();
+    if (t < end) g.stencil[t] = out[lane];
+    __syncthreads();
   }
 }
 
@@ -433,8 +455,7 @@ hipError_t launch_grid_group_prepare(const GridView& v, const GroupView& g, hipS
   }
   // Four passes end in val[0].
   if (g.to_leader)
-    hipLaunchKernelGGL(grid_stencil_leader_kernel, dim3((v.n_pairs + 63) / 64), dim3(64), 0, st,
-                       v, g);
+    hipLaunchKernelGGL(grid_stencil_leader_kernel, dim3(v.n_pairs), dim3(64), 0, st, v, g);
   else
     hipLaunchKernelGGL(grid_stencil_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, v, g);
   size_t bytes = g.temp_bytes;
