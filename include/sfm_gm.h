@@ -405,8 +405,10 @@ int sfm_set_covis_method(sfm_ctx* ctx, int32_t method);
  * equations (x p3 - p1).(X, 1) = 0, (y p3 - p2).(X, 1) = 0, solved by the
  * FP64 normal equations.  X[3 r ..] (device, 3 n_nodes doubles) receives the
  * point, NaN for tracks of one observation or a singular system;
- * n_obs[r] its number of observations, 0 for non-roots.  Uses 80 n_nodes
- * bytes of workspace.  Asynchronous on `stream`. */
+ * n_obs[r] its number of observations, 0 for non-roots.  Uses 16 n_nodes
+ * bytes of workspace (per-track member lists) plus a scan's storage.  A
+ * label or image index out of range raises the device error flag.
+ * Asynchronous on `stream`. */
 int sfm_tracks(sfm_ctx* ctx, int64_t n_nodes, const int32_t* edges, int64_t n_edges,
                int32_t* label, void* stream);
 int sfm_triangulate(sfm_ctx* ctx, int64_t n_nodes, const int32_t* label, const int32_t* node_image,

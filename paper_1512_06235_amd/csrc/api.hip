@@ -1203,11 +1203,15 @@ int sfm_triangulate(sfm_ctx* ctx, int64_t n_nodes, const int32_t* label, const i
     return fail(ctx, SFM_EINVAL, "a pointer is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  int rc = ensure_workspace(ctx, align_up(size_t(std::max<int64_t>(n_nodes, 1)) * 10 * sizeof(double)));
+  size_t temp_bytes = 0;
+  HIP_TRY(ctx, triangulate_temp_bytes(n_nodes, &temp_bytes));
+  const size_t lists = align_up(size_t(std::max<int64_t>(n_nodes, 1)) * 4 * sizeof(int32_t));
+  int rc = ensure_workspace(ctx, lists + align_up(temp_bytes));
   if (rc) return rc;
   if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
   HIP_TRY(ctx, launch_triangulate(n_nodes, label, node_image, node_xy, P, n_images,
-                                  reinterpret_cast<double*>(ctx->ws), X, n_obs, ctx->err_dev, st));
+                                  reinterpret_cast<int32_t*>(ctx->ws), ctx->ws + lists, temp_bytes,
+                                  X, n_obs, ctx->err_dev, st));
   HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
   ctx->has_work = true;
   ctx->last_pairs = 0;

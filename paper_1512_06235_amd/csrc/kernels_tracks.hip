@@ -11,20 +11,24 @@
 //
 // Each track is then triangulated by linear least squares in FP64: an
 // observation (x, y) in a camera with rows p1, p2, p3 gives the equations
-// (x p3 - p1) . (X, 1) = 0 and (y p3 - p2) . (X, 1) = 0; the normal
-// equations of X are summed per track and solved in closed form.
+// (x p3 - p1) . (X, 1) = 0 and (y p3 - p2) . (X, 1) = 0.  The members of
+// every track are gathered into lists (count, scan, scatter), and one thread
+// per track sums its normal equations in registers and solves them in
+// closed form.
 #include <algorithm>
 #include <cmath>
+
+#include <hipcub/hipcub.hpp>
 
 #include "sfm_internal.h"
 
 namespace sfm {
 namespace {
 
-__global__ __launch_bounds__(256) void fill_f64_kernel(double* p, int64_t n) {
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x)
-    p[i] = 0.0;
+    p[i] = 0;
 }
 
 // Parent links are read and written as device-scope atomics: another CU's
@@ -103,13 +107,12 @@ __global__ __launch_bounds__(256) void uf_label_kernel(int32_t* parent, int64_t 
     store_link(&parent[i], uf_root(parent, int32_t(i)));
 }
 
-// Per observation: its two equations' contributions to the normal equations
-// of its track (root r = label[i]): acc[10 r ..] = the upper triangle of
-// M = sum a a^T over the first three coefficients (6), the right side
-// sum -a a4 (3), and the number of observations.
-__global__ __launch_bounds__(256) void tri_accumulate_kernel(
-    const int32_t* label, const int32_t* node_image, const float* node_xy, const double* P,
-    int32_t n_images, int64_t n_nodes, double* acc, int32_t* err) {
+// Observations per track: count per root, then (after a scan) each node's
+// slot in its root's member list.
+__global__ __launch_bounds__(256) void tri_count_kernel(const int32_t* label,
+                                                        const int32_t* node_image,
+                                                        int32_t n_images, int64_t n_nodes,
+                                                        int32_t* cnt, int32_t* err) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_nodes;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int32_t r = label[i], img = node_image[i];
@@ -117,54 +120,78 @@ __global__ __launch_bounds__(256) void tri_accumulate_kernel(
       *err = 1;
       continue;
     }
-    const double* p = P + 12 * int64_t(img);
-    const double x = node_xy[2 * i], y = node_xy[2 * i + 1];
-    double a[2][4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      a[0][c] = x * p[8 + c] - p[c];
-      a[1][c] = y * p[8 + c] - p[4 + c];
-    }
-    double m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      m[0] += a[e][0] * a[e][0];
-      m[1] += a[e][0] * a[e][1];
-      m[2] += a[e][0] * a[e][2];
-      m[3] += a[e][1] * a[e][1];
-      m[4] += a[e][1] * a[e][2];
-      m[5] += a[e][2] * a[e][2];
-      m[6] -= a[e][0] * a[e][3];
-      m[7] -= a[e][1] * a[e][3];
-      m[8] -= a[e][2] * a[e][3];
-    }
-    double* t = acc + 10 * int64_t(r);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) atomicAdd(&t[c], m[c]);
-    atomicAdd(&t[9], 1.0);
+    atomicAdd(&cnt[r], 1);
   }
 }
 
-// Per root with at least two observations: X = M^-1 b by the adjugate; NaN
-// when M is singular (all rays through one centre, or one observation).
-__global__ __launch_bounds__(256) void tri_solve_kernel(const int32_t* label, const double* acc,
-                                                        int64_t n_nodes, double* X,
-                                                        int32_t* n_obs) {
+// Skips exactly the nodes the count pass skipped, so no list overflows.
+__global__ __launch_bounds__(256) void tri_scatter_kernel(const int32_t* label,
+                                                          const int32_t* node_image,
+                                                          int32_t n_images, int64_t n_nodes,
+                                                          const int32_t* start, int32_t* fill,
+                                                          int32_t* members) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_nodes;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t r = label[i], img = node_image[i];
+    if (r < 0 || int64_t(r) >= n_nodes || img < 0 || img >= n_images) continue;
+    members[start[r] + atomicAdd(&fill[r], 1)] = int32_t(i);
+  }
+}
+
+// Per root with at least two observations: the normal equations of its
+// track summed in registers over its members (each observation (x, y) in
+// camera P gives the rows x p3 - p1 and y p3 - p2 of A; M = sum of the
+// first three columns' outer products, b = -sum a a4), then X = M^-1 b by
+// the adjugate; NaN when M is singular (all rays through one centre) or
+// the track has one observation.
+__global__ __launch_bounds__(256) void tri_solve_kernel(
+    const int32_t* label, const int32_t* node_image, const float* node_xy, const double* P,
+    int32_t n_images, int64_t n_nodes, const int32_t* start, const int32_t* cnt,
+    const int32_t* members, double* X, int32_t* n_obs) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_nodes;
        i += int64_t(gridDim.x) * blockDim.x) {
     if (label[i] != int32_t(i)) {
       n_obs[i] = 0;
       continue;
     }
-    const double* t = acc + 10 * i;
+    const int32_t m = cnt[i];
+    n_obs[i] = m;
+    if (m < 2) {
+      X[3 * i] = X[3 * i + 1] = X[3 * i + 2] = NAN;
+      continue;
+    }
+    double t[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int32_t k = start[i], e = start[i] + m; k < e; ++k) {
+      const int32_t j = members[k];
+      const int32_t img = node_image[j];
+      if (img < 0 || img >= n_images) continue;   // flagged by the count pass
+      const double* p = P + 12 * int64_t(img);
+      const double x = node_xy[2 * int64_t(j)], y = node_xy[2 * int64_t(j) + 1];
+      double a[2][4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        a[0][c] = x * p[8 + c] - p[c];
+        a[1][c] = y * p[8 + c] - p[4 + c];
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        t[0] += a[q][0] * a[q][0];
+        t[1] += a[q][0] * a[q][1];
+        t[2] += a[q][0] * a[q][2];
+        t[3] += a[q][1] * a[q][1];
+        t[4] += a[q][1] * a[q][2];
+        t[5] += a[q][2] * a[q][2];
+        t[6] -= a[q][0] * a[q][3];
+        t[7] -= a[q][1] * a[q][3];
+        t[8] -= a[q][2] * a[q][3];
+      }
+    }
     const double a = t[0], b = t[1], c = t[2], d = t[3], e = t[4], f = t[5];
     const double c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
     const double c11 = a * f - c * c, c12 = b * c - a * e, c22 = a * d - b * b;
     const double det = a * c00 + b * c01 + c * c02;
-    const int32_t n = int32_t(t[9]);
-    n_obs[i] = n;
     const double scale = fabs(a) * fabs(d) * fabs(f) + 1e-300;
-    if (n < 2 || !(fabs(det) > 1e-12 * scale)) {
+    if (!(fabs(det) > 1e-12 * scale)) {
       X[3 * i] = X[3 * i + 1] = X[3 * i + 2] = NAN;
       continue;
     }
@@ -193,17 +220,33 @@ hipError_t launch_tracks(int64_t n_nodes, const int32_t* edges, int64_t n_edges,
   return hipGetLastError();
 }
 
+hipError_t triangulate_temp_bytes(int64_t n_nodes, size_t* bytes) {
+  *bytes = 0;
+  return hipcub::DeviceScan::ExclusiveSum(nullptr, *bytes, static_cast<const int32_t*>(nullptr),
+                                          static_cast<int32_t*>(nullptr), int(n_nodes));
+}
+
 hipError_t launch_triangulate(int64_t n_nodes, const int32_t* label, const int32_t* node_image,
                               const float* node_xy, const double* P, int32_t n_images,
-                              double* acc, double* X, int32_t* n_obs, int32_t* err,
-                              hipStream_t st) {
+                              int32_t* ws, void* temp, size_t temp_bytes, double* X,
+                              int32_t* n_obs, int32_t* err, hipStream_t st) {
   if (n_nodes <= 0) return hipSuccess;
-  const int64_t n_acc = 10 * n_nodes;
-  hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks_for(n_acc)), dim3(256), 0, st, acc, n_acc);
-  hipLaunchKernelGGL(tri_accumulate_kernel, dim3(blocks_for(n_nodes)), dim3(256), 0, st, label,
-                     node_image, node_xy, P, n_images, n_nodes, acc, err);
-  hipLaunchKernelGGL(tri_solve_kernel, dim3(blocks_for(n_nodes)), dim3(256), 0, st, label, acc,
-                     n_nodes, X, n_obs);
+  int32_t* cnt = ws;
+  int32_t* start = ws + n_nodes;
+  int32_t* fill = ws + 2 * n_nodes;
+  int32_t* members = ws + 3 * n_nodes;
+  const dim3 grid(blocks_for(n_nodes));
+  hipLaunchKernelGGL(fill_i32_kernel, grid, dim3(256), 0, st, cnt, n_nodes);
+  hipLaunchKernelGGL(fill_i32_kernel, grid, dim3(256), 0, st, fill, n_nodes);
+  hipLaunchKernelGGL(tri_count_kernel, grid, dim3(256), 0, st, label, node_image, n_images,
+                     n_nodes, cnt, err);
+  size_t bytes = temp_bytes;
+  hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, bytes, cnt, start, int(n_nodes), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(tri_scatter_kernel, grid, dim3(256), 0, st, label, node_image, n_images,
+                     n_nodes, start, fill, members);
+  hipLaunchKernelGGL(tri_solve_kernel, grid, dim3(256), 0, st, label, node_image, node_xy, P,
+                     n_images, n_nodes, start, cnt, members, X, n_obs);
   return hipGetLastError();
 }
 

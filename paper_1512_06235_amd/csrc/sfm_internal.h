@@ -182,10 +182,13 @@ int64_t covis_scan_limit();   // longest array the two-level scan handles
 // Tracks and triangulation (kernels_tracks.hip).
 hipError_t launch_tracks(int64_t n_nodes, const int32_t* edges, int64_t n_edges, int32_t* label,
                          int32_t* err, hipStream_t st);
+// ws: 4 n_nodes int32 (counts, starts, fill cursors, member lists); temp:
+// the scan's storage (triangulate_temp_bytes).
+hipError_t triangulate_temp_bytes(int64_t n_nodes, size_t* bytes);
 hipError_t launch_triangulate(int64_t n_nodes, const int32_t* label, const int32_t* node_image,
                               const float* node_xy, const double* P, int32_t n_images,
-                              double* acc, double* X, int32_t* n_obs, int32_t* err,
-                              hipStream_t st);
+                              int32_t* ws, void* temp, size_t temp_bytes, double* X,
+                              int32_t* n_obs, int32_t* err, hipStream_t st);
 
 // Grid-based approximate candidate search (kernels_grid.hip).
 constexpr int32_t kGridMaxTargets = 65536;            // features of b (one LDS bit each)

@@ -170,3 +170,26 @@ def test_tracks_large_graphs_equal_oracle(sfm):
             assert bad.size == 0, f"{what}, run {rep}: {bad.size} labels differ, first {bad[:5]}"
         say(f"  {what}: {n} nodes, {e.shape[0]} edges, {np.unique(ref).size} components")
     m.close()
+
+
+def test_bad_image_index_raises(sfm, graph):
+    """An image index out of range raises the error flag; the node is left
+    out of its track's list, so no list overflows."""
+    import torch
+    m, n, edges, node_image, node_xy, _, P, _ = graph
+    label = torch.empty(n, dtype=torch.int32, device="cuda")
+    sfm.sfm_tracks(m.ctx, n, torch.as_tensor(edges).cuda(), label)
+    sfm.sfm_sync(m.ctx)
+    bad_img = node_image.copy()
+    bad_img[int(edges[0, 0])] = P.shape[0] + 3
+    d = {k: torch.as_tensor(v).cuda() for k, v in (("img", bad_img), ("xy", node_xy), ("P", P))}
+    X = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    n_obs = torch.empty(n, dtype=torch.int32, device="cuda")
+    with pytest.raises(sfm.SfmError) as e:
+        sfm.sfm_triangulate(m.ctx, label, d["img"], d["xy"], d["P"], X, n_obs)
+        sfm.sfm_sync(m.ctx)
+    assert e.value.status == sfm.SFM_EKERNEL
+    # The context still works.
+    d["img"] = torch.as_tensor(node_image).cuda()
+    sfm.sfm_triangulate(m.ctx, label, d["img"], d["xy"], d["P"], X, n_obs)
+    sfm.sfm_sync(m.ctx)
