@@ -145,12 +145,13 @@ __device__ __forceinline__ bool line_crossings(const GridView& v, const GridPair
   return nh > 0;
 }
 
-// C' of query i of pair pr into the LDS list `cand` (count in *ncand; the
-// bitmap, one bit per feature of b, is clear on entry).  Lanes take the
-// sample points k = lane, lane + 64, ...
-__device__ __forceinline__ void grid_collect(const GridView& v, const GridPair* P, int32_t pr,
-                                             const ImageDev& A, int32_t i, uint32_t* bitmap,
-                                             int32_t* cand, int32_t* ncand) {
+// Walks the cells of query i of pair pr and calls on_new(j) once for every
+// feature j of C' (the bitmap, one bit per feature of b, clear on entry,
+// makes C' a set).  Lanes take the sample points k = lane, lane + 64, ...
+template <class OnNew>
+__device__ __forceinline__ void grid_walk(const GridView& v, const GridPair* P, int32_t pr,
+                                          const ImageDev& A, int32_t i, uint32_t* bitmap,
+                                          OnNew&& on_new) {
   const int lane = threadIdx.x;
   double xA = 0.0, yA = 0.0, xB = 0.0, yB = 0.0;
   const bool crosses = line_crossings(v, P, pr, A, i, xA, yA, xB, yB);
@@ -190,47 +191,68 @@ __device__ __forceinline__ void grid_collect(const GridView& v, const GridPair* 
         const int32_t j = items[s];
         const uint32_t bit = 1u << (j & 31);
         if (atomicOr(&bitmap[j >> 5], bit) & bit) continue;
-        const int32_t slot = atomicAdd(ncand, 1);
-        if (slot < kGridMaxCand) cand[slot] = j;
+        on_new(j);
       }
     }
   }
 }
 
-// Two nearest of C' and the ratio test for query i of pair pr.
-__device__ __forceinline__ void grid_decide(const GridView& v, int64_t q_off, int32_t pr,
-                                            const ImageDev& A, const ImageDev& B, int32_t i,
-                                            const int32_t* cand, int32_t n) {
-  const int lane = threadIdx.x;
-  // Packed keys (D << 32 | j) order by distance, then index.
-  uint32_t q[32];
+// C' of query i into the LDS list `cand` (count in *ncand).
+__device__ __forceinline__ void grid_collect(const GridView& v, const GridPair* P, int32_t pr,
+                                             const ImageDev& A, int32_t i, uint32_t* bitmap,
+                                             int32_t* cand, int32_t* ncand) {
+  grid_walk(v, P, pr, A, i, bitmap, [&](int32_t j) {
+    const int32_t slot = atomicAdd(ncand, 1);
+    if (slot < kGridMaxCand) cand[slot] = j;
+  });
+}
+
+// The query's 128 descriptor bytes as 32 words, and its exact squared
+// distance to feature j of b: |q|^2 + |b_j|^2 - 2 q.b_j.
+__device__ __forceinline__ void query_words(const ImageDev& A, int32_t i, uint32_t q[32]) {
   const uint4* qd = reinterpret_cast<const uint4*>(A.desc + 128 * int64_t(i));
 #pragma unroll
   for (int w = 0; w < 8; ++w) {
     const uint4 u = qd[w];
     q[4 * w] = u.x; q[4 * w + 1] = u.y; q[4 * w + 2] = u.z; q[4 * w + 3] = u.w;
   }
-  const int32_t qn = A.norm2[i];
-  unsigned long long b1 = ~0ull, b2 = ~0ull;
-  for (int32_t s = lane; s < n; s += 64) {
-    const int32_t j = cand[s];
-    const uint4* bd = reinterpret_cast<const uint4*>(B.desc + 128 * int64_t(j));
-    uint32_t dot = 0;
+}
+
+__device__ __forceinline__ unsigned long long dist_key(const uint32_t q[32], int32_t qn,
+                                                       const ImageDev& B, int32_t j) {
+  const uint4* bd = reinterpret_cast<const uint4*>(B.desc + 128 * int64_t(j));
+  uint32_t dot = 0;
 #pragma unroll
-    for (int w = 0; w < 8; ++w) {
-      const uint4 u = bd[w];
-      dot = __builtin_amdgcn_udot4(q[4 * w], u.x, dot, false);
-      dot = __builtin_amdgcn_udot4(q[4 * w + 1], u.y, dot, false);
-      dot = __builtin_amdgcn_udot4(q[4 * w + 2], u.z, dot, false);
-      dot = __builtin_amdgcn_udot4(q[4 * w + 3], u.w, dot, false);
-    }
-    const int32_t D = qn + B.norm2[j] - 2 * int32_t(dot);
-    const unsigned long long key = (static_cast<unsigned long long>(uint32_t(D)) << 32) | uint32_t(j);
-    if (key < b1) { b2 = b1; b1 = key; } else if (key < b2) { b2 = key; }
+  for (int w = 0; w < 8; ++w) {
+    const uint4 u = bd[w];
+    dot = __builtin_amdgcn_udot4(q[4 * w], u.x, dot, false);
+    dot = __builtin_amdgcn_udot4(q[4 * w + 1], u.y, dot, false);
+    dot = __builtin_amdgcn_udot4(q[4 * w + 2], u.z, dot, false);
+    dot = __builtin_amdgcn_udot4(q[4 * w + 3], u.w, dot, false);
   }
+  const int32_t D = qn + B.norm2[j] - 2 * int32_t(dot);
+  // Packed keys (D << 32 | j) order by distance, then index.
+  return (static_cast<unsigned long long>(uint32_t(D)) << 32) | uint32_t(j);
+}
+
+// Branch-free, so the two stay in registers (a conditional store to one of
+// the two references made the compiler keep them in scratch).
+__device__ __forceinline__ void push_two(unsigned long long key, unsigned long long& b1,
+                                         unsigned long long& b2) {
+  const bool lt1 = key < b1;
+  const unsigned long long n2 = lt1 ? b1 : (key < b2 ? key : b2);
+  b1 = lt1 ? key : b1;
+  b2 = n2;
+}
+
+// Wave-wide two nearest of the lanes' pairs and the ratio test; lane 0
+// writes the query's result and adds to its pair's counters.
+__device__ __forceinline__ void grid_finish(const GridView& v, int64_t q_off, int32_t pr,
+                                            int32_t i, unsigned long long b1,
+                                            unsigned long long b2, int32_t n) {
   const unsigned long long m1 = wave_min(b1);
   const unsigned long long m2 = wave_min(b1 == m1 ? b2 : b1);
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     QueryResult r;
     r.match = n > 0 ? int32_t(uint32_t(m1)) : -1;
     r.d1 = n > 0 ? int32_t(m1 >> 32) : kDistInf;
@@ -247,10 +269,24 @@ __device__ __forceinline__ void grid_decide(const GridView& v, int64_t q_off, in
   }
 }
 
+// Two nearest of the listed C' and the ratio test for query i of pair pr.
+__device__ __forceinline__ void grid_decide(const GridView& v, int64_t q_off, int32_t pr,
+                                            const ImageDev& A, const ImageDev& B, int32_t i,
+                                            const int32_t* cand, int32_t n) {
+  uint32_t q[32];
+  query_words(A, i, q);
+  const int32_t qn = A.norm2[i];
+  unsigned long long b1 = ~0ull, b2 = ~0ull;
+  for (int32_t s = threadIdx.x; s < n; s += 64) push_two(dist_key(q, qn, B, cand[s]), b1, b2);
+  grid_finish(v, q_off, pr, i, b1, b2, n);
+}
+
 // One wave per workgroup, taking up to kGridQueriesPerBlock consecutive
 // queries of one pair (an entry of the host's block table) one after the
 // other.  LDS: a bitmap with one bit per feature of the largest b of the
-// call, then kGridMaxCand candidate slots and their count.
+// call, then kGridMaxCand candidate slots and their count.  (Computing each
+// distance in the walk, by the lane that finds the candidate, needs no list
+// but measured 10% slower: the walk's lanes diverge, the list pass does not.)
 __global__ __launch_bounds__(64) void grid_query_kernel(GridView v) {
   extern __shared__ uint32_t lds[];
   const int2 blk = v.blocks[blockIdx.x];
