@@ -653,7 +653,7 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   if ((rc = check_F(ctx, F, n_pairs))) return rc;
   const size_t P = size_t(n_pairs);
   std::vector<GridPair> gp(P);
-  int64_t sum_na = 0, cells = 0, items = 0;
+  int64_t sum_na = 0, cells = 0, items = 0, max_cells = 0;
   for (size_t k = 0; k < P; ++k) {
     const sfm_pair& s = pairs[k];
     if (!(s.band_px > 0.0) || !std::isfinite(s.band_px)) {
@@ -695,6 +695,7 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
       g.ncy[t] = int32_t(ncy);
       g.cell_off[t] = cells;
       cells += int64_t(ncx) * int64_t(ncy) + 1;
+      max_cells = std::max(max_cells, int64_t(ncx) * int64_t(ncy));
     }
     sum_na += g.na;
     items += 4 * int64_t(g.nb);
@@ -777,6 +778,7 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   gv.items = reinterpret_cast<int32_t*>(ctx->ws + o_items);
   gv.blocks = reinterpret_cast<const int2*>(ctx->ws + o_blk);
   gv.bitmap_words = std::max(1, (max_nb + 31) / 32);
+  gv.lds_cells = int32_t(std::min<int64_t>(max_cells, kGridLdsCells));
   gv.res = reinterpret_cast<QueryResult*>(ctx->ws + o_res);
   gv.counters = reinterpret_cast<PairCounters*>(ctx->ws + o_cnt);
   gv.err = ctx->err_dev;

@@ -51,7 +51,10 @@ __device__ __forceinline__ int32_t load_count(const int32_t* p) {
 
 // One workgroup per (pair, grid): count per cell, scan, scatter.  Features
 // of one cell land in any order; C' is a set, so the order never matters.
+// The counts live in LDS when the grid has at most v.lds_cells cells, else in
+// the HBM cursor array (atomics there are many times slower).
 __global__ __launch_bounds__(kBinThreads) void grid_bin_kernel(GridView v) {
+  extern __shared__ int32_t lcnt[];
   __shared__ int64_t part[kBinThreads];
   const int32_t p = blockIdx.x >> 2, g = blockIdx.x & 3;
   const GridPair* P = v.pairs + p;
@@ -59,8 +62,9 @@ __global__ __launch_bounds__(kBinThreads) void grid_bin_kernel(GridView v) {
   const int32_t nb = P->nb;
   const int64_t ncell = int64_t(P->ncx[g]) * P->ncy[g];
   int32_t* start = v.cell_start + P->cell_off[g];
-  int32_t* cur = v.cursor + P->cell_off[g];
   int32_t* items = v.items + P->item_off + int64_t(g) * nb;
+  const bool local = ncell <= v.lds_cells;
+  int32_t* cur = local ? lcnt : v.cursor + P->cell_off[g];
   const int t = threadIdx.x;
   for (int64_t c = t; c < ncell; c += kBinThreads) cur[c] = 0;
   __syncthreads();
@@ -73,11 +77,12 @@ __global__ __launch_bounds__(kBinThreads) void grid_bin_kernel(GridView v) {
     atomicAdd(&cur[c], 1);
   }
   __syncthreads();
-  // Exclusive scan: each thread owns a contiguous run of cells.
+  // Exclusive scan: each thread owns a contiguous run of cells.  (HBM counts
+  // are read as device-scope atomics: the adds happened in L2.)
   const int64_t chunk = (ncell + kBinThreads - 1) / kBinThreads;
   const int64_t c0 = std::min<int64_t>(ncell, chunk * t), c1 = std::min<int64_t>(ncell, c0 + chunk);
   int64_t sum = 0;
-  for (int64_t c = c0; c < c1; ++c) sum += load_count(&cur[c]);
+  for (int64_t c = c0; c < c1; ++c) sum += local ? cur[c] : load_count(&cur[c]);
   part[t] = sum;
   __syncthreads();
   for (int o = 1; o < kBinThreads; o <<= 1) {
@@ -88,9 +93,12 @@ __global__ __launch_bounds__(kBinThreads) void grid_bin_kernel(GridView v) {
   }
   int64_t run = part[t] - sum;
   for (int64_t c = c0; c < c1; ++c) {
-    const int32_t n = load_count(&cur[c]);
+    const int32_t n = local ? cur[c] : load_count(&cur[c]);
     start[c] = int32_t(run);
-    __hip_atomic_store(&cur[c], int32_t(run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (local)
+      cur[c] = int32_t(run);
+    else
+      __hip_atomic_store(&cur[c], int32_t(run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     run += n;
   }
   if (t == kBinThreads - 1) start[ncell] = int32_t(part[t]);
@@ -512,7 +520,8 @@ hipError_t launch_grid_groups(const GridView& v, const GroupView& g, int32_t n_g
 
 hipError_t launch_grid(const GridView& v, int64_t n_blocks, hipStream_t st) {
   if (v.n_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(grid_bin_kernel, dim3(4 * v.n_pairs), dim3(kBinThreads), 0, st, v);
+  hipLaunchKernelGGL(grid_bin_kernel, dim3(4 * v.n_pairs), dim3(kBinThreads),
+                     sizeof(int32_t) * size_t(v.lds_cells), st, v);
   if (n_blocks > 0) {
     const size_t lds = sizeof(uint32_t) * (size_t(v.bitmap_words) + kGridMaxCand + 1);
     hipLaunchKernelGGL(grid_query_kernel, dim3(uint32_t(n_blocks)), dim3(64), lds, st, v);

@@ -224,7 +224,9 @@ struct GridView {
   int32_t accept_single;
   int32_t keep_counts;
   int32_t bitmap_words;     // ceil(largest n_b of the call / 32)
+  int32_t lds_cells;        // cell counts the binning keeps in LDS (larger grids use HBM)
 };
+constexpr int32_t kGridLdsCells = 15360;              // 60 KB of LDS counts (64 KB with the scan)
 // Bins b's features into the four grids of every pair, then finds C', the
 // two nearest candidates and the ratio test for every query (n_blocks
 // entries of the block table; 0 = binning only).
