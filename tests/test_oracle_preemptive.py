@@ -135,3 +135,20 @@ def test_pair_direction_and_several_pairs():
     assert res[2]["stages"] == 2
     assert len(res[2]["query"]) == 400
     assert np.array_equal(res[2]["query"], res[2]["match"])
+
+
+def test_edge_cases():
+    """An image without features is below any positive size limit: its pairs
+    are matched whole and find nothing.  With query_pct = 100 stage 1 takes
+    every query, so stage 2 has none and never runs."""
+    rng = np.random.default_rng(8)
+    A, B = _pair(rng, 1200, 1500)
+    empty = [np.zeros((0, 2), np.float32), np.zeros((0, 128), np.uint8), np.zeros(0, np.float32)]
+    r = preemptive_match([A, B, empty], [(0, 2), (2, 1)])
+    assert [x["stages"] for x in r] == [0, 0]
+    assert all(len(x["query"]) == 0 and x["n_comparisons"] == 0 for x in r)
+    for i in range(10):                          # ten planted copies among the top 100%
+        B[1][i] = A[1][i]
+    r = preemptive_match([A, B], [(0, 1)], query_pct=100, target_pct=100, min_matches=0)[0]
+    assert r["stages"] == 1 and len(r["query"]) == 10
+    assert r["n_comparisons"] == 1200 * 1500
