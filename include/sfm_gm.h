@@ -169,8 +169,8 @@ int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, c
  * |C'|).  C' approximates the band: it may include features up to 2d from
  * the line's sample points and miss band members near cell corners.
  * Limits: n_b <= 65536 per pair; at most 2^22 cells per grid (SFM_ECAPACITY);
- * a query (with grouping, a group) whose C' exceeds 2048 features raises
- * the device error flag (SFM_EKERNEL at sfm_sync) and keeps the first 2048
+ * a query (with grouping, a group) whose C' exceeds 1024 features raises
+ * the device error flag (SFM_EKERNEL at sfm_sync) and keeps the first 1024
  * found.
  * SFM_EINVAL: bad index, d, F or options. */
 int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,

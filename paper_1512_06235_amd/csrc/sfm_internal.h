@@ -192,7 +192,7 @@ hipError_t launch_triangulate(int64_t n_nodes, const int32_t* label, const int32
 
 // Grid-based approximate candidate search (kernels_grid.hip).
 constexpr int32_t kGridMaxTargets = 65536;            // features of b (one LDS bit each)
-constexpr int32_t kGridMaxCand = 2048;                // |C'| per query (LDS slots)
+constexpr int32_t kGridMaxCand = 1024;                // |C'| per query (LDS slots)
 constexpr int32_t kGridQueriesPerBlock = 16;          // queries one workgroup takes in turn
 constexpr int64_t kGridMaxCells = int64_t(1) << 22;   // cells of one grid of one pair
 
