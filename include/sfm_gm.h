@@ -183,9 +183,11 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
  * new group starts where A or B lies more than px from the previous line's
  * (to_leader = 0, App. A's stencil) or from the group's first line's
  * (to_leader = 1), or where either line has no crossing; every query of a
- * group takes the C' of the group's first line.  A grouped call is host-synchronous: the host
- * reads the group count before the last launch.  sfm_grid_groups reports the
- * groups of the last grouped call.  SFM_EINVAL: px negative or not finite. */
+ * group takes the C' of the group's first line.  A grouped call is
+ * host-synchronous: the host reads the group count before the last launch.
+ * sfm_grid_groups reports the groups of the last grouped call.  Pairs, F and
+ * the outputs are as for sfm_grid_match.  SFM_EINVAL: px negative or not
+ * finite. */
 int sfm_set_grid_grouping(sfm_ctx* ctx, double px, int32_t to_leader);
 int sfm_grid_groups(sfm_ctx* ctx, int64_t* n_groups);
 
