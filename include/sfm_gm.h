@@ -21,10 +21,15 @@
  * candidates.
  *
  * Exactness.  Epipolar distances are evaluated in FP32 on centred
- * coordinates from lines normalised in FP64; a candidate whose FP64 distance
- * lies within 1e-3 px of d may be classified differently from an FP64
- * evaluation.  Every other result -- membership, the match index, D1, D2 and
- * the candidate count -- equals an FP64 evaluation bit for bit.
+ * coordinates from lines normalised in FP64.  A candidate whose FP32 distance
+ * lies within recheck_margin_px of d (sfm_options, default 1e-3 px) is
+ * decided again in FP64 on the caller's F and the original keypoints, with
+ * the operations of the definition above in order: l = F (x, y, 1)^T row by
+ * row, s = sqrt(l_0^2 + l_1^2), |l . (x', y', 1)| / s <= d.  The FP32 error
+ * is below 1e-4 px on centred coordinates (sfm_band_error measures it), so
+ * with the default margin membership, the match index, D1, D2 and the
+ * candidate count all equal that FP64 evaluation bit for bit.  The number of
+ * candidates decided in FP64 is reported per pair (sfm_matches.n_borderline).
  *
  * Memory.  All image, descriptor and output buffers are device memory owned
  * by the caller.  Pair lists and fundamental matrices are host memory, read
@@ -89,6 +94,8 @@ typedef struct {
   int32_t ratio_den;      /* 100 */
   int32_t accept_single;  /* 0: a query with exactly one candidate is rejected */
   int32_t emit_all;       /* 0: fill the all_* arrays of sfm_matches when nonzero */
+  double recheck_margin_px; /* 1e-3: FP32 distances within this of d are decided
+                             * again in FP64 (0: FP32 only); finite, >= 0 */
 } sfm_options;
 
 /* Outputs, all device memory owned by the caller.
@@ -99,6 +106,9 @@ typedef struct {
  * most), so a call never runs out of room.
  * n_comparisons (optional, int64[n_pairs]) receives the number of candidate
  * comparisons of each pair, i.e. the sum over its queries of |C|.
+ * n_borderline (optional, int64[n_pairs]) receives the number of (query,
+ * candidate) slots of each pair whose FP32 distance lay within
+ * recheck_margin_px of d and was decided again in FP64.
  * With emit_all, all_match/all_d1/all_d2/all_count (int32[sum n_a], pair-major,
  * query order) receive every query's match (-1 if no candidate), D1, D2
  * (INT32_MAX if absent) and |C|. */
@@ -114,6 +124,7 @@ typedef struct {
   int32_t* all_d1;
   int32_t* all_d2;
   int32_t* all_count;
+  int64_t* n_borderline;    /* optional */
 } sfm_matches;
 
 /* Create a context on HIP device `device`.  workspace_budget_bytes caps the
@@ -154,6 +165,19 @@ int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
  * with band_px = +inf on queries whose line is not degenerate. */
 int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                          const sfm_options* opt, const sfm_matches* out, void* stream);
+
+/* Accuracy of the FP32 band test (eqs. 2-3).  Runs the batched form's
+ * preparation for these pairs and then, over every (query, candidate) slot
+ * that the match kernel evaluates (every candidate range of every query
+ * tile), compares the FP32 distance the kernel computes with the FP64
+ * distance of the definition (the caller's F, the original keypoints, no
+ * contraction).  Writes to host memory the largest |FP32 - FP64| in pixels
+ * over the slots whose FP64 distance is at most 2 band_px (*max_err_px, 0
+ * if there are none) and their number (*n_slots).  Host-synchronous; uses
+ * the context's workspace like a matching call.  SFM_EINVAL: as
+ * sfm_guided_match, or a NULL output pointer. */
+int sfm_band_error(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                   double* max_err_px, int64_t* n_slots, void* stream);
 
 /* Grid-based approximate candidate search (Section 6.2.1, eqs. 4-9; the
  * paper's own search, kept as an alternative to the exact band).  band_px of
@@ -242,10 +266,11 @@ int sfm_phase_times(sfm_ctx* ctx, double ms[3], int64_t* n_records);
 
 /* Totals of the last matching call, summed over its pairs (waits for it):
  * out[0] candidate comparisons (sum of |C|), out[1] (query, candidate) slots
- * the match kernel evaluated (superset ranges padded to 32, so
+ * the match kernel evaluated (superset ranges padded to whole MFMA blocks, so
  * out[0] / out[1] is the fraction of useful work), out[2] chunks that took the
- * exact tie-break pass, out[3] accepted matches. */
-int sfm_last_stats(sfm_ctx* ctx, int64_t out[4]);
+ * exact tie-break pass, out[3] accepted matches, out[4] slots decided in FP64
+ * (the sum of n_borderline). */
+int sfm_last_stats(sfm_ctx* ctx, int64_t out[5]);
 
 /* ---------------------------------------------------------------------------
  * Serving loop.  Single-pair requests (the image pairs that Section 6.1

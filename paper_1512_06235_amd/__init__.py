@@ -44,14 +44,16 @@ class sfm_pair(C.Structure):
 
 class sfm_options(C.Structure):
     _fields_ = [("ratio_num", C.c_int32), ("ratio_den", C.c_int32),
-                ("accept_single", C.c_int32), ("emit_all", C.c_int32)]
+                ("accept_single", C.c_int32), ("emit_all", C.c_int32),
+                ("recheck_margin_px", C.c_double)]
 
 
 class sfm_matches(C.Structure):
     _fields_ = [("query", C.c_void_p), ("match", C.c_void_p), ("d1", C.c_void_p),
                 ("d2", C.c_void_p), ("capacity", C.c_int64), ("offset", C.c_void_p),
                 ("n_comparisons", C.c_void_p), ("all_match", C.c_void_p),
-                ("all_d1", C.c_void_p), ("all_d2", C.c_void_p), ("all_count", C.c_void_p)]
+                ("all_d1", C.c_void_p), ("all_d2", C.c_void_p), ("all_count", C.c_void_p),
+                ("n_borderline", C.c_void_p)]
 
 
 class sfm_candidates(C.Structure):
@@ -101,6 +103,8 @@ def lib() -> C.CDLL:
                                    C.POINTER(sfm_matches), vp],
         "sfm_bruteforce_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
                                  C.POINTER(sfm_matches), vp],
+        "sfm_band_error": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(C.c_double),
+                           C.POINTER(i64), vp],
         "sfm_grid_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
                            C.POINTER(sfm_matches), vp],
         "sfm_set_grid_grouping": [vp, C.c_double, i32],
@@ -144,7 +148,8 @@ def lib() -> C.CDLL:
 def exported_symbols():
     """Names of the entry points include/sfm_gm.h declares."""
     return ["sfm_create", "sfm_destroy", "sfm_register_images", "sfm_workspace_size",
-            "sfm_guided_match", "sfm_guided_match_plain", "sfm_bruteforce_match", "sfm_sync",
+            "sfm_guided_match", "sfm_guided_match_plain", "sfm_bruteforce_match",
+            "sfm_band_error", "sfm_sync",
             "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
             "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
@@ -253,6 +258,19 @@ def sfm_bruteforce_match(ctx, pairs, F, out, opt, stream=None):
     _call("sfm_bruteforce_match", ctx, pairs, F, out, opt, stream)
 
 
+def sfm_band_error(ctx, pairs, F=None, stream=None):
+    """(largest |FP32 - FP64| epipolar distance in px over the evaluated slots
+    within 2d, number of those slots); host-synchronous."""
+    batch = pairs if isinstance(pairs, PairBatch) and F is None else PairBatch(pairs, F)
+    err = C.c_double()
+    n = C.c_int64()
+    _check(ctx, lib().sfm_band_error(ctx, batch.c_pairs, batch.n,
+                                     batch.F.ctypes.data if batch.F is not None else None,
+                                     C.byref(err), C.byref(n),
+                                     stream.cuda_stream if stream is not None else None))
+    return err.value, n.value
+
+
 def preemptive_cfg(query_pct=10, target_pct=20, min_matches=4, enough=0,
                    small_image=1000) -> sfm_preemptive_cfg:
     return sfm_preemptive_cfg(int(query_pct), int(target_pct), int(min_matches), int(enough),
@@ -308,9 +326,10 @@ def sfm_phase_times(ctx):
 
 def sfm_last_stats(ctx) -> dict:
     """Totals of the last matching call (waits for it)."""
-    v = (C.c_int64 * 4)()
+    v = (C.c_int64 * 5)()
     _check(ctx, lib().sfm_last_stats(ctx, v))
-    return {"comparisons": v[0], "slots": v[1], "tie_passes": v[2], "accepted": v[3]}
+    return {"comparisons": v[0], "slots": v[1], "tie_passes": v[2], "accepted": v[3],
+            "borderline": v[4]}
 
 
 def sfm_server_now_ns() -> int:
@@ -472,9 +491,10 @@ def sfm_autotune(ctx, pairs, F, opt=None, stream=None, repeats: int = 3):
             for j, f in enumerate(AUTOTUNE_FEATURES_PER_BIN)}
 
 
-def options(ratio_num=64, ratio_den=100, accept_single=False, emit_all=False) -> sfm_options:
+def options(ratio_num=64, ratio_den=100, accept_single=False, emit_all=False,
+            recheck_margin_px=1e-3) -> sfm_options:
     return sfm_options(int(ratio_num), int(ratio_den), int(bool(accept_single)),
-                       int(bool(emit_all)))
+                       int(bool(emit_all)), float(recheck_margin_px))
 
 
 class MatchBuffers:
@@ -492,6 +512,7 @@ class MatchBuffers:
         self.d2 = torch.empty(cap, **i32)
         self.offset = torch.zeros(n_pairs + 1, dtype=torch.int64, device=device)
         self.n_comparisons = torch.zeros(max(1, n_pairs), dtype=torch.int64, device=device)
+        self.n_borderline = torch.zeros(max(1, n_pairs), dtype=torch.int64, device=device)
         self.emit_all = emit_all
         if emit_all:
             self.all_match = torch.empty(cap, **i32)
@@ -512,7 +533,8 @@ class MatchBuffers:
                            self.all_match.data_ptr() if ea else None,
                            self.all_d1.data_ptr() if ea else None,
                            self.all_d2.data_ptr() if ea else None,
-                           self.all_count.data_ptr() if ea else None)
+                           self.all_count.data_ptr() if ea else None,
+                           self.n_borderline.data_ptr())
 
     def pair(self, p: int):
         """Host copies of pair p's accepted (query, match, d1, d2)."""

@@ -38,6 +38,7 @@ struct sfm_ctx {
   hipEvent_t staging_done = nullptr;   // last copy out of the pinned buffer
   hipEvent_t work_done = nullptr;      // end of the last matching call
   int32_t* err_dev = nullptr;
+  unsigned long long* diag_dev = nullptr;   // sfm_band_error's two result words
   bool has_work = false;
   int32_t last_pairs = 0;              // pairs of the last matching call
   size_t last_counters = 0;            // workspace offset of its counters
@@ -213,7 +214,24 @@ int ensure_pinned(sfm_ctx* ctx, size_t bytes) {
   return SFM_OK;
 }
 
-enum class Form { kBatched, kPlain, kExhaustive };
+enum class Form { kBatched, kPlain, kExhaustive, kBandError };
+
+sfm_options default_options() {
+  sfm_options o;
+  memset(&o, 0, sizeof o);
+  o.ratio_num = 64;
+  o.ratio_den = 100;
+  o.recheck_margin_px = 1e-3;
+  return o;
+}
+
+int check_options(sfm_ctx* ctx, const sfm_options& opt) {
+  if (opt.ratio_den <= 0 || opt.ratio_num < 0)
+    return fail(ctx, SFM_EINVAL, "ratio_den must be > 0 and ratio_num >= 0");
+  if (!(opt.recheck_margin_px >= 0.0) || !std::isfinite(opt.recheck_margin_px))
+    return fail(ctx, SFM_EINVAL, "recheck_margin_px must be finite and >= 0");
+  return SFM_OK;
+}
 
 // Everything the batched form's kernels take: a graph captured for one Key
 // is valid for every call with the same Key.
@@ -246,7 +264,7 @@ int replay_batched(sfm_ctx* ctx, const GraphKey& key, int32_t* am, int32_t* ad1,
                                          key.max_na, cs);
     const hipError_t e2 = launch_match(v, key.sum_groups > 0 ? key.wgs : 0, cs);
     const hipError_t e3 = launch_emit(v, 0, key.n_pairs, out.offset, out.query, out.match, out.d1,
-                                      out.d2, out.n_comparisons, am, ad1, ad2, ac, cs);
+                                      out.d2, out.n_comparisons, out.n_borderline, am, ad1, ad2, ac, cs);
     hipGraph_t g = nullptr;
     HIP_TRY(ctx, hipStreamEndCapture(cs, &g));
     const hipError_t ei = (e1 != hipSuccess)   ? e1
@@ -301,29 +319,38 @@ int check_F(sfm_ctx* ctx, const double* F, int32_t n_pairs) {
 }
 
 // One matching call over the images of `tab`; the caller holds ctx->mu.
+// kBandError runs the preparation and the FP32-accuracy diagnostic instead
+// of matching (`out` is unused; diag receives the two result words).
 int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int32_t n_pairs,
                  const double* F, const sfm_options* opt_in, const sfm_matches* out, void* stream,
-                 Form form) {
+                 Form form, unsigned long long* diag = nullptr) {
+  const bool diagnostic = form == Form::kBandError;
+  sfm_matches none;
+  memset(&none, 0, sizeof none);
+  if (diagnostic) out = &none;
   if (!out) return fail(ctx, SFM_EINVAL, "out is NULL");
-  sfm_options opt = {64, 100, 0, 0};
+  sfm_options opt = default_options();
   if (opt_in) opt = *opt_in;
-  if (opt.ratio_den <= 0 || opt.ratio_num < 0)
-    return fail(ctx, SFM_EINVAL, "ratio_den must be > 0 and ratio_num >= 0");
+  int rc = check_options(ctx, opt);
+  if (rc) return rc;
   const bool exhaustive = form == Form::kExhaustive;
   std::vector<PairDesc> pd;
-  int rc = describe_pairs(ctx, tab, pairs, n_pairs, exhaustive, pd);
+  rc = describe_pairs(ctx, tab, pairs, n_pairs, exhaustive, pd);
   if (rc) return rc;
   if (!exhaustive && (rc = check_F(ctx, F, n_pairs))) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const Layout L = plan(pd, ctx->device, ctx->group_tiles);
-  if (!out->offset) return fail(ctx, SFM_EINVAL, "out->offset is NULL");
-  if (out->capacity < L.sum_na) {
+  if (diagnostic) {
+    // no outputs
+  } else if (!out->offset) {
+    return fail(ctx, SFM_EINVAL, "out->offset is NULL");
+  } else if (out->capacity < L.sum_na) {
     char buf[128];
     snprintf(buf, sizeof buf, "output capacity %lld < %lld queries", (long long)out->capacity,
              (long long)L.sum_na);
     return fail(ctx, SFM_ECAPACITY, buf);
   }
-  if (L.sum_na > 0 && (!out->query || !out->match || !out->d1 || !out->d2))
+  if (!diagnostic && L.sum_na > 0 && (!out->query || !out->match || !out->d1 || !out->d2))
     return fail(ctx, SFM_EINVAL, "output arrays are NULL");
   if (opt.emit_all && L.sum_na > 0 &&
       (!out->all_match || !out->all_d1 || !out->all_d2 || !out->all_count))
@@ -331,7 +358,7 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (n_pairs == 0) {
-    HIP_TRY(ctx, hipMemsetAsync(out->offset, 0, sizeof(int64_t), st));
+    if (!diagnostic) HIP_TRY(ctx, hipMemsetAsync(out->offset, 0, sizeof(int64_t), st));
     return SFM_OK;
   }
   if ((rc = ensure_workspace(ctx, L.total))) return rc;
@@ -380,13 +407,21 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
   v.accept_single = opt.accept_single ? 1 : 0;
   v.keep_counts = opt.emit_all ? 1 : 0;
   v.group_tiles = ctx->group_tiles;
+  v.margin = opt.recheck_margin_px;
   v.groups = reinterpret_cast<TileGroup*>(ctx->ws + L.groups);
 
   int32_t* am = opt.emit_all ? out->all_match : nullptr;
   int32_t* ad1 = opt.emit_all ? out->all_d1 : nullptr;
   int32_t* ad2 = opt.emit_all ? out->all_d2 : nullptr;
   int32_t* ac = opt.emit_all ? out->all_count : nullptr;
-  if (form == Form::kPlain) {
+  if (diagnostic) {
+    int32_t max_na = 0;
+    for (const PairDesc& pp : pd) max_na = std::max(max_na, pp.na);
+    HIP_TRY(ctx, hipMemsetAsync(diag, 0, 2 * sizeof(unsigned long long), st));
+    HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, 0, int32_t(L.sum_groups), L.wgs,
+                                reinterpret_cast<const int32_t*>(ctx->ws + L.order), max_na, st));
+    HIP_TRY(ctx, launch_band_error(v, L.sum_groups, diag, st));
+  } else if (form == Form::kPlain) {
     for (int32_t p = 0; p < n_pairs; ++p) {
       HIP_TRY(ctx, prof_mark(ctx, st));
       const int32_t g0 = int32_t(pd[size_t(p)].grp_off), gn = pd[size_t(p)].ngroups;
@@ -396,7 +431,7 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
       HIP_TRY(ctx, launch_match(v, gn > 0 ? wgs : 0, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
       HIP_TRY(ctx, launch_emit(v, p, 1, out->offset, out->query, out->match, out->d1, out->d2,
-                               out->n_comparisons, am, ad1, ad2, ac, st));
+                               out->n_comparisons, out->n_borderline, am, ad1, ad2, ac, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
     }
   } else if (ctx->graph_replay && !ctx->profiling && form == Form::kBatched) {
@@ -423,7 +458,8 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
     HIP_TRY(ctx, launch_match(v, L.sum_groups > 0 ? L.wgs : 0, st));
     HIP_TRY(ctx, prof_mark(ctx, st));
     HIP_TRY(ctx, launch_emit(v, 0, n_pairs, out->offset, out->query, out->match, out->d1,
-                             out->d2, out->n_comparisons, am, ad1, ad2, ac, st));
+                             out->d2, out->n_comparisons, out->n_borderline, am, ad1, ad2, ac,
+                             st));
     HIP_TRY(ctx, prof_mark(ctx, st));
   }
   HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
@@ -532,6 +568,7 @@ int sfm_destroy(sfm_ctx* ctx) {
   free_registration(ctx);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->stage_buf) (void)hipFree(ctx->stage_buf);
+  if (ctx->diag_dev) (void)hipFree(ctx->diag_dev);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->err_dev) (void)hipFree(ctx->err_dev);
   for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
@@ -638,15 +675,37 @@ int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, c
   return run_match(ctx, pairs, n_pairs, F, opt, out, stream, Form::kExhaustive);
 }
 
+int sfm_band_error(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                   double* max_err_px, int64_t* n_slots, void* stream) {
+  if (!ctx) return SFM_EINVAL;
+  if (!max_err_px || !n_slots) return fail(ctx, SFM_EINVAL, "output pointer is NULL");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (!ctx->diag_dev) HIP_TRY(ctx, hipMalloc(&ctx->diag_dev, 2 * sizeof(unsigned long long)));
+  *max_err_px = 0.0;
+  *n_slots = 0;
+  const int rc = match_locked(ctx, registered(ctx), pairs, n_pairs, F, nullptr, nullptr, stream,
+                              Form::kBandError, ctx->diag_dev);
+  if (rc || n_pairs == 0) return rc;
+  unsigned long long h[2] = {0, 0};
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, hipMemcpyAsync(h, ctx->diag_dev, sizeof h, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  double e;
+  memcpy(&e, &h[0], sizeof e);
+  *max_err_px = e;
+  *n_slots = int64_t(h[1]);
+  return SFM_OK;
+}
+
 int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                    const sfm_options* opt_in, const sfm_matches* out, void* stream) {
   if (!ctx) return SFM_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (!out || !out->offset) return fail(ctx, SFM_EINVAL, "out or out->offset is NULL");
-  sfm_options opt = {64, 100, 0, 0};
+  sfm_options opt = default_options();
   if (opt_in) opt = *opt_in;
-  if (opt.ratio_den <= 0 || opt.ratio_num < 0)
-    return fail(ctx, SFM_EINVAL, "ratio_den must be > 0 and ratio_num >= 0");
+  if (const int orc = check_options(ctx, opt)) return orc;
   std::vector<PairDesc> pd;
   int rc = describe_pairs(ctx, registered(ctx), pairs, n_pairs, false, pd);
   if (rc) return rc;
@@ -833,7 +892,7 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   int32_t* ad2 = opt.emit_all ? out->all_d2 : nullptr;
   int32_t* ac = opt.emit_all ? out->all_count : nullptr;
   HIP_TRY(ctx, launch_emit(v, 0, n_pairs, out->offset, out->query, out->match, out->d1, out->d2,
-                           out->n_comparisons, am, ad1, ad2, ac, st));
+                           out->n_comparisons, out->n_borderline, am, ad1, ad2, ac, st));
   HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
   ctx->has_work = true;
   ctx->last_pairs = n_pairs;
@@ -868,7 +927,7 @@ int sfm_preemptive_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
       cfg.min_matches < 0 || cfg.enough < 0 || cfg.small_image < 0)
     return fail(ctx, SFM_EINVAL,
                 "cfg: query_pct and target_pct must be in 1..100, the counts >= 0");
-  sfm_options opt = {64, 100, 0, 0};
+  sfm_options opt = default_options();
   if (opt_in) opt = *opt_in;
   if (opt.emit_all) return fail(ctx, SFM_EINVAL, "emit_all is not available for staged matching");
   if (!out || !out->offset) return fail(ctx, SFM_EINVAL, "out or out->offset is NULL");
@@ -1051,10 +1110,10 @@ int sfm_phase_times(sfm_ctx* ctx, double ms[3], int64_t* n_records) {
   return SFM_OK;
 }
 
-int sfm_last_stats(sfm_ctx* ctx, int64_t out[4]) {
+int sfm_last_stats(sfm_ctx* ctx, int64_t out[5]) {
   if (!ctx || !out) return SFM_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
-  out[0] = out[1] = out[2] = out[3] = 0;
+  out[0] = out[1] = out[2] = out[3] = out[4] = 0;
   if (!ctx->has_work || ctx->last_pairs == 0) return SFM_OK;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipEventSynchronize(ctx->work_done));
@@ -1066,6 +1125,7 @@ int sfm_last_stats(sfm_ctx* ctx, int64_t out[4]) {
     out[1] += int64_t(k.elements);
     out[2] += k.ties;
     out[3] += k.accepted;
+    out[4] += int64_t(k.borderline);
   }
   return SFM_OK;
 }

@@ -12,7 +12,8 @@ constexpr int kEmitThreads = 1024;
 
 // offset[pb + k + 1] = offset[pb] + sum of accepted over pairs pb..pb+k.
 __global__ __launch_bounds__(1024) void scan_pairs_kernel(BatchView v, int32_t pb, int32_t pc,
-                                                          int64_t* offset, int64_t* n_cmp) {
+                                                          int64_t* offset, int64_t* n_cmp,
+                                                          int64_t* n_bl) {
   __shared__ long long wtot[16];
   __shared__ long long carry;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -25,6 +26,7 @@ __global__ __launch_bounds__(1024) void scan_pairs_kernel(BatchView v, int32_t p
     const int32_t k = base + t;
     long long x = k < pc ? (long long)v.counters[pb + k].accepted : 0;
     if (k < pc && n_cmp) n_cmp[pb + k] = (long long)v.counters[pb + k].comparisons;
+    if (k < pc && n_bl) n_bl[pb + k] = (long long)v.counters[pb + k].borderline;
     for (int o = 1; o < 64; o <<= 1) {
       const long long y = __shfl_up(x, o, 64);
       if (lane >= o) x += y;
@@ -124,10 +126,11 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(BatchView v, int32_t
 }  // namespace
 
 hipError_t launch_emit(const BatchView& v, int32_t pb, int32_t pc, int64_t* offset, int32_t* oq,
-                       int32_t* om, int32_t* od1, int32_t* od2, int64_t* n_cmp, int32_t* am,
-                       int32_t* ad1, int32_t* ad2, int32_t* ac, hipStream_t st) {
+                       int32_t* om, int32_t* od1, int32_t* od2, int64_t* n_cmp, int64_t* n_bl,
+                       int32_t* am, int32_t* ad1, int32_t* ad2, int32_t* ac, hipStream_t st) {
   if (pc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, st, v, pb, pc, offset, n_cmp);
+  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, st, v, pb, pc, offset, n_cmp,
+                     n_bl);
   hipLaunchKernelGGL(emit_kernel, dim3(pc), dim3(kEmitThreads), 0, st, v, pb, offset, oq, om, od1,
                      od2, am, ad1, ad2, ac);
   return hipGetLastError();

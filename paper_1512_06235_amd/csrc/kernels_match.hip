@@ -50,11 +50,64 @@ struct Split {
 };
 constexpr int kMetaSlots = 3;
 
-// Band test of eqs. (2)-(3) on centred FP32 coordinates: |a x + b y + c| <= d
-// with (a, b) unit.  The single definition used by every pass.
-__device__ __forceinline__ bool in_band(float a, float b, float c, float x, float y, float d) {
-  const float e = __builtin_fmaf(a, x, __builtin_fmaf(b, y, c));
-  return __builtin_fabsf(e) <= d;
+// Epipolar distance of eqs. (2)-(3) on centred FP32 coordinates,
+// |a x + b y + c| with (a, b) unit.  The single FP32 evaluation every pass uses.
+__device__ __forceinline__ float band_dist32(float a, float b, float c, float x, float y) {
+  return __builtin_fabsf(__builtin_fmaf(a, x, __builtin_fmaf(b, y, c)));
+}
+
+// The epipolar distance of eqs. (2)-(3) in FP64, on the caller's F and the
+// original keypoints, every operation as written (no contraction): the line
+// l = F (x, y, 1)^T row by row, s = sqrt(l0^2 + l1^2), then
+// |l0 x' + l1 y' + l2| / s.  NaN when s = 0 or s or l2 is not finite (such a
+// line has no candidates).
+__device__ __forceinline__ double band_dist64(const double* F, float xq, float yq, float xb,
+                                           float yb) {
+#pragma clang fp contract(off)
+  const double x = xq, y = yq;
+  const double a = F[0] * x + F[1] * y + F[2];
+  const double b = F[3] * x + F[4] * y + F[5];
+  const double c = F[6] * x + F[7] * y + F[8];
+  const double s = sqrt(a * a + b * b);
+  if (!(s > 0.0) || !isfinite(s) || !isfinite(c)) return NAN;
+  return fabs(a * double(xb) + b * double(yb) + c) / s;
+}
+
+// The band decision in FP64.  The FP32 test is decided again by this function
+// for every distance within the margin of d, so results equal an FP64
+// evaluation as long as the FP32 error stays below the margin.
+__device__ __forceinline__ bool band_exact(const double* F, float xq, float yq, float xb, float yb,
+                                           double d) {
+  return band_dist64(F, xq, yq, xb, yb) <= d;
+}
+
+// What the FP64 re-decision of one pair needs, read when a step first has a
+// borderline slot.
+struct ExactCtx {
+  const double* F;          // the caller's F of the pair
+  const float* a_xy;        // original keypoints of a and b
+  const float* b_xy;
+  double d;
+};
+
+__device__ __forceinline__ ExactCtx exact_ctx(const BatchView& v, int32_t pair) {
+  const PairDesc P = v.pairs[pair];
+  ExactCtx x;
+  x.F = v.F + 9 * int64_t(pair);
+  x.a_xy = v.images[P.a].xy;
+  x.b_xy = v.images[P.b].xy;
+  x.d = P.band;
+  return x;
+}
+
+// Band membership of query i (original index in a) and target j (original
+// index in b) from the FP32 distance e32: in below band_lo, out above band_hi,
+// decided in FP64 in between.
+__device__ __forceinline__ bool member(float e32, float lo, float hi, const ExactCtx& x, int32_t i,
+                                       int32_t j) {
+  if (e32 <= lo) return true;
+  if (!(e32 <= hi)) return false;
+  return band_exact(x.F, x.a_xy[2 * i], x.a_xy[2 * i + 1], x.b_xy[2 * j], x.b_xy[2 * j + 1], x.d);
 }
 
 // Per-byte negation of four bytes in 0..127 (no borrow crosses a byte).
@@ -70,6 +123,23 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
 __device__ inline int32_t row_dist(const uint8_t* p, const uint8_t* q, int32_t np, int32_t nq) {
   uint32_t dot = 0;
 #pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    const uint4 u = reinterpret_cast<const uint4*>(p)[w];
+    const uint4 v = reinterpret_cast<const uint4*>(q)[w];
+    dot = __builtin_amdgcn_udot4(u.x, v.x, dot, false);
+    dot = __builtin_amdgcn_udot4(u.y, v.y, dot, false);
+    dot = __builtin_amdgcn_udot4(u.z, v.z, dot, false);
+    dot = __builtin_amdgcn_udot4(u.w, v.w, dot, false);
+  }
+  return np + nq - 2 * int32_t(dot);
+}
+
+// The same with one pair of 16-byte loads in flight (few registers: for the
+// rare FP64 re-decision inside the step loop).
+__device__ inline int32_t row_dist_lean(const uint8_t* p, const uint8_t* q, int32_t np,
+                                        int32_t nq) {
+  uint32_t dot = 0;
+#pragma unroll 1
   for (int w = 0; w < 8; ++w) {
     const uint4 u = reinterpret_cast<const uint4*>(p)[w];
     const uint4 v = reinterpret_cast<const uint4*>(q)[w];
@@ -148,16 +218,24 @@ __device__ __forceinline__ void read_a(const GroupLds& L, int st, int lane, v4i 
 
 // The four MFMAs on one step's rows, then this lane's 16 results folded into
 // the running two smallest keys (k1, k2), with the candidates' coordinates and
-// keys read from metadata slot st.
+// keys read from metadata slot st.  A slot is folded when its FP32 distance is
+// at most band_lo; when any slot of the wave lies within (band_lo, band_hi],
+// those slots are decided in FP64 afterwards, one at a time, and folded with
+// their distance recomputed on the VALU.  In-band slots are counted per lane
+// when counts are kept, per wave (scalar) otherwise.
+template <bool kKeepCounts>
 __device__ __forceinline__ void tile_compute(const v4i (&ac)[4], const v4i (&bq)[4],
-                                             const QueryRec& qr, float band, const GroupLds& L,
-                                             int st, int half, uint32_t& k1, uint32_t& k2,
-                                             int32_t& cnt) {
+                                             const QueryRec& qr, int32_t nq, float lo, float hi,
+                                             const GroupLds& L, int st, int half, uint32_t& k1,
+                                             uint32_t& k2, int32_t& cnt, uint32_t& wcnt,
+                                             uint32_t& wbl, const BatchView& v,
+                                             const TileGroup& G, int32_t t0) {
   v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(ac[s], bq[s], acc, 0, 0, 0);
 
   // Lane (col, half) holds rows 8g + 4*half + e of the tile, e = 0..3.
+  unsigned long long border = 0;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     const int r0 = 8 * g + 4 * half;
@@ -169,14 +247,59 @@ __device__ __forceinline__ void tile_compute(const v4i (&ac)[4], const v4i (&bq)
     const uint32_t nv[4] = {ns.x, ns.y, ns.z, ns.w};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const bool mem = in_band(qr.a, qr.b, qr.c, xv[e], yv[e], band);
+      const float d32 = band_dist32(qr.a, qr.b, qr.c, xv[e], yv[e]);
+      const bool mem = d32 <= lo;
+      border |= __ballot(d32 <= hi) ^ __ballot(mem);   // lo <= hi: mem implies d32 <= hi
       uint32_t key = nv[e] + (uint32_t(acc[4 * g + e]) << 11);
       key = mem ? key : kKeyInf;
       k2 = umed3(k1, key, k2);
       k1 = min(k1, key);
-      cnt += mem ? 1 : 0;
+      if (kKeepCounts)
+        cnt += mem ? 1 : 0;
+      else
+        wcnt += __builtin_popcountll(__ballot(mem));
     }
   }
+  if (border == 0) return;
+
+  // Rare: this lane's slots within the margin of d, decided in FP64.
+  uint32_t bm = 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = 8 * g + 4 * half + e;
+      const float d32 = band_dist32(qr.a, qr.b, qr.c, L.x[st][r], L.y[st][r]);
+      if (d32 <= hi && !(d32 <= lo)) bm |= 1u << (4 * g + e);
+    }
+  }
+  int32_t nbl = __builtin_popcount(bm), nin = 0;
+  const ExactCtx x = exact_ctx(v, G.pair);
+  const CandRec* cand = v.cand + G.c_off;
+  while (bm) {
+    const int sidx = __builtin_ctz(bm);
+    bm &= bm - 1;
+    const int r = 8 * (sidx >> 2) + 4 * half + (sidx & 3);
+    const int32_t j = cand[t0 + r].j;
+    if (!band_exact(x.F, x.a_xy[2 * qr.i], x.a_xy[2 * qr.i + 1], x.b_xy[2 * j],
+                    x.b_xy[2 * j + 1], x.d))
+      continue;
+    const uint32_t nc = L.nc[st][r];
+    const int32_t D = row_dist_lean(G.a_desc + int64_t(qr.i) * kDescBytes,
+                               G.b_desc + int64_t(j) * kDescBytes, nq,
+                               int32_t(nc >> kPosBits) - int32_t(kDistBias));
+    const uint32_t key = (uint32_t(D - nq + int32_t(kDistBias)) << kPosBits) | (nc & (kChunk - 1));
+    k2 = umed3(k1, key, k2);
+    k1 = min(k1, key);
+    ++nin;
+  }
+  if (kKeepCounts) cnt += nin;
+  for (int o = 32; o > 0; o >>= 1) {
+    nbl += __shfl_xor(nbl, o, 64);
+    nin += __shfl_xor(nin, o, 64);
+  }
+  wbl += uint32_t(nbl);
+  if (!kKeepCounts) wcnt += uint32_t(nin);
 }
 
 // Running result of one query column across chunks of 1024 positions.
@@ -187,9 +310,10 @@ struct QueryState {
 
 // End of a chunk [c0, c1): merge the halves' keys, decode (D1, position, D2),
 // resolve equal smallest distances exactly, fold into the running result.
-__device__ __forceinline__ void finish_chunk(const CandRec* cand, const uint8_t* a_desc,
+__device__ __forceinline__ void finish_chunk(const BatchView& v, const TileGroup& G,
+                                             const CandRec* cand, const uint8_t* a_desc,
                                              const uint8_t* b_desc, const QueryRec& qr, int32_t nq,
-                                             float band, int32_t c0, int32_t c1, int lane,
+                                             float lo, float hi, int32_t c0, int32_t c1, int lane,
                                              uint32_t k1, uint32_t k2, QueryState& q) {
   const int col = lane & 31, half = lane >> 5;
   {
@@ -211,6 +335,7 @@ __device__ __forceinline__ void finish_chunk(const CandRec* cand, const uint8_t*
   // Equal smallest distances: choose the lowest index of b exactly.
   const bool tie = k2 != kKeyInf && (k1 >> kPosBits) == (k2 >> kPosBits);
   unsigned long long tmask = __ballot(tie && half == 0);
+  const ExactCtx x = tmask ? exact_ctx(v, G.pair) : ExactCtx{nullptr, nullptr, nullptr, 0.0};
   while (tmask) {
     const int Lq = __builtin_ctzll(tmask);
     tmask &= tmask - 1;
@@ -221,7 +346,7 @@ __device__ __forceinline__ void finish_chunk(const CandRec* cand, const uint8_t*
     int32_t jbest = 0x7FFFFFFF;
     for (int32_t s = c0 + lane; s < c1; s += 64) {
       const CandRec r = cand[s];
-      if (!in_band(la, lb, lc, r.x, r.y, band)) continue;
+      if (!member(band_dist32(la, lb, lc, r.x, r.y), lo, hi, x, li, r.j)) continue;
       const int32_t nc = int32_t(r.ncpos >> kPosBits) - int32_t(kDistBias);
       const int32_t D = row_dist(qrow, b_desc + int64_t(r.j) * kDescBytes, lnq, nc);
       if (D == lD) jbest = min(jbest, r.j);
@@ -242,7 +367,7 @@ __device__ __forceinline__ void finish_chunk(const CandRec* cand, const uint8_t*
 // Per-wave statistics of the groups of one pair, flushed when the pair changes.
 struct WaveStats {
   int32_t pair;
-  unsigned long long comparisons, elements;
+  unsigned long long comparisons, elements, borderline;
   uint32_t accepted, ties;
 };
 
@@ -250,10 +375,11 @@ __device__ __forceinline__ void flush_stats(const BatchView& v, WaveStats& w, in
   if (w.pair >= 0 && lane == 0) {
     if (w.comparisons) atomicAdd(&v.counters[w.pair].comparisons, w.comparisons);
     if (w.elements) atomicAdd(&v.counters[w.pair].elements, w.elements);
+    if (w.borderline) atomicAdd(&v.counters[w.pair].borderline, w.borderline);
     if (w.accepted) atomicAdd(&v.counters[w.pair].accepted, w.accepted);
     if (w.ties) atomicAdd(&v.counters[w.pair].ties, w.ties);
   }
-  w.comparisons = w.elements = 0;
+  w.comparisons = w.elements = w.borderline = 0;
   w.accepted = w.ties = 0;
 }
 
@@ -290,7 +416,7 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
     my_e = wave == t ? G.t_end[t] : my_e;
   }
   if (!wv) my_b = my_e = 0;
-  const float band = G.band;
+  const float lo = G.band_lo, hi = G.band_hi;
   const uint8_t* const a_desc = G.a_desc;
   const uint8_t* const b_desc = G.b_desc;
 
@@ -328,7 +454,9 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
   const int32_t nq = ((g_i32*)G.a_norm)[qr.i];
 
   QueryState q = {kDistInf, kDistInf, -1, 0};
-  int32_t cnt = 0;
+  int32_t cnt = 0;       // in-band slots of this lane (counts kept)
+  uint32_t wcnt = 0;     // in-band slots of this wave (counts not kept)
+  uint32_t wbl = 0;      // slots decided in FP64
 
   if (any) {
     // Software pipeline over steps u = 0, 1, ... of 32 candidates.  Iteration
@@ -370,14 +498,15 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
         __builtin_amdgcn_s_setprio(2);
         v4i a[4];
         read_a(L, rs, lane, a);
-        tile_compute(a, bq, qr, band, L, ms, half, k1, k2, cnt);
+        tile_compute<kKeepCounts>(a, bq, qr, nq, lo, hi, L, ms, half, k1, k2, cnt, wcnt, wbl, v,
+                                  G, t0);
         __builtin_amdgcn_s_setprio(0);
       }
       // Keys hold positions mod 1024: close a chunk every 1024 positions.
       const int32_t t1 = t0 + kCandTile;
       if (t1 >= S1 || t1 - c0 >= kChunk) {
         const int32_t c1 = min(S1, c0 + kChunk);
-        finish_chunk(cand, a_desc, b_desc, qr, nq, band, c0, c1, lane, k1, k2, q);
+        finish_chunk(v, G, cand, a_desc, b_desc, qr, nq, lo, hi, c0, c1, lane, k1, k2, q);
         k1 = kKeyInf;
         k2 = kKeyInf;
         c0 = c1;
@@ -402,7 +531,7 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
   } else {
     accept = q.d1 != kDistInf && v.accept_single;
   }
-  cnt += __shfl_xor(cnt, 32, 64);   // |C| of this lane's query
+  if (kKeepCounts) cnt += __shfl_xor(cnt, 32, 64);   // |C| of this lane's query
   if (qv && half == 0) {
     QueryResult out;
     out.match = q.j1;
@@ -412,8 +541,12 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
     v.res[G.q_off + qr.i] = out;
   }
   // In-band comparisons of the tile: the sum of its queries' counts.
-  int32_t tsum = (half == 0) ? cnt : 0;
-  for (int o = 16; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
+  int32_t tsum = int32_t(wcnt);
+  if (kKeepCounts) {
+    tsum = (half == 0) ? cnt : 0;
+    for (int o = 16; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
+    tsum = __shfl(tsum, 0, 64);
+  }
   const uint32_t nacc = __builtin_popcountll(__ballot(accept && qv && half == 0));
   if (wv) {
     if (G.pair != ws.pair) {
@@ -426,7 +559,8 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
       const int32_t last = (my_e - 1 - S0) / kCandTile;
       steps = last - first + 1;
     }
-    ws.comparisons += (unsigned long long)__shfl(tsum, 0, 64);
+    ws.comparisons += (unsigned long long)tsum;
+    ws.borderline += wbl;
     ws.elements += (unsigned long long)steps * (kCandTile * kQueryTile);
     ws.accepted += nacc;
     ws.ties += q.ties;
@@ -471,12 +605,53 @@ void match_kernel(BatchView v) {
   const int32_t g_first = ((c_i32*)v.wg_start)[run];
   const int32_t g_end = ((c_i32*)v.wg_start)[run + 1];
 #endif
-  WaveStats ws = {-1, 0, 0, 0, 0};
+  WaveStats ws = {-1, 0, 0, 0, 0, 0};
   for (int32_t g = g_first; g < g_end; g += w) {
     const TileGroup G = load_group(v.groups, g);
     match_group<kKeepCounts, W>(v, G, lds, wave, lane, ws);
   }
   flush_stats(v, ws, lane);
+}
+
+// Diagnostic of the FP32 band test: over every (query, candidate) slot of
+// every query tile's candidate range whose FP64 distance is at most 2d, the
+// largest |FP32 distance - FP64 distance| (as the bits of a non-negative
+// double, which order like the integers) and the number of such slots.  One
+// wave per tile, one lane per query.
+__global__ __launch_bounds__(64) void band_error_kernel(BatchView v,
+                                                        unsigned long long* out) {
+  const int32_t g = blockIdx.x / v.group_tiles, t = blockIdx.x % v.group_tiles;
+  const TileGroup& G = v.groups[g];
+  const int lane = threadIdx.x;
+  if (t >= G.ntiles || lane >= kQueryTile) return;
+  const int32_t qs = (G.tile0 + t) * kQueryTile + lane;
+  const int32_t b = G.t_begin[t], e = G.t_end[t];
+  double worst = 0.0;
+  unsigned long long n = 0;
+  if (qs < G.na && e > b) {
+    const QueryRec qr = v.qrec[G.q_off + qs];
+    const ExactCtx x = exact_ctx(v, G.pair);
+    const CandRec* cand = v.cand + G.c_off;
+    const double two_d = 2.0 * x.d;
+    const float xq = x.a_xy[2 * qr.i], yq = x.a_xy[2 * qr.i + 1];
+    for (int32_t s = b; s < e; ++s) {
+      const CandRec r = cand[s];
+      const double e64 = band_dist64(x.F, xq, yq, x.b_xy[2 * r.j], x.b_xy[2 * r.j + 1]);
+      if (!(e64 <= two_d)) continue;
+      const double e32 = band_dist32(qr.a, qr.b, qr.c, r.x, r.y);
+      worst = fmax(worst, fabs(e32 - e64));
+      ++n;
+    }
+  }
+  unsigned long long bits = __double_as_longlong(worst);
+  for (int o = 32; o > 0; o >>= 1) {
+    bits = max(bits, (unsigned long long)__shfl_xor((long long)bits, o, 64));
+    n += (unsigned long long)__shfl_xor((long long)n, o, 64);
+  }
+  if (lane == 0) {
+    if (bits) atomicMax(&out[0], bits);
+    if (n) atomicAdd(&out[1], n);
+  }
 }
 
 }  // namespace
@@ -523,6 +698,15 @@ hipError_t launch_match(const BatchView& v, int32_t wgs, hipStream_t st) {
     launch_match_w<4>(v, wgs, st);
   else
     launch_match_w<2>(v, wgs, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_error(const BatchView& v, int64_t n_groups, unsigned long long* out,
+                             hipStream_t st) {
+  const int64_t blocks = n_groups * v.group_tiles;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(band_error_kernel, dim3(uint32_t(blocks)), dim3(64), 0, st, v, out);
   return hipGetLastError();
 }
 

@@ -81,7 +81,8 @@ __device__ inline void cross3(const double* p, const double* q, double* r) {
   r[2] = p[0] * q[1] - p[1] * q[0];
 }
 
-__device__ void setup_pair(const PairDesc& P, const ImageDev& B, const double* Fin, PairGeom& g) {
+__device__ void setup_pair(const PairDesc& P, const ImageDev& B, const double* Fin, double margin,
+                           PairGeom& g) {
   double fro = 0.0;
   for (int k = 0; k < 9; ++k) fro += Fin[k] * Fin[k];
   fro = sqrt(fro);
@@ -110,7 +111,10 @@ __device__ void setup_pair(const PairDesc& P, const ImageDev& B, const double* F
   for (int k = 0; k < 4; ++k) rbox = fmax(rbox, hypot(cx[k] - g.ox, cy[k] - g.oy));
   g.rbox = rbox;
   g.half_width = P.band + kBandSlackPx;
-  g.band32 = float(P.band);
+  // The match kernel decides |e| <= band_lo as in and |e| > band_hi as out in
+  // FP32; distances in between are decided again in FP64.
+  g.band_lo = float(P.band - margin);
+  g.band_hi = float(P.band + margin);
   g.nbins = P.nbins;
   g.mode = kModeFullScan;
   g.ex = g.ey = 0.0; g.ux = 1.0; g.uy = 0.0; g.S = 1.0;
@@ -157,11 +161,12 @@ __global__ void geometry_kernel(BatchView v, int32_t pb, int32_t pc) {
   if (p >= pb + pc) return;
   const PairDesc P = v.pairs[p];
   PairGeom g;
-  setup_pair(P, v.images[P.b], v.F + 9 * int64_t(p), g);
+  setup_pair(P, v.images[P.b], v.F + 9 * int64_t(p), v.margin, g);
   v.geom[p] = g;
   PairCounters z;
   z.comparisons = 0;
   z.elements = 0;
+  z.borderline = 0;
   z.accepted = 0;
   z.ties = 0;
   v.counters[p] = z;
@@ -570,7 +575,8 @@ __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v,
     tg.na = P.na;
     tg.s_begin = gb <= ge ? gb : 0;
     tg.s_end = gb <= ge ? ge : 0;
-    tg.band = v.geom[p].band32;
+    tg.band_lo = v.geom[p].band_lo;
+    tg.band_hi = v.geom[p].band_hi;
     tg.q_off = P.q_off;
     tg.c_off = P.c_off;
     tg.a_desc = A.desc;

@@ -392,10 +392,12 @@ int sfm_server_start(sfm_ctx* ctx, const sfm_server_cfg* cfg_in) {
   cfg.max_batch_queries = int64_t(1) << 22;
   cfg.opt.ratio_num = 64;
   cfg.opt.ratio_den = 100;
+  cfg.opt.recheck_margin_px = 1e-3;
   if (cfg_in) cfg = *cfg_in;
   if (cfg.max_batch_pairs < 1 || cfg.max_inflight < 1 || cfg.max_inflight > 8 ||
       cfg.max_batch_queries < 1 || cfg.opt.ratio_den <= 0 || cfg.opt.ratio_num < 0 ||
-      cfg.opt.emit_all)
+      cfg.opt.emit_all || !(cfg.opt.recheck_margin_px >= 0.0) ||
+      !std::isfinite(cfg.opt.recheck_margin_px))
     return SFM_EINVAL;
   std::shared_ptr<Server> S = std::make_shared<Server>();
   S->ctx = ctx;

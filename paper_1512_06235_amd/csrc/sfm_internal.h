@@ -67,10 +67,9 @@ struct PairGeom {
   double inv_delta;         // nbins / (kmax - kmin)
   double rbox;              // max distance of a bbox corner from the origin
   double half_width;        // d + slack, pixels
-  float band32;             // d rounded to FP32 (+inf allowed)
+  float band_lo, band_hi;   // d - margin and d + margin in FP32 (+inf allowed)
   int32_t mode;
   int32_t nbins;
-  int32_t pad;
 };
 
 // One target feature in binned order (16 bytes).
@@ -96,6 +95,7 @@ struct QueryResult {
 struct PairCounters {
   unsigned long long comparisons;
   unsigned long long elements;   // (query, candidate) slots evaluated, padding included
+  unsigned long long borderline; // slots whose FP32 distance lay within the margin of d
   uint32_t accepted;
   uint32_t ties;            // chunks that needed the tie-break pass
 };
@@ -107,8 +107,7 @@ struct PairCounters {
 struct TileGroup {
   int32_t pair, tile0, ntiles, na;  // na: queries of the pair
   int32_t s_begin, s_end;   // union candidate range (s_begin >= s_end: empty)
-  float band;               // d in FP32
-  int32_t pad0;
+  float band_lo, band_hi;   // FP32 |e| <= band_lo: in; > band_hi: out; else FP64 decides
   int64_t q_off, c_off;     // the pair's query and candidate offsets
   const uint8_t* a_desc;
   const int32_t* a_norm;
@@ -142,6 +141,7 @@ struct BatchView {
   int32_t accept_single;
   int32_t keep_counts;
   int32_t group_tiles;      // tiles per group = waves per match workgroup (1, 2 or 4)
+  double margin;            // FP64 re-decision margin around d, pixels (0 = FP32 only)
 };
 
 }  // namespace sfm
@@ -305,7 +305,12 @@ int32_t match_workgroups(int32_t device, int32_t group_tiles, int64_t groups);
 hipError_t launch_match(const BatchView& v, int32_t wgs, hipStream_t st);
 hipError_t launch_emit(const BatchView& v, int32_t pair_begin, int32_t pair_count,
                        int64_t* offset, int32_t* out_q, int32_t* out_m, int32_t* out_d1,
-                       int32_t* out_d2, int64_t* n_cmp, int32_t* all_m, int32_t* all_d1,
-                       int32_t* all_d2, int32_t* all_c, hipStream_t st);
+                       int32_t* out_d2, int64_t* n_cmp, int64_t* n_bl, int32_t* all_m,
+                       int32_t* all_d1, int32_t* all_d2, int32_t* all_c, hipStream_t st);
+// Diagnostic after a preparation: out[0] receives (atomic max) the bits of
+// the largest |FP32 - FP64| epipolar distance over the evaluated slots whose
+// FP64 distance is at most 2d, out[1] (atomic add) their number.
+hipError_t launch_band_error(const BatchView& v, int64_t n_groups, unsigned long long* out,
+                             hipStream_t st);
 
 }  // namespace sfm

@@ -4,7 +4,8 @@ import pytest
 
 import scenes
 from tests.fixtures import load_hand_fixture, random_pair, translation_F
-from tests.gpu_util import compare_all, gpu_per_query, say
+from tests.gpu_util import (FP32_ERR_PX, check_borderline_counts, compare_all, gpu_per_query,
+                            say)
 
 pytestmark = pytest.mark.gpu
 
@@ -44,25 +45,52 @@ def test_two_view_2k_parity(sfm, oracle_lib, form):
     s = scenes.make_two_view_2k()
     imgs = [(im.xy, im.desc) for im in s.images]
     _, out, ores = run_both(sfm, oracle_lib, imgs, s.pairs, [s.F], form)
-    clean, bl = compare_all(out, ores, 1)
-    say(f"  2-view 2k {form}: {clean} queries exact, {bl} borderline, comparisons {int(ores.n_comparisons[0])}")
-    assert clean > 1900
+    n, bl = compare_all(out, ores, 1)
+    gbl = check_borderline_counts(out, oracle_lib, imgs, s.pairs, [s.F])
+    say(f"  2-view 2k {form}: {n} queries exact ({bl} with a candidate within 1e-3 px of the "
+        f"edge), {int(gbl[0])} slots decided in FP64, comparisons {int(ores.n_comparisons[0])}")
+
+
+@pytest.mark.parametrize("margin", [0.0, 0.05, 0.5])
+def test_recheck_margin(sfm, oracle_lib, margin):
+    """A wide margin sends many slots through the FP64 re-decision (results
+    unchanged, counts bracketed by the oracle's); margin 0 decides in FP32 only
+    and reports no borderline slot."""
+    s = scenes.make_two_view_2k()
+    imgs = [(im.xy, im.desc) for im in s.images]
+    m = sfm.Matcher().register(imgs)
+    out = m.match(s.pairs, [s.F], emit_all=True, recheck_margin_px=margin)
+    ores = oracle_lib.match(imgs, s.pairs, [s.F])
+    if margin == 0.0:
+        assert int(out.n_borderline[0]) == 0
+        # FP32 alone may differ only on queries with a candidate within the FP32 error.
+        tight = oracle_lib.match(imgs, s.pairs, [s.F], borderline_px=2 * FP32_ERR_PX)
+        g = gpu_per_query(out, ores.q_off, 0)
+        clean = tight.pair(0)["borderline"] == 0
+        for k in ("match", "d1", "d2", "count"):
+            assert np.array_equal(g[k][clean], ores.pair(0)[k][clean]), k
+    else:
+        compare_all(out, ores, 1)
+        gbl = check_borderline_counts(out, oracle_lib, imgs, s.pairs, [s.F], margin=margin)
+        say(f"  margin {margin}: {int(gbl[0])} slots decided in FP64, results exact")
+        assert gbl[0] > 100
+    m.close()
 
 
 def test_two_view_16k_parity_and_fp32_error(sfm, oracle_lib):
-    """Full 16k x 16k pair.  Also re-checks with a 1e-4 px borderline margin:
-    every query whose candidates all lie more than 1e-4 px from the band edge
-    must match exactly, which bounds the FP32 distance error by 1e-4 px on
-    the candidates that lie between 1e-4 and 1e-3 px from the edge."""
+    """Full 16k x 16k pair: bit-exact, borderline counts bracketed, and the
+    FP32 distance within 1e-4 px of the FP64 one on every evaluated slot
+    within 2d."""
     s = scenes.make_two_view_16k()
     imgs = [(im.xy, im.desc) for im in s.images]
     m, out, ores = run_both(sfm, oracle_lib, imgs, s.pairs, [s.F])
-    clean, bl = compare_all(out, ores, 1)
-    say(f"  2-view 16k: {clean} exact, {bl} borderline (1e-3 px)")
-    tight = oracle_lib.match(imgs, s.pairs, [s.F], borderline_px=1e-4)
-    clean4, bl4 = compare_all(out, tight, 1)
-    say(f"  2-view 16k: {clean4} exact, {bl4} borderline (1e-4 px)")
-    assert bl4 < bl or bl == 0
+    n, bl = compare_all(out, ores, 1)
+    gbl = check_borderline_counts(out, oracle_lib, imgs, s.pairs, [s.F])
+    err, nslots = sfm.sfm_band_error(m.ctx, s.pairs, [s.F])
+    say(f"  2-view 16k: {n} exact ({bl} with a candidate within 1e-3 px), {int(gbl[0])} slots "
+        f"decided in FP64; max |e32 - e64| = {err:.3e} px over {nslots} slots within 2d")
+    assert nslots > int(ores.n_comparisons[0])
+    assert 0.0 < err <= FP32_ERR_PX
 
 
 def test_arc_batch_sample_batched_vs_plain(sfm, oracle_lib):
@@ -81,9 +109,11 @@ def test_arc_batch_sample_batched_vs_plain(sfm, oracle_lib):
     for form in ("batched", "plain"):
         say(f"  arc batch sample {form}")
         outs[form] = m.match(sp, Fs, form=form, emit_all=True)
-        clean, bl = compare_all(outs[form], ores, len(sp))
-        say(f"  arc batch sample {form}: {clean} exact, {bl} borderline")
-    for k in ("query", "match", "d1", "d2", "offset", "n_comparisons", "all_count"):
+        n, bl = compare_all(outs[form], ores, len(sp))
+        say(f"  arc batch sample {form}: {n} exact ({bl} with a candidate within 1e-3 px)")
+    check_borderline_counts(outs["batched"], oracle_lib, imgs, sp, Fs)
+    for k in ("query", "match", "d1", "d2", "offset", "n_comparisons", "n_borderline",
+              "all_count"):
         a, b = getattr(outs["batched"], k).cpu(), getattr(outs["plain"], k).cpu()
         n = int(outs["batched"].offset[-1]) if k in ("query", "match", "d1", "d2") else a.shape[0]
         assert np.array_equal(a[:n].numpy(), b[:n].numpy()), k
@@ -104,11 +134,13 @@ def test_arc_batch_full_as_benchmarked(sfm, oracle_lib):
     sfm.sfm_sync(m.ctx, st)
     say(f"  500-pair batch: {int(out.offset[-1])} matches, tuning {sfm.sfm_get_tuning(m.ctx)}")
     ores = oracle_lib.match(images, pairs, Fs)
-    clean, bl = compare_all(out, ores, len(pairs))
-    say(f"  500-pair batch: {clean} queries exact, {bl} borderline")
-    # With ~90 in-band candidates per query, ~4% of queries have one within
-    # 1e-3 px of either band edge; those are excused, all others are exact.
-    assert clean > 0.94 * (clean + bl)
+    n, bl = compare_all(out, ores, len(pairs))
+    gbl = check_borderline_counts(out, oracle_lib, images, pairs, Fs)
+    err, nslots = sfm.sfm_band_error(m.ctx, batch)
+    say(f"  500-pair batch: {n} queries exact ({bl} with a candidate within 1e-3 px), "
+        f"{int(gbl.sum())} slots decided in FP64; max |e32 - e64| = {err:.3e} px over {nslots} "
+        f"slots within 2d")
+    assert 0.0 < err <= FP32_ERR_PX
     m.close()
 
 

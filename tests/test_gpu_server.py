@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import scenes
-from tests.gpu_util import say
+from tests.gpu_util import compare_rows, say
 
 pytestmark = pytest.mark.gpu
 
@@ -64,17 +64,11 @@ def test_server_equals_batched_and_oracle(sfm, oracle_lib, ring):
         assert np.array_equal(r["d1"], d1) and np.array_equal(r["d2"], d2)
         assert r["n_comparisons"] == int(ncmp[k])
         assert r["done_ns"] >= r["arrival_ns"] > 0
-    # Two requests straight against the oracle (non-borderline queries).
+    # Two requests straight against the oracle (every query).
     for k in (0, len(pairs) - 1):
         o = oracle_lib.match(images, [pairs[k]], Fs[k:k + 1]).pair(0)
-        clean = o["borderline"] == 0
-        oq = np.nonzero(o["accept"] & clean)[0]
-        q = res[k]["query"]
-        keep = clean[q]
-        assert np.array_equal(q[keep], oq)
-        assert np.array_equal(res[k]["match"][keep], o["match"][oq])
-        assert np.array_equal(res[k]["d1"][keep], o["d1"][oq])
-        assert np.array_equal(res[k]["d2"][keep], o["d2"][oq])
+        compare_rows(res[k]["query"], res[k]["match"], res[k]["d1"], res[k]["d2"], o,
+                     what=f"request {k}: ")
 
 
 def test_server_errors(sfm, ring):

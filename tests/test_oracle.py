@@ -47,6 +47,41 @@ def test_band_inclusive_closed_form(oracle_lib, d):
         assert oracle_lib.epipolar_distance(F, 50.0, y, *xy_b[k]) == want
 
 
+@pytest.mark.parametrize("d", [4.0, 2.5])
+def test_borderline_counter_closed_form(oracle_lib, d):
+    """The borderline count: targets whose FP64 distance e satisfies
+    |e - d| <= borderline_px (inclusive), on both sides of the line, members
+    of the band or not.  Axis-aligned line y' = y; every offset below is a
+    multiple of 2^-15, so y + offset is exact in float32 and e equals |offset|
+    exactly.  Catches counting members only, a strict comparison, and a
+    wrong margin."""
+    F = translation_F((1.0, 0.0, 0.0))
+    y = 300.0
+    m, u = 2**-10, 2**-15
+    offs = [d, -d,                      # on the edge
+            d + m, -(d + m),            # out of the band, exactly m away: counted
+            d - m, -(d - m),            # in the band, exactly m away: counted
+            d + m + u, -(d - m - u),    # one ulp beyond m: not counted
+            d + m - u, d + 2**-11,      # out of the band, within m: counted
+            0.0, 3 * d]                 # far from the edge
+    counted = [1, 1, 1, 1, 1, 1, 0, 0, 1, 1, 0, 0]
+    members = [1, 1, 0, 0, 1, 1, 0, 1, 0, 0, 1, 0]
+    xy_b = np.array([[100.0 + 10 * k, y + o] for k, o in enumerate(offs)], np.float32)
+    assert np.all(xy_b[:, 1].astype(np.float64) - y == np.array(offs))   # exact in float32
+    for k, o in enumerate(offs):
+        assert oracle_lib.epipolar_distance(F, 50.0, y, *xy_b[k]) == abs(o)
+    xy_a = np.array([[50.0, y], [60.0, y]], np.float32)
+    desc_a = np.zeros((2, 128), np.uint8)
+    desc_b = np.zeros((len(offs), 128), np.uint8)
+    desc_b[:, 0] = np.arange(1, len(offs) + 1)
+    for px, want in [(m, sum(counted)), (1e-3, sum(counted)), (0.0, 2), (m - u, 4),
+                     (2 * d - u, len(offs) - 1), (2 * d, len(offs))]:
+        p, r = run(oracle_lib, xy_a, desc_a, xy_b, desc_b, F, d, borderline_px=px)
+        assert list(p["borderline"]) == [want, want], px
+        assert int(r.n_borderline[0]) == 2 * want
+        assert list(p["count"]) == [sum(members)] * 2
+
+
 def test_band_general_line_and_sign(oracle_lib):
     """Pure translation with a finite epipole e: the line of p passes through e
     (textbook F = [e]_x); targets on it are candidates, targets 5 px off it are not."""
