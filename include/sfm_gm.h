@@ -352,9 +352,9 @@ int sfm_server_stop(sfm_ctx* ctx);
 /* ---------------------------------------------------------------------------
  * Tuning.  Two parameters of the batched form trade evaluated slots against
  * scheduling and preparation costs (Appendix A steps 1-2 leave them open):
- *   group_tiles       query tiles of 32 queries (in pencil order) that one
- *                     match workgroup streams one candidate range for:
- *                     1, 2 or 4 (default 2);
+ *   group_tiles       query tiles of 16 queries (in pencil order) that one
+ *                     match workgroup of four waves streams one candidate
+ *                     range for: 4 or 8 (default 8);
  *   features_per_bin  average target features per bin of b's pencil
  *                     binning, 1..1024 (default 8).
  * Results do not depend on them.  They apply to later calls on the context. */
@@ -444,7 +444,7 @@ int sfm_triangulate(sfm_ctx* ctx, int64_t n_nodes, const int32_t* label, const i
                     int32_t* n_obs, void* stream);
 
 /* Time the batched form on the given batch for every group_tiles in
- * {1, 2, 4} and features_per_bin in {4, 8, 16} (one warm-up and `repeats`
+ * {4, 8} and features_per_bin in {4, 8, 16} (one warm-up and `repeats`
  * timed calls each, HIP events on `stream`), keep the fastest setting on the
  * context, and write the mean milliseconds per call to ms_out[3 * i + j]
  * (i over group_tiles, j over features_per_bin; ms_out may be NULL).  Uses

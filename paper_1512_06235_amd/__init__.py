@@ -474,7 +474,7 @@ def sfm_get_tuning(ctx):
     return t.value, f.value
 
 
-AUTOTUNE_GROUP_TILES = (1, 2, 4)
+AUTOTUNE_GROUP_TILES = (4, 8)
 AUTOTUNE_FEATURES_PER_BIN = (4, 8, 16)
 
 
@@ -482,7 +482,7 @@ def sfm_autotune(ctx, pairs, F, opt=None, stream=None, repeats: int = 3):
     """Time every tuning on this batch, keep the fastest; returns
     {(group_tiles, features_per_bin): ms per call}."""
     batch = pairs if isinstance(pairs, PairBatch) and F is None else PairBatch(pairs, F)
-    ms = (C.c_double * 9)()
+    ms = (C.c_double * (len(AUTOTUNE_GROUP_TILES) * len(AUTOTUNE_FEATURES_PER_BIN)))()
     st = lib().sfm_autotune(ctx, batch.c_pairs, batch.n, batch.F.ctypes.data,
                             C.byref(opt if opt is not None else options()),
                             stream.cuda_stream if stream is not None else None, int(repeats), ms)

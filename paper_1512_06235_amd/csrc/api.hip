@@ -87,9 +87,10 @@ int hip_fail(sfm_ctx* ctx, hipError_t e, const char* what) {
 
 // Sections of one call's workspace.
 struct Layout {
-  size_t pairs, F, order, geom, counters, wg_start, cand, bins, qrec, res, qwin, groups, gcost, pcost, total, staged;
+  size_t pairs, F, order, geom, counters, wg_start, cand_x, cand_y, cand_nc, cand_j, bins, qrec,
+      res, qwin, groups, gcost, pcost, total, staged;
   int32_t wgs = 0;
-  int64_t sum_na = 0, sum_nb = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
+  int64_t sum_na = 0, sum_nc = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
 };
 
 int32_t bins_for(int32_t nb, int32_t features_per_bin) {
@@ -100,7 +101,7 @@ Layout plan(const std::vector<PairDesc>& pd, int32_t device, int32_t group_tiles
   Layout L;
   for (const PairDesc& p : pd) {
     L.sum_na += p.na;
-    L.sum_nb += p.nb;
+    L.sum_nc += p.nb + kCandPad;
     L.sum_bins += p.nbins + 1;
     L.sum_blocks += p.nblocks;
     L.sum_groups += p.ngroups;
@@ -115,7 +116,10 @@ Layout plan(const std::vector<PairDesc>& pd, int32_t device, int32_t group_tiles
   L.counters = o; o = align_up(o + P * sizeof(PairCounters));
   L.wgs = match_workgroups(device, group_tiles, L.sum_groups);
   L.wg_start = o; o = align_up(o + size_t(L.wgs + 1) * sizeof(int32_t));
-  L.cand = o; o = align_up(o + size_t(L.sum_nb) * sizeof(CandRec));
+  L.cand_x = o; o = align_up(o + size_t(L.sum_nc) * sizeof(float));
+  L.cand_y = o; o = align_up(o + size_t(L.sum_nc) * sizeof(float));
+  L.cand_nc = o; o = align_up(o + size_t(L.sum_nc) * sizeof(uint32_t));
+  L.cand_j = o; o = align_up(o + size_t(L.sum_nc) * sizeof(int32_t));
   L.bins = o; o = align_up(o + size_t(L.sum_bins) * sizeof(int32_t));
   L.qrec = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryRec));
   L.res = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryResult));
@@ -175,7 +179,7 @@ int describe_pairs(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, i
     p.band = ignore_band ? INFINITY : s.band_px;
     p.ignore_band = ignore_band ? 1 : 0;
     q += p.na;
-    c += p.nb;
+    c += p.nb + kCandPad;
     bo += p.nbins + 1;
     blk += p.nblocks;
     grp += p.ngroups;
@@ -391,7 +395,10 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
   v.F = reinterpret_cast<const double*>(ctx->ws + L.F);
   v.geom = reinterpret_cast<PairGeom*>(ctx->ws + L.geom);
   v.counters = reinterpret_cast<PairCounters*>(ctx->ws + L.counters);
-  v.cand = reinterpret_cast<CandRec*>(ctx->ws + L.cand);
+  v.cand_x = reinterpret_cast<float*>(ctx->ws + L.cand_x);
+  v.cand_y = reinterpret_cast<float*>(ctx->ws + L.cand_y);
+  v.cand_nc = reinterpret_cast<uint32_t*>(ctx->ws + L.cand_nc);
+  v.cand_j = reinterpret_cast<int32_t*>(ctx->ws + L.cand_j);
   v.bin_start = reinterpret_cast<int32_t*>(ctx->ws + L.bins);
   v.qrec = reinterpret_cast<QueryRec*>(ctx->ws + L.qrec);
   v.res = reinterpret_cast<QueryResult*>(ctx->ws + L.res);
@@ -492,7 +499,8 @@ size_t ctx_request_bytes(const sfm_ctx* ctx, int32_t a, int32_t b) {
   const size_t nblocks = (na + kQueryTile - 1) / kQueryTile;
   const size_t ngroups = (nblocks + size_t(ctx->group_tiles) - 1) / size_t(ctx->group_tiles);
   return sizeof(PairDesc) + 9 * sizeof(double) + sizeof(int32_t) + sizeof(PairGeom) +
-         sizeof(PairCounters) + sizeof(long long) + nb * sizeof(CandRec) +
+         sizeof(PairCounters) + sizeof(long long) +
+         (nb + kCandPad) * (2 * sizeof(float) + sizeof(uint32_t) + sizeof(int32_t)) +
          (nbins + 1) * sizeof(int32_t) +
          na * (sizeof(QueryRec) + sizeof(QueryResult) + sizeof(int2)) +
          ngroups * (sizeof(TileGroup) + sizeof(int32_t));
@@ -500,7 +508,7 @@ size_t ctx_request_bytes(const sfm_ctx* ctx, int32_t a, int32_t b) {
 // The alignment of plan()'s sections and the schedule table at its largest.
 size_t ctx_call_bytes(const sfm_ctx* ctx) {
   const int32_t wgs = match_workgroups(ctx->device, ctx->group_tiles, int64_t(1) << 40);
-  return 16 * kAlign + size_t(wgs + 1) * sizeof(int32_t);
+  return 20 * kAlign + size_t(wgs + 1) * sizeof(int32_t);
 }
 size_t ctx_budget(const sfm_ctx* ctx) { return ctx->budget; }
 }  // namespace sfm
@@ -1146,8 +1154,8 @@ int sfm_sync(sfm_ctx* ctx, void* stream) {
 int sfm_set_tuning(sfm_ctx* ctx, int32_t group_tiles, int32_t features_per_bin) {
   if (!ctx) return SFM_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
-  if (group_tiles != 1 && group_tiles != 2 && group_tiles != 4)
-    return fail(ctx, SFM_EINVAL, "group_tiles must be 1, 2 or 4");
+  if (group_tiles != 4 && group_tiles != 8)
+    return fail(ctx, SFM_EINVAL, "group_tiles must be 4 or 8");
   if (features_per_bin < 1 || features_per_bin > 1024)
     return fail(ctx, SFM_EINVAL, "features_per_bin must be in 1..1024");
   ctx->group_tiles = group_tiles;
@@ -1313,7 +1321,7 @@ int sfm_autotune(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const dou
                  const sfm_options* opt, void* stream, int32_t repeats, double* ms_out) {
   if (!ctx) return SFM_EINVAL;
   if (repeats < 1) return fail(ctx, SFM_EINVAL, "repeats must be >= 1");
-  static const int32_t kTiles[3] = {1, 2, 4};
+  static const int32_t kTiles[2] = {4, 8};
   static const int32_t kFpb[3] = {4, 8, 16};
   int64_t rows = 0;
   for (int32_t k = 0; k < n_pairs && pairs; ++k) {
@@ -1350,7 +1358,7 @@ int sfm_autotune(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const dou
   };
   double best = INFINITY;
   int32_t best_t = keep_t, best_f = keep_f;
-  for (int ti = 0; ti < 3 && rc == SFM_OK; ++ti) {
+  for (int ti = 0; ti < 2 && rc == SFM_OK; ++ti) {
     for (int fi = 0; fi < 3 && rc == SFM_OK; ++fi) {
       set(kTiles[ti], kFpb[fi]);
       // One untimed run sizes the workspace for this configuration.

@@ -73,6 +73,8 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(BatchView v, int32_t
       const int32_t i = base + k * kEmitThreads + t;
       if (i < P.na) {
         r[k] = res[i];
+        // The match kernel leaves the binned position of the match.
+        if (v.cand_j && r[k].match >= 0) r[k].match = v.cand_j[P.c_off + r[k].match];
       } else {
         r[k].match = -1; r[k].d1 = r[k].d2 = kDistInf; r[k].flags = 0;
       }

@@ -1,32 +1,37 @@
 // Fused candidate test + distance + two-nearest kernel (a4-a6), Appendix A
 // steps 3-4 redesigned for CDNA4.
 //
-// A workgroup of 1, 2 or 4 waves (default two) owns a group of consecutive query
-// tiles (32 queries each, in pencil order) of one pair, one tile per wave.
-// Their candidate ranges overlap heavily, so the workgroup streams the union
-// range of b's binned features through LDS once, 32 candidates per step:
-//   - each wave fetches its share of the 32 descriptor rows with coalesced
-//     loads (eight lanes per 128-byte row) and stores them XOR-swizzled into
-//     the shared stage; one barrier per step publishes the stage;
-//   - each wave whose own range meets the step reads the rows back as the A
-//     operand of v_mfma_i32_32x32x32_i8; its negated query rows are the
-//     resident B operand, so four MFMAs give -q.c for a 32x32 tile with exact
-//     int32 accumulation (bytes 0..127 fit int8, 128 * 127^2 < 2^31);
-//   - each lane then holds one query and 16 candidates; it runs the exact
-//     band test of eqs. (2)-(3) in FP32 on the candidates' centred
-//     coordinates and folds in-band distances into a running two-smallest
-//     pair of 32-bit keys
-//         key = ((||c||^2 - 2 q.c + 2^21) << 10) | (position mod 1024),
-//     so one unsigned min and one med3 keep (D1, its position) and D2;
-//   - the two lanes of one query merge with one cross-half exchange.
+// Work unit: a group of up to 4 * TPW consecutive query tiles of one pair (16
+// queries each, in pencil order).  A workgroup of four waves streams the union
+// of the group's candidate ranges (b's features in binned order) through an
+// LDS ring of four 64-position segments; wave w owns tiles w and w + 4.
+//   - Segments arrive by LDS DMA (global_load_lds): each wave fetches 16 of a
+//     segment's 64 descriptor rows (two loads of 16 bytes per lane, eight lanes
+//     per 128-byte row, XOR-swizzled) and 16 of its coordinates and keys.  The
+//     rows' indices in b arrive two segments earlier in a ring of their own,
+//     so no loaded value passes through a register on its way to the stage.
+//   - Loads run three segments ahead of the computation, with one wait for the
+//     wave's own loads and one barrier per segment.  The next group's query
+//     records and first row indices are loaded while the current group ends.
+//   - Each tile walks its own candidate range (start rounded down to a
+//     multiple of 4) in steps of 16 positions.  A step's rows are the A
+//     operand of v_mfma_i32_16x16x64_i8 and the tile's negated query rows the
+//     resident B operand: two MFMAs give -q.c for 16 candidates x 16 queries,
+//     exact in int32 (bytes 0..127 fit int8, 128 * 127^2 < 2^31).
+//   - Each lane then holds one query and 4 candidates.  It runs the band test
+//     of eqs. (2)-(3) in FP32 on centred coordinates and folds in-band keys
+//         key = ((||c||^2 - 2 q.c + 2^21) << 10) | (position mod 1024)
+//     into its two smallest with one v_med3_u32 and one v_min_u32.
+//   - Slots whose FP32 distance lies within the margin of d are queued in LDS
+//     with their exact key and index in b, and decided in FP64 when the
+//     group's stream ends (no global load stalls the stream).
 // The key orders equal distances by binned position, not by index in b; when
-// the two smallest keys of a chunk share the distance, an exact pass picks the
-// lowest index among the tied candidates, so results equal the definition.
-// Two tiles per group balance the row fetches each wave issues against the
-// steps a wave idles at the barrier outside its own range (four tiles: 13%
-// slower; one tile, no sharing: 17% slower, bound by the address units).
+// a query's smallest distance is shared, an exact pass picks the lowest index
+// among the tied candidates, so results equal the definition.  Results hold
+// the binned position of the match; emission maps it to the index in b.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 
 #include "sfm_internal.h"
 
@@ -34,21 +39,22 @@ namespace sfm {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
 typedef unsigned int nv4u __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) nv4u g_nv4u;
 typedef const __attribute__((address_space(1))) int32_t g_i32;
+typedef __attribute__((address_space(3))) void lds_void;
 
-// A workgroup of W waves (one query tile each) shares the candidate stream:
-// each wave fetches kCandTile / W rows of every step with (kCandTile / W) / 8
-// loads of 16 bytes per lane.
-template <int W>
-struct Split {
-  static constexpr int kRowsPerWave = kCandTile / W;
-  static constexpr int kRowLoads = kRowsPerWave / 8;
-  static_assert(kRowsPerWave % 8 == 0 && kRowsPerWave <= 64, "waves split a step by 8 rows");
-};
-constexpr int kMetaSlots = 3;
+constexpr int kWaves = kMatchWaves;           // waves per workgroup
+constexpr int kSeg = 64;                      // positions per ring segment
+constexpr int kRing = 4;                      // segments of rows and metadata in LDS
+constexpr int kRingPos = kRing * kSeg;
+constexpr int kJRing = 6;                     // segments of row indices in LDS (per parity)
+constexpr int kRowsPerWave = kSeg / kWaves;   // 16 rows of a segment per wave
+constexpr int kBorderCap = 32;                // queued FP64 decisions per wave and group
+constexpr int kRowLoads = 5;                  // loads per wave for one segment's rows + metadata
+static_assert(kRowsPerWave == 16, "each wave fetches 16 rows and 16 metadata words");
+static_assert(kQueryTile == 16, "one MFMA column block of queries per tile");
+constexpr uint32_t kKeyDistInf = kKeyInf >> kPosBits;
 
 // Epipolar distance of eqs. (2)-(3) on centred FP32 coordinates,
 // |a x + b y + c| with (a, b) unit.  The single FP32 evaluation every pass uses.
@@ -73,43 +79,6 @@ __device__ __forceinline__ double band_dist64(const double* F, float xq, float y
   return fabs(a * double(xb) + b * double(yb) + c) / s;
 }
 
-// The band decision in FP64.  The FP32 test is decided again by this function
-// for every distance within the margin of d, so results equal an FP64
-// evaluation as long as the FP32 error stays below the margin.
-__device__ __forceinline__ bool band_exact(const double* F, float xq, float yq, float xb, float yb,
-                                           double d) {
-  return band_dist64(F, xq, yq, xb, yb) <= d;
-}
-
-// What the FP64 re-decision of one pair needs, read when a step first has a
-// borderline slot.
-struct ExactCtx {
-  const double* F;          // the caller's F of the pair
-  const float* a_xy;        // original keypoints of a and b
-  const float* b_xy;
-  double d;
-};
-
-__device__ __forceinline__ ExactCtx exact_ctx(const BatchView& v, int32_t pair) {
-  const PairDesc P = v.pairs[pair];
-  ExactCtx x;
-  x.F = v.F + 9 * int64_t(pair);
-  x.a_xy = v.images[P.a].xy;
-  x.b_xy = v.images[P.b].xy;
-  x.d = P.band;
-  return x;
-}
-
-// Band membership of query i (original index in a) and target j (original
-// index in b) from the FP32 distance e32: in below band_lo, out above band_hi,
-// decided in FP64 in between.
-__device__ __forceinline__ bool member(float e32, float lo, float hi, const ExactCtx& x, int32_t i,
-                                       int32_t j) {
-  if (e32 <= lo) return true;
-  if (!(e32 <= hi)) return false;
-  return band_exact(x.F, x.a_xy[2 * i], x.a_xy[2 * i + 1], x.b_xy[2 * j], x.b_xy[2 * j + 1], x.d);
-}
-
 // Per-byte negation of four bytes in 0..127 (no borrow crosses a byte).
 __device__ __forceinline__ int neg_bytes(uint32_t w) {
   return int((0x80808080u - w) ^ 0x80808080u);
@@ -122,7 +91,7 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
 // Exact squared L2 of two 128-byte rows with VALU dot products.
 __device__ inline int32_t row_dist(const uint8_t* p, const uint8_t* q, int32_t np, int32_t nq) {
   uint32_t dot = 0;
-#pragma unroll
+#pragma unroll 2
   for (int w = 0; w < 8; ++w) {
     const uint4 u = reinterpret_cast<const uint4*>(p)[w];
     const uint4 v = reinterpret_cast<const uint4*>(q)[w];
@@ -134,235 +103,202 @@ __device__ inline int32_t row_dist(const uint8_t* p, const uint8_t* q, int32_t n
   return np + nq - 2 * int32_t(dot);
 }
 
-// The same with one pair of 16-byte loads in flight (few registers: for the
-// rare FP64 re-decision inside the step loop).
-__device__ inline int32_t row_dist_lean(const uint8_t* p, const uint8_t* q, int32_t np,
-                                        int32_t nq) {
-  uint32_t dot = 0;
-#pragma unroll 1
-  for (int w = 0; w < 8; ++w) {
-    const uint4 u = reinterpret_cast<const uint4*>(p)[w];
-    const uint4 v = reinterpret_cast<const uint4*>(q)[w];
-    dot = __builtin_amdgcn_udot4(u.x, v.x, dot, false);
-    dot = __builtin_amdgcn_udot4(u.y, v.y, dot, false);
-    dot = __builtin_amdgcn_udot4(u.z, v.z, dot, false);
-    dot = __builtin_amdgcn_udot4(u.w, v.w, dot, false);
-  }
-  return np + nq - 2 * int32_t(dot);
-}
-
-// Loads through global-address-space pointers compile to global_load_*,
-// which only count against vmcnt.
 __device__ __forceinline__ nv4u gload16(const void* p) { return *(g_nv4u*)p; }
 
-// Raw binned record {x, y, ncpos, j} of position min(cp, c1 - 1) (c1 > 0).
-__device__ __forceinline__ nv4u load_rec(const CandRec* cand, int32_t cp, int32_t c1) {
-  return gload16(cand + min(cp, c1 - 1));
+// ---------------------------------------------------------------------------
+// LDS of a workgroup (40 KB: four workgroups per CU): the ring of segments
+// (rows XOR-swizzled: chunk c of ring position r at (c ^ (r & 7)) * 16 within
+// the row), two rings of row indices (the current group's and the next
+// group's) and the queues of FP64 decisions.
+// ---------------------------------------------------------------------------
+struct MatchLds {
+  uint8_t rows[kRingPos * kDescBytes];
+  float x[kRingPos];
+  float y[kRingPos];
+  uint32_t nc[kRingPos];
+  int32_t j[2][kJRing * kSeg];
+  uint4 queue[kWaves][kBorderCap];   // {key, rel. position << 7 | tile << 6 | lane, j, -}
+};
+static_assert(sizeof(MatchLds) <= 40960, "four workgroups per CU");
+
+// Keeps the compiler from moving memory accesses across a wait or barrier.
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+// Waits until at most N of this wave's vector-memory operations are in
+// flight (they complete in order); expcnt and lgkmcnt are left alone.
+template <int N>
+__device__ __forceinline__ void wait_loads() {
+  static_assert(N >= 0 && N < 16, "vmcnt range used here");
+  compiler_fence();
+  __builtin_amdgcn_s_waitcnt(N | 0x0F70);
+  compiler_fence();
 }
 
-// Workgroup LDS: two stages of 32 candidate rows and three stages of their
-// metadata.  A row is stored as eight 16-byte chunks with chunk c of row r at
-// slot c ^ (r & 7), so both the coalesced stores (eight lanes per row) and the
-// MFMA operand reads (one row per lane) hit all 32 banks without conflicts.
-struct GroupLds {
-  uint8_t rows[2][kCandTile * kDescBytes];
-  float x[kMetaSlots][kCandTile];
-  float y[kMetaSlots][kCandTile];
-  uint32_t nc[kMetaSlots][kCandTile];
-  uint32_t sink[kMaxGroupTiles][3][64];   // targets of the lanes that own no record
+// Workgroup barrier without the fence __syncthreads() adds (which would wait
+// for every LDS DMA in flight, including those of segments not yet needed).
+__device__ __forceinline__ void barrier() {
+  compiler_fence();
+  __builtin_amdgcn_s_barrier();
+  compiler_fence();
+}
+
+// LDS DMA: lane l's 16 (or 4) bytes at src land at LDS offset lds_off + 16 l
+// (4 l); lds_off is wave-uniform.  Written as inline asm (M0 set in the same
+// statement) so that the compiler does not track these LDS writes: it would
+// otherwise wait for every DMA in flight before each LDS read of the ring.
+// The kernel orders them itself with wait_loads() and barrier(); the
+// compiler's own waits for loads into registers stay correct (they can only
+// become stricter).
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void dma16(const void* src, uint32_t lds_off) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
+               :: "s"(__builtin_amdgcn_readfirstlane(lds_off)), "v"(src) : "memory", "m0");
+}
+__device__ __forceinline__ void dma4(const void* src, uint32_t lds_off) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dword %1, off"
+               :: "s"(__builtin_amdgcn_readfirstlane(lds_off)), "v"(src) : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// One pair's binned candidates, indexed by pair position, as one group
+// streams them.
+struct Stream {
+  const float* x;
+  const float* y;
+  const uint32_t* nc;
+  const int32_t* j;
+  const uint8_t* b_desc;
+  int32_t base;             // pair position of segment 0 (group start rounded down to 4)
+  int32_t last;             // last readable pair position (n_b plus padding, minus 1)
+  int32_t nsc;              // segments holding step starts
+  int32_t nsl;              // segments read (a step reaches 15 positions past its start)
+  uint32_t lds;             // LDS offset of the workgroup's MatchLds
+  int32_t jpar;             // which index ring the group uses
 };
 
-// Wave w owns candidates R*w .. R*w+R-1 of every step (R = kRowsPerWave):
-// lane l < R holds the record of candidate R*w + l.  Those lanes stage the
-// metadata (the other lanes write to distinct sink words: no divergent
-// branch, no bank conflict).  Positions past the range get a NaN coordinate,
-// which no band test passes.
-template <int W>
-__device__ __forceinline__ void stage_meta(GroupLds& L, int st, const nv4u& r, int32_t t0,
-                                           int32_t c1, int wave, int lane) {
-  constexpr int R = Split<W>::kRowsPerWave;
-  const int cand_i = R * wave + (lane % R);
-  const bool own = lane < R;
-  float* px = own ? &L.x[st][cand_i] : reinterpret_cast<float*>(&L.sink[wave][0][lane]);
-  float* py = own ? &L.y[st][cand_i] : reinterpret_cast<float*>(&L.sink[wave][1][lane]);
-  uint32_t* pn = own ? &L.nc[st][cand_i] : &L.sink[wave][2][lane];
-  *px = t0 + cand_i < c1 ? __uint_as_float(r.x) : NAN;
-  *py = __uint_as_float(r.y);
-  *pn = r.z;
+__device__ __forceinline__ Stream make_stream(const BatchView& v, const TileGroup& G,
+                                              const MatchLds& L, int32_t jpar) {
+  Stream s;
+  s.x = v.cand_x + G.c_off;
+  s.y = v.cand_y + G.c_off;
+  s.nc = v.cand_nc + G.c_off;
+  s.j = v.cand_j + G.c_off;
+  s.b_desc = G.b_desc;
+  s.base = G.s_begin & ~3;
+  s.last = G.nb + kCandPad - 1;
+  const bool any = G.s_end > G.s_begin;
+  s.nsc = any ? (G.s_end - s.base + kSeg - 1) / kSeg : 0;
+  s.nsl = any ? (G.s_end + kQueryTile - 1 - s.base + kSeg - 1) / kSeg : 0;
+  s.lds = uint32_t(reinterpret_cast<uintptr_t>((lds_void*)&L));
+  s.jpar = jpar;
+  return s;
 }
 
-// Load k of this wave's coalesced share of a step's rows: lane l fetches
-// 16-byte chunk (l & 7) of row R*w + 8k + (l >> 3), whose index in b lane
-// 8k + (l >> 3) holds.
-__device__ __forceinline__ nv4u load_row_share(const nv4u& r, const uint8_t* desc, int lane,
-                                               int k) {
-  const int32_t j = __shfl(int32_t(r.w), 8 * k + (lane >> 3), 64);
-  return gload16(desc + int64_t(j) * kDescBytes + 16 * (lane & 7));
+__device__ __forceinline__ int jring_index(const Stream& s, int32_t k) {
+  return s.jpar * (kJRing * kSeg) + (k % kJRing) * kSeg;
 }
 
-template <int W>
-__device__ __forceinline__ void store_row_share(GroupLds& L, int st, int wave, int lane, int k,
-                                                const nv4u& rw) {
-  const int m = lane >> 3, c = lane & 7;
-  const int row = Split<W>::kRowsPerWave * wave + 8 * k + m;   // row & 7 == m
-  *reinterpret_cast<nv4u*>(&L.rows[st][row * kDescBytes + ((c ^ m) << 4)]) = rw;
-}
-
-// The MFMA A operand: row (lane & 31), k-slice 16 * half + 32 * s = chunk 2s + half.
-__device__ __forceinline__ void read_a(const GroupLds& L, int st, int lane, v4i (&a)[4]) {
-  const int r = lane & 31, h = lane >> 5;
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-    a[s] = *reinterpret_cast<const v4i*>(&L.rows[st][r * kDescBytes + (((2 * s + h) ^ (r & 7)) << 4)]);
-}
-
-// The four MFMAs on one step's rows, then this lane's 16 results folded into
-// the running two smallest keys (k1, k2), with the candidates' coordinates and
-// keys read from metadata slot st.  A slot is folded when its FP32 distance is
-// at most band_lo; when any slot of the wave lies within (band_lo, band_hi],
-// those slots are decided in FP64 afterwards, one at a time, and folded with
-// their distance recomputed on the VALU.  In-band slots are counted per lane
-// when counts are kept, per wave (scalar) otherwise.
-template <bool kKeepCounts>
-__device__ __forceinline__ void tile_compute(const v4i (&ac)[4], const v4i (&bq)[4],
-                                             const QueryRec& qr, int32_t nq, float lo, float hi,
-                                             const GroupLds& L, int st, int half, uint32_t& k1,
-                                             uint32_t& k2, int32_t& cnt, uint32_t& wcnt,
-                                             uint32_t& wbl, const BatchView& v,
-                                             const TileGroup& G, int32_t t0) {
-  v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(ac[s], bq[s], acc, 0, 0, 0);
-
-  // Lane (col, half) holds rows 8g + 4*half + e of the tile, e = 0..3.
-  unsigned long long border = 0;
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const int r0 = 8 * g + 4 * half;
-    const float4 xs = *reinterpret_cast<const float4*>(&L.x[st][r0]);
-    const float4 ys = *reinterpret_cast<const float4*>(&L.y[st][r0]);
-    const uint4 ns = *reinterpret_cast<const uint4*>(&L.nc[st][r0]);
-    const float xv[4] = {xs.x, xs.y, xs.z, xs.w};
-    const float yv[4] = {ys.x, ys.y, ys.z, ys.w};
-    const uint32_t nv[4] = {ns.x, ns.y, ns.z, ns.w};
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float d32 = band_dist32(qr.a, qr.b, qr.c, xv[e], yv[e]);
-      const bool mem = d32 <= lo;
-      border |= __ballot(d32 <= hi) ^ __ballot(mem);   // lo <= hi: mem implies d32 <= hi
-      uint32_t key = nv[e] + (uint32_t(acc[4 * g + e]) << 11);
-      key = mem ? key : kKeyInf;
-      k2 = umed3(k1, key, k2);
-      k1 = min(k1, key);
-      if (kKeepCounts)
-        cnt += mem ? 1 : 0;
-      else
-        wcnt += __builtin_popcountll(__ballot(mem));
-    }
+// Segment k's row indices of this wave (its 16 positions) into the index
+// ring: one 4-byte load on 16 lanes.
+__device__ __forceinline__ void issue_j(const Stream& s, int32_t k, int w, int lane) {
+  if (lane < kRowsPerWave) {
+    const int32_t p = min(s.base + kSeg * k + kRowsPerWave * w + lane, s.last);
+    dma4(s.j + p, s.lds + uint32_t(offsetof(MatchLds, j)) +
+                      4u * uint32_t(jring_index(s, k) + kRowsPerWave * w));
   }
-  if (border == 0) return;
-
-  // Rare: this lane's slots within the margin of d, decided in FP64.
-  uint32_t bm = 0;
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = 8 * g + 4 * half + e;
-      const float d32 = band_dist32(qr.a, qr.b, qr.c, L.x[st][r], L.y[st][r]);
-      if (d32 <= hi && !(d32 <= lo)) bm |= 1u << (4 * g + e);
-    }
-  }
-  int32_t nbl = __builtin_popcount(bm), nin = 0;
-  const ExactCtx x = exact_ctx(v, G.pair);
-  const CandRec* cand = v.cand + G.c_off;
-  while (bm) {
-    const int sidx = __builtin_ctz(bm);
-    bm &= bm - 1;
-    const int r = 8 * (sidx >> 2) + 4 * half + (sidx & 3);
-    const int32_t j = cand[t0 + r].j;
-    if (!band_exact(x.F, x.a_xy[2 * qr.i], x.a_xy[2 * qr.i + 1], x.b_xy[2 * j],
-                    x.b_xy[2 * j + 1], x.d))
-      continue;
-    const uint32_t nc = L.nc[st][r];
-    const int32_t D = row_dist_lean(G.a_desc + int64_t(qr.i) * kDescBytes,
-                               G.b_desc + int64_t(j) * kDescBytes, nq,
-                               int32_t(nc >> kPosBits) - int32_t(kDistBias));
-    const uint32_t key = (uint32_t(D - nq + int32_t(kDistBias)) << kPosBits) | (nc & (kChunk - 1));
-    k2 = umed3(k1, key, k2);
-    k1 = min(k1, key);
-    ++nin;
-  }
-  if (kKeepCounts) cnt += nin;
-  for (int o = 32; o > 0; o >>= 1) {
-    nbl += __shfl_xor(nbl, o, 64);
-    nin += __shfl_xor(nin, o, 64);
-  }
-  wbl += uint32_t(nbl);
-  if (!kKeepCounts) wcnt += uint32_t(nin);
 }
 
-// Running result of one query column across chunks of 1024 positions.
-struct QueryState {
-  int32_t d1, d2, j1;
-  uint32_t ties;
+// Segment k's rows and metadata of this wave into ring slot k mod 4: two
+// 16-byte loads per lane (lane l: row 8t + (l >> 3) of the wave's 16, chunk
+// (l & 7) ^ (row & 7), landing at slot l & 7 of the row) and three 4-byte
+// loads on 16 lanes.  The rows' indices come from the index ring (loaded
+// earlier by this wave and complete).
+__device__ __forceinline__ void issue_rows(const Stream& s, const MatchLds& L, int32_t k, int w,
+                                           int lane) {
+  const int slot = k % kRing;
+  const int32_t* jr_base = &L.j[0][0] + jring_index(s, k) + kRowsPerWave * w;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int rr = 8 * t + (lane >> 3);
+    const int32_t jr = jr_base[rr];
+    const int c = (lane & 7) ^ (rr & 7);
+    dma16(s.b_desc + int64_t(jr) * kDescBytes + 16 * c,
+          s.lds + uint32_t(offsetof(MatchLds, rows)) +
+              uint32_t((slot * kSeg + kRowsPerWave * w + 8 * t) * kDescBytes));
+  }
+  if (lane < kRowsPerWave) {
+    const int32_t p = min(s.base + kSeg * k + kRowsPerWave * w + lane, s.last);
+    const uint32_t o = 4u * uint32_t(slot * kSeg + kRowsPerWave * w);
+    dma4(s.x + p, s.lds + uint32_t(offsetof(MatchLds, x)) + o);
+    dma4(s.y + p, s.lds + uint32_t(offsetof(MatchLds, y)) + o);
+    dma4(s.nc + p, s.lds + uint32_t(offsetof(MatchLds, nc)) + o);
+  }
+}
+
+// Waits for segment s + 1 (and the row indices of segment s + 3) given which
+// later loads exist: those of iteration s - 1 are the index load of segment
+// s + 4 and the row loads of segment s + 2.
+__device__ __forceinline__ void wait_segment(int32_t s, int32_t nsl) {
+  if (s + 4 < nsl)
+    wait_loads<1 + kRowLoads>();
+  else if (s + 2 < nsl)
+    wait_loads<kRowLoads>();
+  else
+    wait_loads<0>();
+}
+
+// A group record read with scalar loads (its index is uniform).
+typedef const __attribute__((address_space(4))) v4i c_v4i;
+__device__ __forceinline__ TileGroup load_group(const TileGroup* groups, int32_t g) {
+  union {
+    v4i w[sizeof(TileGroup) / 16];
+    TileGroup t;
+  } u;
+  c_v4i* src = (c_v4i*)(groups + g);
+#pragma unroll
+  for (int k = 0; k < int(sizeof(TileGroup) / 16); ++k) u.w[k] = src[k];
+  return u.t;
+}
+
+// The first stage of a group: this wave's query records (in registers) and
+// the row indices of its first three segments (into index ring jpar).
+template <int TPW>
+struct GroupStart {
+  nv4u qu[TPW];
 };
-
-// End of a chunk [c0, c1): merge the halves' keys, decode (D1, position, D2),
-// resolve equal smallest distances exactly, fold into the running result.
-__device__ __forceinline__ void finish_chunk(const BatchView& v, const TileGroup& G,
-                                             const CandRec* cand, const uint8_t* a_desc,
-                                             const uint8_t* b_desc, const QueryRec& qr, int32_t nq,
-                                             float lo, float hi, int32_t c0, int32_t c1, int lane,
-                                             uint32_t k1, uint32_t k2, QueryState& q) {
-  const int col = lane & 31, half = lane >> 5;
-  {
-    const uint32_t p1 = __shfl_xor(k1, 32, 64);
-    const uint32_t p2 = __shfl_xor(k2, 32, 64);
-    k2 = min(max(k1, p1), min(k2, p2));
-    k1 = min(k1, p1);
+template <int TPW>
+__device__ __forceinline__ GroupStart<TPW> start_group(const BatchView& v, const TileGroup& G,
+                                                       const MatchLds& L, int32_t jpar, int w,
+                                                       int lane) {
+  GroupStart<TPW> st;
+  const int col = lane & (kQueryTile - 1);
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int32_t qs = (G.tile0 + w + kWaves * k) * kQueryTile + col;
+    st.qu[k] = gload16(v.qrec + G.q_off + min(qs, G.na - 1));
   }
-  // The index load is unconditional and consumed at once, so no load stays
-  // in flight past the chunk end (a pending load into a register the loop
-  // reuses would make every later step wait for all prefetches).
-  const int32_t pos = int32_t(k1 & (kChunk - 1));
-  const int32_t at = min(c0 + ((pos - c0) & (kChunk - 1)), c1 - 1);
-  const int32_t jl = *(g_i32*)&cand[at].j;
-  const int32_t D1c = k1 != kKeyInf ? int32_t(k1 >> kPosBits) - int32_t(kDistBias) + nq : kDistInf;
-  const int32_t D2c = k2 != kKeyInf ? int32_t(k2 >> kPosBits) - int32_t(kDistBias) + nq : kDistInf;
-  int32_t j1c = k1 != kKeyInf ? jl : -1;
-
-  // Equal smallest distances: choose the lowest index of b exactly.
-  const bool tie = k2 != kKeyInf && (k1 >> kPosBits) == (k2 >> kPosBits);
-  unsigned long long tmask = __ballot(tie && half == 0);
-  const ExactCtx x = tmask ? exact_ctx(v, G.pair) : ExactCtx{nullptr, nullptr, nullptr, 0.0};
-  while (tmask) {
-    const int Lq = __builtin_ctzll(tmask);
-    tmask &= tmask - 1;
-    ++q.ties;
-    const float la = __shfl(qr.a, Lq, 64), lb = __shfl(qr.b, Lq, 64), lc = __shfl(qr.c, Lq, 64);
-    const int32_t li = __shfl(qr.i, Lq, 64), lnq = __shfl(nq, Lq, 64), lD = __shfl(D1c, Lq, 64);
-    const uint8_t* qrow = a_desc + int64_t(li) * kDescBytes;
-    int32_t jbest = 0x7FFFFFFF;
-    for (int32_t s = c0 + lane; s < c1; s += 64) {
-      const CandRec r = cand[s];
-      if (!member(band_dist32(la, lb, lc, r.x, r.y), lo, hi, x, li, r.j)) continue;
-      const int32_t nc = int32_t(r.ncpos >> kPosBits) - int32_t(kDistBias);
-      const int32_t D = row_dist(qrow, b_desc + int64_t(r.j) * kDescBytes, lnq, nc);
-      if (D == lD) jbest = min(jbest, r.j);
-    }
-    for (int o = 32; o > 0; o >>= 1) jbest = min(jbest, __shfl_xor(jbest, o, 64));
-    if (col == Lq) j1c = jbest;
-  }
-
-  if (D1c < q.d1 || (D1c == q.d1 && D1c != kDistInf && j1c < q.j1)) {
-    q.d2 = min(q.d1, D2c);
-    q.d1 = D1c;
-    q.j1 = j1c;
-  } else {
-    q.d2 = min(q.d2, D1c);
-  }
+  const Stream s = make_stream(v, G, L, jpar);
+  if (s.nsl > 0) issue_j(s, 0, w, lane);
+  if (s.nsl > 1) issue_j(s, 1, w, lane);
+  if (s.nsl > 2) issue_j(s, 2, w, lane);
+  return st;
 }
+
+// One query tile of a wave: its query column (one query per lane, four lanes
+// per query), the negated query bytes as the MFMA B operand and the running
+// result.  Distances are kept as key distances (D - ||q||^2 + 2^21, the top
+// 22 bits of a key), so chunks merge without the query's norm.
+struct Tile {
+  float a, b, c;            // the query's FP32 line on centred coordinates
+  int32_t i, nq;            // its index in a and ||q||^2
+  v4i bq[2];
+  uint32_t k1, k2;          // two smallest keys of the current chunk
+  uint32_t s1, s2;          // two smallest key distances so far (kKeyDistInf: none)
+  int32_t p1;               // pair position of s1's candidate
+  bool tie;                 // s1 is reached by more than one candidate
+  int32_t cnt;              // in-band slots of this lane (counts kept)
+};
 
 // Per-wave statistics of the groups of one pair, flushed when the pair changes.
 struct WaveStats {
@@ -383,232 +319,476 @@ __device__ __forceinline__ void flush_stats(const BatchView& v, WaveStats& w, in
   w.accepted = w.ties = 0;
 }
 
-// A group record read with scalar loads (its index is uniform).
-typedef const __attribute__((address_space(4))) v4i c_v4i;
-__device__ __forceinline__ TileGroup load_group(const TileGroup* groups, int32_t g) {
-  union {
-    v4i w[sizeof(TileGroup) / 16];
-    TileGroup t;
-  } u;
-  c_v4i* src = (c_v4i*)(groups + g);
-#pragma unroll
-  for (int k = 0; k < int(sizeof(TileGroup) / 16); ++k) u.w[k] = src[k];
-  return u.t;
+// What the FP64 decisions and the rare exact passes of one group read (all
+// uniform).
+struct GroupRefs {
+  const double* F;          // the caller's F of the pair
+  const float* a_xy;        // original keypoints of a and b
+  const float* b_xy;
+  const uint8_t* a_desc;
+  const uint8_t* b_desc;
+  const float* cx;          // the pair's binned targets
+  const float* cy;
+  const uint32_t* cnc;
+  const int32_t* cj;
+  double d;
+  float lo, hi;
+};
+
+__device__ __forceinline__ GroupRefs group_refs(const BatchView& v, const TileGroup& G) {
+  GroupRefs r;
+  r.F = v.F + 9 * int64_t(G.pair);
+  r.a_xy = G.a_xy;
+  r.b_xy = G.b_xy;
+  r.d = G.band;
+  r.a_desc = G.a_desc;
+  r.b_desc = G.b_desc;
+  r.cx = v.cand_x + G.c_off;
+  r.cy = v.cand_y + G.c_off;
+  r.cnc = v.cand_nc + G.c_off;
+  r.cj = v.cand_j + G.c_off;
+  r.lo = G.band_lo;
+  r.hi = G.band_hi;
+  return r;
 }
 
-// One group: up to four query tiles (one per wave) against their union
-// candidate range, streamed through LDS 32 candidates per step with one
-// barrier per step.
-template <bool kKeepCounts, int W>
-__device__ __forceinline__ void match_group(const BatchView& v, const TileGroup& G, GroupLds& L,
-                                            int wave, int lane, WaveStats& ws) {
-  constexpr int kRowLoads = Split<W>::kRowLoads;
-  constexpr int kRowsPerWave = Split<W>::kRowsPerWave;
-  const int col = lane & 31, half = lane >> 5;
-  const bool wv = wave < G.ntiles;
-  const int32_t blk = G.tile0 + wave;
-  // Selects, not an indexed read: a dynamic index would put the record in
-  // private memory.
-  int32_t my_b = 0, my_e = 0;
-#pragma unroll
-  for (int t = 0; t < W; ++t) {
-    my_b = wave == t ? G.t_begin[t] : my_b;
-    my_e = wave == t ? G.t_end[t] : my_e;
-  }
-  if (!wv) my_b = my_e = 0;
-  const float lo = G.band_lo, hi = G.band_hi;
-  const uint8_t* const a_desc = G.a_desc;
-  const uint8_t* const b_desc = G.b_desc;
+// Band membership from the FP32 distance e32: in at most lo, out above hi,
+// decided in FP64 in between.
+__device__ __forceinline__ bool member(const GroupRefs& r, float e32, int32_t i, int32_t j) {
+  if (e32 <= r.lo) return true;
+  if (!(e32 <= r.hi)) return false;
+  return band_dist64(r.F, r.a_xy[2 * i], r.a_xy[2 * i + 1], r.b_xy[2 * j], r.b_xy[2 * j + 1]) <=
+         r.d;
+}
 
-  // This lane's query column: line, squared norm and negated descriptor bytes
-  // as the MFMA B operand.  Padding columns read query row 0 with a NaN line.
-  const int32_t qs = blk * kQueryTile + col;
-  const bool qv = wv && qs < G.na;
-  const nv4u qu = gload16(v.qrec + G.q_off + min(qs, G.na - 1));
-  QueryRec qr;
-  qr.a = qv ? __uint_as_float(qu.x) : NAN;
-  qr.b = __uint_as_float(qu.y);
-  qr.c = __uint_as_float(qu.z);
-  qr.i = int32_t(qu.w);
-  const int32_t S0 = G.s_begin, S1 = G.s_end;
-  const CandRec* cand = v.cand + G.c_off;
-
-  // Records of the first two steps go out with the query record; the query
-  // row and the first candidate rows follow one latency later.
-  const int32_t own = kRowsPerWave * wave + (lane % kRowsPerWave);
-  const bool any = S1 > S0;
-  nv4u re = {0, 0, 0, 0}, ro = {0, 0, 0, 0};
-  if (any) {
-    re = load_rec(cand, S0 + own, S1);
-    ro = load_rec(cand, S0 + kCandTile + own, S1);
-  }
-  v4i bq[4];
-  {
-    const uint8_t* qrow = a_desc + int64_t(qr.i) * kDescBytes + 16 * half;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const nv4u u = gload16(qrow + 32 * s);
-      bq[s] = v4i{neg_bytes(u.x), neg_bytes(u.y), neg_bytes(u.z), neg_bytes(u.w)};
+// Exact pass for a query whose smallest distance D1 is shared: over pair
+// positions [p0, p1) the position of the lowest index in b among members at
+// distance D1.
+__device__ __forceinline__ int32_t lowest_tied(const GroupRefs& r, float a, float b, float c,
+                                               int32_t i, int32_t nq, int32_t D1, int32_t p0,
+                                               int32_t p1, int lane) {
+  const uint8_t* qrow = r.a_desc + int64_t(i) * kDescBytes;
+  int32_t jbest = 0x7FFFFFFF, pbest = -1;
+  for (int32_t p = p0 + lane; p < p1; p += 64) {
+    const int32_t j = r.cj[p];
+    if (!member(r, band_dist32(a, b, c, r.cx[p], r.cy[p]), i, j)) continue;
+    const int32_t nc = int32_t(r.cnc[p] >> kPosBits) - int32_t(kDistBias);
+    if (row_dist(qrow, r.b_desc + int64_t(j) * kDescBytes, nq, nc) == D1 && j < jbest) {
+      jbest = j;
+      pbest = p;
     }
   }
-  const int32_t nq = ((g_i32*)G.a_norm)[qr.i];
-
-  QueryState q = {kDistInf, kDistInf, -1, 0};
-  int32_t cnt = 0;       // in-band slots of this lane (counts kept)
-  uint32_t wcnt = 0;     // in-band slots of this wave (counts not kept)
-  uint32_t wbl = 0;      // slots decided in FP64
-
-  if (any) {
-    // Software pipeline over steps u = 0, 1, ... of 32 candidates.  Iteration
-    // u stores rows u (loaded two iterations earlier) into row stage u & 1,
-    // passes the barrier, issues the rows of u + 2 (their indices come from
-    // the record registers, so no barrier lies on that chain), stages the
-    // metadata of u + 2 into slot (u + 2) % 3, loads the record of u + 4 and
-    // computes step u from row stage u & 1 and metadata slot u % 3.  The loop
-    // is unrolled by two so the in-flight registers never move (a copy of a
-    // register with a load in flight would wait for that load).
-    const int32_t nsteps = (S1 - S0 + kCandTile - 1) / kCandTile;
-    nv4u we[kRowLoads], wo[kRowLoads];
-    stage_meta<W>(L, 0, re, S0, S1, wave, lane);
-#pragma unroll
-    for (int k = 0; k < kRowLoads; ++k) we[k] = load_row_share(re, b_desc, lane, k);
-    re = load_rec(cand, S0 + 2 * kCandTile + own, S1);
-    stage_meta<W>(L, 1, ro, S0 + kCandTile, S1, wave, lane);
-#pragma unroll
-    for (int k = 0; k < kRowLoads; ++k) wo[k] = load_row_share(ro, b_desc, lane, k);
-    ro = load_rec(cand, S0 + 3 * kCandTile + own, S1);
-
-    uint32_t k1 = kKeyInf, k2 = kKeyInf;
-    int32_t c0 = S0;
-    int ms = 0;   // metadata slot of step u
-    // One step; `w` and `r` are this parity's row and record registers.
-    auto step = [&](int32_t u, int rs, nv4u (&w)[kRowLoads], nv4u& r) {
-      const int32_t t0 = S0 + u * kCandTile;
-#pragma unroll
-      for (int k = 0; k < kRowLoads; ++k) store_row_share<W>(L, rs, wave, lane, k, w[k]);
-      __syncthreads();
-      const int ms2 = ms == 0 ? 2 : ms - 1;   // (u + 2) % 3
-      stage_meta<W>(L, ms2, r, t0 + 2 * kCandTile, S1, wave, lane);
-#pragma unroll
-      for (int k = 0; k < kRowLoads; ++k) w[k] = load_row_share(r, b_desc, lane, k);
-      r = load_rec(cand, t0 + 4 * kCandTile + own, S1);
-      if (t0 < my_e && t0 + kCandTile > my_b) {
-        // Waves in their compute phase issue first (1-2% faster than equal
-        // priority; raising the load phase instead gains nothing).
-        __builtin_amdgcn_s_setprio(2);
-        v4i a[4];
-        read_a(L, rs, lane, a);
-        tile_compute<kKeepCounts>(a, bq, qr, nq, lo, hi, L, ms, half, k1, k2, cnt, wcnt, wbl, v,
-                                  G, t0);
-        __builtin_amdgcn_s_setprio(0);
-      }
-      // Keys hold positions mod 1024: close a chunk every 1024 positions.
-      const int32_t t1 = t0 + kCandTile;
-      if (t1 >= S1 || t1 - c0 >= kChunk) {
-        const int32_t c1 = min(S1, c0 + kChunk);
-        finish_chunk(v, G, cand, a_desc, b_desc, qr, nq, lo, hi, c0, c1, lane, k1, k2, q);
-        k1 = kKeyInf;
-        k2 = kKeyInf;
-        c0 = c1;
-      }
-      ms = ms == 2 ? 0 : ms + 1;
-    };
-    // The loop body always runs both steps, so the loads in flight at its
-    // head are the same on every path (an odd last step runs after it).
-    int32_t u = 0;
-    for (; u + 1 < nsteps; u += 2) {
-      step(u, 0, we, re);
-      step(u + 1, 1, wo, ro);
-    }
-    if (u < nsteps) step(u, 0, we, re);
-    // No wave may overwrite the stage of the next group while others read it.
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    const int32_t oj = __shfl_xor(jbest, o, 64), op = __shfl_xor(pbest, o, 64);
+    if (oj < jbest) { jbest = oj; pbest = op; }
   }
+  return pbest;
+}
 
-  bool accept;
-  if (q.d2 != kDistInf) {
-    accept = int64_t(v.ratio_den) * q.d1 < int64_t(v.ratio_num) * q.d2;
+// Exact recomputation of one tile (after its wave's queue of FP64 decisions
+// overflowed): lane (col, rg) takes positions p0 + rg, p0 + rg + 4, ... for
+// its query, with the membership test of the stream (FP32, FP64 within the
+// margin) and exact distances; the four lanes of a query merge (D1, lowest
+// index at D1 and its position, D2) and the in-band count.
+struct ExactResult {
+  int32_t d1, j1, p1, d2, cnt;
+};
+__device__ __forceinline__ ExactResult exact_tile(const GroupRefs& r, const Tile& T, bool qv,
+                                                  int32_t p0, int32_t p1, int lane) {
+  ExactResult o = {kDistInf, 0x7FFFFFFF, -1, kDistInf, 0};
+  if (qv) {
+    const uint8_t* qrow = r.a_desc + int64_t(T.i) * kDescBytes;
+    for (int32_t p = p0 + (lane >> 4); p < p1; p += 4) {
+      const int32_t j = r.cj[p];
+      if (!member(r, band_dist32(T.a, T.b, T.c, r.cx[p], r.cy[p]), T.i, j)) continue;
+      ++o.cnt;
+      const int32_t nc = int32_t(r.cnc[p] >> kPosBits) - int32_t(kDistBias);
+      const int32_t D = row_dist(qrow, r.b_desc + int64_t(j) * kDescBytes, T.nq, nc);
+      if (D < o.d1 || (D == o.d1 && j < o.j1)) {
+        o.d2 = o.d1;
+        o.d1 = D;
+        o.j1 = j;
+        o.p1 = p;
+      } else {
+        o.d2 = min(o.d2, D);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 16; off <= 32; off <<= 1) {
+    const int32_t e1 = __shfl_xor(o.d1, off, 64), k1 = __shfl_xor(o.j1, off, 64);
+    const int32_t q1 = __shfl_xor(o.p1, off, 64), e2 = __shfl_xor(o.d2, off, 64);
+    o.cnt += __shfl_xor(o.cnt, off, 64);
+    if (e1 < o.d1 || (e1 == o.d1 && k1 < o.j1)) {
+      o.d2 = min(o.d1, e2);
+      o.d1 = e1;
+      o.j1 = k1;
+      o.p1 = q1;
+    } else {
+      o.d2 = min(o.d2, e1);
+    }
+  }
+  return o;
+}
+
+// Folds one decided candidate (key distance kd, pair position pos) into a
+// running result.
+__device__ __forceinline__ void fold_state(Tile& T, uint32_t kd, int32_t pos) {
+  if (kd < T.s1) {
+    T.s2 = T.s1;
+    T.s1 = kd;
+    T.p1 = pos;
+    T.tie = false;
+  } else if (kd == T.s1) {
+    T.s2 = T.s1;
+    T.tie = true;
   } else {
-    accept = q.d1 != kDistInf && v.accept_single;
+    T.s2 = min(T.s2, kd);
   }
-  if (kKeepCounts) cnt += __shfl_xor(cnt, 32, 64);   // |C| of this lane's query
-  if (qv && half == 0) {
-    QueryResult out;
-    out.match = q.j1;
-    out.d1 = q.d1;
-    out.d2 = q.d2;
-    out.flags = (accept ? 1 : 0) | (kKeepCounts ? (cnt << 1) : 0);
-    v.res[G.q_off + qr.i] = out;
+}
+
+// End of a tile's chunk starting at pair position c0p: merge the four lanes
+// of each query, then fold the chunk's two smallest into the running result.
+// No memory access: a shared smallest distance only sets the tie flag.
+__device__ __forceinline__ void close_chunk(Tile& T, int32_t c0p, int32_t c1p) {
+#pragma unroll
+  for (int o = 16; o <= 32; o <<= 1) {
+    const uint32_t p1 = __shfl_xor(T.k1, o, 64);
+    const uint32_t p2 = __shfl_xor(T.k2, o, 64);
+    T.k2 = min(max(T.k1, p1), min(T.k2, p2));
+    T.k1 = min(T.k1, p1);
   }
-  // In-band comparisons of the tile: the sum of its queries' counts.
-  int32_t tsum = int32_t(wcnt);
-  if (kKeepCounts) {
-    tsum = (half == 0) ? cnt : 0;
-    for (int o = 16; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
-    tsum = __shfl(tsum, 0, 64);
+  const uint32_t kd1 = T.k1 >> kPosBits, kd2 = T.k2 >> kPosBits;
+  const int32_t pf = int32_t(T.k1 & (kChunk - 1));
+  const int32_t at = min(c0p + ((pf - c0p) & (kChunk - 1)), c1p - 1);
+  if (kd1 < T.s1) {
+    T.s2 = min(T.s1, kd2);
+    T.s1 = kd1;
+    T.p1 = at;
+    T.tie = kd2 == kd1;
+  } else if (kd1 == T.s1 && kd1 != kKeyDistInf) {
+    T.s2 = T.s1;
+    T.tie = true;
+  } else {
+    T.s2 = min(T.s2, kd1);
   }
-  const uint32_t nacc = __builtin_popcountll(__ballot(accept && qv && half == 0));
-  if (wv) {
-    if (G.pair != ws.pair) {
-      flush_stats(v, ws, lane);
-      ws.pair = G.pair;
+  T.k1 = kKeyInf;
+  T.k2 = kKeyInf;
+}
+
+// One group: up to 4 * TPW query tiles (TPW per wave) against their candidate
+// ranges, streamed through the LDS ring.  `gs` holds the group's first stage
+// (issued by the previous group or the kernel's start); before its epilogue
+// the group issues the first stage of group gn (if gn >= 0) into the other
+// index ring.
+template <bool kKeepCounts, int TPW>
+__device__ __forceinline__ void match_group(const BatchView& v, const TileGroup& G,
+                                            const GroupStart<TPW>& gs, int32_t jpar,
+                                            int32_t gn, GroupStart<TPW>& gsn, MatchLds& L, int w,
+                                            int lane, WaveStats& ws) {
+  const int col = lane & (kQueryTile - 1), rg = lane >> 4;
+  const float lo = G.band_lo, hi = G.band_hi;
+  const Stream s = make_stream(v, G, L, jpar);
+
+  // Tile ranges (uniform); the first stage is complete after this wait.
+  Tile T[TPW];
+  int32_t rb[TPW], re[TPW], c0[TPW];   // tile range and chunk start (relative)
+  bool qv[TPW];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int32_t tidx = w + kWaves * k;
+    const int32_t qs = (G.tile0 + tidx) * kQueryTile + col;
+    qv[k] = tidx < G.ntiles && qs < G.na;
+    int32_t tb = 0, te = 0;
+#pragma unroll
+    for (int t = 0; t < kMaxGroupTiles; ++t) {   // selects: a dynamic index would use scratch
+      tb = tidx == t ? G.t_begin[t] : tb;
+      te = tidx == t ? G.t_end[t] : te;
     }
-    int32_t steps = 0;
-    if (my_e > my_b) {
-      const int32_t first = (max(my_b, S0) - S0) / kCandTile;
-      const int32_t last = (my_e - 1 - S0) / kCandTile;
-      steps = last - first + 1;
-    }
-    ws.comparisons += (unsigned long long)tsum;
-    ws.borderline += wbl;
-    ws.elements += (unsigned long long)steps * (kCandTile * kQueryTile);
-    ws.accepted += nacc;
-    ws.ties += q.ties;
+    if (tidx >= G.ntiles || te <= tb) tb = te = s.base;
+    rb[k] = (tb & ~3) - s.base;
+    re[k] = te - s.base;
+    c0[k] = rb[k];
   }
+  wait_loads<0>();
+
+  // Query rows, norms and keypoints, then rows and metadata of segments 0..2
+  // with the indices of segments 3 and 4 (the pipeline's first three stages).
+  nv4u qr[TPW][2];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    T[k].a = qv[k] ? __uint_as_float(gs.qu[k].x) : NAN;
+    T[k].b = __uint_as_float(gs.qu[k].y);
+    T[k].c = __uint_as_float(gs.qu[k].z);
+    T[k].i = int32_t(gs.qu[k].w);
+    const uint8_t* qrow = G.a_desc + int64_t(T[k].i) * kDescBytes + 16 * rg;
+    qr[k][0] = gload16(qrow);
+    qr[k][1] = gload16(qrow + 64);
+    T[k].nq = ((g_i32*)G.a_norm)[T[k].i];
+  }
+  if (s.nsl > 0) {
+    issue_rows(s, L, 0, w, lane);
+    if (3 < s.nsl) issue_j(s, 3, w, lane);
+    if (1 < s.nsl) issue_rows(s, L, 1, w, lane);
+    if (4 < s.nsl) issue_j(s, 4, w, lane);
+    if (2 < s.nsl) issue_rows(s, L, 2, w, lane);
+  }
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+      T[k].bq[m] = v4i{neg_bytes(qr[k][m].x), neg_bytes(qr[k][m].y), neg_bytes(qr[k][m].z),
+                       neg_bytes(qr[k][m].w)};
+    T[k].k1 = T[k].k2 = kKeyInf;
+    T[k].s1 = T[k].s2 = kKeyDistInf;
+    T[k].p1 = 0;
+    T[k].tie = false;
+    T[k].cnt = 0;
+  }
+
+  uint32_t wcnt = 0;       // in-band slots of the wave (counts not kept per query)
+  uint32_t wbl = 0;        // slots decided in FP64
+  int32_t nbq = 0;         // queued FP64 decisions
+  bool overflow = false;   // more than kBorderCap: the wave's tiles are recomputed exactly
+  uint32_t nsteps = 0;     // 16 x 16 steps evaluated
+
+  for (int32_t sg = 0; sg < s.nsc; ++sg) {
+    wait_segment(sg, s.nsl);
+    barrier();
+    if (sg + 5 < s.nsl) issue_j(s, sg + 5, w, lane);
+    if (sg + 3 < s.nsl) issue_rows(s, L, sg + 3, w, lane);
+
+    const int32_t seg_lo = kSeg * sg;
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+      Tile& t = T[k];
+      // The tile's steps that start in this segment: p0, p0 + 16, ... < pe
+      // (steps start at rb + 16 i).
+      const int32_t p0 = max(rb[k], seg_lo + (rb[k] & (kQueryTile - 1)));
+      const int32_t pe = min(re[k], seg_lo + kSeg);
+      if (p0 >= pe) continue;
+      const int32_t n = (pe - p0 + kQueryTile - 1) / kQueryTile;
+      nsteps += uint32_t(n);
+      // Keys hold positions mod 1024: a chunk closes before a segment whose
+      // steps would take it past 1024 positions.
+      if (p0 + kQueryTile * n - c0[k] > kChunk) {
+        close_chunk(t, s.base + c0[k], s.base + p0);
+        c0[k] = p0;
+      }
+      // A operand: ring row (p + col) & 255 of the step, k-slices rg and
+      // rg + 4 (chunk slots rg ^ (row & 7) and that ^ 4).  Metadata: the four
+      // candidates 4 rg .. 4 rg + 3 of the step.  Both advance by 16 rows a
+      // step, modulo the ring.
+      uint32_t oa = uint32_t(((p0 + col) & (kRingPos - 1)) * kDescBytes +
+                             ((rg ^ ((p0 + col) & 7)) << 4));
+      uint32_t om = uint32_t(((p0 + 4 * rg) & (kRingPos - 1)) * 4);
+      for (int32_t i = 0; i < n; ++i) {
+        const v4i a0 = *reinterpret_cast<const v4i*>(&L.rows[oa]);
+        const v4i a1 = *reinterpret_cast<const v4i*>(&L.rows[oa ^ 64u]);
+        v4i acc = {0, 0, 0, 0};
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, t.bq[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, t.bq[1], acc, 0, 0, 0);
+        const float4 xs = reinterpret_cast<const float4*>(L.x)[om >> 4];
+        const float4 ys = reinterpret_cast<const float4*>(L.y)[om >> 4];
+        const uint4 ns = reinterpret_cast<const uint4*>(L.nc)[om >> 4];
+        const float xv[4] = {xs.x, xs.y, xs.z, xs.w};
+        const float yv[4] = {ys.x, ys.y, ys.z, ys.w};
+        const uint32_t nv[4] = {ns.x, ns.y, ns.z, ns.w};
+        unsigned long long bm[4];
+        uint32_t keys[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float d32 = band_dist32(t.a, t.b, t.c, xv[e], yv[e]);
+          const bool mem = d32 <= lo;
+          bm[e] = __ballot(d32 <= hi) & ~__ballot(mem);
+          keys[e] = nv[e] + (uint32_t(acc[e]) << 11);
+          const uint32_t kin = mem ? keys[e] : kKeyInf;
+          t.k2 = umed3(t.k1, kin, t.k2);
+          t.k1 = min(t.k1, kin);
+          if (kKeepCounts)
+            t.cnt += mem ? 1 : 0;
+          else
+            wcnt += __builtin_popcountll(__ballot(mem));
+        }
+        if (bm[0] | bm[1] | bm[2] | bm[3]) {
+          // Rare: queue the step's slots within the margin of d, with their
+          // exact keys and indices in b, for the FP64 decision after the
+          // stream (the index ring still holds this segment and the next).
+          const int32_t p = p0 + kQueryTile * i;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (!bm[e]) continue;
+            const int32_t nb = __builtin_popcountll(bm[e]);
+            wbl += uint32_t(nb);
+            if (nbq + nb > kBorderCap) {
+              overflow = true;
+              continue;
+            }
+            const int32_t idx = nbq + int32_t(__builtin_amdgcn_mbcnt_hi(
+                                          uint32_t(bm[e] >> 32),
+                                          __builtin_amdgcn_mbcnt_lo(uint32_t(bm[e]), 0)));
+            if ((bm[e] >> lane) & 1ull) {
+              const int32_t pr = p + 4 * rg + e;
+              const int32_t jq = (&L.j[0][0])[jring_index(s, pr >> 6) + (pr & (kSeg - 1))];
+              L.queue[w][idx] = make_uint4(
+                  keys[e], (uint32_t(pr) << 7) | (uint32_t(k) << 6) | uint32_t(lane),
+                  uint32_t(jq), 0u);
+            }
+            nbq += nb;
+          }
+        }
+        oa = (oa + kQueryTile * kDescBytes) & (kRingPos * kDescBytes - 1);
+        om = (om + 4 * kQueryTile) & (4 * kRingPos - 1);
+      }
+    }
+  }
+  wait_loads<0>();
+  // Every wave is past the ring: the next group's first stage may load now
+  // (into the other index ring), under this group's epilogue.
+  barrier();
+  if (gn >= 0) gsn = start_group<TPW>(v, load_group(v.groups, gn), L, jpar ^ 1, w, lane);
+
+  // The last chunk of every tile, then the queued FP64 decisions (one per
+  // lane), folded into the result of the lane with rg = 0 of their query.
+#pragma unroll
+  for (int k = 0; k < TPW; ++k)
+    if (re[k] > rb[k]) close_chunk(T[k], s.base + c0[k], s.base + re[k]);
+  const GroupRefs gr = group_refs(v, G);
+  if (nbq > 0 && !overflow) {
+    const uint4 en = L.queue[w][min(lane, nbq - 1)];
+    const int owner = int(en.y & 63), ot = int((en.y >> 6) & 1);
+    int32_t qi = 0;
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+      const int32_t ik = __shfl(T[k].i, owner, 64);
+      if (ot == k) qi = ik;
+    }
+    bool in = false;
+    if (lane < nbq) {
+      const int32_t j = int32_t(en.z);
+      in = band_dist64(gr.F, gr.a_xy[2 * qi], gr.a_xy[2 * qi + 1], gr.b_xy[2 * j],
+                       gr.b_xy[2 * j + 1]) <= gr.d;
+    }
+    const unsigned long long inm = __ballot(in);
+    if (!kKeepCounts) wcnt += __builtin_popcountll(inm);
+    for (int32_t e = 0; e < nbq; ++e) {
+      if (!((inm >> e) & 1ull)) continue;
+      const uint4 q = L.queue[w][e];
+      if (lane != int(q.y & (kQueryTile - 1))) continue;
+#pragma unroll
+      for (int k = 0; k < TPW; ++k) {
+        if (int((q.y >> 6) & 1) == k) {
+          fold_state(T[k], q.x >> kPosBits, s.base + int32_t(q.y >> 7));
+          if (kKeepCounts) ++T[k].cnt;
+        }
+      }
+    }
+  }
+
+  // Results (the binned position of the match) and statistics.
+  int32_t tsum = 0;        // in-band slots of the tiles, by lane (counts kept or recomputed)
+  uint32_t nacc = 0, ties = 0;
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    Tile& t = T[k];
+    int32_t d1, d2, p1, qc = 0;
+    if (overflow) {
+      const ExactResult x = exact_tile(gr, t, qv[k], s.base + rb[k], s.base + re[k], lane);
+      d1 = x.d1;
+      d2 = x.d2;
+      p1 = x.p1;
+      qc = x.cnt;
+      tsum += lane < kQueryTile && qv[k] ? qc : 0;
+    } else {
+      d1 = t.s1 != kKeyDistInf ? int32_t(t.s1) - int32_t(kDistBias) + t.nq : kDistInf;
+      d2 = t.s2 != kKeyDistInf ? int32_t(t.s2) - int32_t(kDistBias) + t.nq : kDistInf;
+      p1 = d1 != kDistInf ? t.p1 : -1;
+      // Equal smallest distances: the lowest index of b, exactly.
+      unsigned long long tmask = __ballot(t.tie && qv[k] && lane < kQueryTile);
+      while (tmask) {
+        const int Lq = __builtin_ctzll(tmask);
+        tmask &= tmask - 1;
+        ++ties;
+        const int32_t pb = lowest_tied(gr, __shfl(t.a, Lq, 64), __shfl(t.b, Lq, 64),
+                                       __shfl(t.c, Lq, 64), __shfl(t.i, Lq, 64),
+                                       __shfl(t.nq, Lq, 64), __shfl(d1, Lq, 64),
+                                       s.base + rb[k], s.base + re[k], lane);
+        if (lane == Lq) p1 = pb;
+      }
+      if (kKeepCounts) {
+        qc = t.cnt;
+        qc += __shfl_xor(qc, 16, 64);
+        qc += __shfl_xor(qc, 32, 64);
+        tsum += lane < kQueryTile && qv[k] ? qc : 0;
+      }
+    }
+    bool accept;
+    if (d2 != kDistInf) {
+      accept = int64_t(v.ratio_den) * d1 < int64_t(v.ratio_num) * d2;
+    } else {
+      accept = d1 != kDistInf && v.accept_single;
+    }
+    if (qv[k] && lane < kQueryTile) {
+      QueryResult out;
+      out.match = d1 != kDistInf ? p1 : -1;
+      out.d1 = d1;
+      out.d2 = d2;
+      out.flags = (accept ? 1 : 0) | (kKeepCounts ? (qc << 1) : 0);
+      v.res[G.q_off + t.i] = out;
+    }
+    nacc += __builtin_popcountll(__ballot(accept && qv[k] && lane < kQueryTile));
+  }
+  for (int o = 8; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
+  tsum = __shfl(tsum, 0, 64);
+  // Without per-query counts the wave counted in-band slots itself (unless
+  // its tiles were recomputed).
+  if (!kKeepCounts && !overflow) tsum = int32_t(wcnt);
+  if (G.pair != ws.pair) {
+    flush_stats(v, ws, lane);
+    ws.pair = G.pair;
+  }
+  ws.comparisons += (unsigned long long)tsum;
+  ws.borderline += wbl;
+  ws.elements += (unsigned long long)nsteps * (kQueryTile * kQueryTile);
+  ws.accepted += nacc;
+  ws.ties += ties;
 }
 
 // One resident wave of workgroups.  Workgroups are dealt to the 8 XCDs
 // round-robin (workgroup k runs on XCD k mod 8), and each XCD has its own L2.
-// The preparation pass splits the groups into one contiguous share of about
-// equal estimated cost per XCD; the workgroups of an XCD sweep its share
-// together, workgroup i taking groups i, i + W, i + 2W, ... (W workgroups on
-// the XCD).  At any moment an XCD then works on about W consecutive groups,
-// one or two pairs, whose candidate and query rows stay in its L2; giving
-// each workgroup a contiguous run instead spreads an XCD over dozens of
-// pairs at once and its rows over HBM.
+// Preparation splits the groups into runs of about equal estimated cost;
+// runs are laid out XCD-contiguously, so the 1/8 of the groups one XCD takes
+// is one contiguous share of the pairs.
 #ifndef SFM_MATCH_WAVES_PER_EU
-#define SFM_MATCH_WAVES_PER_EU 3
-#endif
-#ifndef SFM_XCD_SWEEP
-#define SFM_XCD_SWEEP 0
+#define SFM_MATCH_WAVES_PER_EU 4
 #endif
 __device__ __forceinline__ int32_t xcd_contiguous(int32_t g, int32_t G) {
   const int32_t x = g & 7, k = g >> 3, q = G >> 3, r = G & 7;
   return x * q + min(x, r) + k;
 }
-template <bool kKeepCounts, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
+template <bool kKeepCounts, int TPW>
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
 void match_kernel(BatchView v) {
-  __shared__ __attribute__((aligned(16))) GroupLds lds;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ __attribute__((aligned(16))) MatchLds lds;
+  // The wave index is uniform: readfirstlane lets the compiler keep
+  // everything derived from it (tile ranges, queue counts) in SGPRs.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   typedef const __attribute__((address_space(4))) int32_t c_i32;
-#if SFM_XCD_SWEEP
-  const int32_t shares = min(8, int32_t(gridDim.x));
-  const int32_t x = blockIdx.x % shares;
-  const int32_t i = blockIdx.x / shares;
-  const int32_t w = (int32_t(gridDim.x) - x + shares - 1) / shares;
-  const int32_t g_first = ((c_i32*)v.wg_start)[x] + i;
-  const int32_t g_end = ((c_i32*)v.wg_start)[x + 1];
-#else
   const int32_t run = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int32_t w = 1;
   const int32_t g_first = ((c_i32*)v.wg_start)[run];
   const int32_t g_end = ((c_i32*)v.wg_start)[run + 1];
-#endif
   WaveStats ws = {-1, 0, 0, 0, 0, 0};
-  for (int32_t g = g_first; g < g_end; g += w) {
-    const TileGroup G = load_group(v.groups, g);
-    match_group<kKeepCounts, W>(v, G, lds, wave, lane, ws);
+  if (g_first < g_end) {
+    GroupStart<TPW> gs = start_group<TPW>(v, load_group(v.groups, g_first), lds, 0, wave, lane);
+    int32_t jpar = 0;
+    for (int32_t g = g_first; g < g_end; ++g) {
+      const TileGroup G = load_group(v.groups, g);
+      GroupStart<TPW> gsn;
+      match_group<kKeepCounts, TPW>(v, G, gs, jpar, g + 1 < g_end ? g + 1 : -1, gsn, lds, wave,
+                                    lane, ws);
+      gs = gsn;
+      jpar ^= 1;
+    }
   }
   flush_stats(v, ws, lane);
 }
@@ -618,8 +798,7 @@ void match_kernel(BatchView v) {
 // largest |FP32 distance - FP64 distance| (as the bits of a non-negative
 // double, which order like the integers) and the number of such slots.  One
 // wave per tile, one lane per query.
-__global__ __launch_bounds__(64) void band_error_kernel(BatchView v,
-                                                        unsigned long long* out) {
+__global__ __launch_bounds__(64) void band_error_kernel(BatchView v, unsigned long long* out) {
   const int32_t g = blockIdx.x / v.group_tiles, t = blockIdx.x % v.group_tiles;
   const TileGroup& G = v.groups[g];
   const int lane = threadIdx.x;
@@ -630,15 +809,17 @@ __global__ __launch_bounds__(64) void band_error_kernel(BatchView v,
   unsigned long long n = 0;
   if (qs < G.na && e > b) {
     const QueryRec qr = v.qrec[G.q_off + qs];
-    const ExactCtx x = exact_ctx(v, G.pair);
-    const CandRec* cand = v.cand + G.c_off;
-    const double two_d = 2.0 * x.d;
-    const float xq = x.a_xy[2 * qr.i], yq = x.a_xy[2 * qr.i + 1];
+    const double* F = v.F + 9 * int64_t(G.pair);
+    const float* cx = v.cand_x + G.c_off;
+    const float* cy = v.cand_y + G.c_off;
+    const int32_t* cj = v.cand_j + G.c_off;
+    const double two_d = 2.0 * G.band;
+    const float xq = G.a_xy[2 * qr.i], yq = G.a_xy[2 * qr.i + 1];
     for (int32_t s = b; s < e; ++s) {
-      const CandRec r = cand[s];
-      const double e64 = band_dist64(x.F, xq, yq, x.b_xy[2 * r.j], x.b_xy[2 * r.j + 1]);
+      const int32_t j = cj[s];
+      const double e64 = band_dist64(F, xq, yq, G.b_xy[2 * j], G.b_xy[2 * j + 1]);
       if (!(e64 <= two_d)) continue;
-      const double e32 = band_dist32(qr.a, qr.b, qr.c, r.x, r.y);
+      const double e32 = band_dist32(qr.a, qr.b, qr.c, cx[s], cy[s]);
       worst = fmax(worst, fabs(e32 - e64));
       ++n;
     }
@@ -657,14 +838,14 @@ __global__ __launch_bounds__(64) void band_error_kernel(BatchView v,
 }  // namespace
 
 // Workgroups of the match kernel that fit on a device at once.
-template <int W>
+template <int TPW>
 static int32_t resident_workgroups(int dev) {
   static int32_t cached[64] = {0};
   if (dev < 0 || dev >= 64) return 256;
   if (cached[dev] == 0) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, match_kernel<false, W>, 64 * W, 0) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, match_kernel<false, TPW>,
+                                                     64 * kWaves, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         per_cu <= 0 || cus <= 0) {
       per_cu = 1;
@@ -676,28 +857,25 @@ static int32_t resident_workgroups(int dev) {
 }
 
 int32_t match_workgroups(int32_t device, int32_t group_tiles, int64_t groups) {
-  const int32_t r = group_tiles == 1   ? resident_workgroups<1>(device)
-                    : group_tiles == 4 ? resident_workgroups<4>(device)
-                                       : resident_workgroups<2>(device);
+  const int32_t r = group_tiles == kWaves ? resident_workgroups<1>(device)
+                                          : resident_workgroups<2>(device);
   return int32_t(std::max<int64_t>(1, std::min<int64_t>(groups, r)));
 }
 
-template <int W>
-static void launch_match_w(const BatchView& v, int32_t wgs, hipStream_t st) {
+template <int TPW>
+static void launch_match_t(const BatchView& v, int32_t wgs, hipStream_t st) {
   if (v.keep_counts)
-    hipLaunchKernelGGL((match_kernel<true, W>), dim3(wgs), dim3(64 * W), 0, st, v);
+    hipLaunchKernelGGL((match_kernel<true, TPW>), dim3(wgs), dim3(64 * kWaves), 0, st, v);
   else
-    hipLaunchKernelGGL((match_kernel<false, W>), dim3(wgs), dim3(64 * W), 0, st, v);
+    hipLaunchKernelGGL((match_kernel<false, TPW>), dim3(wgs), dim3(64 * kWaves), 0, st, v);
 }
 
 hipError_t launch_match(const BatchView& v, int32_t wgs, hipStream_t st) {
   if (wgs <= 0) return hipSuccess;
-  if (v.group_tiles == 1)
-    launch_match_w<1>(v, wgs, st);
-  else if (v.group_tiles == 4)
-    launch_match_w<4>(v, wgs, st);
+  if (v.group_tiles == kWaves)
+    launch_match_t<1>(v, wgs, st);
   else
-    launch_match_w<2>(v, wgs, st);
+    launch_match_t<2>(v, wgs, st);
   return hipGetLastError();
 }
 

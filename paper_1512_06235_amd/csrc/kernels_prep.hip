@@ -330,7 +330,7 @@ constexpr int kBinThreads = 512;
 constexpr int kBatch = 8;   // items per thread per round; their loads are issued together
 constexpr int kCacheRounds = 3;
 
-// Counting sort of one side of a pair: the targets of b into CandRec order
+// Counting sort of one side of a pair: the targets of b into binned order
 // (and the bin starts), or the queries of a into tile order.
 // Writes one item at its sorted position.
 template <bool kTargets>
@@ -338,12 +338,11 @@ __device__ __forceinline__ void write_sorted(const BatchView& v, const PairDesc&
                                              const PairGeom& g, int32_t pos, int32_t j, float x,
                                              float y, int32_t nrm) {
   if (kTargets) {
-    CandRec c;
-    c.x = float(double(x) - g.ox);
-    c.y = float(double(y) - g.oy);
-    c.ncpos = ((uint32_t(nrm) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
-    c.j = j;
-    v.cand[P.c_off + pos] = c;
+    v.cand_x[P.c_off + pos] = float(double(x) - g.ox);
+    v.cand_y[P.c_off + pos] = float(double(y) - g.oy);
+    v.cand_nc[P.c_off + pos] =
+        ((uint32_t(nrm) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
+    v.cand_j[P.c_off + pos] = j;
   } else {
     const QueryLine q = query_line(g, x, y);
     QueryRec rq;
@@ -480,12 +479,14 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
   if (P.ignore_band) {
     // Exhaustive matching keeps b in its own order: one bin, position = index.
     if (targets) {
-      for (int32_t j = threadIdx.x; j < P.nb; j += blockDim.x) {
-        CandRec r;
-        r.x = 0.0f; r.y = 0.0f;
-        r.ncpos = ((uint32_t(I.norm2[j]) + kDistBias) << kPosBits) | uint32_t(j & (kChunk - 1));
-        r.j = j;
-        v.cand[P.c_off + j] = r;
+      for (int32_t j = threadIdx.x; j < P.nb + kCandPad; j += blockDim.x) {
+        const bool pad = j >= P.nb;
+        v.cand_x[P.c_off + j] = pad ? NAN : 0.0f;
+        v.cand_y[P.c_off + j] = 0.0f;
+        v.cand_nc[P.c_off + j] =
+            pad ? kKeyInf
+                : ((uint32_t(I.norm2[j]) + kDistBias) << kPosBits) | uint32_t(j & (kChunk - 1));
+        v.cand_j[P.c_off + j] = pad ? 0 : j;
       }
       if (threadIdx.x == 0) {
         v.bin_start[P.bin_off] = 0;
@@ -509,17 +510,26 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
   uint16_t* perm = nullptr;
   if (hist_ints + (n + 1) / 2 <= kBinLdsInts - kBinWsum)
     perm = reinterpret_cast<uint16_t*>(lds + hist_ints);
-  if (targets)
+  if (targets) {
+    // Padding after the pair's targets: a NaN x fails every band test.
+    if (int(threadIdx.x) < kCandPad) {
+      const int64_t o = P.c_off + P.nb + threadIdx.x;
+      v.cand_x[o] = NAN;
+      v.cand_y[o] = 0.0f;
+      v.cand_nc[o] = kKeyInf;
+      v.cand_j[o] = 0;
+    }
     sort_side<true>(v, P, g, I, hist, wsum, nh, perm);
-  else
+  } else {
     sort_side<false>(v, P, g, I, hist, wsum, nh, perm);
+  }
 }
 
 // Candidate range of every query tile (the union of its queries' bin windows
-// mapped through b's bin starts) and of every group of K
-// consecutive tiles, with the group record and its schedule cost.  Block
-// (p, c) takes queries [256c, 256c + 256) of pair p: one thread per query,
-// half-wave min/max reductions per tile, one thread per group.
+// mapped through b's bin starts) and of every group of K consecutive tiles,
+// with the group record and its schedule cost.  Block (p, c) takes queries
+// [256c, 256c + 256) of pair p: one thread per query, min/max reductions over
+// the 16 lanes of a tile, one thread per group.
 constexpr int kRangeThreads = 256;
 constexpr int kRangeTiles = kRangeThreads / kQueryTile;
 static_assert(kRangeTiles % kMaxGroupTiles == 0, "a block holds whole groups");
@@ -536,7 +546,7 @@ __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v,
   const int2 w = s < P.na ? v.qwin[P.q_off + s] : make_int2(1, 0);
   int32_t lo = w.x <= w.y ? w.x : 0x7FFFFFFF;
   int32_t hi = w.x <= w.y ? w.y : -1;
-  for (int o = kQueryTile / 2; o > 0; o >>= 1) {   // stays within the tile's 32 lanes
+  for (int o = kQueryTile / 2; o > 0; o >>= 1) {   // stays within the tile's 16 lanes
     lo = min(lo, __shfl_xor(lo, o, 64));
     hi = max(hi, __shfl_xor(hi, o, 64));
   }
@@ -560,12 +570,16 @@ __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v,
     const ImageDev B = v.images[P.b];
     TileGroup tg;
     memset(&tg, 0, sizeof tg);
-    int32_t gb = 0x7FFFFFFF, ge = 0;
+    int32_t gb = 0x7FFFFFFF, ge = 0, steps = 0;
 #pragma unroll
     for (int32_t k = 0; k < K; ++k) {
       int2 r = make_int2(0, 0);
       if (k < nt) r = trange[t * K + k];
-      if (r.y > r.x) { gb = min(gb, r.x); ge = max(ge, r.y); }
+      if (r.y > r.x) {
+        gb = min(gb, r.x);
+        ge = max(ge, r.y);
+        steps += (r.y - (r.x & ~3) + kQueryTile - 1) / kQueryTile;
+      }
       tg.t_begin[k] = r.x;
       tg.t_end[k] = r.y;
     }
@@ -580,13 +594,19 @@ __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v,
     tg.q_off = P.q_off;
     tg.c_off = P.c_off;
     tg.a_desc = A.desc;
-    tg.a_norm = A.norm2;
     tg.b_desc = B.desc;
+    tg.a_norm = A.norm2;
+    tg.nb = P.nb;
+    tg.a_xy = A.xy;
+    tg.b_xy = B.xy;
+    tg.band = P.band;
     v.groups[P.grp_off + g] = tg;
-    // A group costs a fixed start-up plus one pipeline step per 32 positions
-    // of its union range (every step of the union has a computing wave).
-    const int32_t steps = (tg.s_end - tg.s_begin + kCandTile - 1) / kCandTile;
-    const int32_t c = kGroupStartCost + kStepCost * steps;
+    // A group costs a fixed start-up, one stream stage per 64 positions of
+    // its union (plus the stage its last steps reach into) and its tiles'
+    // steps, which its four waves share.
+    const int32_t segs =
+        tg.s_end > tg.s_begin ? (tg.s_end + kQueryTile - 1 - (tg.s_begin & ~3) + 63) / 64 : 0;
+    const int32_t c = kGroupStartCost + kSegCost * segs + (kStepCost * steps) / kMatchWaves;
     v.gcost[P.grp_off + g] = c;
     cost = c;
   }
@@ -678,12 +698,10 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t gr
   const int32_t qblocks = (max_queries + kRangeThreads - 1) / kRangeThreads;
   if (qblocks > 0) {
     const dim3 grid(pc, qblocks), block(kRangeThreads);
-    if (v.group_tiles == 1)
-      hipLaunchKernelGGL(tile_ranges_kernel<1>, grid, block, 0, st, v, pb);
-    else if (v.group_tiles == 4)
+    if (v.group_tiles == 4)
       hipLaunchKernelGGL(tile_ranges_kernel<4>, grid, block, 0, st, v, pb);
     else
-      hipLaunchKernelGGL(tile_ranges_kernel<2>, grid, block, 0, st, v, pb);
+      hipLaunchKernelGGL(tile_ranges_kernel<8>, grid, block, 0, st, v, pb);
   }
   if (grp_count > 0)
     hipLaunchKernelGGL(schedule_kernel, dim3((pc + 3) / 4), dim3(256), 0, st, v, pb, pc,

@@ -7,11 +7,12 @@
 namespace sfm {
 
 constexpr int kDescBytes = 128;
-constexpr int kQueryTile = 32;          // queries per wave work item (MFMA N)
-constexpr int kMaxGroupTiles = 4;       // query tiles (waves) sharing one candidate stream, at most
-constexpr int kDefaultGroupTiles = 2;   // the default (1, 2 or 4)
+constexpr int kQueryTile = 16;          // queries per tile (MFMA N); also candidates per MFMA step
+constexpr int kMatchWaves = 4;          // waves per match workgroup
+constexpr int kMaxGroupTiles = 8;       // query tiles sharing one candidate stream, at most
+constexpr int kDefaultGroupTiles = 8;   // the default (4 or 8: one or two tiles per wave)
 constexpr int kDefaultFeaturesPerBin = 8;
-constexpr int kCandTile = 32;           // candidates per MFMA step (MFMA M)
+constexpr int kCandPad = 16;            // padding positions after each pair's candidates
 constexpr int kChunk = 1024;            // candidate positions one key encodes
 constexpr int kPosBits = 10;            // log2(kChunk)
 constexpr uint32_t kKeyInf = 0xFFFFFFFFu;
@@ -19,8 +20,9 @@ constexpr int32_t kDistInf = 0x7FFFFFFF;
 constexpr uint32_t kDistBias = 1u << 21;  // makes norm2(c) - 2 q.c >= 0
 constexpr int kMaxBins = 8192;          // LDS histogram size per pair
 constexpr double kBandSlackPx = 1e-2;   // bin windows widen the band by this
-constexpr int32_t kGroupStartCost = 11;  // schedule cost of starting a tile group
-constexpr int32_t kStepCost = 4;         // schedule cost of one 32-candidate step
+constexpr int32_t kGroupStartCost = 48;  // schedule cost of starting a tile group
+constexpr int32_t kSegCost = 4;          // schedule cost of streaming one 64-position segment
+constexpr int32_t kStepCost = 2;         // schedule cost of one 16 x 16 step of one tile
 
 // Per image, built at registration.
 struct ImageDev {
@@ -39,7 +41,7 @@ struct PairDesc {
   int32_t nbins;            // bins of b (full-scan mode uses bin 0 only)
   int32_t nblocks;          // ceil(na / kQueryTile)
   int64_t q_off;            // into per-query arrays (prefix of na)
-  int64_t c_off;            // into per-candidate arrays (prefix of nb)
+  int64_t c_off;            // into per-candidate arrays (prefix of nb + kCandPad)
   int64_t bin_off;          // into bin arrays (prefix of nbins + 1)
   int64_t blk_off;          // into per-block arrays and the work-item space
   int64_t grp_off;          // into the tile-group table
@@ -72,12 +74,12 @@ struct PairGeom {
   int32_t nbins;
 };
 
-// One target feature in binned order (16 bytes).
-struct CandRec {
-  float x, y;               // centred FP32 coordinates
-  uint32_t ncpos;           // ((norm2 + kDistBias) << kPosBits) | (pos & (kChunk-1))
-  int32_t j;                // original index in b
-};
+// Targets in binned order are kept as four arrays (x, y, key word, index),
+// each with kCandPad positions after every pair's n_b: the padding has a NaN
+// x (no band test passes) and index 0.
+//   x, y   centred FP32 coordinates
+//   nc     ((norm2 + kDistBias) << kPosBits) | (position & (kChunk - 1))
+//   j      original index in b
 
 // One query in tile order (16 bytes): normalised line on centred coordinates.
 struct QueryRec {
@@ -85,7 +87,9 @@ struct QueryRec {
   int32_t i;                // original index in a
 };
 
-// Per-query result in original query order (16 bytes).
+// Per-query result in original query order (16 bytes).  The match kernel
+// writes the binned position of the match in `match`; emission turns it into
+// the index in b (BatchView::cand_j set), other producers write the index.
 struct QueryResult {
   int32_t match;            // -1 if no candidate
   int32_t d1, d2;           // kDistInf if absent
@@ -102,7 +106,7 @@ struct PairCounters {
 
 // Up to kMaxGroupTiles consecutive query tiles of one pair and the union of
 // their candidate ranges; one workgroup streams the union through LDS.  The
-// record holds everything the match kernel needs about the pair (128 bytes,
+// record holds everything the match kernel needs about the pair (176 bytes,
 // read with scalar loads).
 struct TileGroup {
   int32_t pair, tile0, ntiles, na;  // na: queries of the pair
@@ -110,20 +114,25 @@ struct TileGroup {
   float band_lo, band_hi;   // FP32 |e| <= band_lo: in; > band_hi: out; else FP64 decides
   int64_t q_off, c_off;     // the pair's query and candidate offsets
   const uint8_t* a_desc;
-  const int32_t* a_norm;
   const uint8_t* b_desc;
-  int64_t pad1;
+  const int32_t* a_norm;
+  const float* a_xy;        // keypoints of a and b (FP64 decisions)
+  const float* b_xy;
+  double band;              // d
+  int32_t nb, pad[3];       // targets of the pair
   int32_t t_begin[kMaxGroupTiles], t_end[kMaxGroupTiles];   // per tile candidate range
-  int32_t pad2[4];
 };
-static_assert(sizeof(TileGroup) == 128, "TileGroup is read as eight 16-byte words");
+static_assert(sizeof(TileGroup) == 176, "TileGroup is read as eleven 16-byte words");
 
 // Everything a batch launch needs, passed by value.
 struct BatchView {
   const ImageDev* images;
   const PairDesc* pairs;
   PairGeom* geom;
-  CandRec* cand;
+  float* cand_x;            // binned targets (see above), sum of (n_b + kCandPad)
+  float* cand_y;
+  uint32_t* cand_nc;
+  int32_t* cand_j;
   int32_t* bin_start;       // nbins + 1 per pair
   QueryRec* qrec;
   int2* qwin;               // per query in tile order: first, last bin (first > last = none)
@@ -140,7 +149,7 @@ struct BatchView {
   int32_t ratio_num, ratio_den;
   int32_t accept_single;
   int32_t keep_counts;
-  int32_t group_tiles;      // tiles per group = waves per match workgroup (1, 2 or 4)
+  int32_t group_tiles;      // tiles per group (4 or 8: one or two per match wave)
   double margin;            // FP64 re-decision margin around d, pixels (0 = FP32 only)
 };
 

@@ -37,7 +37,7 @@ def oracle_result(oracle_lib, batch):
     return oracle_lib.match(images, pairs, Fs)
 
 
-@pytest.mark.parametrize("group_tiles", [1, 2, 4])
+@pytest.mark.parametrize("group_tiles", [4, 8])
 @pytest.mark.parametrize("features_per_bin", [1, 4, 8, 16, 64])
 def test_every_tuning_matches_oracle(sfm, batch, oracle_result, group_tiles, features_per_bin):
     images, pairs, Fs = batch
@@ -54,11 +54,11 @@ def test_every_tuning_matches_oracle(sfm, batch, oracle_result, group_tiles, fea
 def test_tuning_rejects_bad_values(sfm, batch):
     images, _, _ = batch
     m = sfm.Matcher().register(images)
-    for t, f in ((3, 8), (0, 8), (8, 8), (2, 0), (2, 2000)):
+    for t, f in ((3, 8), (0, 8), (2, 8), (16, 8), (8, 0), (8, 2000)):
         with pytest.raises(sfm.SfmError) as e:
             sfm.sfm_set_tuning(m.ctx, t, f)
         assert e.value.status == sfm.SFM_EINVAL
-    assert sfm.sfm_get_tuning(m.ctx) == (2, 8)
+    assert sfm.sfm_get_tuning(m.ctx) == (8, 8)
     m.close()
 
 
@@ -67,7 +67,7 @@ def test_autotune(sfm, batch, oracle_result):
     m = sfm.Matcher().register(images)
     times = sfm.sfm_autotune(m.ctx, pairs, Fs, repeats=2)
     say("  autotune ms: " + ", ".join(f"{k}: {v:.3f}" for k, v in times.items()))
-    assert len(times) == 9 and all(v > 0 for v in times.values())
+    assert len(times) == 6 and all(v > 0 for v in times.values())
     best = sfm.sfm_get_tuning(m.ctx)
     assert times[best] == min(times.values())
     out = m.match(pairs, Fs, form="batched", emit_all=True)
