@@ -11,10 +11,12 @@
 //     rows' indices in b arrive two segments earlier in a ring of their own,
 //     so no loaded value passes through a register on its way to the stage.
 //   - Loads run three segments ahead of the computation, with one wait for the
-//     wave's own loads and one barrier per segment.  The next group's query
+//     wave's own loads and one barrier per segment.  The workgroups on one XCD
+//     take the groups of one contiguous share in turn, so at any time they
+//     work on one or two pairs whose rows stay in that XCD's L2.  The next group's query
 //     records and first row indices are loaded while the current group ends.
-//   - Each tile walks its own candidate range (start rounded down to a
-//     multiple of 4) in steps of 16 positions.  A step's rows are the A
+//   - Each tile walks its own candidate range in steps of 16 positions,
+//     aligned to 16 so that no step crosses a segment.  A step's rows are the A
 //     operand of v_mfma_i32_16x16x64_i8 and the tile's negated query rows the
 //     resident B operand: two MFMAs give -q.c for 16 candidates x 16 queries,
 //     exact in int32 (bytes 0..127 fit int8, 128 * 127^2 < 2^31).
@@ -169,10 +171,9 @@ struct Stream {
   const uint32_t* nc;
   const int32_t* j;
   const uint8_t* b_desc;
-  int32_t base;             // pair position of segment 0 (group start rounded down to 4)
+  int32_t base;             // pair position of segment 0 (group start rounded down to 16)
   int32_t last;             // last readable pair position (n_b plus padding, minus 1)
-  int32_t nsc;              // segments holding step starts
-  int32_t nsl;              // segments read (a step reaches 15 positions past its start)
+  int32_t nsc;              // segments of the stream (steps are aligned to 16: none crosses one)
   uint32_t lds;             // LDS offset of the workgroup's MatchLds
   int32_t jpar;             // which index ring the group uses
 };
@@ -185,11 +186,10 @@ __device__ __forceinline__ Stream make_stream(const BatchView& v, const TileGrou
   s.nc = v.cand_nc + G.c_off;
   s.j = v.cand_j + G.c_off;
   s.b_desc = G.b_desc;
-  s.base = G.s_begin & ~3;
+  s.base = G.s_begin & ~(kQueryTile - 1);
   s.last = G.nb + kCandPad - 1;
   const bool any = G.s_end > G.s_begin;
   s.nsc = any ? (G.s_end - s.base + kSeg - 1) / kSeg : 0;
-  s.nsl = any ? (G.s_end + kQueryTile - 1 - s.base + kSeg - 1) / kSeg : 0;
   s.lds = uint32_t(reinterpret_cast<uintptr_t>((lds_void*)&L));
   s.jpar = jpar;
   return s;
@@ -236,16 +236,23 @@ __device__ __forceinline__ void issue_rows(const Stream& s, const MatchLds& L, i
   }
 }
 
-// Waits for segment s + 1 (and the row indices of segment s + 3) given which
-// later loads exist: those of iteration s - 1 are the index load of segment
-// s + 4 and the row loads of segment s + 2.
-__device__ __forceinline__ void wait_segment(int32_t s, int32_t nsl) {
-  if (s + 4 < nsl)
-    wait_loads<1 + kRowLoads>();
-  else if (s + 2 < nsl)
+// Waits for segment s and the row indices of segment s + 3.  Iteration t
+// issues the indices of segment t + 5, then the rows of t + 3 (kRowLoads
+// loads), so what may still be in flight are the rows of s + 1, the indices
+// of s + 4 and the rows of s + 2, those that exist (n segments).
+__device__ __forceinline__ void wait_segment(int32_t s, int32_t n) {
+  if (s + 3 < n) {
+    if (s + 4 < n)
+      wait_loads<2 * kRowLoads + 1>();
+    else
+      wait_loads<2 * kRowLoads>();
+  } else if (s + 2 < n) {
+    wait_loads<2 * kRowLoads>();
+  } else if (s + 1 < n) {
     wait_loads<kRowLoads>();
-  else
+  } else {
     wait_loads<0>();
+  }
 }
 
 // A group record read with scalar loads (its index is uniform).
@@ -279,9 +286,9 @@ __device__ __forceinline__ GroupStart<TPW> start_group(const BatchView& v, const
     st.qu[k] = gload16(v.qrec + G.q_off + min(qs, G.na - 1));
   }
   const Stream s = make_stream(v, G, L, jpar);
-  if (s.nsl > 0) issue_j(s, 0, w, lane);
-  if (s.nsl > 1) issue_j(s, 1, w, lane);
-  if (s.nsl > 2) issue_j(s, 2, w, lane);
+  if (s.nsc > 0) issue_j(s, 0, w, lane);
+  if (s.nsc > 1) issue_j(s, 1, w, lane);
+  if (s.nsc > 2) issue_j(s, 2, w, lane);
   return st;
 }
 
@@ -506,7 +513,7 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
       te = tidx == t ? G.t_end[t] : te;
     }
     if (tidx >= G.ntiles || te <= tb) tb = te = s.base;
-    rb[k] = (tb & ~3) - s.base;
+    rb[k] = (tb & ~(kQueryTile - 1)) - s.base;
     re[k] = te - s.base;
     c0[k] = rb[k];
   }
@@ -526,12 +533,12 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
     qr[k][1] = gload16(qrow + 64);
     T[k].nq = ((g_i32*)G.a_norm)[T[k].i];
   }
-  if (s.nsl > 0) {
+  if (s.nsc > 0) {
     issue_rows(s, L, 0, w, lane);
-    if (3 < s.nsl) issue_j(s, 3, w, lane);
-    if (1 < s.nsl) issue_rows(s, L, 1, w, lane);
-    if (4 < s.nsl) issue_j(s, 4, w, lane);
-    if (2 < s.nsl) issue_rows(s, L, 2, w, lane);
+    if (3 < s.nsc) issue_j(s, 3, w, lane);
+    if (1 < s.nsc) issue_rows(s, L, 1, w, lane);
+    if (4 < s.nsc) issue_j(s, 4, w, lane);
+    if (2 < s.nsc) issue_rows(s, L, 2, w, lane);
   }
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
@@ -553,10 +560,10 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
   uint32_t nsteps = 0;     // 16 x 16 steps evaluated
 
   for (int32_t sg = 0; sg < s.nsc; ++sg) {
-    wait_segment(sg, s.nsl);
+    wait_segment(sg, s.nsc);
     barrier();
-    if (sg + 5 < s.nsl) issue_j(s, sg + 5, w, lane);
-    if (sg + 3 < s.nsl) issue_rows(s, L, sg + 3, w, lane);
+    if (sg + 5 < s.nsc) issue_j(s, sg + 5, w, lane);
+    if (sg + 3 < s.nsc) issue_rows(s, L, sg + 3, w, lane);
 
     const int32_t seg_lo = kSeg * sg;
 #pragma unroll
@@ -754,18 +761,12 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
   ws.ties += ties;
 }
 
-// One resident wave of workgroups.  Workgroups are dealt to the 8 XCDs
-// round-robin (workgroup k runs on XCD k mod 8), and each XCD has its own L2.
-// Preparation splits the groups into runs of about equal estimated cost;
-// runs are laid out XCD-contiguously, so the 1/8 of the groups one XCD takes
-// is one contiguous share of the pairs.
+// One resident wave of workgroups.  Preparation splits the groups into
+// kXcds contiguous shares of about equal estimated cost, one per XCD (each
+// XCD has its own L2).
 #ifndef SFM_MATCH_WAVES_PER_EU
 #define SFM_MATCH_WAVES_PER_EU 4
 #endif
-__device__ __forceinline__ int32_t xcd_contiguous(int32_t g, int32_t G) {
-  const int32_t x = g & 7, k = g >> 3, q = G >> 3, r = G & 7;
-  return x * q + min(x, r) + k;
-}
 template <bool kKeepCounts, int TPW>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(SFM_MATCH_WAVES_PER_EU, 8)))
 void match_kernel(BatchView v) {
@@ -774,17 +775,22 @@ void match_kernel(BatchView v) {
   // everything derived from it (tile ranges, queue counts) in SGPRs.
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   typedef const __attribute__((address_space(4))) int32_t c_i32;
-  const int32_t run = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int32_t g_first = ((c_i32*)v.wg_start)[run];
-  const int32_t g_end = ((c_i32*)v.wg_start)[run + 1];
+  // Workgroup k runs on XCD x = k mod 8 (workgroups are dealt to the XCDs
+  // round-robin) and takes every W-th group of share x, W being the number of
+  // workgroups on that XCD.
+  const int32_t shares = min(kXcds, int32_t(gridDim.x));
+  const int32_t x = blockIdx.x % shares, i = blockIdx.x / shares;
+  const int32_t W = (int32_t(gridDim.x) - x + shares - 1) / shares;
+  const int32_t g_first = ((c_i32*)v.wg_start)[x] + i;
+  const int32_t g_end = ((c_i32*)v.wg_start)[x + 1];
   WaveStats ws = {-1, 0, 0, 0, 0, 0};
   if (g_first < g_end) {
     GroupStart<TPW> gs = start_group<TPW>(v, load_group(v.groups, g_first), lds, 0, wave, lane);
     int32_t jpar = 0;
-    for (int32_t g = g_first; g < g_end; ++g) {
+    for (int32_t g = g_first; g < g_end; g += W) {
       const TileGroup G = load_group(v.groups, g);
       GroupStart<TPW> gsn;
-      match_group<kKeepCounts, TPW>(v, G, gs, jpar, g + 1 < g_end ? g + 1 : -1, gsn, lds, wave,
+      match_group<kKeepCounts, TPW>(v, G, gs, jpar, g + W < g_end ? g + W : -1, gsn, lds, wave,
                                     lane, ws);
       gs = gsn;
       jpar ^= 1;

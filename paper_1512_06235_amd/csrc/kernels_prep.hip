@@ -618,10 +618,10 @@ __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v,
   }
 }
 
-// Splits the tile groups of pairs [pb, pb + pc) into `wgs` contiguous runs of
-// about equal cost: group g goes to run floor(pre(g) * wgs / total), pre(g)
-// being the cost of the groups before it, so run k starts at the first group
-// with pre(g) * wgs >= k * total.  One wave per pair finds the starts that
+// Splits the tile groups of pairs [pb, pb + pc) into `wgs` contiguous runs
+// (shares) of about equal cost: group g goes to run floor(pre(g) * wgs /
+// total), pre(g) being the cost of the groups before it, so run k starts at
+// the first group with pre(g) * wgs >= k * total.  One wave per pair finds the starts that
 // fall inside its pair; the pair with the last group also closes the table.
 __global__ __launch_bounds__(256) void schedule_kernel(BatchView v, int32_t pb, int32_t pc,
                                                        int32_t g0, int32_t n, int32_t wgs) {
@@ -686,9 +686,6 @@ hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_
   return hipGetLastError();
 }
 
-#ifndef SFM_XCD_SWEEP
-#define SFM_XCD_SWEEP 0
-#endif
 hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t grp_begin,
                           int32_t grp_count, int32_t wgs, const int32_t* order,
                           int32_t max_queries, hipStream_t st) {
@@ -705,7 +702,7 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t gr
   }
   if (grp_count > 0)
     hipLaunchKernelGGL(schedule_kernel, dim3((pc + 3) / 4), dim3(256), 0, st, v, pb, pc,
-                       grp_begin, grp_count, SFM_XCD_SWEEP ? std::min(8, wgs) : wgs);
+                       grp_begin, grp_count, std::min(kXcds, wgs));
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@ namespace sfm {
 constexpr int kDescBytes = 128;
 constexpr int kQueryTile = 16;          // queries per tile (MFMA N); also candidates per MFMA step
 constexpr int kMatchWaves = 4;          // waves per match workgroup
+constexpr int kXcds = 8;                // XCDs of the GPU (each with its own L2): schedule shares
 constexpr int kMaxGroupTiles = 8;       // query tiles sharing one candidate stream, at most
 constexpr int kDefaultGroupTiles = 8;   // the default (4 or 8: one or two tiles per wave)
 constexpr int kDefaultFeaturesPerBin = 8;
@@ -139,7 +140,7 @@ struct BatchView {
   TileGroup* groups;
   int32_t* gcost;           // per tile group: estimated cost of matching it
   long long* pcost;         // per pair: the sum of its groups' costs
-  int32_t* wg_start;        // match workgroup k takes groups [wg_start[k], wg_start[k + 1])
+  int32_t* wg_start;        // share x (one per XCD) holds groups [wg_start[x], wg_start[x + 1])
   QueryResult* res;
   PairCounters* counters;
   const double* F;          // 9 per pair
@@ -301,16 +302,17 @@ hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_
                            int32_t* norm2_all, const int64_t* norm_off, float* bbox_dev,
                            int32_t* bad_flag, hipStream_t st);
 // Preparation of pairs [pair_begin, pair_begin + pair_count), whose tile groups
-// are [grp_begin, grp_begin + grp_count), split over `wgs` match workgroups.
-// `order` (device, may be NULL) lists the pairs in the order binning takes
-// them; `max_queries` is the largest n_a among the pairs.
+// are [grp_begin, grp_begin + grp_count), for `wgs` match workgroups (the
+// groups are split into min(kXcds, wgs) shares of about equal cost, one per
+// XCD).  `order` (device, may be NULL) lists the pairs in the order binning
+// takes them; `max_queries` is the largest n_a among the pairs.
 hipError_t launch_prepare(const BatchView& v, int32_t pair_begin, int32_t pair_count,
                           int32_t grp_begin, int32_t grp_count, int32_t wgs,
                           const int32_t* order, int32_t max_queries, hipStream_t st);
 // Workgroups the match kernel uses for `groups` tile groups (one resident wave
 // of workgroups at most).
 int32_t match_workgroups(int32_t device, int32_t group_tiles, int64_t groups);
-// Matches the groups that the last preparation split over `wgs` workgroups.
+// Matches the groups of the last preparation with `wgs` workgroups.
 hipError_t launch_match(const BatchView& v, int32_t wgs, hipStream_t st);
 hipError_t launch_emit(const BatchView& v, int32_t pair_begin, int32_t pair_count,
                        int64_t* offset, int32_t* out_q, int32_t* out_m, int32_t* out_d1,
