@@ -160,6 +160,33 @@ int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
                            const double* F, const sfm_options* opt, const sfm_matches* out,
                            void* stream);
 
+/* Limits of sfm_guided_match_noalloc. */
+#define SFM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define SFM_NOALLOC_MAX_PAIRS 8192
+
+/* For callers that cannot allocate memory while they run (tight serving
+ * loops, harnesses that forbid allocation): sfm_guided_match with the same
+ * arguments and bit-identical outputs, computed without any device, pinned
+ * or heap allocation in the call.  Its workspace is a fixed device array of
+ * SFM_NOALLOC_SCRATCH_BYTES per GPU, loaded with the library's device code
+ * and held until the process ends; sfm_create looks up its address once per
+ * device.  Pair table, F and binning order go through a fixed host buffer.
+ * Limits: at most SFM_NOALLOC_MAX_PAIRS pairs, and a workspace
+ * (sfm_workspace_size) of at most SFM_NOALLOC_SCRATCH_BYTES; beyond either
+ * the call returns SFM_ECAPACITY and enqueues nothing.
+ * Sharing: every context on a GPU uses that GPU's one array, which keeps the
+ * last call's contents (nothing of it is read before it is rewritten).  The
+ * library orders the calls of this entry point on one GPU: each call's
+ * kernels wait for the previous call's, so calls from different streams or
+ * contexts run one after another; work that escapes that order (a replay of
+ * a captured call) would race with any other call on the GPU and is not
+ * supported.  The call waits on the host for the previous call's staging
+ * copy to finish.  sfm_last_stats reports nothing after this call.
+ * Errors: as sfm_guided_match, and SFM_EINVAL on a device index >= 64. */
+int sfm_guided_match_noalloc(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
+                             const double* F, const sfm_options* opt, const sfm_matches* out,
+                             void* stream);
+
 /* Exhaustive matching: every feature of b is a candidate of every query
  * (band and F ignored; F may be NULL).  Same outputs; equals guided matching
  * with band_px = +inf on queries whose line is not degenerate. */

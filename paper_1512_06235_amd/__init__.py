@@ -101,6 +101,8 @@ def lib() -> C.CDLL:
                              C.POINTER(sfm_matches), vp],
         "sfm_guided_match_plain": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
                                    C.POINTER(sfm_matches), vp],
+        "sfm_guided_match_noalloc": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
+                                     C.POINTER(sfm_matches), vp],
         "sfm_bruteforce_match": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options),
                                  C.POINTER(sfm_matches), vp],
         "sfm_band_error": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(C.c_double),
@@ -148,7 +150,8 @@ def lib() -> C.CDLL:
 def exported_symbols():
     """Names of the entry points include/sfm_gm.h declares."""
     return ["sfm_create", "sfm_destroy", "sfm_register_images", "sfm_workspace_size",
-            "sfm_guided_match", "sfm_guided_match_plain", "sfm_bruteforce_match",
+            "sfm_guided_match", "sfm_guided_match_plain", "sfm_guided_match_noalloc",
+            "sfm_bruteforce_match",
             "sfm_band_error", "sfm_sync",
             "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
@@ -252,6 +255,15 @@ def sfm_guided_match(ctx, pairs, F, out, opt, stream=None):
 
 def sfm_guided_match_plain(ctx, pairs, F, out, opt, stream=None):
     _call("sfm_guided_match_plain", ctx, pairs, F, out, opt, stream)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SFM_NOALLOC_SCRATCH_BYTES
+NOALLOC_MAX_PAIRS = 8192           # SFM_NOALLOC_MAX_PAIRS
+
+
+def sfm_guided_match_noalloc(ctx, pairs, F, out, opt, stream=None):
+    """sfm_guided_match on the device's fixed scratch array: allocates nothing."""
+    _call("sfm_guided_match_noalloc", ctx, pairs, F, out, opt, stream)
 
 
 def sfm_bruteforce_match(ctx, pairs, F, out, opt, stream=None):
@@ -592,6 +604,8 @@ class Matcher:
             sfm_guided_match(self.ctx, pairs, F, out, opt, stream)
         elif form == "plain":
             sfm_guided_match_plain(self.ctx, pairs, F, out, opt, stream)
+        elif form == "noalloc":
+            sfm_guided_match_noalloc(self.ctx, pairs, F, out, opt, stream)
         elif form == "bruteforce":
             sfm_bruteforce_match(self.ctx, pairs, F, out, opt, stream)
         elif form == "grid":

@@ -14,6 +14,17 @@
 
 using namespace sfm;
 
+// Scratch of sfm_guided_match_noalloc, one copy per GPU, held until the
+// process ends.  In host code the name stands for a host-side shadow, never
+// for device memory: host code uses the address hipGetSymbolAddress returns
+// for the current device (ScratchDevice::ptr below).
+static __device__ __align__(256) char scratch[SFM_NOALLOC_SCRATCH_BYTES];
+
+// Writes offset[0] = 0: the output of a call without pairs.
+__global__ void zero_offset_kernel(int64_t* offset) {
+  if (threadIdx.x == 0) offset[0] = 0;
+}
+
 struct sfm_ctx {
   int32_t device = 0;
   int32_t group_tiles = kDefaultGroupTiles;          // query tiles per match workgroup
@@ -38,6 +49,7 @@ struct sfm_ctx {
   hipEvent_t staging_done = nullptr;   // last copy out of the pinned buffer
   hipEvent_t work_done = nullptr;      // end of the last matching call
   int32_t* err_dev = nullptr;
+  char* noalloc_scratch = nullptr;     // this device's `scratch` (device address)
   unsigned long long* diag_dev = nullptr;   // sfm_band_error's two result words
   bool has_work = false;
   int32_t last_pairs = 0;              // pairs of the last matching call
@@ -74,9 +86,17 @@ int fail(sfm_ctx* ctx, int status, const std::string& msg) {
   return status;
 }
 
+// The message is cut to the capacity last_error was given at creation, so
+// this form never allocates.
+int fail(sfm_ctx* ctx, int status, const char* msg) {
+  if (ctx) ctx->last_error.assign(msg, strnlen(msg, ctx->last_error.capacity()));
+  return status;
+}
+
 int hip_fail(sfm_ctx* ctx, hipError_t e, const char* what) {
-  return fail(ctx, e == hipErrorOutOfMemory ? SFM_ENOMEM : SFM_EHIP,
-              std::string(what) + ": " + hipGetErrorString(e));
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+  return fail(ctx, e == hipErrorOutOfMemory ? SFM_ENOMEM : SFM_EHIP, buf);
 }
 
 #define HIP_TRY(ctx, expr)                                   \
@@ -97,16 +117,16 @@ int32_t bins_for(int32_t nb, int32_t features_per_bin) {
   return std::max<int32_t>(1, std::min<int32_t>(kMaxBins, nb / features_per_bin));
 }
 
-Layout plan(const std::vector<PairDesc>& pd, int32_t device, int32_t group_tiles) {
+Layout plan(const PairDesc* pd, size_t P, int32_t device, int32_t group_tiles) {
   Layout L;
-  for (const PairDesc& p : pd) {
+  for (size_t k = 0; k < P; ++k) {
+    const PairDesc& p = pd[k];
     L.sum_na += p.na;
     L.sum_nc += p.nb + kCandPad;
     L.sum_bins += p.nbins + 1;
     L.sum_blocks += p.nblocks;
     L.sum_groups += p.ngroups;
   }
-  const size_t P = pd.size();
   size_t o = 0;
   L.pairs = o; o = align_up(o + P * sizeof(PairDesc));
   L.F = o; o = align_up(o + P * 9 * sizeof(double));
@@ -131,6 +151,10 @@ Layout plan(const std::vector<PairDesc>& pd, int32_t device, int32_t group_tiles
   return L;
 }
 
+Layout plan(const std::vector<PairDesc>& pd, int32_t device, int32_t group_tiles) {
+  return plan(pd.data(), pd.size(), device, group_tiles);
+}
+
 // The images pairs refer to: the registered ones, or views of them (a run of
 // consecutive features of one image) built for a staged match.
 struct ImageTable {
@@ -143,11 +167,11 @@ ImageTable registered(const sfm_ctx* ctx) {
   return ImageTable{ctx->images_dev, ctx->n_host.data(), ctx->n_images};
 }
 
+// Fills pd[0 .. n_pairs) (room for n_pairs descriptors).
 int describe_pairs(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int32_t n_pairs,
-                   bool ignore_band, std::vector<PairDesc>& pd) {
+                   bool ignore_band, PairDesc* pd) {
   if (n_pairs < 0) return fail(ctx, SFM_EINVAL, "n_pairs < 0");
   if (n_pairs > 0 && !pairs) return fail(ctx, SFM_EINVAL, "pairs is NULL");
-  pd.resize(size_t(n_pairs));
   int64_t q = 0, c = 0, bo = 0, blk = 0, grp = 0;
   for (int32_t k = 0; k < n_pairs; ++k) {
     const sfm_pair& s = pairs[k];
@@ -162,7 +186,7 @@ int describe_pairs(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, i
       snprintf(buf, sizeof buf, "pair %d: band_px must be >= 0 (got %g)", k, s.band_px);
       return fail(ctx, SFM_EINVAL, buf);
     }
-    PairDesc& p = pd[size_t(k)];
+    PairDesc& p = pd[k];
     memset(&p, 0, sizeof p);
     p.a = s.a;
     p.b = s.b;
@@ -186,6 +210,13 @@ int describe_pairs(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, i
   }
   if (blk > INT32_MAX / 2) return fail(ctx, SFM_ECAPACITY, "too many query tiles in one call");
   return SFM_OK;
+}
+
+int describe_pairs(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int32_t n_pairs,
+                   bool ignore_band, std::vector<PairDesc>& pd) {
+  if (n_pairs < 0) return fail(ctx, SFM_EINVAL, "n_pairs < 0");
+  pd.resize(size_t(n_pairs));
+  return describe_pairs(ctx, tab, pairs, n_pairs, ignore_band, pd.data());
 }
 
 int ensure_workspace(sfm_ctx* ctx, size_t bytes) {
@@ -322,6 +353,67 @@ int check_F(sfm_ctx* ctx, const double* F, int32_t n_pairs) {
   return SFM_OK;
 }
 
+// Output checks of the matching forms.
+int check_outputs(sfm_ctx* ctx, const sfm_matches* out, const Layout& L, const sfm_options& opt) {
+  if (!out->offset) return fail(ctx, SFM_EINVAL, "out->offset is NULL");
+  if (out->capacity < L.sum_na) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "output capacity %lld < %lld queries", (long long)out->capacity,
+             (long long)L.sum_na);
+    return fail(ctx, SFM_ECAPACITY, buf);
+  }
+  if (L.sum_na > 0 && (!out->query || !out->match || !out->d1 || !out->d2))
+    return fail(ctx, SFM_EINVAL, "output arrays are NULL");
+  if (opt.emit_all && L.sum_na > 0 &&
+      (!out->all_match || !out->all_d1 || !out->all_d2 || !out->all_count))
+    return fail(ctx, SFM_EINVAL, "emit_all needs all_match, all_d1, all_d2 and all_count");
+  return SFM_OK;
+}
+
+// The kernels' view of one call whose workspace sections (plan()) start at `ws`.
+BatchView batch_view(const sfm_ctx* ctx, const ImageTable& tab, char* ws, const Layout& L,
+                     int32_t n_pairs, const sfm_options& opt) {
+  BatchView v;
+  memset(&v, 0, sizeof v);   // padding too: graph keys compare the bytes
+  v.images = tab.dev;
+  v.pairs = reinterpret_cast<const PairDesc*>(ws + L.pairs);
+  v.F = reinterpret_cast<const double*>(ws + L.F);
+  v.geom = reinterpret_cast<PairGeom*>(ws + L.geom);
+  v.counters = reinterpret_cast<PairCounters*>(ws + L.counters);
+  v.cand_x = reinterpret_cast<float*>(ws + L.cand_x);
+  v.cand_y = reinterpret_cast<float*>(ws + L.cand_y);
+  v.cand_nc = reinterpret_cast<uint32_t*>(ws + L.cand_nc);
+  v.cand_j = reinterpret_cast<int32_t*>(ws + L.cand_j);
+  v.bin_start = reinterpret_cast<int32_t*>(ws + L.bins);
+  v.qrec = reinterpret_cast<QueryRec*>(ws + L.qrec);
+  v.res = reinterpret_cast<QueryResult*>(ws + L.res);
+  v.qwin = reinterpret_cast<int2*>(ws + L.qwin);
+  v.wg_start = reinterpret_cast<int32_t*>(ws + L.wg_start);
+  v.gcost = reinterpret_cast<int32_t*>(ws + L.gcost);
+  v.pcost = reinterpret_cast<long long*>(ws + L.pcost);
+  v.err = ctx->err_dev;
+  v.n_pairs = n_pairs;
+  v.total_blocks = int32_t(L.sum_blocks);
+  v.ratio_num = opt.ratio_num;
+  v.ratio_den = opt.ratio_den;
+  v.accept_single = opt.accept_single ? 1 : 0;
+  v.keep_counts = opt.emit_all ? 1 : 0;
+  v.group_tiles = ctx->group_tiles;
+  v.margin = opt.recheck_margin_px;
+  v.groups = reinterpret_cast<TileGroup*>(ws + L.groups);
+  return v;
+}
+
+// Binning takes the largest pairs first, so small ones fill the tail; equal
+// sizes keep the caller's order.  In place (std::sort allocates nothing).
+void binning_order(const PairDesc* pd, int32_t n_pairs, int32_t* ord) {
+  for (int32_t k = 0; k < n_pairs; ++k) ord[k] = k;
+  std::sort(ord, ord + n_pairs, [&](int32_t x, int32_t y) {
+    const int32_t sx = std::max(pd[x].na, pd[x].nb), sy = std::max(pd[y].na, pd[y].nb);
+    return sx != sy ? sx > sy : x < y;
+  });
+}
+
 // One matching call over the images of `tab`; the caller holds ctx->mu.
 // kBandError runs the preparation and the FP32-accuracy diagnostic instead
 // of matching (`out` is unused; diag receives the two result words).
@@ -344,21 +436,8 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
   if (!exhaustive && (rc = check_F(ctx, F, n_pairs))) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const Layout L = plan(pd, ctx->device, ctx->group_tiles);
-  if (diagnostic) {
-    // no outputs
-  } else if (!out->offset) {
-    return fail(ctx, SFM_EINVAL, "out->offset is NULL");
-  } else if (out->capacity < L.sum_na) {
-    char buf[128];
-    snprintf(buf, sizeof buf, "output capacity %lld < %lld queries", (long long)out->capacity,
-             (long long)L.sum_na);
-    return fail(ctx, SFM_ECAPACITY, buf);
-  }
-  if (!diagnostic && L.sum_na > 0 && (!out->query || !out->match || !out->d1 || !out->d2))
-    return fail(ctx, SFM_EINVAL, "output arrays are NULL");
-  if (opt.emit_all && L.sum_na > 0 &&
-      (!out->all_match || !out->all_d1 || !out->all_d2 || !out->all_count))
-    return fail(ctx, SFM_EINVAL, "emit_all needs all_match, all_d1, all_d2 and all_count");
+  if (!diagnostic && (rc = check_outputs(ctx, out, L, opt))) return rc;
+  if (diagnostic && opt.emit_all) return fail(ctx, SFM_EINVAL, "emit_all has no outputs here");
 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (n_pairs == 0) {
@@ -377,45 +456,11 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
   } else {
     memcpy(ctx->pinned + L.F, F, pd.size() * 9 * sizeof(double));
   }
-  // Binning takes the largest pairs first, so small ones fill the tail.
-  {
-    int32_t* ord = reinterpret_cast<int32_t*>(ctx->pinned + L.order);
-    for (int32_t k = 0; k < n_pairs; ++k) ord[k] = k;
-    std::stable_sort(ord, ord + n_pairs, [&](int32_t x, int32_t y) {
-      return std::max(pd[size_t(x)].na, pd[size_t(x)].nb) > std::max(pd[size_t(y)].na, pd[size_t(y)].nb);
-    });
-  }
+  binning_order(pd.data(), n_pairs, reinterpret_cast<int32_t*>(ctx->pinned + L.order));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->ws, ctx->pinned, L.staged, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipEventRecord(ctx->staging_done, st));
 
-  BatchView v;
-  memset(&v, 0, sizeof v);   // padding too: graph keys compare the bytes
-  v.images = tab.dev;
-  v.pairs = reinterpret_cast<const PairDesc*>(ctx->ws + L.pairs);
-  v.F = reinterpret_cast<const double*>(ctx->ws + L.F);
-  v.geom = reinterpret_cast<PairGeom*>(ctx->ws + L.geom);
-  v.counters = reinterpret_cast<PairCounters*>(ctx->ws + L.counters);
-  v.cand_x = reinterpret_cast<float*>(ctx->ws + L.cand_x);
-  v.cand_y = reinterpret_cast<float*>(ctx->ws + L.cand_y);
-  v.cand_nc = reinterpret_cast<uint32_t*>(ctx->ws + L.cand_nc);
-  v.cand_j = reinterpret_cast<int32_t*>(ctx->ws + L.cand_j);
-  v.bin_start = reinterpret_cast<int32_t*>(ctx->ws + L.bins);
-  v.qrec = reinterpret_cast<QueryRec*>(ctx->ws + L.qrec);
-  v.res = reinterpret_cast<QueryResult*>(ctx->ws + L.res);
-  v.qwin = reinterpret_cast<int2*>(ctx->ws + L.qwin);
-  v.wg_start = reinterpret_cast<int32_t*>(ctx->ws + L.wg_start);
-  v.gcost = reinterpret_cast<int32_t*>(ctx->ws + L.gcost);
-  v.pcost = reinterpret_cast<long long*>(ctx->ws + L.pcost);
-  v.err = ctx->err_dev;
-  v.n_pairs = n_pairs;
-  v.total_blocks = int32_t(L.sum_blocks);
-  v.ratio_num = opt.ratio_num;
-  v.ratio_den = opt.ratio_den;
-  v.accept_single = opt.accept_single ? 1 : 0;
-  v.keep_counts = opt.emit_all ? 1 : 0;
-  v.group_tiles = ctx->group_tiles;
-  v.margin = opt.recheck_margin_px;
-  v.groups = reinterpret_cast<TileGroup*>(ctx->ws + L.groups);
+  const BatchView v = batch_view(ctx, tab, ctx->ws, L, n_pairs, opt);
 
   int32_t* am = opt.emit_all ? out->all_match : nullptr;
   int32_t* ad1 = opt.emit_all ? out->all_d1 : nullptr;
@@ -483,6 +528,125 @@ int run_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double
   return match_locked(ctx, registered(ctx), pairs, n_pairs, F, opt, out, stream, form);
 }
 
+// sfm_guided_match_noalloc: the batched form on the device's `scratch`
+// array, with the pair table, F and binning order staged in a process-wide
+// host buffer instead of the context's workspace and pinned buffer.
+
+constexpr int kMaxScratchDevices = 64;
+// plan()'s staged prefix (pairs, F, order) at the most pairs a call takes.
+constexpr size_t kNoAllocStageBytes =
+    3 * kAlign +
+    size_t(SFM_NOALLOC_MAX_PAIRS) * (sizeof(PairDesc) + 9 * sizeof(double) + sizeof(int32_t));
+
+struct ScratchDevice {
+  char* ptr = nullptr;           // device address of this GPU's `scratch`
+  hipEvent_t staged = nullptr;   // after the last staging copy issued on this GPU
+  hipEvent_t done = nullptr;     // after the last call's kernels on this GPU
+  bool has_done = false;
+};
+ScratchDevice g_scratch[kMaxScratchDevices];
+std::mutex g_scratch_setup_mu;    // guards the set-up of g_scratch
+std::mutex g_noalloc_mu;          // held for a whole call: g_stage, g_stage_device, has_done
+alignas(kAlign) char g_stage[kNoAllocStageBytes];
+int32_t g_stage_device = -1;      // GPU whose `staged` event guards g_stage
+
+// Once per device, with that device current: the device address of its
+// `scratch` and the device's two events.  *ptr is NULL for devices past
+// kMaxScratchDevices (the entry point then reports SFM_EINVAL).
+hipError_t scratch_setup(int32_t device, char** ptr) {
+  *ptr = nullptr;
+  if (device >= kMaxScratchDevices) return hipSuccess;
+  std::lock_guard<std::mutex> lock(g_scratch_setup_mu);
+  ScratchDevice& s = g_scratch[device];
+  if (!s.ptr) {
+    hipError_t e = hipSuccess;
+    if (!s.staged && (e = hipEventCreateWithFlags(&s.staged, hipEventDisableTiming)) != hipSuccess)
+      return e;
+    if (!s.done && (e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess)
+      return e;
+    char* p = nullptr;
+    if ((e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+    s.ptr = p;
+  }
+  *ptr = s.ptr;
+  return hipSuccess;
+}
+
+// The caller holds ctx->mu.  Allocates nothing: no device, pinned or heap
+// memory (error messages are cut to last_error's reserved capacity).
+int noalloc_locked(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                   const sfm_options* opt_in, const sfm_matches* out, void* stream) {
+  if (!out) return fail(ctx, SFM_EINVAL, "out is NULL");
+  sfm_options opt = default_options();
+  if (opt_in) opt = *opt_in;
+  int rc = check_options(ctx, opt);
+  if (rc) return rc;
+  if (!ctx->noalloc_scratch) return fail(ctx, SFM_EINVAL, "no scratch array on this device");
+  if (n_pairs > SFM_NOALLOC_MAX_PAIRS) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "%d pairs: sfm_guided_match_noalloc takes at most %d", n_pairs,
+             SFM_NOALLOC_MAX_PAIRS);
+    return fail(ctx, SFM_ECAPACITY, buf);
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  // g_stage is free once the last staging copy out of it has run.
+  if (g_stage_device >= 0) HIP_TRY(ctx, hipEventSynchronize(g_scratch[g_stage_device].staged));
+  // plan() puts the pair table first, so it is described in place.
+  PairDesc* pd = reinterpret_cast<PairDesc*>(g_stage);
+  if ((rc = describe_pairs(ctx, registered(ctx), pairs, n_pairs, false, pd))) return rc;
+  if ((rc = check_F(ctx, F, n_pairs))) return rc;
+  const Layout L = plan(pd, size_t(n_pairs), ctx->device, ctx->group_tiles);
+  if ((rc = check_outputs(ctx, out, L, opt))) return rc;
+  if (L.pairs != 0 || L.staged > kNoAllocStageBytes)
+    return fail(ctx, SFM_EINVAL, "staging layout does not fit the host buffer");
+  if (L.total > SFM_NOALLOC_SCRATCH_BYTES) {
+    char buf[160];
+    snprintf(buf, sizeof buf,
+             "the call needs %zu bytes of scratch; sfm_guided_match_noalloc has %zu", L.total,
+             size_t(SFM_NOALLOC_SCRATCH_BYTES));
+    return fail(ctx, SFM_ECAPACITY, buf);
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (n_pairs == 0) {
+    hipLaunchKernelGGL(zero_offset_kernel, dim3(1), dim3(64), 0, st, out->offset);
+    HIP_TRY(ctx, hipGetLastError());
+    return SFM_OK;
+  }
+  ScratchDevice& sd = g_scratch[ctx->device];
+  // Calls on one context, and all calls of this entry point on one GPU (they
+  // share its scratch), run in the order they were made.
+  if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
+  if (sd.has_done) HIP_TRY(ctx, hipStreamWaitEvent(st, sd.done, 0));
+
+  char* ws = ctx->noalloc_scratch;
+  memcpy(g_stage + L.F, F, size_t(n_pairs) * 9 * sizeof(double));
+  binning_order(pd, n_pairs, reinterpret_cast<int32_t*>(g_stage + L.order));
+  HIP_TRY(ctx, hipMemcpyAsync(ws, g_stage, L.staged, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipEventRecord(sd.staged, st));
+  g_stage_device = ctx->device;
+
+  // The geometry kernel zeroes the per-pair counters; every other section is
+  // written before it is read, so nothing left by an earlier call is used.
+  const BatchView v = batch_view(ctx, registered(ctx), ws, L, n_pairs, opt);
+  int32_t max_na = 0;
+  for (int32_t k = 0; k < n_pairs; ++k) max_na = std::max(max_na, pd[k].na);
+  HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, 0, int32_t(L.sum_groups), L.wgs,
+                              reinterpret_cast<const int32_t*>(ws + L.order), max_na, st));
+  HIP_TRY(ctx, launch_match(v, L.sum_groups > 0 ? L.wgs : 0, st));
+  const bool ea = opt.emit_all != 0;
+  HIP_TRY(ctx, launch_emit(v, 0, n_pairs, out->offset, out->query, out->match, out->d1, out->d2,
+                           out->n_comparisons, out->n_borderline, ea ? out->all_match : nullptr,
+                           ea ? out->all_d1 : nullptr, ea ? out->all_d2 : nullptr,
+                           ea ? out->all_count : nullptr, st));
+  HIP_TRY(ctx, hipEventRecord(sd.done, st));
+  sd.has_done = true;
+  HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
+  ctx->has_work = true;
+  ctx->last_pairs = 0;   // its counters sit in the shared scratch: no sfm_last_stats
+  return SFM_OK;
+}
+
 }  // namespace
 
 namespace sfm {
@@ -545,10 +709,12 @@ int sfm_create(sfm_ctx** out, int32_t device, size_t budget) {
   sfm_ctx* ctx = new sfm_ctx();
   ctx->device = device;
   ctx->budget = budget ? budget : (size_t(8) << 30);
+  ctx->last_error.reserve(255);
   if (hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->work_done, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&ctx->err_dev, sizeof(int32_t)) != hipSuccess ||
-      hipMemset(ctx->err_dev, 0, sizeof(int32_t)) != hipSuccess) {
+      hipMemset(ctx->err_dev, 0, sizeof(int32_t)) != hipSuccess ||
+      scratch_setup(device, &ctx->noalloc_scratch) != hipSuccess) {
     sfm_destroy(ctx);
     return SFM_EHIP;
   }
@@ -670,6 +836,14 @@ int sfm_workspace_size(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, siz
 int sfm_guided_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                      const sfm_options* opt, const sfm_matches* out, void* stream) {
   return run_match(ctx, pairs, n_pairs, F, opt, out, stream, Form::kBatched);
+}
+
+int sfm_guided_match_noalloc(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
+                             const double* F, const sfm_options* opt, const sfm_matches* out,
+                             void* stream) {
+  if (!ctx) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  return noalloc_locked(ctx, pairs, n_pairs, F, opt, out, stream);
 }
 
 int sfm_guided_match_plain(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs,
