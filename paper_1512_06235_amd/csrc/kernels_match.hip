@@ -2,31 +2,36 @@
 // steps 3-4 redesigned for CDNA4.
 //
 // Work unit: a group of up to 4 * TPW consecutive query tiles of one pair (16
-// queries each, in pencil order).  A workgroup of four waves streams the union
-// of the group's candidate ranges (b's features in binned order) through an
-// LDS ring of four 64-position segments; wave w owns tiles w and w + 4.
-//   - Segments arrive by LDS DMA (global_load_lds): each wave fetches 16 of a
-//     segment's 64 descriptor rows (two loads of 16 bytes per lane, eight lanes
-//     per 128-byte row, XOR-swizzled) and 16 of its coordinates and keys.  The
-//     rows' indices in b arrive two segments earlier in a ring of their own,
-//     so no loaded value passes through a register on its way to the stage.
-//   - Loads run three segments ahead of the computation, with one wait for the
-//     wave's own loads and one barrier per segment.  The workgroups on one XCD
-//     take the groups of one contiguous share in turn, so at any time they
-//     work on one or two pairs whose rows stay in that XCD's L2.  The next group's query
-//     records and first row indices are loaded while the current group ends.
-//   - Each tile walks its own candidate range in steps of 16 positions,
-//     aligned to 16 so that no step crosses a segment.  A step's rows are the A
-//     operand of v_mfma_i32_16x16x64_i8 and the tile's negated query rows the
-//     resident B operand: two MFMAs give -q.c for 16 candidates x 16 queries,
-//     exact in int32 (bytes 0..127 fit int8, 128 * 127^2 < 2^31).
+// queries each, in pencil order).  A workgroup of four waves loads the union
+// of the group's candidate ranges (b's features in binned order, up to 256
+// positions at a time) into one LDS buffer, then each wave runs its own tiles
+// over their ranges without further synchronisation.
+//   - The buffer is filled by LDS DMA (global_load_lds): wave w fetches the
+//     16-position blocks w, w + 4, ... (two 16-byte loads per lane for a
+//     block's 16 descriptor rows, eight lanes per 128-byte row, XOR-swizzled,
+//     and 16 of its coordinates and keys).  The rows' indices in b arrive one
+//     group earlier in an index buffer of their own, so no loaded value passes
+//     through a register on its way to LDS.
+//   - Per group: one wait and one barrier before the buffer is read, one
+//     barrier before it is refilled.  The next group's row indices and query
+//     records load while the current group computes.  The workgroups on one
+//     XCD take the groups of one contiguous share in turn, so at any time they
+//     work on one or two pairs whose rows stay in that XCD's L2.
+//   - Wave w owns tiles w and 2 * 4 - 1 - w (when a group has eight), which
+//     balances the waves of a group whose range lengths drift along it.
+//   - Each tile walks its candidate range in steps of 16 positions aligned to
+//     16.  A step's rows are the A operand of v_mfma_i32_16x16x64_i8 and the
+//     tile's negated query rows the resident B operand: two MFMAs give -q.c
+//     for 16 candidates x 16 queries, exact in int32 (bytes 0..127 fit int8,
+//     128 * 127^2 < 2^31).  The next step's operands are read from LDS before
+//     the current step's fold.
 //   - Each lane then holds one query and 4 candidates.  It runs the band test
 //     of eqs. (2)-(3) in FP32 on centred coordinates and folds in-band keys
 //         key = ((||c||^2 - 2 q.c + 2^21) << 10) | (position mod 1024)
 //     into its two smallest with one v_med3_u32 and one v_min_u32.
 //   - Slots whose FP32 distance lies within the margin of d are queued in LDS
 //     with their exact key and index in b, and decided in FP64 when the
-//     group's stream ends (no global load stalls the stream).
+//     group's tiles are done.
 // The key orders equal distances by binned position, not by index in b; when
 // a query's smallest distance is shared, an exact pass picks the lowest index
 // among the tied candidates, so results equal the definition.  Results hold
@@ -47,15 +52,19 @@ typedef const __attribute__((address_space(1))) int32_t g_i32;
 typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int kWaves = kMatchWaves;           // waves per workgroup
-constexpr int kSeg = 64;                      // positions per ring segment
-constexpr int kRing = 4;                      // segments of rows and metadata in LDS
-constexpr int kRingPos = kRing * kSeg;
-constexpr int kJRing = 6;                     // segments of row indices in LDS (per parity)
-constexpr int kRowsPerWave = kSeg / kWaves;   // 16 rows of a segment per wave
+#ifndef SFM_MATCH_BUF
+#define SFM_MATCH_BUF 256
+#endif
+constexpr int kBuf = SFM_MATCH_BUF;           // candidate positions one buffer fill holds (power of two)
+constexpr int kBlock = 16;                    // positions per DMA block (one step)
+constexpr int kBlocks = kBuf / kBlock;        // blocks of a buffer fill
+constexpr int kBlocksPerWave = kBlocks / kWaves;
 constexpr int kBorderCap = 32;                // queued FP64 decisions per wave and group
-constexpr int kRowLoads = 5;                  // loads per wave for one segment's rows + metadata
-static_assert(kRowsPerWave == 16, "each wave fetches 16 rows and 16 metadata words");
-static_assert(kQueryTile == 16, "one MFMA column block of queries per tile");
+static_assert(kBlocksPerWave * kWaves == kBlocks, "blocks are dealt evenly to the waves");
+static_assert(kBlocksPerWave * kBlock <= 64, "one 64-lane load fetches a wave's row indices");
+static_assert((kBuf & (kBuf - 1)) == 0, "buffer offsets wrap with a mask");
+static_assert(kQueryTile == kBlock, "one MFMA column block of queries per tile");
+static_assert(kBuf <= kChunk, "a tile's steps in one fill fit one key chunk");
 constexpr uint32_t kKeyDistInf = kKeyInf >> kPosBits;
 
 // Epipolar distance of eqs. (2)-(3) on centred FP32 coordinates,
@@ -108,17 +117,18 @@ __device__ inline int32_t row_dist(const uint8_t* p, const uint8_t* q, int32_t n
 __device__ __forceinline__ nv4u gload16(const void* p) { return *(g_nv4u*)p; }
 
 // ---------------------------------------------------------------------------
-// LDS of a workgroup (40 KB: four workgroups per CU): the ring of segments
-// (rows XOR-swizzled: chunk c of ring position r at (c ^ (r & 7)) * 16 within
-// the row), two rings of row indices (the current group's and the next
-// group's) and the queues of FP64 decisions.
+// LDS of a workgroup (40 KB: four workgroups per CU): one buffer fill of
+// candidates (rows XOR-swizzled: chunk c of buffer position r at
+// (c ^ (r & 7)) * 16 within the row), the row indices of two groups (each
+// wave's blocks together, block w + 4 k at 16 k) and the queues of FP64
+// decisions.
 // ---------------------------------------------------------------------------
 struct MatchLds {
-  uint8_t rows[kRingPos * kDescBytes];
-  float x[kRingPos];
-  float y[kRingPos];
-  uint32_t nc[kRingPos];
-  int32_t j[2][kJRing * kSeg];
+  uint8_t rows[kBuf * kDescBytes];
+  float x[kBuf];
+  float y[kBuf];
+  uint32_t nc[kBuf];
+  int32_t j[2][kWaves][kBlocksPerWave * kBlock];
   uint4 queue[kWaves][kBorderCap];   // {key, rel. position << 7 | tile << 6 | lane, j, -}
 };
 static_assert(sizeof(MatchLds) <= 40960, "four workgroups per CU");
@@ -163,100 +173,80 @@ __device__ __forceinline__ void dma4(const void* src, uint32_t lds_off) {
 }
 #pragma clang diagnostic pop
 
-// One pair's binned candidates, indexed by pair position, as one group
-// streams them.
+// One pair's binned candidates as one group reads them, by position
+// relative to `base` (the group's first position rounded down to 16).
 struct Stream {
   const float* x;
   const float* y;
   const uint32_t* nc;
   const int32_t* j;
   const uint8_t* b_desc;
-  int32_t base;             // pair position of segment 0 (group start rounded down to 16)
+  int32_t base;             // pair position of relative position 0
   int32_t last;             // last readable pair position (n_b plus padding, minus 1)
-  int32_t nsc;              // segments of the stream (steps are aligned to 16: none crosses one)
+  int32_t len;              // positions to read, a multiple of 16 (0: none)
   uint32_t lds;             // LDS offset of the workgroup's MatchLds
-  int32_t jpar;             // which index ring the group uses
 };
 
 __device__ __forceinline__ Stream make_stream(const BatchView& v, const TileGroup& G,
-                                              const MatchLds& L, int32_t jpar) {
+                                              const MatchLds& L) {
   Stream s;
   s.x = v.cand_x + G.c_off;
   s.y = v.cand_y + G.c_off;
   s.nc = v.cand_nc + G.c_off;
   s.j = v.cand_j + G.c_off;
   s.b_desc = G.b_desc;
-  s.base = G.s_begin & ~(kQueryTile - 1);
+  s.base = G.s_begin & ~(kBlock - 1);
   s.last = G.nb + kCandPad - 1;
-  const bool any = G.s_end > G.s_begin;
-  s.nsc = any ? (G.s_end - s.base + kSeg - 1) / kSeg : 0;
+  s.len = G.s_end > G.s_begin ? ((G.s_end - s.base + kBlock - 1) & ~(kBlock - 1)) : 0;
   s.lds = uint32_t(reinterpret_cast<uintptr_t>((lds_void*)&L));
-  s.jpar = jpar;
   return s;
 }
 
-__device__ __forceinline__ int jring_index(const Stream& s, int32_t k) {
-  return s.jpar * (kJRing * kSeg) + (k % kJRing) * kSeg;
+// The row indices of this wave's blocks of the fill starting at relative
+// position f into index buffer `par`: one 4-byte load (lane l:
+// block w + 4 (l >> 4), position l & 15; blocks past the stream load a
+// clamped position that is never used).
+__device__ __forceinline__ void issue_j(const Stream& s, int32_t f, int par, int w, int lane) {
+  if (kBlocksPerWave * kBlock < 64 && lane >= kBlocksPerWave * kBlock) return;
+  const int32_t p = min(s.base + f + kBlock * (w + kWaves * (lane >> 4)) + (lane & 15), s.last);
+  dma4(s.j + p, s.lds + uint32_t(offsetof(MatchLds, j)) +
+                    4u * uint32_t((par * kWaves + w) * kBlocksPerWave * kBlock));
 }
 
-// Segment k's row indices of this wave (its 16 positions) into the index
-// ring: one 4-byte load on 16 lanes.
-__device__ __forceinline__ void issue_j(const Stream& s, int32_t k, int w, int lane) {
-  if (lane < kRowsPerWave) {
-    const int32_t p = min(s.base + kSeg * k + kRowsPerWave * w + lane, s.last);
-    dma4(s.j + p, s.lds + uint32_t(offsetof(MatchLds, j)) +
-                      4u * uint32_t(jring_index(s, k) + kRowsPerWave * w));
-  }
-}
-
-// Segment k's rows and metadata of this wave into ring slot k mod 4: two
-// 16-byte loads per lane (lane l: row 8t + (l >> 3) of the wave's 16, chunk
-// (l & 7) ^ (row & 7), landing at slot l & 7 of the row) and three 4-byte
-// loads on 16 lanes.  The rows' indices come from the index ring (loaded
-// earlier by this wave and complete).
-__device__ __forceinline__ void issue_rows(const Stream& s, const MatchLds& L, int32_t k, int w,
-                                           int lane) {
-  const int slot = k % kRing;
-  const int32_t* jr_base = &L.j[0][0] + jring_index(s, k) + kRowsPerWave * w;
+// Rows and metadata of this wave's blocks of the fill starting at relative
+// position f (nblk blocks): per block two 16-byte loads per lane (lane l: row
+// 8 t + (l >> 3) of the block, chunk (l & 7) ^ (row & 7), landing at slot
+// l & 7 of the row) and three 4-byte loads on 16 lanes.  The rows' indices
+// come from index buffer `par` (loaded earlier by this wave and complete).
+__device__ __forceinline__ void issue_rows(const Stream& s, const MatchLds& L, int32_t f,
+                                           int32_t nblk, int par, int w, int lane) {
+  const int32_t* jw = &L.j[par][w][0];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int rr = 8 * t + (lane >> 3);
-    const int32_t jr = jr_base[rr];
-    const int c = (lane & 7) ^ (rr & 7);
-    dma16(s.b_desc + int64_t(jr) * kDescBytes + 16 * c,
-          s.lds + uint32_t(offsetof(MatchLds, rows)) +
-              uint32_t((slot * kSeg + kRowsPerWave * w + 8 * t) * kDescBytes));
-  }
-  if (lane < kRowsPerWave) {
-    const int32_t p = min(s.base + kSeg * k + kRowsPerWave * w + lane, s.last);
-    const uint32_t o = 4u * uint32_t(slot * kSeg + kRowsPerWave * w);
-    dma4(s.x + p, s.lds + uint32_t(offsetof(MatchLds, x)) + o);
-    dma4(s.y + p, s.lds + uint32_t(offsetof(MatchLds, y)) + o);
-    dma4(s.nc + p, s.lds + uint32_t(offsetof(MatchLds, nc)) + o);
-  }
-}
-
-// Waits for segment s and the row indices of segment s + 3.  Iteration t
-// issues the indices of segment t + 5, then the rows of t + 3 (kRowLoads
-// loads), so what may still be in flight are the rows of s + 1, the indices
-// of s + 4 and the rows of s + 2, those that exist (n segments).
-__device__ __forceinline__ void wait_segment(int32_t s, int32_t n) {
-  if (s + 3 < n) {
-    if (s + 4 < n)
-      wait_loads<2 * kRowLoads + 1>();
-    else
-      wait_loads<2 * kRowLoads>();
-  } else if (s + 2 < n) {
-    wait_loads<2 * kRowLoads>();
-  } else if (s + 1 < n) {
-    wait_loads<kRowLoads>();
-  } else {
-    wait_loads<0>();
+  for (int k = 0; k < kBlocksPerWave; ++k) {
+    const int32_t b = w + kWaves * k;
+    if (b >= nblk) break;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int rr = 8 * t + (lane >> 3);
+      const int32_t jr = jw[kBlock * k + rr];
+      const int c = (lane & 7) ^ (rr & 7);
+      dma16(s.b_desc + int64_t(jr) * kDescBytes + 16 * c,
+            s.lds + uint32_t(offsetof(MatchLds, rows)) +
+                uint32_t((kBlock * b + 8 * t) * kDescBytes));
+    }
+    if (lane < kBlock) {
+      const int32_t p = min(s.base + f + kBlock * b + lane, s.last);
+      const uint32_t o = 4u * uint32_t(kBlock * b);
+      dma4(s.x + p, s.lds + uint32_t(offsetof(MatchLds, x)) + o);
+      dma4(s.y + p, s.lds + uint32_t(offsetof(MatchLds, y)) + o);
+      dma4(s.nc + p, s.lds + uint32_t(offsetof(MatchLds, nc)) + o);
+    }
   }
 }
 
 // A group record read with scalar loads (its index is uniform).
 typedef const __attribute__((address_space(4))) v4i c_v4i;
+typedef const __attribute__((address_space(4))) int32_t c_i32;
 __device__ __forceinline__ TileGroup load_group(const TileGroup* groups, int32_t g) {
   union {
     v4i w[sizeof(TileGroup) / 16];
@@ -268,27 +258,31 @@ __device__ __forceinline__ TileGroup load_group(const TileGroup* groups, int32_t
   return u.t;
 }
 
+// Tile k of wave w in a group of 4 * TPW tiles.
+template <int TPW>
+__device__ __forceinline__ int32_t tile_of(int w, int k) {
+  return k == 0 ? w : 2 * kWaves - 1 - w;
+}
+
 // The first stage of a group: this wave's query records (in registers) and
-// the row indices of its first three segments (into index ring jpar).
+// the row indices of its blocks of the first fill (into index buffer par).
 template <int TPW>
 struct GroupStart {
   nv4u qu[TPW];
 };
 template <int TPW>
 __device__ __forceinline__ GroupStart<TPW> start_group(const BatchView& v, const TileGroup& G,
-                                                       const MatchLds& L, int32_t jpar, int w,
+                                                       const MatchLds& L, int par, int w,
                                                        int lane) {
   GroupStart<TPW> st;
   const int col = lane & (kQueryTile - 1);
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
-    const int32_t qs = (G.tile0 + w + kWaves * k) * kQueryTile + col;
+    const int32_t qs = (G.tile0 + tile_of<TPW>(w, k)) * kQueryTile + col;
     st.qu[k] = gload16(v.qrec + G.q_off + min(qs, G.na - 1));
   }
-  const Stream s = make_stream(v, G, L, jpar);
-  if (s.nsc > 0) issue_j(s, 0, w, lane);
-  if (s.nsc > 1) issue_j(s, 1, w, lane);
-  if (s.nsc > 2) issue_j(s, 2, w, lane);
+  const Stream s = make_stream(v, G, L);
+  issue_j(s, 0, par, w, lane);
   return st;
 }
 
@@ -484,43 +478,45 @@ __device__ __forceinline__ void close_chunk(Tile& T, int32_t c0p, int32_t c1p) {
 }
 
 // One group: up to 4 * TPW query tiles (TPW per wave) against their candidate
-// ranges, streamed through the LDS ring.  `gs` holds the group's first stage
-// (issued by the previous group or the kernel's start); before its epilogue
-// the group issues the first stage of group gn (if gn >= 0) into the other
-// index ring.
+// ranges, read from the LDS buffer.  `gs` holds the group's query records and
+// its first fill's row indices are in index buffer `par` (both issued by the
+// previous group or the kernel's start).  The group issues the first stage of
+// group gn (if gn >= 0) into the other index buffer.
 template <bool kKeepCounts, int TPW>
-__device__ __forceinline__ void match_group(const BatchView& v, const TileGroup& G,
-                                            const GroupStart<TPW>& gs, int32_t jpar,
-                                            int32_t gn, GroupStart<TPW>& gsn, MatchLds& L, int w,
-                                            int lane, WaveStats& ws) {
+__device__ __forceinline__ void match_group(const BatchView& v, const TileGroup& G, int32_t g,
+                                            const GroupStart<TPW>& gs, int par, int32_t gn,
+                                            GroupStart<TPW>& gsn, MatchLds& L, int w, int lane,
+                                            WaveStats& ws) {
   const int col = lane & (kQueryTile - 1), rg = lane >> 4;
   const float lo = G.band_lo, hi = G.band_hi;
-  const Stream s = make_stream(v, G, L, jpar);
+  const Stream s = make_stream(v, G, L);
+  const int32_t nfill = (s.len + kBuf - 1) / kBuf;
 
-  // Tile ranges (uniform); the first stage is complete after this wait.
+  // Tile ranges (uniform, relative to s.base; steps start at rb + 16 i).
   Tile T[TPW];
-  int32_t rb[TPW], re[TPW], c0[TPW];   // tile range and chunk start (relative)
+  int32_t rb[TPW], re[TPW], c0[TPW];
   bool qv[TPW];
+  // The record's tile ranges by scalar load at the uniform tile index.
+  c_i32* gw = (c_i32*)(v.groups + g);
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
-    const int32_t tidx = w + kWaves * k;
+    const int32_t tidx = tile_of<TPW>(w, k);
     const int32_t qs = (G.tile0 + tidx) * kQueryTile + col;
     qv[k] = tidx < G.ntiles && qs < G.na;
-    int32_t tb = 0, te = 0;
-#pragma unroll
-    for (int t = 0; t < kMaxGroupTiles; ++t) {   // selects: a dynamic index would use scratch
-      tb = tidx == t ? G.t_begin[t] : tb;
-      te = tidx == t ? G.t_end[t] : te;
-    }
+    int32_t tb = gw[offsetof(TileGroup, t_begin) / 4 + tidx];
+    int32_t te = gw[offsetof(TileGroup, t_end) / 4 + tidx];
     if (tidx >= G.ntiles || te <= tb) tb = te = s.base;
-    rb[k] = (tb & ~(kQueryTile - 1)) - s.base;
+    rb[k] = (tb & ~(kBlock - 1)) - s.base;
     re[k] = te - s.base;
     c0[k] = rb[k];
   }
-  wait_loads<0>();
 
-  // Query rows, norms and keypoints, then rows and metadata of segments 0..2
-  // with the indices of segments 3 and 4 (the pipeline's first three stages).
+  // This wave's own index loads (and everything before them) are complete;
+  // the barrier also ends every wave's reads of the previous group's fill.
+  wait_loads<0>();
+  barrier();
+  const int32_t nblk0 = min(s.len, kBuf) / kBlock;
+  issue_rows(s, L, 0, nblk0, par, w, lane);
   nv4u qr[TPW][2];
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
@@ -533,13 +529,19 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
     qr[k][1] = gload16(qrow + 64);
     T[k].nq = ((g_i32*)G.a_norm)[T[k].i];
   }
-  if (s.nsc > 0) {
-    issue_rows(s, L, 0, w, lane);
-    if (3 < s.nsc) issue_j(s, 3, w, lane);
-    if (1 < s.nsc) issue_rows(s, L, 1, w, lane);
-    if (4 < s.nsc) issue_j(s, 4, w, lane);
-    if (2 < s.nsc) issue_rows(s, L, 2, w, lane);
-  }
+  // The next group's first stage: TPW query records and one index load.
+  const bool next = gn >= 0;
+  if (next) gsn = start_group<TPW>(v, load_group(v.groups, gn), L, par ^ 1, w, lane);
+  // This wave's fill, then (after the barrier) every wave's; then the query rows.
+  if (next)
+    wait_loads<3 * TPW + TPW + 1>();
+  else
+    wait_loads<3 * TPW>();
+  barrier();
+  if (next)
+    wait_loads<TPW + 1>();
+  else
+    wait_loads<0>();
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
 #pragma unroll
@@ -559,48 +561,59 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
   bool overflow = false;   // more than kBorderCap: the wave's tiles are recomputed exactly
   uint32_t nsteps = 0;     // 16 x 16 steps evaluated
 
-  for (int32_t sg = 0; sg < s.nsc; ++sg) {
-    wait_segment(sg, s.nsc);
-    barrier();
-    if (sg + 5 < s.nsc) issue_j(s, sg + 5, w, lane);
-    if (sg + 3 < s.nsc) issue_rows(s, L, sg + 3, w, lane);
-
-    const int32_t seg_lo = kSeg * sg;
+  for (int32_t fi = 0; fi < nfill; ++fi) {
+    const int32_t f = kBuf * fi;   // relative position of the fill's start
+    if (fi > 0) {
+      // A range longer than one fill: every wave is done with the previous
+      // fill; load this one's indices, then its rows.
+      barrier();
+      issue_j(s, f, par, w, lane);
+      wait_loads<0>();
+      issue_rows(s, L, f, min(s.len - f, kBuf) / kBlock, par, w, lane);
+      wait_loads<0>();
+      barrier();
+    }
 #pragma unroll
     for (int k = 0; k < TPW; ++k) {
       Tile& t = T[k];
-      // The tile's steps that start in this segment: p0, p0 + 16, ... < pe
-      // (steps start at rb + 16 i).
-      const int32_t p0 = max(rb[k], seg_lo + (rb[k] & (kQueryTile - 1)));
-      const int32_t pe = min(re[k], seg_lo + kSeg);
+      const int32_t p0 = max(rb[k], f);
+      const int32_t pe = min(re[k], f + kBuf);
       if (p0 >= pe) continue;
-      const int32_t n = (pe - p0 + kQueryTile - 1) / kQueryTile;
+      const int32_t n = (pe - p0 + kBlock - 1) / kBlock;
       nsteps += uint32_t(n);
-      // Keys hold positions mod 1024: a chunk closes before a segment whose
+      // Keys hold positions mod 1024: a chunk closes before a fill whose
       // steps would take it past 1024 positions.
-      if (p0 + kQueryTile * n - c0[k] > kChunk) {
+      if (p0 + kBlock * n - c0[k] > kChunk) {
         close_chunk(t, s.base + c0[k], s.base + p0);
         c0[k] = p0;
       }
-      // A operand: ring row (p + col) & 255 of the step, k-slices rg and
-      // rg + 4 (chunk slots rg ^ (row & 7) and that ^ 4).  Metadata: the four
-      // candidates 4 rg .. 4 rg + 3 of the step.  Both advance by 16 rows a
-      // step, modulo the ring.
-      uint32_t oa = uint32_t(((p0 + col) & (kRingPos - 1)) * kDescBytes +
-                             ((rg ^ ((p0 + col) & 7)) << 4));
-      uint32_t om = uint32_t(((p0 + 4 * rg) & (kRingPos - 1)) * 4);
+      // A operand: buffer row q + col of the step, k-slices rg and rg + 4
+      // (chunk slots rg ^ (row & 7) and that ^ 4).  Metadata: the four
+      // candidates 4 rg .. 4 rg + 3 of the step.  Both advance by 16 rows.
+      const int32_t q0 = p0 - f;
+      uint32_t oa = uint32_t((q0 + col) * kDescBytes + ((rg ^ ((q0 + col) & 7)) << 4));
+      uint32_t om = uint32_t((q0 + 4 * rg) * 4);
+      // The first step's operands; each step reads the next one's before
+      // its own fold (the read after the last step wraps and is unused).
+      v4i na0 = *reinterpret_cast<const v4i*>(&L.rows[oa]);
+      v4i na1 = *reinterpret_cast<const v4i*>(&L.rows[oa ^ 64u]);
+      float4 nxs = reinterpret_cast<const float4*>(L.x)[om >> 4];
+      float4 nys = reinterpret_cast<const float4*>(L.y)[om >> 4];
+      uint4 nns = reinterpret_cast<const uint4*>(L.nc)[om >> 4];
       for (int32_t i = 0; i < n; ++i) {
-        const v4i a0 = *reinterpret_cast<const v4i*>(&L.rows[oa]);
-        const v4i a1 = *reinterpret_cast<const v4i*>(&L.rows[oa ^ 64u]);
         v4i acc = {0, 0, 0, 0};
-        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, t.bq[0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, t.bq[1], acc, 0, 0, 0);
-        const float4 xs = reinterpret_cast<const float4*>(L.x)[om >> 4];
-        const float4 ys = reinterpret_cast<const float4*>(L.y)[om >> 4];
-        const uint4 ns = reinterpret_cast<const uint4*>(L.nc)[om >> 4];
-        const float xv[4] = {xs.x, xs.y, xs.z, xs.w};
-        const float yv[4] = {ys.x, ys.y, ys.z, ys.w};
-        const uint32_t nv[4] = {ns.x, ns.y, ns.z, ns.w};
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(na0, t.bq[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(na1, t.bq[1], acc, 0, 0, 0);
+        const float xv[4] = {nxs.x, nxs.y, nxs.z, nxs.w};
+        const float yv[4] = {nys.x, nys.y, nys.z, nys.w};
+        const uint32_t nv[4] = {nns.x, nns.y, nns.z, nns.w};
+        oa = (oa + kBlock * kDescBytes) & (kBuf * kDescBytes - 1);
+        om = (om + 4 * kBlock) & (4 * kBuf - 1);
+        na0 = *reinterpret_cast<const v4i*>(&L.rows[oa]);
+        na1 = *reinterpret_cast<const v4i*>(&L.rows[oa ^ 64u]);
+        nxs = reinterpret_cast<const float4*>(L.x)[om >> 4];
+        nys = reinterpret_cast<const float4*>(L.y)[om >> 4];
+        nns = reinterpret_cast<const uint4*>(L.nc)[om >> 4];
         unsigned long long bm[4];
         uint32_t keys[4];
 #pragma unroll
@@ -620,8 +633,8 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
         if (bm[0] | bm[1] | bm[2] | bm[3]) {
           // Rare: queue the step's slots within the margin of d, with their
           // exact keys and indices in b, for the FP64 decision after the
-          // stream (the index ring still holds this segment and the next).
-          const int32_t p = p0 + kQueryTile * i;
+          // group's tiles (the index buffer holds the whole fill).
+          const int32_t p = p0 + kBlock * i;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             if (!bm[e]) continue;
@@ -635,8 +648,9 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
                                           uint32_t(bm[e] >> 32),
                                           __builtin_amdgcn_mbcnt_lo(uint32_t(bm[e]), 0)));
             if ((bm[e] >> lane) & 1ull) {
-              const int32_t pr = p + 4 * rg + e;
-              const int32_t jq = (&L.j[0][0])[jring_index(s, pr >> 6) + (pr & (kSeg - 1))];
+              const int32_t pr = p + 4 * rg + e;        // relative position
+              const int32_t bq = (pr - f) >> 4;          // block of the fill
+              const int32_t jq = L.j[par][bq & (kWaves - 1)][kBlock * (bq >> 2) + (pr & 15)];
               L.queue[w][idx] = make_uint4(
                   keys[e], (uint32_t(pr) << 7) | (uint32_t(k) << 6) | uint32_t(lane),
                   uint32_t(jq), 0u);
@@ -644,16 +658,9 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
             nbq += nb;
           }
         }
-        oa = (oa + kQueryTile * kDescBytes) & (kRingPos * kDescBytes - 1);
-        om = (om + 4 * kQueryTile) & (4 * kRingPos - 1);
       }
     }
   }
-  wait_loads<0>();
-  // Every wave is past the ring: the next group's first stage may load now
-  // (into the other index ring), under this group's epilogue.
-  barrier();
-  if (gn >= 0) gsn = start_group<TPW>(v, load_group(v.groups, gn), L, jpar ^ 1, w, lane);
 
   // The last chunk of every tile, then the queued FP64 decisions (one per
   // lane), folded into the result of the lane with rg = 0 of their query.
@@ -774,7 +781,6 @@ void match_kernel(BatchView v) {
   // The wave index is uniform: readfirstlane lets the compiler keep
   // everything derived from it (tile ranges, queue counts) in SGPRs.
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  typedef const __attribute__((address_space(4))) int32_t c_i32;
   // Workgroup k runs on XCD x = k mod 8 (workgroups are dealt to the XCDs
   // round-robin) and takes every W-th group of share x, W being the number of
   // workgroups on that XCD.
@@ -786,14 +792,14 @@ void match_kernel(BatchView v) {
   WaveStats ws = {-1, 0, 0, 0, 0, 0};
   if (g_first < g_end) {
     GroupStart<TPW> gs = start_group<TPW>(v, load_group(v.groups, g_first), lds, 0, wave, lane);
-    int32_t jpar = 0;
+    int par = 0;
     for (int32_t g = g_first; g < g_end; g += W) {
       const TileGroup G = load_group(v.groups, g);
       GroupStart<TPW> gsn;
-      match_group<kKeepCounts, TPW>(v, G, gs, jpar, g + W < g_end ? g + W : -1, gsn, lds, wave,
-                                    lane, ws);
+      match_group<kKeepCounts, TPW>(v, G, g, gs, par, g + W < g_end ? g + W : -1, gsn, lds,
+                                    wave, lane, ws);
       gs = gsn;
-      jpar ^= 1;
+      par ^= 1;
     }
   }
   flush_stats(v, ws, lane);
