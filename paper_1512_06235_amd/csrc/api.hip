@@ -981,7 +981,6 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   if (grouped) HIP_TRY(ctx, grid_group_temp_bytes(int32_t(N), n_pairs, &temp_bytes));
   const size_t o_cross = o; o = align_up(o + (grouped ? N * 4 * sizeof(double) : 0));
   const size_t o_hit = o; o = align_up(o + (grouped ? N * sizeof(int32_t) : 0));
-  const size_t o_key = o; o = align_up(o + (grouped ? 2 * N * sizeof(unsigned long long) : 0));
   const size_t o_val = o; o = align_up(o + (grouped ? 2 * N * sizeof(int32_t) : 0));
   const size_t o_sten = o; o = align_up(o + (grouped ? 3 * N * sizeof(int32_t) : 0));
   const size_t o_temp = o; o = align_up(o + temp_bytes);
@@ -1038,8 +1037,6 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
     memset(&g, 0, sizeof g);
     g.cross = reinterpret_cast<double*>(ctx->ws + o_cross);
     g.hit = reinterpret_cast<int32_t*>(ctx->ws + o_hit);
-    g.key[0] = reinterpret_cast<unsigned long long*>(ctx->ws + o_key);
-    g.key[1] = g.key[0] + N;
     g.val[0] = reinterpret_cast<int32_t*>(ctx->ws + o_val);
     g.val[1] = g.val[0] + N;
     g.seg_begin = reinterpret_cast<const int32_t*>(ctx->ws + o_seg);
@@ -1345,7 +1342,7 @@ int sfm_candidate_images(sfm_ctx* ctx, const int32_t* vis_off, const int32_t* vi
   if (!out) return fail(ctx, SFM_EINVAL, "out is NULL");
   if (n_images < 0 || n_images > kMaxCovisImages)
     return fail(ctx, SFM_EINVAL, "n_images must be in 0..4096");
-  if (n_points < 0 || int64_t(n_points) + 1 > covis_scan_limit())
+  if (n_points < 0 || int64_t(n_points) + 1 > scan_limit())
     return fail(ctx, SFM_EINVAL, "n_points out of range");
   if (nnz < 0 || nnz > INT32_MAX) return fail(ctx, SFM_EINVAL, "nnz must be in 0..2^31-1");
   if (threshold < 0 || top_k < 0) return fail(ctx, SFM_EINVAL, "threshold and top_k must be >= 0");

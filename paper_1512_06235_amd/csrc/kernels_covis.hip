@@ -24,8 +24,6 @@ namespace sfm {
 namespace {
 
 constexpr int kCovisThreads = 1024;
-constexpr int kScanPer = 8;                          // items per thread of one scan block
-constexpr int kScanBlock = kCovisThreads * kScanPer; // items per scan block
 
 __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t n, int32_t value) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -54,79 +52,6 @@ __global__ __launch_bounds__(256) void covis_count_kernel(const int32_t* vis_off
       continue;
     }
     atomicAdd(&pt_count[p], 1);
-  }
-}
-
-// Exclusive scan of one block of kScanBlock items; block sums to `sums`.
-__global__ __launch_bounds__(kCovisThreads) void scan_block_kernel(const int32_t* in,
-                                                                   int32_t* out, int64_t n,
-                                                                   int32_t* sums) {
-  __shared__ int32_t wtot[kCovisThreads / 64];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int64_t base = int64_t(blockIdx.x) * kScanBlock + int64_t(t) * kScanPer;
-  int32_t v[kScanPer];
-  int32_t run = 0;
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    v[k] = base + k < n ? in[base + k] : 0;
-    run += v[k];
-  }
-  int32_t x = run;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) wtot[wv] = x;
-  __syncthreads();
-  int32_t before = 0;
-  for (int w = 0; w < wv; ++w) before += wtot[w];
-  int32_t acc = before + x - run;
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < n) out[base + k] = acc;
-    acc += v[k];
-  }
-  if (t == kCovisThreads - 1) sums[blockIdx.x] = before + x;
-}
-
-// In place exclusive scan of the block sums (one block; at most kScanBlock).
-__global__ __launch_bounds__(kCovisThreads) void scan_sums_kernel(int32_t* sums, int32_t nb) {
-  __shared__ int32_t wtot[kCovisThreads / 64];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  int32_t v[kScanPer];
-  int32_t run = 0;
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    const int32_t i = t * kScanPer + k;
-    v[k] = i < nb ? sums[i] : 0;
-    run += v[k];
-  }
-  int32_t x = run;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) wtot[wv] = x;
-  __syncthreads();
-  int32_t before = 0;
-  for (int w = 0; w < wv; ++w) before += wtot[w];
-  int32_t acc = before + x - run;
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    const int32_t i = t * kScanPer + k;
-    if (i < nb) sums[i] = acc;
-    acc += v[k];
-  }
-}
-
-// Adds each block's offset; also writes a copy (the scatter cursors).
-__global__ __launch_bounds__(256) void scan_add_kernel(int32_t* out, int64_t n,
-                                                       const int32_t* sums, int32_t* copy) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int32_t v = out[i] + sums[i / kScanBlock];
-    out[i] = v;
-    if (copy) copy[i] = v;
   }
 }
 
@@ -412,19 +337,9 @@ int32_t grid_for(int64_t n, int32_t per_block) {
   return int32_t(std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, 65535)));
 }
 
-// Exclusive scan of in[0..n) into out (n <= kScanBlock^2); `copy` may be NULL.
-void launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, int32_t* copy,
-                 hipStream_t st) {
-  const int32_t nb = int32_t((n + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(kCovisThreads), 0, st, in, out, n, sums);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kCovisThreads), 0, st, sums, nb);
-  hipLaunchKernelGGL(scan_add_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, out, n, sums,
-                     copy);
-}
-
 }  // namespace
 
-int64_t covis_scan_limit() { return int64_t(kScanBlock) * kScanBlock; }
+
 
 hipError_t launch_candidates(const CovisArgs& a, hipStream_t st) {
   const int64_t np1 = int64_t(a.n_points) + 1;
@@ -459,7 +374,8 @@ hipError_t launch_candidates(const CovisArgs& a, hipStream_t st) {
     if (a.n_images > 0)
       hipLaunchKernelGGL(covis_count_kernel, dim3(a.n_images), dim3(256), 0, st, a.vis_off,
                          a.vis_pts, a.nnz, a.n_points, a.pt_count, a.err);
-    launch_scan(a.pt_count, a.pt_off, np1, a.sums, a.cursor, st);
+    if (const hipError_t e = launch_scan(a.pt_count, a.pt_off, np1, false, a.sums, a.cursor, st); e != hipSuccess)
+      return e;
     if (a.n_images > 0) {
       hipLaunchKernelGGL(covis_scatter_kernel, dim3(a.n_images), dim3(256), 0, st, a.vis_off,
                          a.vis_pts, a.nnz, a.n_points, a.cursor, a.pt_imgs, a.err);
@@ -480,7 +396,8 @@ hipError_t launch_candidates(const CovisArgs& a, hipStream_t st) {
                        0, st, a.row_count, int64_t(a.n_images) + 1, 0);
     hipLaunchKernelGGL(pair_count_kernel, dim3(a.n_images), dim3(256), 0, st, a.bits, words,
                        a.row_count);
-    launch_scan(a.row_count, a.row_off, int64_t(a.n_images) + 1, a.sums, nullptr, st);
+    if (const hipError_t e = launch_scan(a.row_count, a.row_off, int64_t(a.n_images) + 1, false, a.sums, nullptr, st); e != hipSuccess)
+      return e;
     hipLaunchKernelGGL(pair_write_kernel, dim3(a.n_images), dim3(128), 0, st, a.bits, words,
                        a.row_off, a.n_images, a.pairs, a.n_pairs);
   } else if (a.pairs && a.n_pairs) {

@@ -18,7 +18,6 @@
 #include <algorithm>
 #include <cmath>
 
-#include <hipcub/hipcub.hpp>
 
 #include "sfm_internal.h"
 
@@ -363,14 +362,141 @@ __global__ __launch_bounds__(256) void grid_cross_kernel(GridView v, GroupView g
   g.val[0][t] = t;
 }
 
-// key[t] = component c of the crossings of position val[t]; lines without a
-// crossing sort last.
-__global__ __launch_bounds__(256) void grid_key_kernel(GroupView g, int c, const int32_t* val,
-                                                       unsigned long long* key) {
+// ---------------------------------------------------------------------------
+// Least-significant-digit radix sort of the positions by (pair, A.x, A.y,
+// B.x, B.y), the crossing components as 64-bit order-preserving keys (lines
+// without a crossing sort last) and the pair index as the most significant
+// key: 8-bit digits, least significant first, each pass a stable counting
+// sort, so equal keys keep position order.  A pass counts the digits of each
+// 2048-position tile, scans the counts (digit-major, so each digit's tiles
+// follow each other), then sorts every tile by the digit in LDS (eight
+// stable one-bit splits) and scatters it.
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortPer = 8;                              // positions per thread
+constexpr int kSortTile = kSortThreads * kSortPer;       // positions per tile
+constexpr int kRadix = 256;
+
+// Digit `byte` of the sort key `comp` (0..3: crossing component, 4: pair) of
+// original position s.
+__device__ __forceinline__ uint32_t sort_digit(const GridView& v, const GroupView& g, int32_t s,
+                                               int comp, int byte) {
+  unsigned long long key;
+  if (comp < 4)
+    key = g.hit[s] ? sortable(g.cross[4 * int64_t(s) + comp]) : ~0ull;
+  else
+    key = static_cast<unsigned long long>(pair_of(g.seg_begin, v.n_pairs, s));
+  return uint32_t(key >> (8 * byte)) & (kRadix - 1);
+}
+
+// counts[d * ntiles + tile]: positions of the tile with digit d.
+__global__ __launch_bounds__(kSortThreads) void sort_count_kernel(GridView v, GroupView g,
+                                                                  const int32_t* val, int comp,
+                                                                  int byte, int32_t* counts,
+                                                                  int32_t ntiles) {
+  __shared__ int32_t h[kRadix];
+  const int t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const int32_t base = blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortPer; ++k) {
+    const int32_t i = base + k * kSortThreads + t;
+    if (i < g.n) atomicAdd(&h[sort_digit(v, g, val[i], comp, byte)], 1);
+  }
+  __syncthreads();
+  counts[int64_t(t) * ntiles + blockIdx.x] = h[t];
+}
+
+// Exclusive scan of one value per thread over the block; returns the total.
+__device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t& total, int32_t* wsum) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int32_t inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int32_t before = 0;
+  total = 0;
+  for (int w = 0; w < kSortThreads / 64; ++w) {
+    before += w < wv ? wsum[w] : 0;
+    total += wsum[w];
+  }
+  __syncthreads();
+  return before + inc - x;
+}
+
+// One pass: the tile sorted stably by the digit, then every position written
+// at (scanned count of its digit and tile) + (its rank among the tile's
+// positions with that digit).
+__global__ __launch_bounds__(kSortThreads) void sort_scatter_kernel(
+    GridView v, GroupView g, const int32_t* val_in, int32_t* val_out, int comp, int byte,
+    const int32_t* offsets, int32_t ntiles) {
+  __shared__ int32_t sval[kSortTile];
+  __shared__ uint8_t sdig[kSortTile];
+  __shared__ int32_t dstart[kRadix];
+  __shared__ int32_t wsum[kSortThreads / 64];
+  const int t = threadIdx.x;
+  const int32_t base = blockIdx.x * kSortTile;
+  const int32_t cnt = min(kSortTile, g.n - base);
+  // Thread t holds tile positions kSortPer t .. kSortPer t + kSortPer - 1.
+  // Past the end: digit 255 and last in order, so they stay behind every
+  // real position and are never written.
+  int32_t vals[kSortPer];
+  uint32_t dig[kSortPer];
+#pragma unroll
+  for (int k = 0; k < kSortPer; ++k) {
+    const int32_t i = kSortPer * t + k;
+    vals[k] = i < cnt ? val_in[base + i] : 0;
+    dig[k] = i < cnt ? sort_digit(v, g, vals[k], comp, byte) : kRadix - 1;
+  }
+  for (int bit = 0; bit < 8; ++bit) {
+    int32_t zeros = 0;
+#pragma unroll
+    for (int k = 0; k < kSortPer; ++k) zeros += ((dig[k] >> bit) & 1) ? 0 : 1;
+    int32_t total_zeros;
+    int32_t zb = block_excl_scan(zeros, total_zeros, wsum);   // zeros before this thread
+    const int32_t first = kSortPer * t;
+#pragma unroll
+    for (int k = 0; k < kSortPer; ++k) {
+      const bool one = (dig[k] >> bit) & 1;
+      const int32_t pos = one ? total_zeros + (first + k - zb) : zb;
+      zb += one ? 0 : 1;
+      sval[pos] = vals[k];
+      sdig[pos] = uint8_t(dig[k]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortPer; ++k) {
+      vals[k] = sval[kSortPer * t + k];
+      dig[k] = sdig[kSortPer * t + k];
+    }
+    __syncthreads();
+  }
+  // First tile position of each digit among the real positions.
+  dstart[t] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSortPer; ++k)
+    if (kSortPer * t + k < cnt) atomicAdd(&dstart[dig[k]], 1);
+  __syncthreads();
+  int32_t total;
+  const int32_t start = block_excl_scan(dstart[t], total, wsum);
+  dstart[t] = start;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSortPer; ++k) {
+    const int32_t i = kSortPer * t + k;
+    if (i < cnt)
+      val_out[offsets[int64_t(dig[k]) * ntiles + blockIdx.x] + (i - dstart[dig[k]])] = vals[k];
+  }
+}
+
+__global__ __launch_bounds__(256) void copy_i32_kernel(const int32_t* src, int32_t* dst,
+                                                       int32_t n) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.n) return;
-  const int32_t s = val[t];
-  key[t] = g.hit[s] ? sortable(g.cross[4 * int64_t(s) + c]) : ~0ull;
+  if (t < n) dst[t] = src[t];
 }
 
 __global__ __launch_bounds__(256) void grid_stencil_kernel(GridView v, GroupView g) {
@@ -471,42 +597,54 @@ int32_t blocks256(int32_t n) { return (n + 255) / 256; }
 
 }  // namespace
 
+// Radix-sort tile counts, then the scan's block sums (reused by the stencil
+// scan).
+static int32_t sort_tiles(int32_t n) { return (n + kSortTile - 1) / kSortTile; }
+
 hipError_t grid_group_temp_bytes(int32_t n, int32_t n_pairs, size_t* bytes) {
-  size_t sort_bytes = 0, scan_bytes = 0;
-  hipError_t e = hipcub::DeviceSegmentedRadixSort::SortPairs(
-      nullptr, sort_bytes, static_cast<const unsigned long long*>(nullptr),
-      static_cast<unsigned long long*>(nullptr), static_cast<const int32_t*>(nullptr),
-      static_cast<int32_t*>(nullptr), n, n_pairs, static_cast<const int32_t*>(nullptr),
-      static_cast<const int32_t*>(nullptr));
-  if (e != hipSuccess) return e;
-  e = hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, static_cast<const int32_t*>(nullptr),
-                                       static_cast<int32_t*>(nullptr), n);
-  *bytes = std::max(sort_bytes, scan_bytes);
-  return e;
+  (void)n_pairs;
+  const int64_t ncount = int64_t(kRadix) * sort_tiles(n);
+  if (ncount > scan_limit() || int64_t(n) > scan_limit()) return hipErrorInvalidValue;
+  *bytes = sizeof(int32_t) * size_t(ncount) + std::max(scan_temp_bytes(ncount), scan_temp_bytes(n));
+  return hipSuccess;
 }
 
 hipError_t launch_grid_group_prepare(const GridView& v, const GroupView& g, hipStream_t st) {
   if (g.n <= 0) return hipSuccess;
+  const int32_t ntiles = sort_tiles(g.n);
+  const int64_t ncount = int64_t(kRadix) * ntiles;
+  int32_t* counts = static_cast<int32_t*>(g.temp);
+  int32_t* sums = counts + ncount;
+  size_t need = 0;
+  hipError_t e = grid_group_temp_bytes(g.n, v.n_pairs, &need);
+  if (e != hipSuccess) return e;
+  if (g.temp_bytes < need) return hipErrorInvalidValue;
   hipLaunchKernelGGL(grid_cross_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, v, g);
-  // Least significant component first; each pass is a stable sort.
+  // Passes: every byte of components 3, 2, 1, 0, then the pair index's bytes.
+  int pair_bytes = 0;
+  while (pair_bytes < 4 && (int64_t(1) << (8 * pair_bytes)) < int64_t(v.n_pairs)) ++pair_bytes;
   int cur = 0;
-  for (int c = 3; c >= 0; --c) {
-    hipLaunchKernelGGL(grid_key_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, g, c,
-                       g.val[cur], g.key[0]);
-    size_t bytes = g.temp_bytes;
-    hipError_t e = hipcub::DeviceSegmentedRadixSort::SortPairs(
-        g.temp, bytes, g.key[0], g.key[1], g.val[cur], g.val[1 - cur], g.n, v.n_pairs,
-        g.seg_begin, g.seg_end, 0, 64, st);
-    if (e != hipSuccess) return e;
-    cur = 1 - cur;
+  for (int comp = 3; comp >= -1; --comp) {
+    const int key = comp >= 0 ? comp : 4;
+    const int nbytes = comp >= 0 ? 8 : pair_bytes;
+    for (int byte = 0; byte < nbytes; ++byte) {
+      hipLaunchKernelGGL(sort_count_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, v, g,
+                         g.val[cur], key, byte, counts, ntiles);
+      e = launch_scan(counts, counts, ncount, false, sums, nullptr, st);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(sort_scatter_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, v, g,
+                         g.val[cur], g.val[1 - cur], key, byte, counts, ntiles);
+      cur = 1 - cur;
+    }
   }
-  // Four passes end in val[0].
+  if (cur != 0)
+    hipLaunchKernelGGL(copy_i32_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, g.val[1],
+                       g.val[0], g.n);
   if (g.to_leader)
     hipLaunchKernelGGL(grid_stencil_leader_kernel, dim3(v.n_pairs), dim3(64), 0, st, v, g);
   else
     hipLaunchKernelGGL(grid_stencil_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, v, g);
-  size_t bytes = g.temp_bytes;
-  hipError_t e = hipcub::DeviceScan::InclusiveSum(g.temp, bytes, g.stencil, g.gid, g.n, st);
+  e = launch_scan(g.stencil, g.gid, g.n, true, sums, nullptr, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(grid_gstart_kernel, dim3(blocks256(g.n)), dim3(256), 0, st, g);
   return hipGetLastError();

@@ -18,7 +18,6 @@
 #include <algorithm>
 #include <cmath>
 
-#include <hipcub/hipcub.hpp>
 
 #include "sfm_internal.h"
 
@@ -221,9 +220,8 @@ hipError_t launch_tracks(int64_t n_nodes, const int32_t* edges, int64_t n_edges,
 }
 
 hipError_t triangulate_temp_bytes(int64_t n_nodes, size_t* bytes) {
-  *bytes = 0;
-  return hipcub::DeviceScan::ExclusiveSum(nullptr, *bytes, static_cast<const int32_t*>(nullptr),
-                                          static_cast<int32_t*>(nullptr), int(n_nodes));
+  *bytes = scan_temp_bytes(n_nodes);
+  return n_nodes > scan_limit() ? hipErrorInvalidValue : hipSuccess;
 }
 
 hipError_t launch_triangulate(int64_t n_nodes, const int32_t* label, const int32_t* node_image,
@@ -240,8 +238,8 @@ hipError_t launch_triangulate(int64_t n_nodes, const int32_t* label, const int32
   hipLaunchKernelGGL(fill_i32_kernel, grid, dim3(256), 0, st, fill, n_nodes);
   hipLaunchKernelGGL(tri_count_kernel, grid, dim3(256), 0, st, label, node_image, n_images,
                      n_nodes, cnt, err);
-  size_t bytes = temp_bytes;
-  hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, bytes, cnt, start, int(n_nodes), st);
+  if (temp_bytes < scan_temp_bytes(n_nodes)) return hipErrorInvalidValue;
+  hipError_t e = launch_scan(cnt, start, n_nodes, false, static_cast<int32_t*>(temp), nullptr, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(tri_scatter_kernel, grid, dim3(256), 0, st, label, node_image, n_images,
                      n_nodes, start, fill, members);

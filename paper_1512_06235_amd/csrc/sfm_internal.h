@@ -187,7 +187,15 @@ struct CovisArgs {
   int32_t* err;
 };
 hipError_t launch_candidates(const CovisArgs& a, hipStream_t st);
-int64_t covis_scan_limit();   // longest array the two-level scan handles
+
+// Device-wide prefix sums of int32 (kernels_scan.hip): out[i] = sum of in[0..i)
+// (exclusive) or in[0..i] (inclusive), in place allowed; `copy` (may be NULL)
+// receives the same values.  sums: scan_temp_bytes(n) bytes of scratch.
+// hipErrorInvalidValue for n > scan_limit().
+int64_t scan_limit();
+size_t scan_temp_bytes(int64_t n);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, bool inclusive,
+                       int32_t* sums, int32_t* copy, hipStream_t st);
 
 // Tracks and triangulation (kernels_tracks.hip).
 hipError_t launch_tracks(int64_t n_nodes, const int32_t* edges, int64_t n_edges, int32_t* label,
@@ -247,14 +255,13 @@ hipError_t launch_grid(const GridView& v, int64_t n_blocks, hipStream_t st);
 struct GroupView {
   double* cross;                 // 4 per position: A.x, A.y, B.x, B.y
   int32_t* hit;                  // 1 if the line crosses b's box
-  unsigned long long* key[2];    // sort keys, ping-pong
   int32_t* val[2];               // positions in sorted order, ping-pong (result in val[0])
   const int32_t* seg_begin;      // per pair: first position
   const int32_t* seg_end;        // per pair: one past the last
   int32_t* stencil;              // 1 where a group starts
   int32_t* gid;                  // inclusive scan of the stencil
   int32_t* gstart;               // per group: its first sorted position
-  void* temp;                    // library sort / scan storage
+  void* temp;                    // radix-sort counts and scan sums (grid_group_temp_bytes)
   size_t temp_bytes;
   int32_t n;
   int32_t to_leader;             // compare with the group's first line, not the previous one

@@ -171,3 +171,27 @@ def test_grid_grouped_equals_oracle(sfm):
     out = m.match(pairs, Fs, form="grid", emit_all=True)
     _check(out, images, pairs, Fs, grid_match(images, pairs, Fs))
     m.close()
+
+
+def test_grid_grouped_many_pairs_equals_oracle(sfm):
+    """More than 256 pairs in one grouped call: the grouping sort's pair key
+    spans two digits; per-query results and the group count equal the
+    oracle's."""
+    from oracle.grid import grid_match, query_groups
+    centers = [(20 * np.sin(a), 0.0, 20 * np.cos(a)) for a in np.deg2rad(np.linspace(-25, 25, 6))]
+    scene = scenes.make_multiview_scene(centers, 60, 140, seed=6)
+    images = [(scene.image(k).xy, scene.image(k).desc) for k in range(6)]
+    base = [(a, b) for a in range(6) for b in range(6) if a != b]
+    pairs = [(a, b, (2.0, 3.0, 4.0, 6.0)[i % 4]) for i, (a, b) in enumerate(base * 9)]
+    assert len(pairs) > 256
+    Fs = np.stack([scene.F(a, b) for a, b, _ in pairs])
+    m = sfm.Matcher().register(images)
+    sfm.sfm_set_grid_grouping(m.ctx, 2.0, False)
+    out = m.match(pairs, Fs, form="grid", emit_all=True)
+    want = grid_match(images, pairs, Fs, group_px=2.0, to_leader=False)
+    _check(out, images, pairs, Fs, want)
+    groups = sum(len(query_groups(images[a][0], images[b][0], Fs[p], 2.0, False)[1])
+                 for p, (a, b, _) in enumerate(pairs))
+    assert sfm.sfm_grid_groups(m.ctx) == groups
+    say(f"  grouped, {len(pairs)} pairs: {groups} groups")
+    m.close()
