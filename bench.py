@@ -52,10 +52,12 @@ def unique_bytes(images, pairs):
     return sum(136 * images[k][0].shape[0] for k in used)
 
 
-def algorithmic_bytes(images, pairs):
-    """Bytes the match step must read: 128-B descriptor + 8-B keypoint per
-    feature of both images of every pair."""
-    return sum(136 * (images[a][0].shape[0] + images[b][0].shape[0]) for a, b, _ in pairs)
+def algorithmic_bytes(images, pairs, matches=0):
+    """Bytes one match step must move: 128-B descriptor + 8-B keypoint per
+    feature of both images of every pair, 72 B of F per pair, and one 16-B
+    output row (query, match, D1, D2) per accepted match."""
+    feats = sum(136 * (images[a][0].shape[0] + images[b][0].shape[0]) for a, b, _ in pairs)
+    return feats + 72 * len(pairs) + 16 * int(matches)
 
 
 def source_digest(path=MATCH_SOURCE):
@@ -553,8 +555,8 @@ def main():
                     help="keep the default tuning (2 tiles per group, 8 features per bin)")
     ap.add_argument("--tuning", default=None, metavar="TILESxFEATURES",
                     help="use this tuning instead of autotuning, e.g. 2x4")
-    ap.add_argument("--serving-seconds", type=float, default=3.0)
-    ap.add_argument("--serving-rates", default="1000,5000",
+    ap.add_argument("--serving-seconds", type=float, default=20.0)
+    ap.add_argument("--serving-rates", default="200,1000,5000",
                     help="offered pair requests per second, comma-separated")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
@@ -643,8 +645,12 @@ def main():
         comparisons, matches, stats = step_totals()   # every step computes the same
     value = comparisons * args.steps / elapsed
     match_s = match_ms / 1e3 / max(1, nrec)
-    bytes_launch = algorithmic_bytes(images, pairs)
+    bytes_launch = algorithmic_bytes(images, pairs, matches)
     achieved_gbs = bytes_launch / match_s / 1e9
+    step_s = elapsed / args.steps
+    borderline = int(out.n_borderline[:len(pairs)].sum())
+    log("bench: FP32 band-test error against FP64 over the batch's evaluated slots")
+    fp32_err_px, fp32_err_slots = sfm.sfm_band_error(m.ctx, batch)
 
     # The same steps with the kernels replayed from a captured HIP graph.
     sfm.sfm_set_graph_replay(m.ctx, True)
@@ -723,7 +729,10 @@ def main():
                    "matches_per_step": matches, "form": "batched",
                    "slots_per_step": stats["slots"],
                    "useful_slot_fraction": comparisons / max(1, stats["slots"]),
-                   "tie_passes": stats["tie_passes"]},
+                   "tie_passes": stats["tie_passes"],
+                   "borderline_slots_per_step": borderline,
+                   "max_fp32_err_px": fp32_err_px,
+                   "fp32_err_slots_within_2d": fp32_err_slots},
         "tuning": tuning,
         "plain_form": plain,
         "graph_replay_ms_per_step": graph_elapsed / args.steps * 1e3,
@@ -734,6 +743,8 @@ def main():
                      "traffic": measured_traffic(sfm.sfm_get_tuning(m.ctx)),
                      "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": match_s * 1e3,
+                     "step_achieved": bytes_launch / step_s / 1e9,
+                     "step_frac": bytes_launch / step_s / 1e9 / HBM_PEAK_GBS,
                      "int8_mfma_frac": 256.0 * comparisons / match_s / 1e12 / INT8_PEAK_TOPS,
                      "unique_bytes_per_launch": unique_bytes(images, pairs),
                      "unique_frac": unique_bytes(images, pairs) / match_s / 1e9 / HBM_PEAK_GBS},
