@@ -158,6 +158,54 @@ def summarize_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_mi
     return "\n".join(lines) + "\n"
 
 
+def summarize_overlap(directory, command):
+    """Concurrency of kernels from a `rocprofv3 --kernel-trace` csv run: busy
+    time, time with two or more kernels running, and the match-kernel
+    launches that overlap a kernel of another queue (one sweep over the
+    start and end times)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
+    ev = []
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            q = r.get("Stream_Id") or r.get("Queue_Id") or "0"
+            ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), q,
+                       _kernel_key(r["Kernel_Name"]).startswith("match_kernel")))
+    marks = sorted([(s, 1, i) for i, (s, _, _, _) in enumerate(ev)] +
+                   [(e, 0, i) for i, (_, e, _, _) in enumerate(ev)])   # ends first at a tie
+    active, per_queue = set(), {}
+    overlapped = set()
+    busy = multi = 0
+    last = None
+    for t, kind, i in marks:
+        if last is not None and t > last and active:
+            busy += t - last
+            if len(active) >= 2:
+                multi += t - last
+            if len(per_queue) >= 2:
+                overlapped.update(k for k in active if ev[k][3])
+        q = ev[i][2]
+        if kind:
+            active.add(i)
+            per_queue[q] = per_queue.get(q, 0) + 1
+        else:
+            active.discard(i)
+            per_queue[q] -= 1
+            if not per_queue[q]:
+                del per_queue[q]
+        last = t
+    n_match = sum(1 for x in ev if x[3])
+    lines = ["kernel concurrency (rocprofv3 --kernel-trace)", f"command: {command}", "",
+             f"kernels: {len(ev)}", f"queues_or_streams: {len({x[2] for x in ev})}",
+             f"busy_us: {busy / 1e3:.1f}",
+             f"two_or_more_running_us: {multi / 1e3:.1f}",
+             f"two_or_more_fraction_of_busy: {multi / max(1, busy):.3f}",
+             f"match_kernel_launches: {n_match}",
+             f"match_kernel_launches_overlapping_another_queue: {len(overlapped)}"]
+    return "\n".join(lines) + "\n"
+
+
 def serving(sfm, rates, duration_s, log_fn):
     """Open-loop Poisson streams of single-pair requests on the 300-camera
     three-ring scene (covisible pairs, top 30 per image), served by
@@ -560,6 +608,10 @@ def main():
                     help="offered pair requests per second, comma-separated")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving sweep and print its JSON")
+    ap.add_argument("--summarize-overlap", nargs=2, metavar=("DIR", "COMMAND"),
+                    help="print the kernel concurrency of a rocprofv3 --kernel-trace csv run")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DIR", "COMMAND"),
                     help="print a summary of a rocprofv3 --kernel-trace --stats csv run")
     ap.add_argument("--summarize-traffic", nargs=7,
@@ -572,6 +624,9 @@ def main():
         ap.error("--steps must be >= 1 and --warmup >= 0")
     if args.summarize_trace:
         print(summarize_trace(*args.summarize_trace), end="")
+        return
+    if args.summarize_overlap:
+        print(summarize_overlap(*args.summarize_overlap), end="")
         return
     if args.summarize_traffic:
         f, w, cf, cw, mib, tun, cmds = args.summarize_traffic
@@ -594,6 +649,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
+        return
+
+    if args.serving_only:
+        print(json.dumps(serving(sfm, [float(r) for r in args.serving_rates.split(",")],
+                                 args.serving_seconds, log)), flush=True)
         return
 
     dev = torch.device("cuda", 0)

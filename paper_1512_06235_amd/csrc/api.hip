@@ -219,35 +219,57 @@ int describe_pairs(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, i
   return describe_pairs(ctx, tab, pairs, n_pairs, ignore_band, pd.data());
 }
 
-int ensure_workspace(sfm_ctx* ctx, size_t bytes) {
-  if (bytes > ctx->budget) {
+// A device workspace, its pinned staging buffer and their events: the
+// context's own, or one of a server's slots (serve_space_create), which lets
+// launches of different slots overlap on the device.
+struct Space {
+  char** ws;
+  size_t* ws_cap;
+  char** pinned;
+  size_t* pinned_cap;
+  hipEvent_t staging_done;   // last copy out of the pinned buffer
+  hipEvent_t work_done;      // end of the last call on the workspace
+  bool* has_work;
+  size_t budget;
+};
+
+Space ctx_space(sfm_ctx* ctx) {
+  return Space{&ctx->ws,          &ctx->ws_cap,    &ctx->pinned,   &ctx->pinned_cap,
+               ctx->staging_done, ctx->work_done,  &ctx->has_work, ctx->budget};
+}
+
+int ensure_ws(sfm_ctx* ctx, const Space& sp, size_t bytes) {
+  if (bytes > sp.budget) {
     char buf[160];
     snprintf(buf, sizeof buf, "workspace of %zu bytes exceeds the budget of %zu bytes", bytes,
-             ctx->budget);
+             sp.budget);
     return fail(ctx, SFM_ECAPACITY, buf);
   }
-  if (bytes <= ctx->ws_cap) return SFM_OK;
-  if (ctx->has_work) HIP_TRY(ctx, hipEventSynchronize(ctx->work_done));
-  if (ctx->ws) HIP_TRY(ctx, hipFree(ctx->ws));
-  ctx->ws = nullptr;
-  ctx->ws_cap = 0;
-  const size_t cap = std::min(ctx->budget, std::max(bytes, bytes + bytes / 4));
-  HIP_TRY(ctx, hipMalloc(&ctx->ws, cap));
-  ctx->ws_cap = cap;
+  if (bytes <= *sp.ws_cap) return SFM_OK;
+  if (*sp.has_work) HIP_TRY(ctx, hipEventSynchronize(sp.work_done));
+  if (*sp.ws) HIP_TRY(ctx, hipFree(*sp.ws));
+  *sp.ws = nullptr;
+  *sp.ws_cap = 0;
+  const size_t cap = std::min(sp.budget, std::max(bytes, bytes + bytes / 4));
+  HIP_TRY(ctx, hipMalloc(sp.ws, cap));
+  *sp.ws_cap = cap;
   return SFM_OK;
 }
 
-int ensure_pinned(sfm_ctx* ctx, size_t bytes) {
-  if (bytes <= ctx->pinned_cap) return SFM_OK;
-  HIP_TRY(ctx, hipEventSynchronize(ctx->staging_done));
-  if (ctx->pinned) HIP_TRY(ctx, hipHostFree(ctx->pinned));
-  ctx->pinned = nullptr;
-  ctx->pinned_cap = 0;
+int ensure_pin(sfm_ctx* ctx, const Space& sp, size_t bytes) {
+  if (bytes <= *sp.pinned_cap) return SFM_OK;
+  HIP_TRY(ctx, hipEventSynchronize(sp.staging_done));
+  if (*sp.pinned) HIP_TRY(ctx, hipHostFree(*sp.pinned));
+  *sp.pinned = nullptr;
+  *sp.pinned_cap = 0;
   const size_t cap = std::max<size_t>(bytes, 1 << 16);
-  HIP_TRY(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), cap, hipHostMallocDefault));
-  ctx->pinned_cap = cap;
+  HIP_TRY(ctx, hipHostMalloc(reinterpret_cast<void**>(sp.pinned), cap, hipHostMallocDefault));
+  *sp.pinned_cap = cap;
   return SFM_OK;
 }
+
+int ensure_workspace(sfm_ctx* ctx, size_t bytes) { return ensure_ws(ctx, ctx_space(ctx), bytes); }
+int ensure_pinned(sfm_ctx* ctx, size_t bytes) { return ensure_pin(ctx, ctx_space(ctx), bytes); }
 
 enum class Form { kBatched, kPlain, kExhaustive, kBandError };
 
@@ -419,7 +441,8 @@ void binning_order(const PairDesc* pd, int32_t n_pairs, int32_t* ord) {
 // of matching (`out` is unused; diag receives the two result words).
 int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int32_t n_pairs,
                  const double* F, const sfm_options* opt_in, const sfm_matches* out, void* stream,
-                 Form form, unsigned long long* diag = nullptr) {
+                 Form form, unsigned long long* diag = nullptr, const Space* alt = nullptr) {
+  const Space S = alt ? *alt : ctx_space(ctx);
   const bool diagnostic = form == Form::kBandError;
   sfm_matches none;
   memset(&none, 0, sizeof none);
@@ -444,23 +467,23 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
     if (!diagnostic) HIP_TRY(ctx, hipMemsetAsync(out->offset, 0, sizeof(int64_t), st));
     return SFM_OK;
   }
-  if ((rc = ensure_workspace(ctx, L.total))) return rc;
-  if ((rc = ensure_pinned(ctx, L.staged))) return rc;
+  if ((rc = ensure_ws(ctx, S, L.total))) return rc;
+  if ((rc = ensure_pin(ctx, S, L.staged))) return rc;
   // Calls on one context are ordered: wait for the previous one on this stream.
-  if (ctx->has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->work_done, 0));
+  if (*S.has_work) HIP_TRY(ctx, hipStreamWaitEvent(st, S.work_done, 0));
 
-  HIP_TRY(ctx, hipEventSynchronize(ctx->staging_done));
-  memcpy(ctx->pinned + L.pairs, pd.data(), pd.size() * sizeof(PairDesc));
+  HIP_TRY(ctx, hipEventSynchronize(S.staging_done));
+  memcpy((*S.pinned) + L.pairs, pd.data(), pd.size() * sizeof(PairDesc));
   if (exhaustive) {
-    memset(ctx->pinned + L.F, 0, pd.size() * 9 * sizeof(double));
+    memset((*S.pinned) + L.F, 0, pd.size() * 9 * sizeof(double));
   } else {
-    memcpy(ctx->pinned + L.F, F, pd.size() * 9 * sizeof(double));
+    memcpy((*S.pinned) + L.F, F, pd.size() * 9 * sizeof(double));
   }
-  binning_order(pd.data(), n_pairs, reinterpret_cast<int32_t*>(ctx->pinned + L.order));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->ws, ctx->pinned, L.staged, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipEventRecord(ctx->staging_done, st));
+  binning_order(pd.data(), n_pairs, reinterpret_cast<int32_t*>((*S.pinned) + L.order));
+  HIP_TRY(ctx, hipMemcpyAsync((*S.ws), (*S.pinned), L.staged, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipEventRecord(S.staging_done, st));
 
-  const BatchView v = batch_view(ctx, tab, ctx->ws, L, n_pairs, opt);
+  const BatchView v = batch_view(ctx, tab, (*S.ws), L, n_pairs, opt);
 
   int32_t* am = opt.emit_all ? out->all_match : nullptr;
   int32_t* ad1 = opt.emit_all ? out->all_d1 : nullptr;
@@ -471,7 +494,7 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
     for (const PairDesc& pp : pd) max_na = std::max(max_na, pp.na);
     HIP_TRY(ctx, hipMemsetAsync(diag, 0, 2 * sizeof(unsigned long long), st));
     HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, 0, int32_t(L.sum_groups), L.wgs,
-                                reinterpret_cast<const int32_t*>(ctx->ws + L.order), max_na, st));
+                                reinterpret_cast<const int32_t*>((*S.ws) + L.order), max_na, st));
     HIP_TRY(ctx, launch_band_error(v, L.sum_groups, diag, st));
   } else if (form == Form::kPlain) {
     for (int32_t p = 0; p < n_pairs; ++p) {
@@ -486,7 +509,7 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
                                out->n_comparisons, out->n_borderline, am, ad1, ad2, ac, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
     }
-  } else if (ctx->graph_replay && !ctx->profiling && form == Form::kBatched) {
+  } else if (!alt && ctx->graph_replay && !ctx->profiling && form == Form::kBatched) {
     GraphKey key;
     memset(&key, 0, sizeof key);
     key.v = v;
@@ -495,7 +518,7 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
     key.sum_groups = int32_t(L.sum_groups);
     key.wgs = L.wgs;
     for (const PairDesc& pp : pd) key.max_na = std::max(key.max_na, pp.na);
-    key.order = reinterpret_cast<const int32_t*>(ctx->ws + L.order);
+    key.order = reinterpret_cast<const int32_t*>((*S.ws) + L.order);
     if (!opt.emit_all) {
       key.out.all_match = key.out.all_d1 = key.out.all_d2 = key.out.all_count = nullptr;
     }
@@ -505,7 +528,7 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
     int32_t max_na = 0;
     for (const PairDesc& pp : pd) max_na = std::max(max_na, pp.na);
     HIP_TRY(ctx, launch_prepare(v, 0, n_pairs, 0, int32_t(L.sum_groups), L.wgs,
-                                reinterpret_cast<const int32_t*>(ctx->ws + L.order), max_na, st));
+                                reinterpret_cast<const int32_t*>((*S.ws) + L.order), max_na, st));
     HIP_TRY(ctx, prof_mark(ctx, st));
     HIP_TRY(ctx, launch_match(v, L.sum_groups > 0 ? L.wgs : 0, st));
     HIP_TRY(ctx, prof_mark(ctx, st));
@@ -514,9 +537,10 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
                              st));
     HIP_TRY(ctx, prof_mark(ctx, st));
   }
-  HIP_TRY(ctx, hipEventRecord(ctx->work_done, st));
-  ctx->has_work = true;
-  ctx->last_pairs = n_pairs;
+  HIP_TRY(ctx, hipEventRecord(S.work_done, st));
+  *S.has_work = true;
+  // sfm_last_stats reads the counters from the context workspace only.
+  ctx->last_pairs = alt ? 0 : n_pairs;
   ctx->last_counters = L.counters;
   return SFM_OK;
 }
@@ -675,6 +699,52 @@ size_t ctx_call_bytes(const sfm_ctx* ctx) {
   return 20 * kAlign + size_t(wgs + 1) * sizeof(int32_t);
 }
 size_t ctx_budget(const sfm_ctx* ctx) { return ctx->budget; }
+
+struct ServeSpace {
+  char* ws = nullptr;
+  size_t ws_cap = 0;
+  char* pinned = nullptr;
+  size_t pinned_cap = 0;
+  hipEvent_t staging_done = nullptr, work_done = nullptr;
+  bool has_work = false;
+  size_t budget = 0;
+  int32_t device = 0;
+};
+
+void serve_space_destroy(ServeSpace* sp) {
+  if (!sp) return;
+  (void)hipSetDevice(sp->device);
+  if (sp->has_work) (void)hipEventSynchronize(sp->work_done);
+  if (sp->staging_done) (void)hipEventSynchronize(sp->staging_done);
+  if (sp->ws) (void)hipFree(sp->ws);
+  if (sp->pinned) (void)hipHostFree(sp->pinned);
+  if (sp->staging_done) (void)hipEventDestroy(sp->staging_done);
+  if (sp->work_done) (void)hipEventDestroy(sp->work_done);
+  delete sp;
+}
+
+ServeSpace* serve_space_create(sfm_ctx* ctx, size_t budget) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return nullptr;
+  ServeSpace* sp = new ServeSpace();
+  sp->device = ctx->device;
+  sp->budget = budget;
+  if (hipEventCreateWithFlags(&sp->staging_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&sp->work_done, hipEventDisableTiming) != hipSuccess) {
+    serve_space_destroy(sp);
+    return nullptr;
+  }
+  return sp;
+}
+
+int serve_match(sfm_ctx* ctx, ServeSpace* sp, const sfm_pair* pairs, int32_t n_pairs,
+                const double* F, const sfm_options* opt, const sfm_matches* out, hipStream_t st) {
+  if (!ctx || !sp) return SFM_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  const Space S{&sp->ws,          &sp->ws_cap,   &sp->pinned,   &sp->pinned_cap,
+                sp->staging_done, sp->work_done, &sp->has_work, sp->budget};
+  return match_locked(ctx, registered(ctx), pairs, n_pairs, F, opt, out, st, Form::kBatched,
+                      nullptr, &S);
+}
 }  // namespace sfm
 
 extern "C" {

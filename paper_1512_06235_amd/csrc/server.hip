@@ -4,9 +4,10 @@
 // Pairs are independent (Section 6.1 matches them in parallel), so a request
 // stream can be served by concatenating whatever requests are waiting into
 // one batched launch.  A worker thread admits up to max_batch_pairs waiting
-// requests whenever one of max_inflight result slots is free and enqueues the
-// batch on the server's own stream; while that batch runs, new arrivals queue
-// up and form the next batch.  A completion thread waits for each batch in
+// requests whenever one of max_inflight slots is free and enqueues the batch
+// on that slot's own stream and workspace (a share of the context's budget),
+// so the launches of different slots overlap on the device; while they run,
+// new arrivals queue up and form the next batch.  A completion thread waits for each batch in
 // launch order, copies exactly the accepted matches into pinned host memory,
 // and hands every request its rows.  A request's latency runs from its
 // arrival time to the moment its rows are in host memory.
@@ -65,6 +66,8 @@ struct Slot {
   int32_t *hq = nullptr, *hm = nullptr, *hd1 = nullptr, *hd2 = nullptr;
   int64_t *hoffset = nullptr, *hncmp = nullptr;
   hipEvent_t meta = nullptr, rows = nullptr;
+  hipStream_t stream = nullptr;   // this slot's matching and metadata copies
+  ServeSpace* space = nullptr;    // this slot's workspace
   std::vector<Request> reqs;
   int32_t status = SFM_OK;
 };
@@ -73,7 +76,6 @@ struct Server {
   sfm_ctx* ctx = nullptr;
   int32_t device = 0;
   sfm_server_cfg cfg{};
-  hipStream_t stream = nullptr;   // matching and metadata copies
   hipStream_t copy = nullptr;     // row copies
   std::vector<Slot> slots;
 
@@ -90,6 +92,7 @@ struct Server {
   bool worker_done = false;          // the worker has launched everything and exited
   bool closed = false;               // stopped: threads joined, slots freed
   int64_t launches = 0, launched_pairs = 0;
+  size_t slot_budget = 0;            // device workspace per slot
 
   std::thread worker, completer;
 };
@@ -120,13 +123,17 @@ void free_slot(Slot& s) {
   if (s.hncmp) (void)hipHostFree(s.hncmp);
   if (s.meta) (void)hipEventDestroy(s.meta);
   if (s.rows) (void)hipEventDestroy(s.rows);
+  serve_space_destroy(s.space);
+  if (s.stream) (void)hipStreamDestroy(s.stream);
   s = Slot();
 }
 
-bool alloc_slot(Slot& s, int64_t rows, int32_t pairs) {
+bool alloc_slot(Slot& s, sfm_ctx* ctx, size_t budget, int64_t rows, int32_t pairs) {
   const size_t r4 = size_t(std::max<int64_t>(rows, 1)) * sizeof(int32_t);
   const size_t p8 = size_t(pairs + 1) * sizeof(int64_t);
-  return hipMalloc(&s.q, r4) == hipSuccess && hipMalloc(&s.m, r4) == hipSuccess &&
+  s.space = serve_space_create(ctx, budget);
+  return s.space && hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) == hipSuccess &&
+         hipMalloc(&s.q, r4) == hipSuccess && hipMalloc(&s.m, r4) == hipSuccess &&
          hipMalloc(&s.d1, r4) == hipSuccess && hipMalloc(&s.d2, r4) == hipSuccess &&
          hipMalloc(&s.offset, p8) == hipSuccess && hipMalloc(&s.ncmp, p8) == hipSuccess &&
          hipHostMalloc(reinterpret_cast<void**>(&s.hq), r4, hipHostMallocDefault) == hipSuccess &&
@@ -173,7 +180,7 @@ void worker_main(Server* Sp) {
       // and query caps and its workspace within the context's budget.
       int64_t queries = 0;
       size_t bytes = ctx_call_bytes(S.ctx);
-      const size_t budget = ctx_budget(S.ctx);
+      const size_t budget = S.slot_budget;
       while (!S.queue.empty() && int32_t(batch.size()) < S.cfg.max_batch_pairs) {
         const Request& r = S.queue.front();
         const int64_t na = ctx_image_size(S.ctx, r.pair.a);
@@ -209,16 +216,16 @@ void worker_main(Server* Sp) {
     if (need > S.cfg.max_batch_queries) {
       rc = SFM_ECAPACITY;   // a single request larger than the slot
     } else {
-      rc = sfm_guided_match(S.ctx, pairs.data(), int32_t(pairs.size()), F.data(), &S.cfg.opt, &out,
-                            S.stream);
+      rc = serve_match(S.ctx, s.space, pairs.data(), int32_t(pairs.size()), F.data(),
+                       &S.cfg.opt, &out, s.stream);
     }
     const int32_t n = int32_t(batch.size());
     if (rc == SFM_OK) {
       if (hipMemcpyAsync(s.hoffset, s.offset, size_t(n + 1) * sizeof(int64_t),
-                         hipMemcpyDeviceToHost, S.stream) != hipSuccess ||
+                         hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
           hipMemcpyAsync(s.hncmp, s.ncmp, size_t(n) * sizeof(int64_t), hipMemcpyDeviceToHost,
-                         S.stream) != hipSuccess ||
-          hipEventRecord(s.meta, S.stream) != hipSuccess)
+                         s.stream) != hipSuccess ||
+          hipEventRecord(s.meta, s.stream) != hipSuccess)
         rc = SFM_EHIP;
     }
     std::lock_guard<std::mutex> lk(S.mu);
@@ -349,12 +356,12 @@ void shutdown(Server* S) {
   }
   if (S->completer.joinable()) S->completer.join();
   (void)hipSetDevice(S->device);
-  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  for (Slot& s : S->slots)
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
   if (S->copy) (void)hipStreamSynchronize(S->copy);
   for (Slot& s : S->slots) free_slot(s);
-  if (S->stream) (void)hipStreamDestroy(S->stream);
   if (S->copy) (void)hipStreamDestroy(S->copy);
-  S->stream = S->copy = nullptr;
+  S->copy = nullptr;
   std::lock_guard<std::mutex> lk(S->mu);
   S->closed = true;
   S->cv_done.notify_all();   // pollers still waiting return SFM_EBUSY
@@ -403,15 +410,18 @@ int sfm_server_start(sfm_ctx* ctx, const sfm_server_cfg* cfg_in) {
   S->ctx = ctx;
   S->device = ctx_device(ctx);
   S->cfg = cfg;
+  // Each slot matches on its own stream and workspace, its share of the
+  // context's budget.
+  S->slot_budget = ctx_budget(ctx) / size_t(cfg.max_inflight);
   if (hipSetDevice(S->device) != hipSuccess ||
-      hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) != hipSuccess) {
     shutdown(S.get());
     return SFM_EHIP;
   }
   S->slots.resize(size_t(cfg.max_inflight));
   for (int k = 0; k < cfg.max_inflight; ++k) {
-    if (!alloc_slot(S->slots[size_t(k)], cfg.max_batch_queries, cfg.max_batch_pairs)) {
+    if (!alloc_slot(S->slots[size_t(k)], ctx, S->slot_budget, cfg.max_batch_queries,
+                    cfg.max_batch_pairs)) {
       shutdown(S.get());
       return SFM_ENOMEM;
     }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sfm_gm.h"
+
 namespace sfm {
 
 constexpr int kDescBytes = 128;
@@ -303,6 +305,16 @@ size_t ctx_request_bytes(const sfm_ctx* ctx, int32_t a, int32_t b);
 size_t ctx_call_bytes(const sfm_ctx* ctx);
 size_t ctx_budget(const sfm_ctx* ctx);
 void server_release(sfm_ctx* ctx);
+// A workspace of its own for one server slot (device workspace within
+// `budget`, pinned staging, events): batched launches on different slots'
+// spaces and streams overlap on the device.  serve_match is the batched form
+// (sfm_guided_match) on that space; NULL from serve_space_create when HIP
+// fails.
+struct ServeSpace;
+ServeSpace* serve_space_create(sfm_ctx* ctx, size_t budget);
+void serve_space_destroy(ServeSpace* sp);
+int serve_match(sfm_ctx* ctx, ServeSpace* sp, const sfm_pair* pairs, int32_t n_pairs,
+                const double* F, const sfm_options* opt, const sfm_matches* out, hipStream_t st);
 
 // Host launchers (one translation unit each).
 hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_t n_images,
