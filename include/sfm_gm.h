@@ -388,16 +388,14 @@ int sfm_server_stop(sfm_ctx* ctx);
 int sfm_set_tuning(sfm_ctx* ctx, int32_t group_tiles, int32_t features_per_bin);
 int sfm_get_tuning(sfm_ctx* ctx, int32_t* group_tiles, int32_t* features_per_bin);
 
-/* Graph replay of the batched form (enable != 0; default off).  The kernels
- * of a call are captured into a HIP graph for its launch layout (pairs,
- * feature counts, workspace, outputs, options and tuning) and the graph is
- * replayed by later calls with the same layout; any other layout captures
- * anew.  The copy of the pairs and F into the workspace stays a stream copy.
- * Results are identical to stream launches.  Measured on MI355X for the
- * 500-pair batch, replay and launching the seven kernels on the stream are
- * within 3% of each other either way, so it is off by default; it serves
- * callers that replay one batch shape.  Disabling frees the graph.
- * Profiling (sfm_set_profiling) uses stream launches. */
+/* Graph replay of the batched form (enable != 0; on by default).  A call
+ * whose launch layout (pairs, feature counts, workspace, outputs, options and
+ * tuning) equals the previous batched call's has the kernels captured into a
+ * HIP graph, which later calls with the same layout replay; a layout seen for
+ * the first time is launched directly, so callers whose batches change every
+ * call pay no capture.  The copy of the pairs and F into the workspace stays
+ * a stream copy.  Results are identical to stream launches.  Disabling frees
+ * the graph.  Profiling (sfm_set_profiling) uses stream launches. */
 int sfm_set_graph_replay(sfm_ctx* ctx, int32_t enable);
 
 /* ---------------------------------------------------------------------------
@@ -478,6 +476,19 @@ int sfm_triangulate(sfm_ctx* ctx, int64_t n_nodes, const int32_t* label, const i
  * scratch outputs it allocates and frees; blocks until done. */
 int sfm_autotune(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                  const sfm_options* opt, void* stream, int32_t repeats, double* ms_out);
+
+/* sfm_autotune with a persisted result.  cache_path names a JSON file of
+ * tunings keyed by the device (architecture and CU count) and the batch's
+ * shape (log2 buckets of its total queries and of its mean target count, its
+ * mean band in half-octaves).  When the key is present the stored tuning is
+ * set on the context and *from_cache is 1 (ms_out untouched); otherwise the
+ * batch is tuned as sfm_autotune does, the winner is added to the file
+ * (created if missing) and *from_cache is 0.  SFM_EINVAL: as sfm_autotune,
+ * no pairs, NULL cache_path or from_cache, or a file that cannot be
+ * written. */
+int sfm_autotune_cached(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                        const sfm_options* opt, void* stream, int32_t repeats,
+                        const char* cache_path, double* ms_out, int32_t* from_cache);
 
 /* Human-readable name of a status code (static string). */
 const char* sfm_strerror(int status);

@@ -134,6 +134,8 @@ def lib() -> C.CDLL:
         "sfm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32)],
         "sfm_autotune": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options), vp, i32,
                          C.POINTER(C.c_double)],
+        "sfm_autotune_cached": [vp, C.POINTER(sfm_pair), i32, vp, C.POINTER(sfm_options), vp,
+                                i32, C.c_char_p, C.POINTER(C.c_double), C.POINTER(i32)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -156,7 +158,8 @@ def exported_symbols():
             "sfm_set_profiling", "sfm_phase_times", "sfm_last_stats", "sfm_strerror",
             "sfm_last_error", "sfm_server_now_ns", "sfm_server_start", "sfm_server_submit",
             "sfm_server_submit_batch", "sfm_server_poll", "sfm_server_stats", "sfm_server_stop", "sfm_set_tuning",
-            "sfm_get_tuning", "sfm_autotune", "sfm_set_graph_replay", "sfm_candidate_images",
+            "sfm_get_tuning", "sfm_autotune", "sfm_autotune_cached", "sfm_set_graph_replay",
+            "sfm_candidate_images",
             "sfm_set_covis_method", "sfm_tracks", "sfm_triangulate", "sfm_preemptive_match",
             "sfm_grid_match", "sfm_set_grid_grouping", "sfm_grid_groups"]
 
@@ -501,6 +504,27 @@ def sfm_autotune(ctx, pairs, F, opt=None, stream=None, repeats: int = 3):
     _check(ctx, st)
     return {(t, f): ms[3 * i + j] for i, t in enumerate(AUTOTUNE_GROUP_TILES)
             for j, f in enumerate(AUTOTUNE_FEATURES_PER_BIN)}
+
+
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def sfm_autotune_cached(ctx, pairs, F, cache_path=TUNE_CACHE, opt=None, stream=None,
+                        repeats: int = 3):
+    """sfm_autotune through the tuning cache at cache_path; returns
+    (from_cache, {(group_tiles, features_per_bin): ms per call} or None)."""
+    batch = pairs if isinstance(pairs, PairBatch) and F is None else PairBatch(pairs, F)
+    ms = (C.c_double * (len(AUTOTUNE_GROUP_TILES) * len(AUTOTUNE_FEATURES_PER_BIN)))()
+    hit = C.c_int32()
+    st = lib().sfm_autotune_cached(ctx, batch.c_pairs, batch.n, batch.F.ctypes.data,
+                                   C.byref(opt if opt is not None else options()),
+                                   stream.cuda_stream if stream is not None else None,
+                                   int(repeats), os.fsencode(cache_path), ms, C.byref(hit))
+    _check(ctx, st)
+    if hit.value:
+        return True, None
+    return False, {(t, f): ms[3 * i + j] for i, t in enumerate(AUTOTUNE_GROUP_TILES)
+                   for j, f in enumerate(AUTOTUNE_FEATURES_PER_BIN)}
 
 
 def options(ratio_num=64, ratio_den=100, accept_single=False, emit_all=False,

@@ -64,9 +64,11 @@ struct sfm_ctx {
   std::vector<hipEvent_t> prof_events;
   std::vector<hipEvent_t> prof_pool;
 
-  // Graph replay of the batched form (sfm_set_graph_replay): the kernels of
-  // one launch layout captured once and replayed while the layout repeats.
-  bool graph_replay = false;
+  // Graph replay of the batched form (sfm_set_graph_replay, on by default):
+  // the kernels of one launch layout are captured once the layout repeats
+  // and replayed while it keeps repeating.
+  bool graph_replay = true;
+  std::vector<char> last_key;   // layout of the last batched call launched directly
   int32_t covis_method = 0;   // candidate images: 0 choose, 1 point histogram, 2 bit matrix
   double grid_group_px = 0.0; // grid search: query grouping distance (0 = off)
   int32_t grid_group_leader = 0;  // grouping against the group's first line
@@ -337,6 +339,16 @@ int replay_batched(sfm_ctx* ctx, const GraphKey& key, int32_t* am, int32_t* ad1,
   return SFM_OK;
 }
 
+// True when `key` is the captured graph's layout or the last directly
+// launched batched call's.
+bool key_repeats(const sfm_ctx* ctx, const GraphKey& key) {
+  const char* kb = reinterpret_cast<const char*>(&key);
+  const auto same = [&](const std::vector<char>& k) {
+    return k.size() == sizeof key && memcmp(k.data(), kb, sizeof key) == 0;
+  };
+  return (ctx->graph && same(ctx->graph_key)) || same(ctx->last_key);
+}
+
 // Records an event on `st` when profiling is enabled.
 hipError_t prof_mark(sfm_ctx* ctx, hipStream_t st) {
   if (!ctx->profiling) return hipSuccess;
@@ -485,6 +497,22 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
 
   const BatchView v = batch_view(ctx, tab, (*S.ws), L, n_pairs, opt);
 
+  // The layout of a batched call, for graph replay.
+  const bool replay = !alt && ctx->graph_replay && !ctx->profiling && form == Form::kBatched;
+  GraphKey key;
+  memset(&key, 0, sizeof key);
+  if (replay) {
+    key.v = v;
+    key.out = *out;
+    key.n_pairs = n_pairs;
+    key.sum_groups = int32_t(L.sum_groups);
+    key.wgs = L.wgs;
+    for (const PairDesc& pp : pd) key.max_na = std::max(key.max_na, pp.na);
+    key.order = reinterpret_cast<const int32_t*>((*S.ws) + L.order);
+    if (!opt.emit_all) {
+      key.out.all_match = key.out.all_d1 = key.out.all_d2 = key.out.all_count = nullptr;
+    }
+  }
   int32_t* am = opt.emit_all ? out->all_match : nullptr;
   int32_t* ad1 = opt.emit_all ? out->all_d1 : nullptr;
   int32_t* ad2 = opt.emit_all ? out->all_d2 : nullptr;
@@ -509,21 +537,15 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
                                out->n_comparisons, out->n_borderline, am, ad1, ad2, ac, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
     }
-  } else if (!alt && ctx->graph_replay && !ctx->profiling && form == Form::kBatched) {
-    GraphKey key;
-    memset(&key, 0, sizeof key);
-    key.v = v;
-    key.out = *out;
-    key.n_pairs = n_pairs;
-    key.sum_groups = int32_t(L.sum_groups);
-    key.wgs = L.wgs;
-    for (const PairDesc& pp : pd) key.max_na = std::max(key.max_na, pp.na);
-    key.order = reinterpret_cast<const int32_t*>((*S.ws) + L.order);
-    if (!opt.emit_all) {
-      key.out.all_match = key.out.all_d1 = key.out.all_d2 = key.out.all_count = nullptr;
-    }
+  } else if (replay && key_repeats(ctx, key)) {
     if ((rc = replay_batched(ctx, key, am, ad1, ad2, ac, st))) return rc;
   } else {
+    // A layout seen for the first time launches directly; the next call with
+    // the same layout is captured and replayed.
+    if (replay) {
+      const char* kb = reinterpret_cast<const char*>(&key);
+      ctx->last_key.assign(kb, kb + sizeof key);
+    }
     HIP_TRY(ctx, prof_mark(ctx, st));
     int32_t max_na = 0;
     for (const PairDesc& pp : pd) max_na = std::max(max_na, pp.na);
@@ -1541,6 +1563,7 @@ int sfm_set_graph_replay(sfm_ctx* ctx, int32_t enable) {
   if (!ctx) return SFM_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   ctx->graph_replay = enable != 0;
+  ctx->last_key.clear();
   if (!ctx->graph_replay && ctx->graph) {
     if (ctx->has_work) HIP_TRY(ctx, hipEventSynchronize(ctx->work_done));
     HIP_TRY(ctx, hipGraphExecDestroy(ctx->graph));
@@ -1633,6 +1656,108 @@ int sfm_autotune(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const dou
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   return rc;
+}
+
+// Tuning cache: a JSON object, one entry per line,
+//   "KEY": {"group_tiles": T, "features_per_bin": F, "ms": X},
+// written by sfm_autotune_cached and read back by later calls.
+static std::string tune_key(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  int64_t q = 0, c = 0;
+  double band = 0.0;
+  for (int32_t k = 0; k < n_pairs; ++k) {
+    q += ctx->n_host[size_t(pairs[k].a)];
+    c += ctx->n_host[size_t(pairs[k].b)];
+    band += std::isfinite(pairs[k].band_px) ? pairs[k].band_px : 0.0;
+  }
+  const int qb = int(std::floor(std::log2(double(q) + 1.0)));
+  const int fb = int(std::floor(std::log2(double(c) / std::max(1, n_pairs) + 1.0)));
+  const int bb = int(std::lround(2.0 * std::log2(band / std::max(1, n_pairs) + 1e-9)));
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s|cu%d|q%d|f%d|b%d", arch.c_str(), cus, qb, fb, bb);
+  return buf;
+}
+
+static std::vector<std::string> tune_cache_lines(const char* path) {
+  std::vector<std::string> lines;
+  FILE* f = fopen(path, "r");
+  if (!f) return lines;
+  char buf[1024];
+  while (fgets(buf, sizeof buf, f)) {
+    std::string l(buf);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r' || l.back() == ',')) l.pop_back();
+    if (l.find("\"group_tiles\"") != std::string::npos) lines.push_back(l);
+  }
+  fclose(f);
+  return lines;
+}
+
+static bool tune_entry(const std::string& line, std::string* key, int32_t* t, int32_t* fpb) {
+  const size_t k0 = line.find('"'), k1 = line.find('"', k0 + 1);
+  const size_t pt = line.find("\"group_tiles\":"), pf = line.find("\"features_per_bin\":");
+  if (k0 == std::string::npos || k1 == std::string::npos || pt == std::string::npos ||
+      pf == std::string::npos)
+    return false;
+  *key = line.substr(k0 + 1, k1 - k0 - 1);
+  *t = int32_t(strtol(line.c_str() + pt + 14, nullptr, 10));
+  *fpb = int32_t(strtol(line.c_str() + pf + 19, nullptr, 10));
+  return true;
+}
+
+int sfm_autotune_cached(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
+                        const sfm_options* opt, void* stream, int32_t repeats,
+                        const char* cache_path, double* ms_out, int32_t* from_cache) {
+  if (!ctx || !cache_path || !from_cache) return SFM_EINVAL;
+  if (n_pairs < 1 || !pairs) return fail(ctx, SFM_EINVAL, "autotuning needs at least one pair");
+  for (int32_t k = 0; k < n_pairs; ++k)
+    if (pairs[k].a < 0 || pairs[k].a >= ctx->n_images || pairs[k].b < 0 ||
+        pairs[k].b >= ctx->n_images)
+      return fail(ctx, SFM_EINVAL, "bad pair");
+  *from_cache = 0;
+  const std::string key = tune_key(ctx, pairs, n_pairs);
+  std::vector<std::string> lines = tune_cache_lines(cache_path);
+  for (const std::string& l : lines) {
+    std::string k;
+    int32_t t = 0, fpb = 0;
+    if (tune_entry(l, &k, &t, &fpb) && k == key) {
+      const int rc = sfm_set_tuning(ctx, t, fpb);
+      if (rc == SFM_OK) *from_cache = 1;
+      return rc;
+    }
+  }
+  double ms[6];
+  int rc = sfm_autotune(ctx, pairs, n_pairs, F, opt, stream, repeats, ms);
+  if (rc) return rc;
+  if (ms_out) memcpy(ms_out, ms, sizeof ms);
+  int32_t t = 0, fpb = 0;
+  sfm_get_tuning(ctx, &t, &fpb);
+  const double best = ms[3 * (t == 8 ? 1 : 0) + (fpb == 4 ? 0 : fpb == 8 ? 1 : 2)];
+  char entry[512];
+  snprintf(entry, sizeof entry,
+           "  \"%s\": {\"group_tiles\": %d, \"features_per_bin\": %d, \"ms\": %.4f}", key.c_str(), t,
+           fpb, best);
+  lines.push_back(entry);
+  const std::string tmp = std::string(cache_path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return fail(ctx, SFM_EINVAL, std::string("cannot write the tuning cache ") + tmp);
+  fputs("{\n", f);
+  for (size_t k = 0; k < lines.size(); ++k) {
+    std::string l = lines[k];
+    if (l.compare(0, 2, "  ") != 0) l = "  " + l.substr(l.find('"'));
+    fputs(l.c_str(), f);
+    fputs(k + 1 < lines.size() ? ",\n" : "\n", f);
+  }
+  fputs("}\n", f);
+  fclose(f);
+  if (rename(tmp.c_str(), cache_path) != 0)
+    return fail(ctx, SFM_EINVAL, std::string("cannot replace the tuning cache ") + cache_path);
+  return SFM_OK;
 }
 
 }  // extern "C"

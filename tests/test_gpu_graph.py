@@ -107,3 +107,38 @@ def test_graph_replay_equals_stream_launches(sfm):
     sfm.sfm_set_graph_replay(m.ctx, False)
     say(f"  graph replays equal stream launches ({n} matches)")
     m.close()
+
+
+def test_default_replay_on_repeated_layouts(sfm):
+    """Graph replay is on by default: a layout's first call launches directly,
+    a repeat is captured and replayed; alternating layouts stay exact."""
+    import torch
+    scene, pairs = scenes.make_arc_batch()
+    used = sorted({a for a, _, _ in pairs[:30]} | {b for _, b, _ in pairs[:30]})
+    remap = {k: i for i, k in enumerate(used)}
+    m = sfm.Matcher().register([(scene.image(k).xy, scene.image(k).desc) for k in used])
+    sp = [(remap[a], remap[b], band) for a, b, band in pairs[:30]]
+    Fs = np.stack([scene.F(a, b) for a, b, _ in pairs[:30]])
+    A = sfm.PairBatch(sp[:20], Fs[:20])
+    B = sfm.PairBatch(sp[20:], Fs[20:])
+    st = torch.cuda.current_stream()
+    opt = sfm.options(emit_all=True)
+    outA, outB = m.buffers(sp[:20], emit_all=True), m.buffers(sp[20:], emit_all=True)
+    sfm.sfm_set_graph_replay(m.ctx, False)
+    sfm.sfm_guided_match(m.ctx, A, None, outA, opt, st)
+    sfm.sfm_guided_match(m.ctx, B, None, outB, opt, st)
+    sfm.sfm_sync(m.ctx, st)
+    refA, refB = _snapshot(outA, 20), _snapshot(outB, 10)
+    sfm.sfm_set_graph_replay(m.ctx, True)
+    for rep, (X, out, n, ref) in enumerate([(A, outA, 20, refA), (A, outA, 20, refA),
+                                            (A, outA, 20, refA), (B, outB, 10, refB),
+                                            (A, outA, 20, refA), (B, outB, 10, refB),
+                                            (B, outB, 10, refB), (B, outB, 10, refB)]):
+        _poison(out)
+        sfm.sfm_guided_match(m.ctx, X, None, out, opt, st)
+        sfm.sfm_sync(m.ctx, st)
+        got = _snapshot(out, n)
+        for k in FIELDS:
+            assert np.array_equal(got[k], ref[k]), f"call {rep}: {k} differs"
+    say("  default replay: repeated and alternating layouts exact")
+    m.close()

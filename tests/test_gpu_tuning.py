@@ -73,3 +73,29 @@ def test_autotune(sfm, batch, oracle_result):
     out = m.match(pairs, Fs, form="batched", emit_all=True)
     compare_all(out, oracle_result, len(pairs))
     m.close()
+
+
+def test_autotune_cache(sfm, batch, tmp_path):
+    """sfm_autotune_cached tunes a new batch shape and stores the winner; a
+    later call with the same shape reads it back without timing anything; a
+    new shape adds an entry.  The file stays valid JSON."""
+    import json
+    images, pairs, Fs = batch
+    path = str(tmp_path / "tune.json")
+    m = sfm.Matcher().register(images)
+    hit, times = sfm.sfm_autotune_cached(m.ctx, pairs, Fs, path, repeats=1)
+    assert not hit and len(times) == 6
+    best = sfm.sfm_get_tuning(m.ctx)
+    entries = json.loads(open(path).read())
+    assert len(entries) == 1
+    (key, rec), = entries.items()
+    assert (rec["group_tiles"], rec["features_per_bin"]) == best and "gfx" in key
+    m2 = sfm.Matcher().register(images)
+    sfm.sfm_set_tuning(m2.ctx, *((4, 16) if best != (4, 16) else (8, 8)))
+    hit2, t2 = sfm.sfm_autotune_cached(m2.ctx, pairs, Fs, path)
+    assert hit2 and t2 is None and sfm.sfm_get_tuning(m2.ctx) == best
+    hit3, _ = sfm.sfm_autotune_cached(m2.ctx, pairs[:2], Fs[:2], path, repeats=1)
+    assert not hit3 and len(json.loads(open(path).read())) == 2
+    say(f"  tuning cache: {key} -> {best}")
+    m.close()
+    m2.close()
