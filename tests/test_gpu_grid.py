@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import scenes
+from tests.fixtures import translation_F
 from tests.gpu_util import say
 
 pytestmark = pytest.mark.gpu
@@ -194,4 +195,31 @@ def test_grid_grouped_many_pairs_equals_oracle(sfm):
                  for p, (a, b, _) in enumerate(pairs))
     assert sfm.sfm_grid_groups(m.ctx) == groups
     say(f"  grouped, {len(pairs)} pairs: {groups} groups")
+    m.close()
+
+
+def test_grid_candidate_overflow_raises_and_context_recovers(sfm):
+    """A query with more than 1,024 grid candidates C' (the LDS list of one
+    query): the kernel keeps the first 1,024 and raises the device error
+    flag, which sfm_sync reports as SFM_EKERNEL; the context then matches
+    exactly again."""
+    from oracle.grid import grid_match
+    rng = np.random.default_rng(3)
+    n_b = 20000
+    # b's features fill a 2-px strip; lines y' = y (translation along x).
+    xy_b = np.stack([rng.uniform(0, 1000, n_b), rng.uniform(500, 502, n_b)], 1).astype(np.float32)
+    desc_b = rng.integers(0, 128, (n_b, 128), dtype=np.uint8)
+    xy_a = np.array([[100.0, 501.0], [600.0, 501.5], [900.0, 100.0]], np.float32)
+    desc_a = rng.integers(0, 128, (3, 128), dtype=np.uint8)
+    sc = scenes.make_two_view_2k()
+    images = [(xy_a, desc_a), (xy_b, desc_b)] + [(im.xy, im.desc) for im in sc.images]
+    m = sfm.Matcher().register(images)
+    with pytest.raises(sfm.SfmError) as e:
+        m.match([(0, 1, 8.0)], [translation_F((1.0, 0.0, 0.0))], form="grid")
+    assert e.value.status == sfm.SFM_EKERNEL
+    pairs = [(2, 3, 4.0)]
+    Fs = np.stack([sc.F])
+    out = m.match(pairs, Fs, form="grid", emit_all=True)
+    _check(out, images, pairs, Fs, grid_match(images, pairs, Fs))
+    say("  grid C' overflow: SFM_EKERNEL, then exact")
     m.close()
