@@ -206,6 +206,50 @@ def summarize_overlap(directory, command):
     return "\n".join(lines) + "\n"
 
 
+def summarize_counters(directories, commands, title, top=8):
+    """Per-kernel means (over dispatches) of every counter in the rocprofv3
+    --pmc csv runs under `directories`, with the SQ ratios."""
+    import csv
+    import glob
+    sums, counts = {}, {}
+    for d in directories:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                k = (_kernel_key(r["Kernel_Name"]), r["Counter_Name"])
+                sums[k] = sums.get(k, 0.0) + float(r["Counter_Value"])
+                counts[k] = counts.get(k, 0) + 1
+    # The kernels with the most wave-cycles over all their dispatches (or the
+    # most dispatches when the runs hold no SQ_WAVE_CYCLES), at most `top`.
+    def weight(k):
+        c = "SQ_WAVE_CYCLES" if (k, "SQ_WAVE_CYCLES") in sums else None
+        return sums[(k, c)] if c else max(counts[(kk, cc)] for kk, cc in counts if kk == k)
+    kernels = sorted({k for k, _ in sums}, key=weight, reverse=True)[:top]
+    lines = [title, *[f"command_{i}: {c}" for i, c in enumerate(commands)], "",
+             f"the {len(kernels)} kernels with the most wave-cycles; per kernel: mean per "
+             "dispatch of each counter (summed over the device's SQs), then ratios to "
+             "SQ_WAVE_CYCLES and, for instruction counts, per SQ_INSTS_MFMA/2 (one 16 x 16 "
+             "step issues two MFMAs)"]
+    for kern in kernels:
+        vals = {c: sums[(kern, c)] / counts[(kern, c)] for kk, c in sums if kk == kern}
+        n = max(counts[(kern, c)] for kk, c in counts if kk == kern)
+        lines.append("")
+        lines.append(f"{kern}  (dispatches: {n})")
+        for c in sorted(vals):
+            lines.append(f"  {c:28s} {vals[c]:18,.0f}")
+        wc = vals.get("SQ_WAVE_CYCLES")
+        if wc:
+            for c in ("SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU",
+                      "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_ANY"):
+                if c in vals:
+                    lines.append(f"  {c + ' / SQ_WAVE_CYCLES':44s} {vals[c] / wc:.3f}")
+        steps = vals.get("SQ_INSTS_MFMA", 0.0) / 2
+        if steps:
+            for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM"):
+                if c in vals:
+                    lines.append(f"  {c + ' per 16x16 step':44s} {vals[c] / steps:.1f}")
+    return "\n".join(lines) + "\n"
+
+
 def serving(sfm, rates, duration_s, log_fn):
     """Open-loop Poisson streams of single-pair requests on the 300-camera
     three-ring scene (covisible pairs, top 30 per image), served by
@@ -611,6 +655,11 @@ def main():
                     help="offered pair requests per second, comma-separated")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--context-only", choices=("guided", "exhaustive"), default=None,
+                    help="run only one side of the 16k-pair context comparison (10 calls)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("DIRS", "COMMANDS", "TITLE"),
+                    help="print per-kernel means of rocprofv3 --pmc runs (DIRS and COMMANDS "
+                         "joined by ' || ')")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving sweep and print its JSON")
     ap.add_argument("--summarize-overlap", nargs=2, metavar=("DIR", "COMMAND"),
@@ -630,6 +679,10 @@ def main():
         return
     if args.summarize_overlap:
         print(summarize_overlap(*args.summarize_overlap), end="")
+        return
+    if args.summarize_counters:
+        dirs, cmds, title = args.summarize_counters
+        print(summarize_counters(dirs.split(" || "), cmds.split(" || "), title), end="")
         return
     if args.summarize_traffic:
         f, w, cf, cw, mib, tun, cmds = args.summarize_traffic
@@ -654,6 +707,22 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
         return
 
+    if args.context_only:
+        import scenes
+        stream = torch.cuda.current_stream(torch.device("cuda", 0))
+        s2 = scenes.make_two_view_16k()
+        m2 = sfm.Matcher(device=0).register([(im.xy, im.desc) for im in s2.images])
+        o2 = m2.buffers(s2.pairs)
+        if args.context_only == "guided":
+            fn = lambda: sfm.sfm_guided_match(m2.ctx, s2.pairs, [s2.F], o2, sfm.options(), stream)  # noqa
+        else:
+            fn = lambda: sfm.sfm_bruteforce_match(m2.ctx, s2.pairs, None, o2, sfm.options(), stream)  # noqa
+        fn()
+        ms = timed(fn, 10, stream) / 10 * 1e3
+        print(json.dumps({"context_only": args.context_only, "ms_per_call": ms,
+                          "comparisons": int(o2.n_comparisons[0])}), flush=True)
+        m2.close()
+        return
     if args.serving_only:
         print(json.dumps(serving(sfm, [float(r) for r in args.serving_rates.split(",")],
                                  args.serving_seconds, log)), flush=True)
