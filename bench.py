@@ -768,8 +768,8 @@ def main():
     if args.warmup > 0:
         comparisons, matches, stats = step_totals()
 
-    # The headline: the library's default path (the batched call replays its
-    # captured kernels once the layout repeats).
+    # The headline: the library's default path (the batched form's kernels
+    # launched on the stream).
     log(f"bench: timing {args.steps} batched steps")
     elapsed = timed(step, args.steps, stream)
     sfm.sfm_sync(m.ctx, stream)

@@ -64,10 +64,10 @@ struct sfm_ctx {
   std::vector<hipEvent_t> prof_events;
   std::vector<hipEvent_t> prof_pool;
 
-  // Graph replay of the batched form (sfm_set_graph_replay, on by default):
+  // Graph replay of the batched form (sfm_set_graph_replay, off by default):
   // the kernels of one launch layout are captured once the layout repeats
   // and replayed while it keeps repeating.
-  bool graph_replay = true;
+  bool graph_replay = false;
   std::vector<char> last_key;   // layout of the last batched call launched directly
   int32_t covis_method = 0;   // candidate images: 0 choose, 1 point histogram, 2 bit matrix
   double grid_group_px = 0.0; // grid search: query grouping distance (0 = off)

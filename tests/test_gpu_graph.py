@@ -109,9 +109,10 @@ def test_graph_replay_equals_stream_launches(sfm):
     m.close()
 
 
-def test_default_replay_on_repeated_layouts(sfm):
-    """Graph replay is on by default: a layout's first call launches directly,
-    a repeat is captured and replayed; alternating layouts stay exact."""
+def test_replay_on_repeated_layouts(sfm):
+    """With graph replay on, a layout's first call launches directly, a
+    repeat is captured and replayed; repeated and alternating layouts stay
+    exact."""
     import torch
     scene, pairs = scenes.make_arc_batch()
     used = sorted({a for a, _, _ in pairs[:30]} | {b for _, b, _ in pairs[:30]})
@@ -140,5 +141,5 @@ def test_default_replay_on_repeated_layouts(sfm):
         got = _snapshot(out, n)
         for k in FIELDS:
             assert np.array_equal(got[k], ref[k]), f"call {rep}: {k} differs"
-    say("  default replay: repeated and alternating layouts exact")
+    say("  replay: repeated and alternating layouts exact")
     m.close()
