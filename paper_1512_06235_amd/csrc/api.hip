@@ -113,6 +113,7 @@ struct Layout {
       res, qwin, groups, gcost, pcost, total, staged;
   int32_t wgs = 0;
   int64_t sum_na = 0, sum_nc = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
+  int32_t max_na = 0;
 };
 
 int32_t bins_for(int32_t nb, int32_t features_per_bin) {
@@ -124,6 +125,7 @@ Layout plan(const PairDesc* pd, size_t P, int32_t device, int32_t group_tiles) {
   for (size_t k = 0; k < P; ++k) {
     const PairDesc& p = pd[k];
     L.sum_na += p.na;
+    L.max_na = std::max(L.max_na, p.na);
     L.sum_nc += p.nb + kCandPad;
     L.sum_bins += p.nbins + 1;
     L.sum_blocks += p.nblocks;
@@ -433,6 +435,7 @@ BatchView batch_view(const sfm_ctx* ctx, const ImageTable& tab, char* ws, const 
   v.accept_single = opt.accept_single ? 1 : 0;
   v.keep_counts = opt.emit_all ? 1 : 0;
   v.group_tiles = ctx->group_tiles;
+  v.max_na = L.max_na;
   v.margin = opt.recheck_margin_px;
   v.groups = reinterpret_cast<TileGroup*>(ws + L.groups);
   return v;
@@ -1056,11 +1059,12 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   const size_t o_pd = o; o = align_up(o + P * sizeof(PairDesc));
   const size_t o_F = o; o = align_up(o + P * 9 * sizeof(double));
   std::vector<int2> blocks;
-  int32_t max_nb = 0;
+  int32_t max_nb = 0, max_na = 0;
   for (size_t k = 0; k < P; ++k) {
     for (int32_t q0 = 0; q0 < gp[k].na; q0 += kGridQueriesPerBlock)
       blocks.push_back(make_int2(int32_t(k), q0));
     max_nb = std::max(max_nb, gp[k].nb);
+    max_na = std::max(max_na, gp[k].na);
   }
   if (blocks.size() > size_t(INT32_MAX)) return fail(ctx, SFM_ECAPACITY, "too many queries");
   const size_t o_blk = o; o = align_up(o + std::max<size_t>(blocks.size(), 1) * sizeof(int2));
@@ -1158,6 +1162,7 @@ int sfm_grid_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const d
   v.res = gv.res;
   v.counters = gv.counters;
   v.n_pairs = n_pairs;
+  v.max_na = max_na;
   int32_t* am = opt.emit_all ? out->all_match : nullptr;
   int32_t* ad1 = opt.emit_all ? out->all_d1 : nullptr;
   int32_t* ad2 = opt.emit_all ? out->all_d2 : nullptr;

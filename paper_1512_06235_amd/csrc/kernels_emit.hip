@@ -1,8 +1,11 @@
 // Ordered emission of accepted matches (a7).
 //
 // Per pair: a prefix over pairs gives each pair's first output row; then one
-// workgroup per pair compacts its accepted queries in ascending query index
-// with a ballot + mbcnt prefix inside each wave and a scan over waves.
+// workgroup per chunk of a pair's queries compacts its accepted queries in
+// ascending query index with a ballot + mbcnt prefix inside each wave and a
+// scan over waves.
+#include <algorithm>
+
 #include "sfm_internal.h"
 
 namespace sfm {
@@ -42,13 +45,17 @@ __global__ __launch_bounds__(1024) void scan_pairs_kernel(BatchView v, int32_t p
   }
 }
 
-// One workgroup per pair; a round covers kEmitPer slices of kEmitThreads
-// consecutive queries, whose results are read together with coalesced loads
-// (thread t reads query t of every slice).  Ranks come from a ballot + mbcnt
-// inside each wave and one scan over the (slice, wave) counts of the round,
-// so even the largest pair needs only a few rounds.
+// One workgroup per chunk of kEmitChunk consecutive queries of a pair (the
+// last chunk of a pair takes whatever remains, in rounds of kEmitChunk).  A
+// round covers kEmitPer slices of kEmitThreads consecutive queries, whose
+// results are read together with coalesced loads (thread t reads query t of
+// every slice).  Ranks come from a ballot + mbcnt inside each wave and one
+// scan over the (slice, wave) counts of the round; the accepted queries of
+// the pair's earlier chunks are counted first from their flags, so the
+// chunks of a large pair are emitted side by side.
 constexpr int kEmitPer = 8;
 constexpr int kEmitWaves = kEmitThreads / 64;
+constexpr int32_t kEmitChunk = kEmitThreads * kEmitPer;
 
 __global__ __launch_bounds__(kEmitThreads) void emit_kernel(BatchView v, int32_t pb,
                                                             const int64_t* offset, int32_t* oq,
@@ -60,30 +67,48 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(BatchView v, int32_t
   __shared__ int32_t run;
   const int32_t p = pb + blockIdx.x;
   const PairDesc P = v.pairs[p];
+  const int32_t first = int32_t(blockIdx.y) * kEmitChunk;
+  if (first >= P.na) return;
+  const int32_t last = blockIdx.y + 1 < gridDim.y ? min(P.na, first + kEmitChunk) : P.na;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t out0 = offset[p];
   const QueryResult* res = v.res + P.q_off;
-  if (t == 0) run = 0;
+  // Accepted queries of the chunks before this one.
+  int32_t before = 0;
+#pragma unroll 8
+  for (int32_t i = t; i < first; i += kEmitThreads) before += res[i].flags & 1;
+  for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
+  if (lane == 0) cnt[wv] = before;
   __syncthreads();
-  for (int32_t base = 0; base < P.na; base += kEmitThreads * kEmitPer) {
+  if (t == 0) {
+    int32_t r = 0;
+    for (int w = 0; w < kEmitWaves; ++w) r += cnt[w];
+    run = r;
+  }
+  __syncthreads();
+  for (int32_t base = first; base < last; base += kEmitChunk) {
     const int32_t rbase = run;   // rows before this round (read before its first barrier)
     QueryResult r[kEmitPer];
 #pragma unroll
     for (int k = 0; k < kEmitPer; ++k) {
       const int32_t i = base + k * kEmitThreads + t;
-      if (i < P.na) {
+      if (i < last) {
         r[k] = res[i];
-        // The match kernel leaves the binned position of the match.
-        if (v.cand_j && r[k].match >= 0) r[k].match = v.cand_j[P.c_off + r[k].match];
       } else {
         r[k].match = -1; r[k].d1 = r[k].d2 = kDistInf; r[k].flags = 0;
       }
     }
+    // The match kernel leaves the binned position of the match; only rows
+    // that are written need its index in b.
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k)
+      if (v.cand_j && r[k].match >= 0 && (am || (r[k].flags & 1)))
+        r[k].match = v.cand_j[P.c_off + r[k].match];
     int32_t pre[kEmitPer];
 #pragma unroll
     for (int k = 0; k < kEmitPer; ++k) {
       const int32_t i = base + k * kEmitThreads + t;
-      if (am && i < P.na) {
+      if (am && i < last) {
         am[P.q_off + i] = r[k].match;
         ad1[P.q_off + i] = r[k].d1;
         ad2[P.q_off + i] = r[k].d2;
@@ -133,8 +158,9 @@ hipError_t launch_emit(const BatchView& v, int32_t pb, int32_t pc, int64_t* offs
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, st, v, pb, pc, offset, n_cmp,
                      n_bl);
-  hipLaunchKernelGGL(emit_kernel, dim3(pc), dim3(kEmitThreads), 0, st, v, pb, offset, oq, om, od1,
-                     od2, am, ad1, ad2, ac);
+  const uint32_t chunks = uint32_t(std::max(1, (v.max_na + kEmitChunk - 1) / kEmitChunk));
+  hipLaunchKernelGGL(emit_kernel, dim3(pc, chunks), dim3(kEmitThreads), 0, st, v, pb, offset, oq,
+                     om, od1, od2, am, ad1, ad2, ac);
   return hipGetLastError();
 }
 

@@ -528,35 +528,59 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
 // Candidate range of every query tile (the union of its queries' bin windows
 // mapped through b's bin starts) and of every group of K consecutive tiles,
 // with the group record and its schedule cost.  Block (p, c) takes queries
-// [256c, 256c + 256) of pair p: one thread per query, min/max reductions over
-// the 16 lanes of a tile, one thread per group.
+// [1024c, 1024c + 1024) of pair p: four queries per thread (their loads
+// issued together), min/max reductions over the 16 lanes of a tile, one
+// thread per group.  Few, fuller blocks: each block is one chain of
+// dependent loads, and the chains of all blocks are what the kernel waits on.
 constexpr int kRangeThreads = 256;
-constexpr int kRangeTiles = kRangeThreads / kQueryTile;
+constexpr int kRangeQpt = 4;
+constexpr int kRangeQueries = kRangeThreads * kRangeQpt;
+constexpr int kRangeTiles = kRangeQueries / kQueryTile;
 static_assert(kRangeTiles % kMaxGroupTiles == 0, "a block holds whole groups");
+static_assert(kRangeTiles / 4 <= 64, "a block's groups fit in its first wave");
 
 template <int K>
 __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v, int32_t pb) {
   __shared__ int2 trange[kRangeTiles];
   const int32_t p = pb + blockIdx.x;
   const PairDesc P = v.pairs[p];
-  const int32_t q0 = int32_t(blockIdx.y) * kRangeThreads;
+  const int32_t q0 = int32_t(blockIdx.y) * kRangeQueries;
   if (q0 >= P.na) return;
   const int t = threadIdx.x, lane = t & 63;
-  const int32_t s = q0 + t;
-  const int2 w = s < P.na ? v.qwin[P.q_off + s] : make_int2(1, 0);
-  int32_t lo = w.x <= w.y ? w.x : 0x7FFFFFFF;
-  int32_t hi = w.x <= w.y ? w.y : -1;
-  for (int o = kQueryTile / 2; o > 0; o >>= 1) {   // stays within the tile's 16 lanes
-    lo = min(lo, __shfl_xor(lo, o, 64));
-    hi = max(hi, __shfl_xor(hi, o, 64));
+  // What the group records take from the pair's images and geometry, read
+  // before the queries' windows so the loads overlap.
+  const ImageDev A = v.images[P.a];
+  const ImageDev B = v.images[P.b];
+  const float band_lo = v.geom[p].band_lo, band_hi = v.geom[p].band_hi;
+  int2 w[kRangeQpt];
+#pragma unroll
+  for (int u = 0; u < kRangeQpt; ++u) {
+    const int32_t s = q0 + kRangeThreads * u + t;
+    w[u] = s < P.na ? v.qwin[P.q_off + s] : make_int2(1, 0);
+  }
+  int32_t lo[kRangeQpt], hi[kRangeQpt];
+#pragma unroll
+  for (int u = 0; u < kRangeQpt; ++u) {
+    lo[u] = w[u].x <= w[u].y ? w[u].x : 0x7FFFFFFF;
+    hi[u] = w[u].x <= w[u].y ? w[u].y : -1;
+    for (int o = kQueryTile / 2; o > 0; o >>= 1) {   // stays within the tile's 16 lanes
+      lo[u] = min(lo[u], __shfl_xor(lo[u], o, 64));
+      hi[u] = max(hi[u], __shfl_xor(hi[u], o, 64));
+    }
   }
   if ((t & (kQueryTile - 1)) == 0) {
-    int32_t sb = 0, se = 0;
-    if (lo <= hi) {
-      sb = v.bin_start[P.bin_off + lo];
-      se = v.bin_start[P.bin_off + hi + 1];
+    int32_t sb[kRangeQpt], se[kRangeQpt];
+#pragma unroll
+    for (int u = 0; u < kRangeQpt; ++u) {
+      sb[u] = se[u] = 0;
+      if (lo[u] <= hi[u]) {
+        sb[u] = v.bin_start[P.bin_off + lo[u]];
+        se[u] = v.bin_start[P.bin_off + hi[u] + 1];
+      }
     }
-    trange[t / kQueryTile] = make_int2(sb, se);
+#pragma unroll
+    for (int u = 0; u < kRangeQpt; ++u)
+      trange[(kRangeThreads * u + t) / kQueryTile] = make_int2(sb[u], se[u]);
   }
   __syncthreads();
   const int32_t tiles_here = min(kRangeTiles, (P.na - q0 + kQueryTile - 1) / kQueryTile);
@@ -566,8 +590,6 @@ __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v,
     const int32_t g = int32_t(blockIdx.y) * (kRangeTiles / K) + t;
     const int32_t k0 = g * K;
     const int32_t nt = min(K, P.nblocks - k0);
-    const ImageDev A = v.images[P.a];
-    const ImageDev B = v.images[P.b];
     TileGroup tg;
     memset(&tg, 0, sizeof tg);
     int32_t gb = 0x7FFFFFFF, ge = 0, steps = 0;
@@ -589,8 +611,8 @@ __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v,
     tg.na = P.na;
     tg.s_begin = gb <= ge ? gb : 0;
     tg.s_end = gb <= ge ? ge : 0;
-    tg.band_lo = v.geom[p].band_lo;
-    tg.band_hi = v.geom[p].band_hi;
+    tg.band_lo = band_lo;
+    tg.band_hi = band_hi;
     tg.q_off = P.q_off;
     tg.c_off = P.c_off;
     tg.a_desc = A.desc;
@@ -692,7 +714,7 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t gr
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
   hipLaunchKernelGGL(bin_kernel, dim3(2 * pc), dim3(kBinThreads), 0, st, v, pb, order);
-  const int32_t qblocks = (max_queries + kRangeThreads - 1) / kRangeThreads;
+  const int32_t qblocks = (max_queries + kRangeQueries - 1) / kRangeQueries;
   if (qblocks > 0) {
     const dim3 grid(pc, qblocks), block(kRangeThreads);
     if (v.group_tiles == 4)

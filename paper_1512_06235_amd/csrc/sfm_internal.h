@@ -153,6 +153,7 @@ struct BatchView {
   int32_t accept_single;
   int32_t keep_counts;
   int32_t group_tiles;      // tiles per group (4 or 8: one or two per match wave)
+  int32_t max_na;           // most queries of one pair (sizes the emission grid)
   double margin;            // FP64 re-decision margin around d, pixels (0 = FP32 only)
 };
 
