@@ -110,7 +110,7 @@ int hip_fail(sfm_ctx* ctx, hipError_t e, const char* what) {
 // Sections of one call's workspace.
 struct Layout {
   size_t pairs, F, order, geom, counters, wg_start, cand_x, cand_y, cand_nc, cand_j, bins, qrec,
-      res, qwin, groups, gcost, pcost, total, staged;
+      res, twin, groups, gcost, pcost, total, staged;
   int32_t wgs = 0;
   int64_t sum_na = 0, sum_nc = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
   int32_t max_na = 0;
@@ -147,7 +147,7 @@ Layout plan(const PairDesc* pd, size_t P, int32_t device, int32_t group_tiles) {
   L.bins = o; o = align_up(o + size_t(L.sum_bins) * sizeof(int32_t));
   L.qrec = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryRec));
   L.res = o; o = align_up(o + size_t(L.sum_na) * sizeof(QueryResult));
-  L.qwin = o; o = align_up(o + size_t(L.sum_na) * sizeof(int2));
+  L.twin = o; o = align_up(o + size_t(L.sum_blocks) * sizeof(int2));
   L.groups = o; o = align_up(o + size_t(L.sum_groups) * sizeof(TileGroup));
   L.gcost = o; o = align_up(o + size_t(L.sum_groups) * sizeof(int32_t));
   L.pcost = o; o = align_up(o + P * sizeof(long long));
@@ -423,7 +423,7 @@ BatchView batch_view(const sfm_ctx* ctx, const ImageTable& tab, char* ws, const 
   v.bin_start = reinterpret_cast<int32_t*>(ws + L.bins);
   v.qrec = reinterpret_cast<QueryRec*>(ws + L.qrec);
   v.res = reinterpret_cast<QueryResult*>(ws + L.res);
-  v.qwin = reinterpret_cast<int2*>(ws + L.qwin);
+  v.twin = reinterpret_cast<int2*>(ws + L.twin);
   v.wg_start = reinterpret_cast<int32_t*>(ws + L.wg_start);
   v.gcost = reinterpret_cast<int32_t*>(ws + L.gcost);
   v.pcost = reinterpret_cast<long long*>(ws + L.pcost);

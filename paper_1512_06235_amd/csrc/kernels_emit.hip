@@ -115,7 +115,8 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(BatchView v, int32_t
         ac[P.q_off + i] = r[k].flags >> 1;
       }
       const unsigned long long m = __ballot((r[k].flags & 1) != 0);
-      pre[k] = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0));
+      pre[k] = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
+                                         __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0));
       if (lane == 0) cnt[k * kEmitWaves + wv] = __builtin_popcountll(m);
     }
     __syncthreads();

@@ -332,9 +332,10 @@ constexpr int kCacheRounds = 3;
 
 // Counting sort of one side of a pair: the targets of b into binned order
 // (and the bin starts), or the queries of a into tile order.
-// Writes one item at its sorted position.
+// Writes one item at its sorted position; a query also returns its bin
+// window (first, last bin; first > last: none).
 template <bool kTargets>
-__device__ __forceinline__ void write_sorted(const BatchView& v, const PairDesc& P,
+__device__ __forceinline__ int2 write_sorted(const BatchView& v, const PairDesc& P,
                                              const PairGeom& g, int32_t pos, int32_t j, float x,
                                              float y, int32_t nrm) {
   if (kTargets) {
@@ -343,13 +344,30 @@ __device__ __forceinline__ void write_sorted(const BatchView& v, const PairDesc&
     v.cand_nc[P.c_off + pos] =
         ((uint32_t(nrm) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
     v.cand_j[P.c_off + pos] = j;
+    return make_int2(1, 0);
   } else {
     const QueryLine q = query_line(g, x, y);
     QueryRec rq;
     rq.a = q.a; rq.b = q.b; rq.c = q.c; rq.i = j;
     v.qrec[P.q_off + pos] = rq;
-    v.qwin[P.q_off + pos] = make_int2(q.wlo, q.whi);
+    return make_int2(q.wlo, q.whi);
   }
+}
+
+// The bin window of a query tile (positions 16 t .. 16 t + 15, held by 16
+// consecutive lanes): the union of its queries' windows, by min / max
+// shuffles within the 16 lanes (every lane takes part; lanes without a query
+// pass an empty window), stored by the tile's first lane.
+__device__ __forceinline__ void store_tile_window(const BatchView& v, const PairDesc& P,
+                                                  int32_t pos, int32_t n, int2 w) {
+  int32_t lo = w.x <= w.y ? w.x : 0x7FFFFFFF;
+  int32_t hi = w.x <= w.y ? w.y : -1;
+  for (int o = kQueryTile / 2; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
+  if ((pos & (kQueryTile - 1)) == 0 && pos < n)
+    v.twin[P.blk_off + pos / kQueryTile] = make_int2(lo, hi);
 }
 
 // When `perm` is given (the side fits in LDS), pass 2 only records which
@@ -403,14 +421,29 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
       if (j >= n) continue;
       const int32_t bin = keep ? keep[k] : item_bin(px[k], py[k]);
       const int32_t pos = atomicAdd(&hist[bin], 1);
-      if (perm)
+      if (perm) {
         perm[pos] = uint16_t(j);
-      else
-        write_sorted<kTargets>(v, P, g, pos, j, px[k], py[k], kTargets ? nrm[k] : 0);
+      } else {
+        const int2 w =
+            write_sorted<kTargets>(v, P, g, pos, j, px[k], py[k], kTargets ? nrm[k] : 0);
+        // Scattered positions: the tile windows (cleared before the count
+        // pass) are merged with atomics.
+        if (!kTargets && w.x <= w.y) {
+          int2* tw = v.twin + P.blk_off + pos / kQueryTile;
+          atomicMin(&tw->x, w.x);
+          atomicMax(&tw->y, w.y);
+        }
+      }
     }
   };
 
   const int32_t rounds = (n + kStride - 1) / kStride;
+  if (!kTargets && !perm) {
+    // Empty windows for the atomics of the direct path (the barriers of the
+    // scan order these stores before them).
+    for (int32_t t = threadIdx.x; t < P.nblocks; t += blockDim.x)
+      v.twin[P.blk_off + t] = make_int2(0x7FFFFFFF, -1);
+  }
   int32_t keep[kCacheRounds][kBatch];
 #pragma unroll
   for (int32_t r = 0; r < kCacheRounds; ++r)
@@ -429,8 +462,10 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
   for (int32_t r = kCacheRounds; r < rounds; ++r) place_round(r, nullptr);
   if (!perm) return;
   __syncthreads();
-  // Gather pass: positions in order, kBatch per thread per round.
-  for (int32_t base = threadIdx.x; base < n; base += kStride) {
+  // Gather pass: positions in order, kBatch per thread per round (every
+  // thread runs every round: the tile windows shuffle across lanes).
+  for (int32_t r = 0; r < rounds; ++r) {
+    const int32_t base = r * kStride + threadIdx.x;
     int32_t jj[kBatch], nrm[kBatch];
     float px[kBatch], py[kBatch];
 #pragma unroll
@@ -449,7 +484,10 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
       const int32_t pos = base + k * kBinThreads;
-      if (pos < n) write_sorted<kTargets>(v, P, g, pos, jj[k], px[k], py[k], kTargets ? nrm[k] : 0);
+      int2 w = make_int2(1, 0);
+      if (pos < n)
+        w = write_sorted<kTargets>(v, P, g, pos, jj[k], px[k], py[k], kTargets ? nrm[k] : 0);
+      if (!kTargets) store_tile_window(v, P, pos, n, w);
     }
   }
 }
@@ -460,8 +498,8 @@ constexpr int kBinLdsInts = 16384;
 constexpr int kBinWsum = kBinThreads / 64;
 static_assert(kMaxBins + 2 + kBinWsum <= kBinLdsInts, "histogram fits");
 
-__global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t pb,
-                                                          const int32_t* order) {
+__global__ __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void bin_kernel(BatchView v, int32_t pb, const int32_t* order) {
   __shared__ int32_t lds[kBinLdsInts];
   int32_t* const wsum = lds + kBinLdsInts - kBinWsum;
   int32_t* const hist = lds;
@@ -497,8 +535,9 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
         QueryRec r;
         r.a = 0.0f; r.b = 0.0f; r.c = 0.0f; r.i = i;
         v.qrec[P.q_off + i] = r;
-        v.qwin[P.q_off + i] = make_int2(0, 0);
       }
+      for (int32_t t = threadIdx.x; t < P.nblocks; t += blockDim.x)
+        v.twin[P.blk_off + t] = make_int2(0, 0);
     }
     return;
   }
@@ -525,17 +564,12 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BatchView v, int32_t p
   }
 }
 
-// Candidate range of every query tile (the union of its queries' bin windows
-// mapped through b's bin starts) and of every group of K consecutive tiles,
-// with the group record and its schedule cost.  Block (p, c) takes queries
-// [1024c, 1024c + 1024) of pair p: four queries per thread (their loads
-// issued together), min/max reductions over the 16 lanes of a tile, one
-// thread per group.  Few, fuller blocks: each block is one chain of
-// dependent loads, and the chains of all blocks are what the kernel waits on.
+// Candidate range of every query tile (its bin window mapped through b's
+// bin starts) and of every group of K consecutive tiles, with the group
+// record and its schedule cost.  Block (p, c) takes tiles [256c, 256c + 256)
+// of pair p: one thread per tile, one thread per group.
 constexpr int kRangeThreads = 256;
-constexpr int kRangeQpt = 4;
-constexpr int kRangeQueries = kRangeThreads * kRangeQpt;
-constexpr int kRangeTiles = kRangeQueries / kQueryTile;
+constexpr int kRangeTiles = kRangeThreads;
 static_assert(kRangeTiles % kMaxGroupTiles == 0, "a block holds whole groups");
 static_assert(kRangeTiles / 4 <= 64, "a block's groups fit in its first wave");
 
@@ -544,46 +578,23 @@ __global__ __launch_bounds__(kRangeThreads) void tile_ranges_kernel(BatchView v,
   __shared__ int2 trange[kRangeTiles];
   const int32_t p = pb + blockIdx.x;
   const PairDesc P = v.pairs[p];
-  const int32_t q0 = int32_t(blockIdx.y) * kRangeQueries;
-  if (q0 >= P.na) return;
+  const int32_t tile0 = int32_t(blockIdx.y) * kRangeTiles;
+  if (tile0 >= P.nblocks) return;
   const int t = threadIdx.x, lane = t & 63;
   // What the group records take from the pair's images and geometry, read
-  // before the queries' windows so the loads overlap.
+  // before the tile windows so the loads overlap.
   const ImageDev A = v.images[P.a];
   const ImageDev B = v.images[P.b];
   const float band_lo = v.geom[p].band_lo, band_hi = v.geom[p].band_hi;
-  int2 w[kRangeQpt];
-#pragma unroll
-  for (int u = 0; u < kRangeQpt; ++u) {
-    const int32_t s = q0 + kRangeThreads * u + t;
-    w[u] = s < P.na ? v.qwin[P.q_off + s] : make_int2(1, 0);
+  int2 r = make_int2(0, 0);
+  if (tile0 + t < P.nblocks) {
+    const int2 w = v.twin[P.blk_off + tile0 + t];
+    if (w.x <= w.y)
+      r = make_int2(v.bin_start[P.bin_off + w.x], v.bin_start[P.bin_off + w.y + 1]);
   }
-  int32_t lo[kRangeQpt], hi[kRangeQpt];
-#pragma unroll
-  for (int u = 0; u < kRangeQpt; ++u) {
-    lo[u] = w[u].x <= w[u].y ? w[u].x : 0x7FFFFFFF;
-    hi[u] = w[u].x <= w[u].y ? w[u].y : -1;
-    for (int o = kQueryTile / 2; o > 0; o >>= 1) {   // stays within the tile's 16 lanes
-      lo[u] = min(lo[u], __shfl_xor(lo[u], o, 64));
-      hi[u] = max(hi[u], __shfl_xor(hi[u], o, 64));
-    }
-  }
-  if ((t & (kQueryTile - 1)) == 0) {
-    int32_t sb[kRangeQpt], se[kRangeQpt];
-#pragma unroll
-    for (int u = 0; u < kRangeQpt; ++u) {
-      sb[u] = se[u] = 0;
-      if (lo[u] <= hi[u]) {
-        sb[u] = v.bin_start[P.bin_off + lo[u]];
-        se[u] = v.bin_start[P.bin_off + hi[u] + 1];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kRangeQpt; ++u)
-      trange[(kRangeThreads * u + t) / kQueryTile] = make_int2(sb[u], se[u]);
-  }
+  trange[t] = r;
   __syncthreads();
-  const int32_t tiles_here = min(kRangeTiles, (P.na - q0 + kQueryTile - 1) / kQueryTile);
+  const int32_t tiles_here = min(kRangeTiles, P.nblocks - tile0);
   const int32_t groups_here = (tiles_here + K - 1) / K;
   long long cost = 0;
   if (t < groups_here) {
@@ -714,7 +725,8 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t gr
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
   hipLaunchKernelGGL(bin_kernel, dim3(2 * pc), dim3(kBinThreads), 0, st, v, pb, order);
-  const int32_t qblocks = (max_queries + kRangeQueries - 1) / kRangeQueries;
+  const int32_t tiles = (max_queries + kQueryTile - 1) / kQueryTile;
+  const int32_t qblocks = (tiles + kRangeTiles - 1) / kRangeTiles;
   if (qblocks > 0) {
     const dim3 grid(pc, qblocks), block(kRangeThreads);
     if (v.group_tiles == 4)

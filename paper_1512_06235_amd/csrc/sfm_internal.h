@@ -138,7 +138,7 @@ struct BatchView {
   int32_t* cand_j;
   int32_t* bin_start;       // nbins + 1 per pair
   QueryRec* qrec;
-  int2* qwin;               // per query in tile order: first, last bin (first > last = none)
+  int2* twin;               // per query tile: first, last bin of its queries (first > last: none)
   TileGroup* groups;
   int32_t* gcost;           // per tile group: estimated cost of matching it
   long long* pcost;         // per pair: the sum of its groups' costs
