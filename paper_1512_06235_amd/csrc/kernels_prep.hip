@@ -332,6 +332,20 @@ constexpr int kCacheRounds = 3;
 
 // Counting sort of one side of a pair: the targets of b into binned order
 // (and the bin starts), or the queries of a into tile order.
+// Global loads and stores through address-space-1 pointers (the pointers
+// live in records, so the compiler would otherwise emit flat accesses, which
+// also count against the LDS counter).  The passes below load every slot of a
+// round unconditionally at a clamped index, so a round's loads are all in
+// flight together instead of each waiting in its own branch.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void stg(T* p, const T& x) {
+  *(__attribute__((address_space(1))) T*)p = x;
+}
+
 // Writes one item at its sorted position; a query also returns its bin
 // window (first, last bin; first > last: none).
 template <bool kTargets>
@@ -339,17 +353,18 @@ __device__ __forceinline__ int2 write_sorted(const BatchView& v, const PairDesc&
                                              const PairGeom& g, int32_t pos, int32_t j, float x,
                                              float y, int32_t nrm) {
   if (kTargets) {
-    v.cand_x[P.c_off + pos] = float(double(x) - g.ox);
-    v.cand_y[P.c_off + pos] = float(double(y) - g.oy);
-    v.cand_nc[P.c_off + pos] =
-        ((uint32_t(nrm) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1));
-    v.cand_j[P.c_off + pos] = j;
+    stg(v.cand_x + P.c_off + pos, float(double(x) - g.ox));
+    stg(v.cand_y + P.c_off + pos, float(double(y) - g.oy));
+    stg(v.cand_nc + P.c_off + pos,
+        ((uint32_t(nrm) + kDistBias) << kPosBits) | uint32_t(pos & (kChunk - 1)));
+    stg(v.cand_j + P.c_off + pos, j);
     return make_int2(1, 0);
   } else {
     const QueryLine q = query_line(g, x, y);
-    QueryRec rq;
-    rq.a = q.a; rq.b = q.b; rq.c = q.c; rq.i = j;
-    v.qrec[P.q_off + pos] = rq;
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    static_assert(sizeof(QueryRec) == sizeof(u4), "a query record is one 16-byte store");
+    const u4 rq = {__float_as_uint(q.a), __float_as_uint(q.b), __float_as_uint(q.c), uint32_t(j)};
+    stg(reinterpret_cast<u4*>(v.qrec + P.q_off + pos), rq);
     return make_int2(q.wlo, q.whi);
   }
 }
@@ -390,8 +405,9 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
     float px[kBatch], py[kBatch];
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
-      const int32_t j = base + k * kBinThreads;
-      if (j < n) { px[k] = I.xy[2 * j]; py[k] = I.xy[2 * j + 1]; }
+      const int32_t j = min(base + k * kBinThreads, n - 1);
+      px[k] = ldg(I.xy + 2 * j);
+      py[k] = ldg(I.xy + 2 * j + 1);
     }
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
@@ -407,12 +423,13 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
     const int32_t base = r * kStride + threadIdx.x;
     float px[kBatch], py[kBatch];
     int32_t nrm[kBatch];
+    if (!perm || !keep) {
 #pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-      const int32_t j = base + k * kBinThreads;
-      if (j < n && (!perm || !keep)) {
-        px[k] = I.xy[2 * j]; py[k] = I.xy[2 * j + 1];
-        if (kTargets && !perm) nrm[k] = I.norm2[j];
+      for (int k = 0; k < kBatch; ++k) {
+        const int32_t j = min(base + k * kBinThreads, n - 1);
+        px[k] = ldg(I.xy + 2 * j);
+        py[k] = ldg(I.xy + 2 * j + 1);
+        if (kTargets) nrm[k] = ldg(I.norm2 + j);   // used by the direct path only
       }
     }
 #pragma unroll
@@ -469,17 +486,12 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
     int32_t jj[kBatch], nrm[kBatch];
     float px[kBatch], py[kBatch];
 #pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-      const int32_t pos = base + k * kBinThreads;
-      if (pos < n) jj[k] = perm[pos];
-    }
+    for (int k = 0; k < kBatch; ++k) jj[k] = perm[min(base + k * kBinThreads, n - 1)];
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
-      const int32_t pos = base + k * kBinThreads;
-      if (pos < n) {
-        px[k] = I.xy[2 * jj[k]]; py[k] = I.xy[2 * jj[k] + 1];
-        if (kTargets) nrm[k] = I.norm2[jj[k]];
-      }
+      px[k] = ldg(I.xy + 2 * jj[k]);
+      py[k] = ldg(I.xy + 2 * jj[k] + 1);
+      if (kTargets) nrm[k] = ldg(I.norm2 + jj[k]);
     }
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
