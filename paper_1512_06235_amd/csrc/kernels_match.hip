@@ -67,6 +67,14 @@ static_assert(kQueryTile == kBlock, "one MFMA column block of queries per tile")
 static_assert(kBuf <= kChunk, "a tile's steps in one fill fit one key chunk");
 constexpr uint32_t kKeyDistInf = kKeyInf >> kPosBits;
 
+// A global load through an address-space-1 pointer: the pointers used with
+// it come from records, and the flat loads the compiler would otherwise emit
+// also count against the LDS counter, so each would be waited for alone.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // Epipolar distance of eqs. (2)-(3) on centred FP32 coordinates,
 // |a x + b y + c| with (a, b) unit.  The single FP32 evaluation every pass uses.
 __device__ __forceinline__ float band_dist32(float a, float b, float c, float x, float y) {
@@ -82,12 +90,18 @@ __device__ __forceinline__ double band_dist64(const double* F, float xq, float y
                                            float yb) {
 #pragma clang fp contract(off)
   const double x = xq, y = yq;
-  const double a = F[0] * x + F[1] * y + F[2];
-  const double b = F[3] * x + F[4] * y + F[5];
-  const double c = F[6] * x + F[7] * y + F[8];
+  double f[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) f[k] = ldg(F + k);
+  const double a = f[0] * x + f[1] * y + f[2];
+  const double b = f[3] * x + f[4] * y + f[5];
+  const double c = f[6] * x + f[7] * y + f[8];
   const double s = sqrt(a * a + b * b);
-  if (!(s > 0.0) || !isfinite(s) || !isfinite(c)) return NAN;
-  return fabs(a * double(xb) + b * double(yb) + c) / s;
+  const bool line = s > 0.0 && isfinite(s) && isfinite(c);
+  // Computed either way and selected, so the loads of (xb, yb) are not
+  // moved into a branch behind this one's.
+  const double e = fabs(a * double(xb) + b * double(yb) + c) / s;
+  return line ? e : NAN;
 }
 
 // Per-byte negation of four bytes in 0..127 (no borrow crosses a byte).
@@ -680,8 +694,10 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
     bool in = false;
     if (lane < nbq) {
       const int32_t j = int32_t(en.z);
-      in = band_dist64(gr.F, gr.a_xy[2 * qi], gr.a_xy[2 * qi + 1], gr.b_xy[2 * j],
-                       gr.b_xy[2 * j + 1]) <= gr.d;
+      // The keypoints' and F's loads are independent: all are in flight together.
+      const float xq = ldg(gr.a_xy + 2 * qi), yq = ldg(gr.a_xy + 2 * qi + 1);
+      const float xb = ldg(gr.b_xy + 2 * j), yb = ldg(gr.b_xy + 2 * j + 1);
+      in = band_dist64(gr.F, xq, yq, xb, yb) <= gr.d;
     }
     const unsigned long long inm = __ballot(in);
     if (!kKeepCounts) wcnt += __builtin_popcountll(inm);
