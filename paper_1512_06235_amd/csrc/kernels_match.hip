@@ -609,11 +609,16 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
       uint32_t om = uint32_t((q0 + 4 * rg) * 4);
       // The first step's operands; each step reads the next one's before
       // its own fold (the read after the last step wraps and is unused).
+      const uint32_t oa0 = oa, om0 = om;
       v4i na0 = *reinterpret_cast<const v4i*>(&L.rows[oa]);
       v4i na1 = *reinterpret_cast<const v4i*>(&L.rows[oa ^ 64u]);
       float4 nxs = reinterpret_cast<const float4*>(L.x)[om >> 4];
       float4 nys = reinterpret_cast<const float4*>(L.y)[om >> 4];
       uint4 nns = reinterpret_cast<const uint4*>(L.nc)[om >> 4];
+      // Steps of this fill (at most kBuf / 16) with a slot within the margin
+      // of d: only marked here, so the loop keeps nothing live for them.
+      static_assert(kBuf / kBlock <= 32, "one bit per step of a fill");
+      uint32_t bsteps = 0;
       for (int32_t i = 0; i < n; ++i) {
         v4i acc = {0, 0, 0, 0};
         acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(na0, t.bq[0], acc, 0, 0, 0);
@@ -628,15 +633,13 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
         nxs = reinterpret_cast<const float4*>(L.x)[om >> 4];
         nys = reinterpret_cast<const float4*>(L.y)[om >> 4];
         nns = reinterpret_cast<const uint4*>(L.nc)[om >> 4];
-        unsigned long long bm[4];
-        uint32_t keys[4];
+        unsigned long long border = 0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const float d32 = band_dist32(t.a, t.b, t.c, xv[e], yv[e]);
           const bool mem = d32 <= lo;
-          bm[e] = __ballot(d32 <= hi) & ~__ballot(mem);
-          keys[e] = nv[e] + (uint32_t(acc[e]) << 11);
-          const uint32_t kin = mem ? keys[e] : kKeyInf;
+          border |= __ballot(d32 <= hi) & ~__ballot(mem);
+          const uint32_t kin = mem ? nv[e] + (uint32_t(acc[e]) << 11) : kKeyInf;
           t.k2 = umed3(t.k1, kin, t.k2);
           t.k1 = min(t.k1, kin);
           if (kKeepCounts)
@@ -644,10 +647,37 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
           else
             wcnt += __builtin_popcountll(__ballot(mem));
         }
-        if (bm[0] | bm[1] | bm[2] | bm[3]) {
-          // Rare: queue the step's slots within the margin of d, with their
-          // exact keys and indices in b, for the FP64 decision after the
-          // group's tiles (the index buffer holds the whole fill).
+        if (border) bsteps |= 1u << i;
+      }
+      // Rare: the marked steps again (the same operations, so the same keys),
+      // queueing their slots within the margin of d with their exact keys and
+      // indices in b for the FP64 decision after the group's tiles (the index
+      // buffer holds the whole fill).
+      while (bsteps) {
+        const int32_t i = __builtin_ctz(bsteps);
+        bsteps &= bsteps - 1;
+        const uint32_t oai = (oa0 + uint32_t(i) * (kBlock * kDescBytes)) & (kBuf * kDescBytes - 1);
+        const uint32_t omi = (om0 + uint32_t(i) * (4 * kBlock)) & (4 * kBuf - 1);
+        const v4i a0 = *reinterpret_cast<const v4i*>(&L.rows[oai]);
+        const v4i a1 = *reinterpret_cast<const v4i*>(&L.rows[oai ^ 64u]);
+        const float4 xs = reinterpret_cast<const float4*>(L.x)[omi >> 4];
+        const float4 ys = reinterpret_cast<const float4*>(L.y)[omi >> 4];
+        const uint4 ns = reinterpret_cast<const uint4*>(L.nc)[omi >> 4];
+        v4i acc = {0, 0, 0, 0};
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, t.bq[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, t.bq[1], acc, 0, 0, 0);
+        const float xv[4] = {xs.x, xs.y, xs.z, xs.w};
+        const float yv[4] = {ys.x, ys.y, ys.z, ys.w};
+        const uint32_t nv[4] = {ns.x, ns.y, ns.z, ns.w};
+        unsigned long long bm[4];
+        uint32_t keys[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float d32 = band_dist32(t.a, t.b, t.c, xv[e], yv[e]);
+          bm[e] = __ballot(d32 <= hi) & ~__ballot(d32 <= lo);
+          keys[e] = nv[e] + (uint32_t(acc[e]) << 11);
+        }
+        {
           const int32_t p = p0 + kBlock * i;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -701,14 +731,18 @@ __device__ __forceinline__ void match_group(const BatchView& v, const TileGroup&
     }
     const unsigned long long inm = __ballot(in);
     if (!kKeepCounts) wcnt += __builtin_popcountll(inm);
-    for (int32_t e = 0; e < nbq; ++e) {
-      if (!((inm >> e) & 1ull)) continue;
-      const uint4 q = L.queue[w][e];
-      if (lane != int(q.y & (kQueryTile - 1))) continue;
+    // Entry e is in lane e's registers: broadcast each member to its owner.
+    unsigned long long todo = inm;
+    while (todo) {
+      const int e = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const uint32_t qx = __builtin_amdgcn_readlane(en.x, e);
+      const uint32_t qy = __builtin_amdgcn_readlane(en.y, e);
+      if (lane != int(qy & (kQueryTile - 1))) continue;
 #pragma unroll
       for (int k = 0; k < TPW; ++k) {
-        if (int((q.y >> 6) & 1) == k) {
-          fold_state(T[k], q.x >> kPosBits, s.base + int32_t(q.y >> 7));
+        if (int((qy >> 6) & 1) == k) {
+          fold_state(T[k], qx >> kPosBits, s.base + int32_t(qy >> 7));
           if (kKeepCounts) ++T[k].cnt;
         }
       }
