@@ -324,9 +324,12 @@ __device__ void block_exclusive_scan(int32_t* cnt, int32_t n, int32_t* wsum) {
 // the passes, so their FP64 keys are computed once.  `order` (may be NULL)
 // maps blockIdx.x to the pair, largest pairs first.
 // ---------------------------------------------------------------------------
-// 512 threads at 128 VGPRs fit two binning workgroups per CU (1,024 fit
-// one), which overlaps one pair's barrier phases with another's work.
+// 512 threads at 128 VGPRs fit two binning workgroups per CU, which
+// overlaps one pair's barrier phases with another's work; a batch of few
+// pairs (at most one workgroup per CU) takes 1,024 threads per side
+// instead, which halves each side's passes.
 constexpr int kBinThreads = 512;
+constexpr int kBinThreadsFew = 1024;
 constexpr int kBatch = 8;   // items per thread per round; their loads are issued together
 constexpr int kCacheRounds = 3;
 
@@ -389,11 +392,11 @@ __device__ __forceinline__ void store_tile_window(const BatchView& v, const Pair
 // item lands at each position; a gather pass then writes the outputs in
 // position order, so the stores are coalesced instead of scattered 8- and
 // 16-byte writes that the L2 cannot merge once a batch outgrows it.
-template <bool kTargets>
+template <int NT, bool kTargets>
 __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
                                           const PairGeom& g, const ImageDev& I, int32_t* hist,
                                           int32_t* wsum, int32_t nh, uint16_t* perm) {
-  constexpr int32_t kStride = kBatch * kBinThreads;
+  constexpr int32_t kStride = kBatch * NT;
   const int32_t n = kTargets ? P.nb : P.na;
   // The bin of one item (FP64 key of a target, sort key of a query).
   auto item_bin = [&](float x, float y) -> int32_t {
@@ -405,13 +408,13 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
     float px[kBatch], py[kBatch];
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
-      const int32_t j = min(base + k * kBinThreads, n - 1);
+      const int32_t j = min(base + k * NT, n - 1);
       px[k] = ldg(I.xy + 2 * j);
       py[k] = ldg(I.xy + 2 * j + 1);
     }
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
-      if (base + k * kBinThreads < n) {
+      if (base + k * NT < n) {
         const int32_t bin = item_bin(px[k], py[k]);
         atomicAdd(&hist[bin], 1);
         if (keep) keep[k] = bin;
@@ -426,7 +429,7 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
     if (!perm || !keep) {
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
-        const int32_t j = min(base + k * kBinThreads, n - 1);
+        const int32_t j = min(base + k * NT, n - 1);
         px[k] = ldg(I.xy + 2 * j);
         py[k] = ldg(I.xy + 2 * j + 1);
         if (kTargets) nrm[k] = ldg(I.norm2 + j);   // used by the direct path only
@@ -434,7 +437,7 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
     }
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
-      const int32_t j = base + k * kBinThreads;
+      const int32_t j = base + k * NT;
       if (j >= n) continue;
       const int32_t bin = keep ? keep[k] : item_bin(px[k], py[k]);
       const int32_t pos = atomicAdd(&hist[bin], 1);
@@ -467,7 +470,7 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
     if (r < rounds) count_round(r, keep[r]);
   for (int32_t r = kCacheRounds; r < rounds; ++r) count_round(r, nullptr);
   __syncthreads();
-  block_exclusive_scan<kBinThreads>(hist, nh, wsum);
+  block_exclusive_scan<NT>(hist, nh, wsum);
   if (kTargets) {
     for (int k = threadIdx.x; k < nh; k += blockDim.x) v.bin_start[P.bin_off + k] = hist[k];
     if (threadIdx.x == 0) v.bin_start[P.bin_off + nh] = P.nb;
@@ -486,7 +489,7 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
     int32_t jj[kBatch], nrm[kBatch];
     float px[kBatch], py[kBatch];
 #pragma unroll
-    for (int k = 0; k < kBatch; ++k) jj[k] = perm[min(base + k * kBinThreads, n - 1)];
+    for (int k = 0; k < kBatch; ++k) jj[k] = perm[min(base + k * NT, n - 1)];
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
       px[k] = ldg(I.xy + 2 * jj[k]);
@@ -495,7 +498,7 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
     }
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
-      const int32_t pos = base + k * kBinThreads;
+      const int32_t pos = base + k * NT;
       int2 w = make_int2(1, 0);
       if (pos < n)
         w = write_sorted<kTargets>(v, P, g, pos, jj[k], px[k], py[k], kTargets ? nrm[k] : 0);
@@ -507,11 +510,13 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
 // LDS of the binning workgroup: the histogram, the scan's wave sums and,
 // when the side fits, the 16-bit permutation of its items.
 constexpr int kBinLdsInts = 16384;
-constexpr int kBinWsum = kBinThreads / 64;
-static_assert(kMaxBins + 2 + kBinWsum <= kBinLdsInts, "histogram fits");
+constexpr int kBinWsumMax = kBinThreadsFew / 64;
+static_assert(kMaxBins + 2 + kBinWsumMax <= kBinLdsInts, "histogram fits");
 
-__global__ __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(4)))
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 void bin_kernel(BatchView v, int32_t pb, const int32_t* order) {
+  constexpr int kBinWsum = NT / 64;
   __shared__ int32_t lds[kBinLdsInts];
   int32_t* const wsum = lds + kBinLdsInts - kBinWsum;
   int32_t* const hist = lds;
@@ -570,9 +575,9 @@ void bin_kernel(BatchView v, int32_t pb, const int32_t* order) {
       v.cand_nc[o] = kKeyInf;
       v.cand_j[o] = 0;
     }
-    sort_side<true>(v, P, g, I, hist, wsum, nh, perm);
+    sort_side<NT, true>(v, P, g, I, hist, wsum, nh, perm);
   } else {
-    sort_side<false>(v, P, g, I, hist, wsum, nh, perm);
+    sort_side<NT, false>(v, P, g, I, hist, wsum, nh, perm);
   }
 }
 
@@ -731,12 +736,21 @@ hipError_t launch_register(const ImageDev* imgs_host, ImageDev* imgs_dev, int32_
   return hipGetLastError();
 }
 
+// Binning workgroups that one wave of 1,024-thread workgroups runs at once
+// (one per CU).
+constexpr int32_t kFewPairsWorkgroups = 256;
+
 hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t grp_begin,
                           int32_t grp_count, int32_t wgs, const int32_t* order,
                           int32_t max_queries, hipStream_t st) {
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
-  hipLaunchKernelGGL(bin_kernel, dim3(2 * pc), dim3(kBinThreads), 0, st, v, pb, order);
+  if (2 * pc <= kFewPairsWorkgroups)
+    hipLaunchKernelGGL(bin_kernel<kBinThreadsFew>, dim3(2 * pc), dim3(kBinThreadsFew), 0, st, v,
+                       pb, order);
+  else
+    hipLaunchKernelGGL(bin_kernel<kBinThreads>, dim3(2 * pc), dim3(kBinThreads), 0, st, v, pb,
+                       order);
   const int32_t tiles = (max_queries + kQueryTile - 1) / kQueryTile;
   const int32_t qblocks = (tiles + kRangeTiles - 1) / kRangeTiles;
   if (qblocks > 0) {
