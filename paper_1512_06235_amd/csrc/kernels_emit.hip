@@ -52,26 +52,49 @@ __global__ __launch_bounds__(1024) void scan_pairs_kernel(BatchView v, int32_t p
 // every slice).  Ranks come from a ballot + mbcnt inside each wave and one
 // scan over the (slice, wave) counts of the round; the accepted queries of
 // the pair's earlier chunks are counted first from their flags, so the
-// chunks of a large pair are emitted side by side.
+// chunks of a large pair are emitted side by side.  With `fused` (batches of
+// at most kEmitThreads pairs) the workgroup also sums the accepted queries of
+// the batch's earlier pairs for its first row, and the pair's first chunk
+// writes its offset and counts, so no separate scan over pairs runs first.
 constexpr int kEmitPer = 8;
 constexpr int kEmitWaves = kEmitThreads / 64;
 constexpr int32_t kEmitChunk = kEmitThreads * kEmitPer;
 
-__global__ __launch_bounds__(kEmitThreads) void emit_kernel(BatchView v, int32_t pb,
-                                                            const int64_t* offset, int32_t* oq,
+__global__ __launch_bounds__(kEmitThreads) void emit_kernel(BatchView v, int32_t pb, int32_t fused,
+                                                            int64_t* offset, int64_t* n_cmp,
+                                                            int64_t* n_bl, int32_t* oq,
                                                             int32_t* om, int32_t* od1,
                                                             int32_t* od2, int32_t* am,
                                                             int32_t* ad1, int32_t* ad2,
                                                             int32_t* ac) {
   __shared__ int32_t cnt[kEmitPer * kEmitWaves];   // accepted per (slice, wave), then prefix
   __shared__ int32_t run;
+  __shared__ long long wtot[kEmitWaves];
   const int32_t p = pb + blockIdx.x;
   const PairDesc P = v.pairs[p];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int64_t out0;
+  if (fused) {
+    // Rows of the batch's pairs before this one (p - pb < kEmitThreads).
+    long long a = t < p - pb ? (long long)v.counters[pb + t].accepted : 0;
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane == 0) wtot[wv] = a;
+    __syncthreads();
+    long long sum = 0;
+    for (int w = 0; w < kEmitWaves; ++w) sum += wtot[w];
+    out0 = (pb == 0 ? 0 : offset[pb]) + sum;   // offset[pb] comes from an earlier launch
+    if (blockIdx.y == 0 && t == 0) {
+      if (p == 0) offset[0] = 0;
+      offset[p + 1] = out0 + (long long)v.counters[p].accepted;
+      if (n_cmp) n_cmp[p] = (long long)v.counters[p].comparisons;
+      if (n_bl) n_bl[p] = (long long)v.counters[p].borderline;
+    }
+  } else {
+    out0 = offset[p];
+  }
   const int32_t first = int32_t(blockIdx.y) * kEmitChunk;
   if (first >= P.na) return;
   const int32_t last = blockIdx.y + 1 < gridDim.y ? min(P.na, first + kEmitChunk) : P.na;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int64_t out0 = offset[p];
   const QueryResult* res = v.res + P.q_off;
   // Accepted queries of the chunks before this one.
   int32_t before = 0;
@@ -157,11 +180,13 @@ hipError_t launch_emit(const BatchView& v, int32_t pb, int32_t pc, int64_t* offs
                        int32_t* om, int32_t* od1, int32_t* od2, int64_t* n_cmp, int64_t* n_bl,
                        int32_t* am, int32_t* ad1, int32_t* ad2, int32_t* ac, hipStream_t st) {
   if (pc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, st, v, pb, pc, offset, n_cmp,
-                     n_bl);
+  const int32_t fused = pc <= kEmitThreads ? 1 : 0;
+  if (!fused)
+    hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, st, v, pb, pc, offset, n_cmp,
+                       n_bl);
   const uint32_t chunks = uint32_t(std::max(1, (v.max_na + kEmitChunk - 1) / kEmitChunk));
-  hipLaunchKernelGGL(emit_kernel, dim3(pc, chunks), dim3(kEmitThreads), 0, st, v, pb, offset, oq,
-                     om, od1, od2, am, ad1, ad2, ac);
+  hipLaunchKernelGGL(emit_kernel, dim3(pc, chunks), dim3(kEmitThreads), 0, st, v, pb, fused,
+                     offset, n_cmp, n_bl, oq, om, od1, od2, am, ad1, ad2, ac);
   return hipGetLastError();
 }
 
