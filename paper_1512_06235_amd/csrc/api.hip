@@ -109,8 +109,8 @@ int hip_fail(sfm_ctx* ctx, hipError_t e, const char* what) {
 
 // Sections of one call's workspace.
 struct Layout {
-  size_t pairs, F, order, geom, counters, wg_start, cand_x, cand_y, cand_nc, cand_j, bins, qrec,
-      res, twin, groups, gcost, pcost, total, staged;
+  size_t pairs, F, order, items, geom, counters, wg_start, cand_x, cand_y, cand_nc, cand_j, bins,
+      qrec, res, twin, groups, gcost, pcost, part, total, staged;
   int32_t wgs = 0;
   int64_t sum_na = 0, sum_nc = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
   int32_t max_na = 0;
@@ -120,7 +120,10 @@ int32_t bins_for(int32_t nb, int32_t features_per_bin) {
   return std::max<int32_t>(1, std::min<int32_t>(kMaxBins, nb / features_per_bin));
 }
 
-Layout plan(const PairDesc* pd, size_t P, int32_t device, int32_t group_tiles) {
+// n_items and n_part: the exhaustive form's work items (staged with the pair
+// table) and partial results; 0 for the other forms.
+Layout plan(const PairDesc* pd, size_t P, int32_t device, int32_t group_tiles,
+            int64_t n_items = 0, int64_t n_part = 0) {
   Layout L;
   for (size_t k = 0; k < P; ++k) {
     const PairDesc& p = pd[k];
@@ -135,6 +138,7 @@ Layout plan(const PairDesc* pd, size_t P, int32_t device, int32_t group_tiles) {
   L.pairs = o; o = align_up(o + P * sizeof(PairDesc));
   L.F = o; o = align_up(o + P * 9 * sizeof(double));
   L.order = o; o = align_up(o + P * sizeof(int32_t));
+  L.items = o; o = align_up(o + size_t(n_items) * sizeof(int2));
   L.staged = o;
   L.geom = o; o = align_up(o + P * sizeof(PairGeom));
   L.counters = o; o = align_up(o + P * sizeof(PairCounters));
@@ -151,12 +155,14 @@ Layout plan(const PairDesc* pd, size_t P, int32_t device, int32_t group_tiles) {
   L.groups = o; o = align_up(o + size_t(L.sum_groups) * sizeof(TileGroup));
   L.gcost = o; o = align_up(o + size_t(L.sum_groups) * sizeof(int32_t));
   L.pcost = o; o = align_up(o + P * sizeof(long long));
+  L.part = o; o = align_up(o + size_t(n_part) * sizeof(uint2));
   L.total = o;
   return L;
 }
 
-Layout plan(const std::vector<PairDesc>& pd, int32_t device, int32_t group_tiles) {
-  return plan(pd.data(), pd.size(), device, group_tiles);
+Layout plan(const std::vector<PairDesc>& pd, int32_t device, int32_t group_tiles,
+            int64_t n_items = 0, int64_t n_part = 0) {
+  return plan(pd.data(), pd.size(), device, group_tiles, n_items, n_part);
 }
 
 // The images pairs refer to: the registered ones, or views of them (a run of
@@ -472,8 +478,22 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
   rc = describe_pairs(ctx, tab, pairs, n_pairs, exhaustive, pd);
   if (rc) return rc;
   if (!exhaustive && (rc = check_F(ctx, F, n_pairs))) return rc;
+  int64_t n_items = 0, n_part = 0;
+  if (exhaustive) {
+    for (int32_t k = 0; k < n_pairs; ++k) {
+      if (pd[size_t(k)].na > kExhaustiveMaxQueries || pd[size_t(k)].nb > kExhaustiveMaxTargets) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "pair %d: exhaustive matching takes at most %d queries and %d targets", k,
+                 kExhaustiveMaxQueries, kExhaustiveMaxTargets);
+        return fail(ctx, SFM_ECAPACITY, buf);
+      }
+    }
+    exhaustive_plan(pd.data(), n_pairs, nullptr, &n_items, &n_part);
+    if (n_items > INT32_MAX) return fail(ctx, SFM_ECAPACITY, "too many work items in one call");
+  }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  const Layout L = plan(pd, ctx->device, ctx->group_tiles);
+  const Layout L = plan(pd, ctx->device, ctx->group_tiles, n_items, n_part);
   if (!diagnostic && (rc = check_outputs(ctx, out, L, opt))) return rc;
   if (diagnostic && opt.emit_all) return fail(ctx, SFM_EINVAL, "emit_all has no outputs here");
 
@@ -491,6 +511,8 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
   memcpy((*S.pinned) + L.pairs, pd.data(), pd.size() * sizeof(PairDesc));
   if (exhaustive) {
     memset((*S.pinned) + L.F, 0, pd.size() * 9 * sizeof(double));
+    exhaustive_plan(pd.data(), n_pairs, reinterpret_cast<int2*>((*S.pinned) + L.items), &n_items,
+                    &n_part);
   } else {
     memcpy((*S.pinned) + L.F, F, pd.size() * 9 * sizeof(double));
   }
@@ -540,6 +562,20 @@ int match_locked(sfm_ctx* ctx, const ImageTable& tab, const sfm_pair* pairs, int
                                out->n_comparisons, out->n_borderline, am, ad1, ad2, ac, st));
       HIP_TRY(ctx, prof_mark(ctx, st));
     }
+  } else if (exhaustive) {
+    // No preparation: the exhaustive kernels read the images directly and
+    // leave the index in b (emission maps nothing).
+    BatchView ve = v;
+    ve.cand_j = nullptr;
+    HIP_TRY(ctx, prof_mark(ctx, st));
+    HIP_TRY(ctx, prof_mark(ctx, st));
+    HIP_TRY(ctx, launch_exhaustive(ve, reinterpret_cast<const int2*>((*S.ws) + L.items), n_items,
+                                   reinterpret_cast<uint2*>((*S.ws) + L.part), st));
+    HIP_TRY(ctx, prof_mark(ctx, st));
+    HIP_TRY(ctx, launch_emit(ve, 0, n_pairs, out->offset, out->query, out->match, out->d1,
+                             out->d2, out->n_comparisons, out->n_borderline, am, ad1, ad2, ac,
+                             st));
+    HIP_TRY(ctx, prof_mark(ctx, st));
   } else if (replay && key_repeats(ctx, key)) {
     if ((rc = replay_batched(ctx, key, am, ad1, ad2, ac, st))) return rc;
   } else {

@@ -53,6 +53,7 @@ struct PairDesc {
   double band;              // d, pixels (may be +inf)
   int32_t ignore_band;      // exhaustive matching
   int32_t pad;
+  int64_t ex_off;           // exhaustive matching: first partial result (prefix of n_a * slices)
 };
 
 enum GeomMode : int32_t {
@@ -338,6 +339,19 @@ hipError_t launch_emit(const BatchView& v, int32_t pair_begin, int32_t pair_coun
                        int64_t* offset, int32_t* out_q, int32_t* out_m, int32_t* out_d1,
                        int32_t* out_d2, int64_t* n_cmp, int64_t* n_bl, int32_t* all_m,
                        int32_t* all_d1, int32_t* all_d2, int32_t* all_c, hipStream_t st);
+// Exhaustive matching (kernels_exhaustive.hip), without preparation: work
+// items of (pair, 256 queries, 1024 targets).  exhaustive_plan sets each
+// pair's ex_off and, when `items` is not NULL, writes the item table (one
+// int2 {pair, query block << 16 | slice} per item); n_part receives the
+// partial results (uint2) the call needs.  launch_exhaustive resets the
+// pairs' counters, matches every item and merges each query's slices into
+// v.res (the index in b: emission runs with v.cand_j NULL).
+constexpr int32_t kExhaustiveMaxQueries = 32767 * 256;   // query blocks fit 15 bits
+constexpr int32_t kExhaustiveMaxTargets = 65535 * 1024;  // slices fit 16 bits
+void exhaustive_plan(PairDesc* pd, int32_t n_pairs, int2* items, int64_t* n_items,
+                     int64_t* n_part);
+hipError_t launch_exhaustive(const BatchView& v, const int2* items, int64_t n_items, uint2* part,
+                             hipStream_t st);
 // Diagnostic after a preparation: out[0] receives (atomic max) the bits of
 // the largest |FP32 - FP64| epipolar distance over the evaluated slots whose
 // FP64 distance is at most 2d, out[1] (atomic add) their number.
