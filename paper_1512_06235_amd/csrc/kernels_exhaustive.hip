@@ -88,6 +88,13 @@ __device__ __forceinline__ void dma16(const void* src, uint32_t lds_off) {
   asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
                :: "s"(__builtin_amdgcn_readfirstlane(lds_off)), "v"(src) : "memory", "m0");
 }
+// The same with a uniform base address in SGPRs plus a 32-bit lane offset:
+// no per-lane address arithmetic.
+__device__ __forceinline__ void dma16s(const void* base, uint32_t voff, uint32_t lds_off) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2"
+               :: "s"(__builtin_amdgcn_readfirstlane(lds_off)), "v"(voff), "s"(base)
+               : "memory", "m0");
+}
 #pragma clang diagnostic pop
 
 // Per-byte negation of four bytes in 0..127 (no borrow crosses a byte).
@@ -102,15 +109,27 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
 // Rows of targets t .. t + kExBuf - 1 into buffer `buf`: wave w fetches rows
 // kExRowsPerWave w .. + kExRowsPerWave - 1, eight per instruction (lane l:
 // row 8 u + (l >> 3), chunk (l & 7) ^ (row & 7), landing at slot l & 7).
+// A buffer wholly inside b takes the base-address form: the lane's offset
+// voff = (kExRowsPerWave w + (l >> 3)) * 128 + 16 ((l & 7) ^ (l >> 3)) is the
+// same for every buffer and instruction (row 8 u + (l >> 3) of the wave's
+// rows: the base advances by 8 rows per instruction).
 __device__ __forceinline__ void issue_rows(const uint8_t* b_desc, int32_t nb, int32_t t,
-                                           uint32_t lds_rows, int w, int lane) {
+                                           uint32_t lds_rows, uint32_t voff, int w, int lane) {
+  const uint32_t lw = lds_rows + uint32_t(kExRowsPerWave * w * kDescBytes);
+  if (t + kExBuf <= nb) {
+    const uint8_t* base = b_desc + int64_t(t) * kDescBytes;
+#pragma unroll
+    for (int u = 0; u < kExRowsPerWave / 8; ++u)
+      dma16s(base + 8 * u * kDescBytes, voff, lw + uint32_t(8 * u * kDescBytes));
+    return;
+  }
 #pragma unroll
   for (int u = 0; u < kExRowsPerWave / 8; ++u) {
     const int r = kExRowsPerWave * w + 8 * u + (lane >> 3);
     const int c = (lane & 7) ^ (r & 7);
     const int32_t j = t + r;
     const uint8_t* src = j < nb ? b_desc + int64_t(j) * kDescBytes + 16 * c : zero_row + 16 * c;
-    dma16(src, lds_rows + uint32_t((kExRowsPerWave * w + 8 * u) * kDescBytes));
+    dma16(src, lw + uint32_t(8 * u * kDescBytes));
   }
 }
 
@@ -190,7 +209,9 @@ void exhaustive_kernel(BatchView v, const int2* items, int32_t n_items, uint2* p
   const uint32_t lrows = lbase + uint32_t(offsetof(ExLds, rows));
 
   // The first buffer, the wave's query rows and the first norm words.
-  issue_rows(B.desc, P.nb, t0, lrows, w, lane);
+  const uint32_t voff = uint32_t((kExRowsPerWave * w + (lane >> 3)) * kDescBytes +
+                                 16 * ((lane & 7) ^ ((lane >> 3) & 7)));
+  issue_rows(B.desc, P.nb, t0, lrows, voff, w, lane);
   const int col = lane & (kQueryTile - 1), g = lane >> 4;
   const int32_t qw = qb * kExQueries + kExTiles * kQueryTile * w;   // the wave's first query
   nv4u qr[kExTiles][2];
@@ -222,8 +243,8 @@ void exhaustive_kernel(BatchView v, const int2* items, int32_t n_items, uint2* p
     const bool more = f + 1 < nfill;
     // The next buffer: its rows by DMA, its norm words into a register.
     if (more) {
-      issue_rows(B.desc, P.nb, tf + kExBuf, lrows + uint32_t((cur ^ 1) * kExBuf * kDescBytes), w,
-                 lane);
+      issue_rows(B.desc, P.nb, tf + kExBuf, lrows + uint32_t((cur ^ 1) * kExBuf * kDescBytes),
+                 voff, w, lane);
       if (tid < kExBuf) nw = norm_word(B.norm2, P.nb, tf + kExBuf + tid);
     }
     const int32_t nsteps = (min(kExBuf, t0 + cnt - tf) + kQueryTile - 1) / kQueryTile;
