@@ -831,12 +831,24 @@ def main():
         cg = int(o2.n_comparisons[0])
         tb = timed(b2, 5, stream) / 5
         cb = int(o2.n_comparisons[0])
+        m2.close()
+        # Exhaustive matching of the whole batch (its own output buffers).
+        log("bench: exhaustive matching of the batch")
+        ob = m.buffers(pairs)
+        bb = lambda: sfm.sfm_bruteforce_match(m.ctx, pairs, None, ob, opt, stream)  # noqa
+        bb()
+        tbb = timed(bb, 3, stream) / 3
+        cbb = int(ob.n_comparisons[: len(pairs)].sum())
         context = {"workload": "one pair, 16,000 features per image, band 4 px",
                    "guided_ms": round(tg * 1e3, 4), "guided_comparisons": cg,
                    "bruteforce_ms": round(tb * 1e3, 4), "bruteforce_comparisons": cb,
                    "bruteforce_int8_tops": round(256.0 * cb / tb / 1e12, 2),
-                   "guided_speedup_vs_bruteforce": round(tb / tg, 2)}
-        m2.close()
+                   "guided_speedup_vs_bruteforce": round(tb / tg, 2),
+                   "batch_bruteforce_ms": round(tbb * 1e3, 4),
+                   "batch_bruteforce_comparisons": cbb,
+                   "batch_bruteforce_int8_tops": round(256.0 * cbb / tbb / 1e12, 2),
+                   "batch_guided_speedup_vs_bruteforce": round(tbb / (elapsed / args.steps), 2)}
+        del ob
 
     serve = None
     if not args.no_serving:

@@ -189,7 +189,9 @@ int sfm_guided_match_noalloc(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pair
 
 /* Exhaustive matching: every feature of b is a candidate of every query
  * (band and F ignored; F may be NULL).  Same outputs; equals guided matching
- * with band_px = +inf on queries whose line is not degenerate. */
+ * with band_px = +inf on queries whose line is not degenerate.  n_borderline
+ * is 0.  Errors: as sfm_guided_match, and SFM_ECAPACITY for an image of more
+ * than 8,388,352 queries or 67,107,840 targets in a pair. */
 int sfm_bruteforce_match(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, const double* F,
                          const sfm_options* opt, const sfm_matches* out, void* stream);
 
