@@ -113,7 +113,7 @@ struct Layout {
       qrec, res, twin, groups, gcost, pcost, part, total, staged;
   int32_t wgs = 0;
   int64_t sum_na = 0, sum_nc = 0, sum_bins = 0, sum_blocks = 0, sum_groups = 0;
-  int32_t max_na = 0;
+  int32_t max_na = 0, max_nb = 0;
 };
 
 int32_t bins_for(int32_t nb, int32_t features_per_bin) {
@@ -129,6 +129,7 @@ Layout plan(const PairDesc* pd, size_t P, int32_t device, int32_t group_tiles,
     const PairDesc& p = pd[k];
     L.sum_na += p.na;
     L.max_na = std::max(L.max_na, p.na);
+    L.max_nb = std::max(L.max_nb, p.nb);
     L.sum_nc += p.nb + kCandPad;
     L.sum_bins += p.nbins + 1;
     L.sum_blocks += p.nblocks;
@@ -442,6 +443,7 @@ BatchView batch_view(const sfm_ctx* ctx, const ImageTable& tab, char* ws, const 
   v.keep_counts = opt.emit_all ? 1 : 0;
   v.group_tiles = ctx->group_tiles;
   v.max_na = L.max_na;
+  v.max_nb = L.max_nb;
   v.margin = opt.recheck_margin_px;
   v.groups = reinterpret_cast<TileGroup*>(ws + L.groups);
   return v;

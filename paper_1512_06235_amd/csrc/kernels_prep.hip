@@ -482,6 +482,20 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
   for (int32_t r = kCacheRounds; r < rounds; ++r) place_round(r, nullptr);
   if (!perm) return;
   __syncthreads();
+  if (NT == kBinThreadsFew) {
+    // A batch of few pairs: the item of every position, in position order
+    // (coalesced), into cand_j for targets (one of their outputs) or into
+    // the records' index field for queries; gather_kernel then writes the
+    // records over the whole GPU instead of this one workgroup.
+    for (int32_t pos = threadIdx.x; pos < n; pos += NT) {
+      const int32_t j = perm[pos];
+      if (kTargets)
+        stg(v.cand_j + P.c_off + pos, j);
+      else
+        stg(&v.qrec[P.q_off + pos].i, j);
+    }
+    return;
+  }
   // Gather pass: positions in order, kBatch per thread per round (every
   // thread runs every round: the tile windows shuffle across lanes).
   for (int32_t r = 0; r < rounds; ++r) {
@@ -512,6 +526,12 @@ __device__ __forceinline__ void sort_side(const BatchView& v, const PairDesc& P,
 constexpr int kBinLdsInts = 16384;
 constexpr int kBinWsumMax = kBinThreadsFew / 64;
 static_assert(kMaxBins + 2 + kBinWsumMax <= kBinLdsInts, "histogram fits");
+
+// Whether a side of n items and nh bins sorts through an LDS permutation
+// (its records then come from gather_kernel) or scatters them directly.
+__host__ __device__ constexpr bool perm_fits(int32_t nh, int32_t n, int32_t wsum_ints) {
+  return ((nh + 2) & ~1) + (n + 1) / 2 <= kBinLdsInts - wsum_ints;
+}
 
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
@@ -564,8 +584,7 @@ void bin_kernel(BatchView v, int32_t pb, const int32_t* order) {
   const int32_t n = targets ? P.nb : P.na;
   const int32_t hist_ints = (nh + 2) & ~1;
   uint16_t* perm = nullptr;
-  if (hist_ints + (n + 1) / 2 <= kBinLdsInts - kBinWsum)
-    perm = reinterpret_cast<uint16_t*>(lds + hist_ints);
+  if (perm_fits(nh, n, kBinWsum)) perm = reinterpret_cast<uint16_t*>(lds + hist_ints);
   if (targets) {
     // Padding after the pair's targets: a NaN x fails every band test.
     if (int(threadIdx.x) < kCandPad) {
@@ -578,6 +597,43 @@ void bin_kernel(BatchView v, int32_t pb, const int32_t* order) {
     sort_side<NT, true>(v, P, g, I, hist, wsum, nh, perm);
   } else {
     sort_side<NT, false>(v, P, g, I, hist, wsum, nh, perm);
+  }
+}
+
+// Batches of few pairs (1,024-thread binning): the records of every side
+// that binning sorted through its LDS permutation, one thread per sorted
+// position of block (pair, y, side): the
+// position's item (left in cand_j or the record's index by bin_kernel), its
+// keypoint and norm or its FP64 line and window, the outputs in position
+// order, and per 16-query tile the union of its windows (16 consecutive
+// positions on 16 lanes).  Spreading these random reads and the FP64 line
+// arithmetic over the GPU takes them off the one workgroup per side.
+constexpr int kGatherThreads = 256;
+__global__ __launch_bounds__(kGatherThreads) void gather_kernel(BatchView v, int32_t pb,
+                                                                int32_t wsum_ints) {
+  const int32_t p = pb + int32_t(blockIdx.x);
+  const PairDesc P = v.pairs[p];
+  const bool targets = blockIdx.z != 0;
+  const int32_t n = targets ? P.nb : P.na;
+  const int32_t base = int32_t(blockIdx.y) * kGatherThreads;
+  if (P.ignore_band || base >= n) return;   // uniform
+  const PairGeom& g = v.geom[p];
+  const int32_t nh = targets ? g.nbins : g.nbins + 1;
+  if (!perm_fits(nh, n, wsum_ints)) return;   // scattered by bin_kernel itself
+  const ImageDev& I = v.images[targets ? P.b : P.a];
+  const int32_t pos = base + int32_t(threadIdx.x);
+  const int32_t pc = min(pos, n - 1);
+  if (targets) {
+    const int32_t j = ldg(v.cand_j + P.c_off + pc);
+    const float x = ldg(I.xy + 2 * j), y = ldg(I.xy + 2 * j + 1);
+    const int32_t nrm = ldg(I.norm2 + j);
+    if (pos < n) write_sorted<true>(v, P, g, pos, j, x, y, nrm);
+  } else {
+    const int32_t j = ldg(&v.qrec[P.q_off + pc].i);
+    const float x = ldg(I.xy + 2 * j), y = ldg(I.xy + 2 * j + 1);
+    int2 w = make_int2(1, 0);
+    if (pos < n) w = write_sorted<false>(v, P, g, pos, j, x, y, 0);
+    store_tile_window(v, P, pos, n, w);
   }
 }
 
@@ -745,12 +801,18 @@ hipError_t launch_prepare(const BatchView& v, int32_t pb, int32_t pc, int32_t gr
                           int32_t max_queries, hipStream_t st) {
   if (pc <= 0) return hipSuccess;
   hipLaunchKernelGGL(geometry_kernel, dim3((pc + 63) / 64), dim3(64), 0, st, v, pb, pc);
-  if (2 * pc <= kFewPairsWorkgroups)
+  const bool few = 2 * pc <= kFewPairsWorkgroups;
+  if (few)
     hipLaunchKernelGGL(bin_kernel<kBinThreadsFew>, dim3(2 * pc), dim3(kBinThreadsFew), 0, st, v,
                        pb, order);
   else
     hipLaunchKernelGGL(bin_kernel<kBinThreads>, dim3(2 * pc), dim3(kBinThreads), 0, st, v, pb,
                        order);
+  if (few) {
+    const int32_t nmax = std::max(std::max(max_queries, v.max_nb), 1);
+    hipLaunchKernelGGL(gather_kernel, dim3(pc, (nmax + kGatherThreads - 1) / kGatherThreads, 2),
+                       dim3(kGatherThreads), 0, st, v, pb, kBinThreadsFew / 64);
+  }
   const int32_t tiles = (max_queries + kQueryTile - 1) / kQueryTile;
   const int32_t qblocks = (tiles + kRangeTiles - 1) / kRangeTiles;
   if (qblocks > 0) {

@@ -155,6 +155,8 @@ struct BatchView {
   int32_t keep_counts;
   int32_t group_tiles;      // tiles per group (4 or 8: one or two per match wave)
   int32_t max_na;           // most queries of one pair (sizes the emission grid)
+  int32_t max_nb;           // most targets of one pair (sizes the gather grid)
+  int32_t pad_nb;
   double margin;            // FP64 re-decision margin around d, pixels (0 = FP32 only)
 };
 
