@@ -106,7 +106,8 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
   return max(min(a, b), min(max(a, b), c));   // selects v_med3_u32
 }
 
-// Rows of targets t .. t + kExBuf - 1 into buffer `buf`: wave w fetches rows
+// Rows of targets t .. t + kExBuf - 1 into the buffer at LDS offset
+// lds_rows: wave w fetches rows
 // kExRowsPerWave w .. + kExRowsPerWave - 1, eight per instruction (lane l:
 // row 8 u + (l >> 3), chunk (l & 7) ^ (row & 7), landing at slot l & 7).
 // A buffer wholly inside b takes the base-address form: the lane's offset
@@ -251,8 +252,8 @@ void exhaustive_kernel(BatchView v, const int2* items, int32_t n_items, uint2* p
     // Step i: A operand from buffer row 16 i + col, k-slices g and g + 4
     // (chunk slots g ^ (row & 7) and that ^ 4); norm words of rows
     // 16 i + 4 g .. + 3.  A whole buffer runs unrolled with step i + 1's
-    // MFMAs issued before step i's fold, so the matrix core and the VALU of
-    // one wave overlap; a partial buffer (the end of b) runs step by step.
+    // MFMAs issued before step i's fold, so the matrix core's work can
+    // overlap the fold; a partial buffer (the end of b) runs step by step.
     const uint8_t* r0 = lds.rows[cur] + col * kDescBytes + ((g ^ (col & 7)) << 4);
     const uint8_t* r1 = lds.rows[cur] + col * kDescBytes + (((g ^ (col & 7)) ^ 4) << 4);
     const uint32_t* nb4 = lds.nc[cur] + 4 * g;
