@@ -140,7 +140,10 @@ int sfm_destroy(sfm_ctx* ctx);
  * The caller's buffers must stay valid while the registration is in use. */
 int sfm_register_images(sfm_ctx* ctx, const sfm_image* images, int32_t n_images);
 
-/* Device workspace bytes that matching these pairs needs. */
+/* Device workspace bytes that guided matching of these pairs needs (the
+ * batched, plain and no-alloc forms).  Exhaustive matching needs, on top,
+ * 8 bytes per query per 1,024 targets of b and 8 bytes per work item of
+ * 256 queries x 1,024 targets. */
 int sfm_workspace_size(sfm_ctx* ctx, const sfm_pair* pairs, int32_t n_pairs, size_t* bytes);
 
 /* Batched guided matching (Section 6.2, Appendix A steps 1-4), every pair in
