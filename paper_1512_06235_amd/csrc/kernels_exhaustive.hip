@@ -248,7 +248,10 @@ void exhaustive_kernel(BatchView v, const int2* items, int32_t n_items, uint2* p
                  voff, w, lane);
       if (tid < kExBuf) nw = norm_word(B.norm2, P.nb, tf + kExBuf + tid);
     }
-    const int32_t nsteps = (min(kExBuf, t0 + cnt - tf) + kQueryTile - 1) / kQueryTile;
+    // A wave whose queries all lie past n_a only fetches its share of the
+    // buffers and meets the barriers.
+    const int32_t nsteps =
+        qw < P.na ? (min(kExBuf, t0 + cnt - tf) + kQueryTile - 1) / kQueryTile : 0;
     // Step i: A operand from buffer row 16 i + col, k-slices g and g + 4
     // (chunk slots g ^ (row & 7) and that ^ 4); norm words of rows
     // 16 i + 4 g .. + 3.  A whole buffer runs unrolled with step i + 1's
