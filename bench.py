@@ -7,7 +7,7 @@ per-image feature counts log-uniform in 2k-20k, pairs 5-30 deg apart, band
 binning, query tiles, the fused match kernel, ordered emission), with every
 image's keypoints and descriptors already resident in HBM.  The plain
 per-pair form is timed on the same pairs, and the exhaustive GPU matcher on
-the 16k-feature pair as context.  Prints one JSON line.
+the 16k-feature pair and on the whole batch as context.  Prints one JSON line.
 """
 from __future__ import annotations
 
